@@ -1,0 +1,220 @@
+/*
+ * octo.h -- C interface of an MI355X (gfx950) implementation of the gravity
+ * solve of Octo-Tiger (Marcello et al., arXiv 2101.08226): a Cartesian fast
+ * multipole method (FMM) on an adaptive octree of 8x8x8 sub-grids with the
+ * angular-momentum correction (Sec. 2.2, "Gravity Update and the Angular
+ * Momentum Correction").
+ *
+ * Problem solved (Sec. 2.1, Poisson equation and g = -grad phi; code units
+ * with G = 1, Sec. 2.9; isolated boundaries, Sec. 2.6): every leaf cell of the
+ * octree is a point mass m = rho h^3 at its centre; the library returns, for
+ * each leaf cell, the potential phi and the acceleration g = -grad phi of all
+ * other cells, computed by the multipole method with opening angle theta.
+ *
+ * Geometry: the domain is the unit cube [-1/2, 1/2]^3.  The root sub-grid
+ * (level 0) has 8^3 cells of width 1/8; a sub-grid at level l with index
+ * (ix, iy, iz) in [0, 2^l)^3 covers cells of width h = 1/(8 * 2^l) whose
+ * global indices are 8*(ix, iy, iz) + [0, 8)^3; the centre of global cell i
+ * is -1/2 + (i + 1/2) h (Sec. 2.4 octree, Sec. 3.2 level numbering).
+ *
+ * Memory: "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ * device memory on the context's device.  The library never keeps a caller
+ * pointer beyond the call that receives it, except the output buffers of a
+ * submitted request (octo_submit), which must stay valid until the request
+ * completes.  Device memory owned by the library is obtained through the
+ * context's allocator (or hipMalloc when none is given) at tree-build time; a
+ * solve allocates nothing.
+ *
+ * Errors: every call returns an octo_status; nothing throws or aborts across
+ * this interface.  octo_last_error() returns a thread-local description of the
+ * last failure on the calling thread.
+ */
+#ifndef OCTO_H
+#define OCTO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OCTO_OK = 0,
+    OCTO_E_INVALID = 1,     /* bad argument, malformed tree or density */
+    OCTO_E_DEVICE = 2,      /* a HIP call failed */
+    OCTO_E_BUDGET = 3,      /* the request does not fit the context's HBM budget */
+    OCTO_E_UNSUPPORTED = 4, /* valid but unsupported option (e.g. theta < 0.34) */
+    OCTO_E_STATE = 5,       /* object in the wrong state (e.g. tree from another context) */
+    OCTO_E_PENDING = 6      /* request not finished yet (octo_poll) */
+} octo_status;
+
+typedef struct octo_ctx octo_ctx;
+typedef struct octo_tree octo_tree;
+
+/* Device-memory provider: alloc(bytes, user) returns device memory on the
+ * context's device (NULL on failure), free(ptr, user) releases it.  Lets a
+ * caller route the library's memory through its own pool (e.g. PyTorch's
+ * caching allocator). */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} octo_allocator;
+
+/* One leaf sub-grid: refinement level and sub-grid index at that level. */
+typedef struct {
+    int32_t level, ix, iy, iz;
+} octo_leaf;
+
+enum { OCTO_FP64 = 0, OCTO_MIXED = 1 };
+
+/* Solve options.
+ * theta: opening angle; cells A, B at one level are well separated when
+ *   dx/|x_A - x_B| < theta on geometric centres (Sec. 2.2), evaluated as
+ *   (theta*theta)*|i_A - i_B|^2 > 1 on integer cell indices in IEEE double.
+ *   Must lie in [0.34, 1): 0.34 is the paper's minimum for 8^3 sub-grids.
+ * G: gravitational constant (1 in code units, Sec. 2.9).
+ * precision: OCTO_FP64 computes everything in double precision;
+ *   OCTO_MIXED evaluates the bulk of the multipole-to-local and near-field
+ *   terms in single precision with single-precision partial sums, keeping the
+ *   moments, the angular-momentum correction and the final accumulation in
+ *   double precision.
+ * amc: 1 applies the angular-momentum correction (Sec. 2.2), 0 omits it. */
+typedef struct {
+    double theta;
+    double G;
+    int32_t precision;
+    int32_t amc;
+} octo_opts;
+
+/* Per-solve diagnostics (all over leaf cells; x about the origin):
+ * total_mass = sum m; net_force = sum m g; net_torque = sum x cross m g;
+ * force_scale = sum m |g|; torque_scale = sum |x| m |g| (so
+ * |net_torque| / torque_scale is the relative torque residual, the quantity
+ * the correction drives to rounding level, Sec. 2.2); pair counts are the
+ * ordered cell pairs evaluated by the multipole and the direct kernels;
+ * device_ms is the device time of the solve measured with HIP events. */
+typedef struct {
+    double total_mass;
+    double net_force[3];
+    double net_torque[3];
+    double force_scale;
+    double torque_scale;
+    int64_t n_leaf_cells;
+    int64_t m2l_pairs;
+    int64_t direct_pairs;
+    double device_ms;
+    /* per-phase device time (ms) when profiling is on (octo_ctx_set_profiling):
+     * [0] leaf masses (P2M), [1] upward pass (M2M, all levels), [2] multipole
+     * interactions (M2L with the correction, all levels), [3] downward pass
+     * (L2L, interior levels), [4] leaf kernel (near field, cross-level pairs,
+     * final shift, potential and acceleration), [5] statistics reduction;
+     * zeros otherwise */
+    double phase_ms[6];
+} octo_stats;
+
+/* Density at n points: xyz is 3n doubles (x0,y0,z0,x1,...), rho_out n doubles. */
+typedef void (*octo_density_fn)(int64_t n, const double *xyz, double *rho_out, void *user);
+/* Maximum density over n boxes: lo, hi are 3n doubles (corners), out n doubles. */
+typedef void (*octo_boxmax_fn)(int64_t n, const double *lo, const double *hi, double *out, void *user);
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t on that
+ * device used for every launch of this context, or NULL to create a private
+ * stream (default priority).  alloc: optional device-memory provider (copied;
+ * NULL means hipMalloc/hipFree).  hbm_budget: maximum bytes of device memory
+ * the context may hold for trees (0 = no limit).
+ * Errors: OCTO_E_INVALID (out == NULL), OCTO_E_DEVICE (device not usable). */
+octo_status octo_ctx_create(int device, void *hip_stream, const octo_allocator *alloc, size_t hbm_budget,
+                            octo_ctx **out);
+/* Waits for outstanding work, then frees the context.  Trees must be
+ * destroyed first (OCTO_E_STATE otherwise). */
+octo_status octo_ctx_destroy(octo_ctx *ctx);
+/* Profiling: when on != 0, solves launch their kernels one by one (no graph
+ * replay) with HIP events between phases, and octo_stats.phase_ms is filled. */
+octo_status octo_ctx_set_profiling(octo_ctx *ctx, int on);
+/* Bytes of device memory currently held by the context's trees. */
+octo_status octo_ctx_memory(const octo_ctx *ctx, size_t *bytes_in_use, size_t *budget);
+
+/* ---- trees (Sec. 2.4: one 8^3 sub-grid per octree node; interior nodes have
+ *      8 children; neighbouring sub-grids, across faces, edges and corners,
+ *      differ by at most one level) ---------------------------------------- */
+
+/* Tree from an explicit leaf list.  The leaves must tile the unit box
+ * exactly once and be properly nested.  rho: n_leaves x 512 densities, leaf
+ * by leaf in the given order, cells (ix, iy, iz) within a sub-grid with iz
+ * fastest; host memory, or device memory when rho_on_device != 0; copied.
+ * Results of octo_solve use the same layout.
+ * Errors: OCTO_E_INVALID (gap, overlap, duplicate, level > 9, improper
+ * nesting, density negative or not finite), OCTO_E_BUDGET, OCTO_E_DEVICE. */
+octo_status octo_tree_build(octo_ctx *ctx, const octo_leaf *leaves, int64_t n_leaves, const double *rho,
+                            int rho_on_device, octo_tree **out);
+/* Uniform tree: every leaf at `level` (0..6), n = 8 * 2^level cells per axis.
+ * rho: n^3 densities indexed (ix*n + iy)*n + iz (iz fastest); results of
+ * octo_solve use this same grid layout.  Errors as octo_tree_build. */
+octo_status octo_tree_build_uniform(octo_ctx *ctx, int level, const double *rho, int rho_on_device,
+                                    octo_tree **out);
+/* Adaptive tree from a density field (Sec. 2.8, fixed-threshold form):
+ * starting from the root, a node at level < max_level is refined when
+ * boxmax over its cube exceeds `threshold`; nodes are then refined until the
+ * tree is properly nested.  The density is evaluated at every leaf-cell
+ * centre.  Leaves are ordered by (level, ix, iy, iz); octo_tree_leaves
+ * returns that order, and results use the leaf layout of octo_tree_build.
+ * Callbacks run on the calling thread during this call only. */
+octo_status octo_tree_build_adaptive(octo_ctx *ctx, octo_density_fn density, octo_boxmax_fn boxmax, void *user,
+                                     int max_level, double threshold, octo_tree **out);
+/* Replace the tree's density (same layout as at build time). */
+octo_status octo_tree_set_density(octo_tree *tree, const double *rho, int rho_on_device);
+/* Sizes: leaf cells, levels (deepest level + 1), device bytes held. */
+octo_status octo_tree_info(const octo_tree *tree, int64_t *n_leaf_cells, int32_t *n_levels, size_t *bytes);
+/* Copy the leaf list (n_leaves entries) into caller memory. */
+octo_status octo_tree_leaves(const octo_tree *tree, octo_leaf *out);
+octo_status octo_tree_destroy(octo_tree *tree);
+
+/* ---- solve -------------------------------------------------------------- */
+
+/* Potential and acceleration at every leaf cell of `tree`.
+ * phi: n_leaf_cells doubles; g: 3 x n_leaf_cells doubles, component-major
+ * (gx for all cells, then gy, then gz); both in the tree's density layout.
+ * out_on_device != 0: phi and g are device pointers and the call returns once
+ * the work is enqueued on the context stream (stream-ordered, like a kernel
+ * launch) unless stats != NULL; out_on_device == 0: host pointers, the call
+ * returns when the results are copied.  stats may be NULL.
+ * Errors: OCTO_E_UNSUPPORTED (theta outside [0.34, 1), unknown precision),
+ * OCTO_E_INVALID (NULL outputs, non-finite G), OCTO_E_STATE (tree from another
+ * context), OCTO_E_DEVICE. */
+octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, double *phi, double *g,
+                       int out_on_device, octo_stats *stats);
+
+/* Solve n independent trees with one launch per phase of the method, all
+ * trees together (the phases are captured once into a HIP graph per batch
+ * signature and replayed).  phi[i], g[i] as in octo_solve for trees[i];
+ * stats: NULL or n entries.  Results are identical, bit for bit, to solving
+ * each tree alone. */
+octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, const octo_opts *opts,
+                             double *const *phi, double *const *g, int out_on_device, octo_stats *stats);
+
+/* ---- asynchronous requests (continuous batching) ------------------------ */
+
+typedef int64_t octo_ticket;
+
+/* Enqueue a solve of `tree` (outputs on the device).  Requests submitted
+ * while others run are merged into the next launch wave; results are identical
+ * to octo_solve.  Returns OCTO_E_BUDGET if the context cannot hold the
+ * request's scratch right now (the caller retries later). */
+octo_status octo_submit(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, double *phi_dev, double *g_dev,
+                        octo_ticket *ticket);
+/* Drive pending work; *done = 1 when the ticket's results are ready. */
+octo_status octo_poll(octo_ctx *ctx, octo_ticket ticket, int *done);
+/* Block until the ticket's results are ready; fills stats if not NULL. */
+octo_status octo_wait(octo_ctx *ctx, octo_ticket ticket, octo_stats *stats);
+
+const char *octo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCTO_H */

@@ -1,0 +1,42 @@
+/*
+ * octo_host.h -- host-only introspection of liboctofmm (no GPU needed).
+ *
+ * These calls expose the library's host logic -- tree validation and layout,
+ * adaptive refinement, interaction stencils -- so that it can be checked on a
+ * machine without a GPU.  They allocate only host memory and never touch a
+ * device.  Return values and errors follow include/octo.h (octo_status, with
+ * octo_last_error() describing failures).
+ */
+#ifndef OCTO_HOST_H
+#define OCTO_HOST_H
+
+#include "octo.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Stencil sizes for opening angle theta (levels >= 1), per parity class p of
+ * the target cell (p = (ix&1)<<2 | (iy&1)<<1 | (iz&1)):
+ * out[p] = multipole partners (well separated, parents not; Sec. 2.2),
+ * out[8+p] = near partners (neither, excluding the cell itself),
+ * out[16+p] = maximum |offset| component over both lists.
+ * Errors: OCTO_E_UNSUPPORTED for theta outside [0.34, 1). */
+octo_status octo_host_stencil_sizes(double theta, int32_t *out);
+
+/* Validate a leaf list exactly as octo_tree_build does and report its layout:
+ * out[3*l+0] = nodes at level l, out[3*l+1] = interior nodes, out[3*l+2] =
+ * leaf nodes that touch an interior node of their level; *n_levels = deepest
+ * level + 1.  out must hold 3 * 10 entries. */
+octo_status octo_host_layout(const octo_leaf *leaves, int64_t n_leaves, int32_t *n_levels, int64_t *out);
+
+/* Leaf list of octo_tree_build_adaptive (same refinement and nesting rule,
+ * same order).  If out is NULL or cap is too small only *n is set. */
+octo_status octo_host_adaptive_leaves(octo_boxmax_fn boxmax, void *user, int max_level, double threshold,
+                                      octo_leaf *out, int64_t cap, int64_t *n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCTO_HOST_H */

@@ -121,11 +121,12 @@ class Tree:
             raise RuntimeError(f"orc_solve failed ({rc})")
         return phi, g
 
-    def last_counts(self):
-        """(multipole pairs, direct pairs) of the last solve, ordered pairs."""
-        out = np.zeros(2, dtype=np.int64)
+    def last_counts(self, split=False):
+        """(multipole pairs, direct pairs) of the last solve, ordered pairs;
+        with split=True also the multipole pairs between two leaf cells."""
+        out = np.zeros(3, dtype=np.int64)
         lib().orc_last_counts(self._h, out.ctypes.data_as(_I64))
-        return int(out[0]), int(out[1])
+        return (int(out[0]), int(out[1]), int(out[2])) if split else (int(out[0]), int(out[1]))
 
     def cell_moments(self, level, gx, gy, gz):
         out = np.empty(40)

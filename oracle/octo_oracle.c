@@ -69,7 +69,7 @@ typedef struct {
 } onode;
 
 typedef struct {
-    int64_t m2l, direct;
+    int64_t m2l, direct, m2l_leaf_leaf;
 } ocount;
 
 typedef struct {
@@ -272,11 +272,13 @@ otree *orc_tree_new(int nleaves, const int32_t *leaves, const double *rho) {
 
 int orc_tree_nlev(const otree *t) { return t->nlev; }
 
-/* Ordered-pair counts of the last solve: multipole interactions and direct
- * point-mass pairs. */
+/* Ordered-pair counts of the last solve: multipole interactions, direct
+ * point-mass pairs, and the multipole interactions between two leaf cells
+ * (which reduce to point-mass pairs). */
 void orc_last_counts(const otree *t, int64_t *out) {
     out[0] = t->last.m2l;
     out[1] = t->last.direct;
+    out[2] = t->last.m2l_leaf_leaf;
 }
 int orc_tree_nnodes(const otree *t) { return t->nnodes; }
 
@@ -507,7 +509,10 @@ static void m2l_cells(const ocell *A, const ocell *B, const oparams *p, double *
 
 static void m2l(otree *t, cref a, cref b, const oparams *p) {
     ocell *A = C(t, a);
-    if (p->cnt) p->cnt->m2l++;
+    if (p->cnt) {
+        p->cnt->m2l++;
+        if (is_leaf(t, a) && is_leaf(t, b)) p->cnt->m2l_leaf_leaf++;
+    }
     m2l_cells(A, C(t, b), p, &A->L0, A->L1, A->L2, A->L3, A->C);
 }
 
@@ -701,10 +706,11 @@ int orc_solve(otree *t, double theta, double G, int amc, int mode, const double 
             if (j != i) interact(t, a, (cref){root, j}, &pt);
         siblings(t, a, &pt);
     }
-    t->last.m2l = t->last.direct = 0;
+    t->last.m2l = t->last.direct = t->last.m2l_leaf_leaf = 0;
     for (int i = 0; i < 512; ++i) {
         t->last.m2l += counts[i].m2l;
         t->last.direct += counts[i].direct;
+        t->last.m2l_leaf_leaf += counts[i].m2l_leaf_leaf;
     }
     free(counts);
     /* downward */

@@ -1,0 +1,402 @@
+"""Python binding of liboctofmm: an MI355X (gfx950) HIP implementation of the
+gravity solve of Octo-Tiger (Marcello et al., arXiv 2101.08226, Sec. 2.2).
+
+The functions named `octo_*` mirror the C interface in include/octo.h one to
+one (ctypes marshalling only).  The small classes below (`Context`, `Tree`)
+route device memory through PyTorch's caching allocator, use a PyTorch stream
+and return results as PyTorch tensors; every step of the solve runs in the HIP
+library.  Importing works without a GPU; any call that needs the library
+raises if it has not been built or no GPU is present.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboctofmm.so")
+
+# status codes (include/octo.h)
+OCTO_OK, OCTO_E_INVALID, OCTO_E_DEVICE, OCTO_E_BUDGET, OCTO_E_UNSUPPORTED, OCTO_E_STATE, OCTO_E_PENDING = range(7)
+OCTO_FP64, OCTO_MIXED = 0, 1
+STATUS_NAMES = {0: "OCTO_OK", 1: "OCTO_E_INVALID", 2: "OCTO_E_DEVICE", 3: "OCTO_E_BUDGET",
+                4: "OCTO_E_UNSUPPORTED", 5: "OCTO_E_STATE", 6: "OCTO_E_PENDING"}
+
+# every symbol include/octo.h declares
+EXPORTS = [
+    "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_tree_build", "octo_tree_build_uniform",
+    "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
+    "octo_solve", "octo_solve_batch", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
+    "octo_host_stencil_sizes", "octo_host_layout", "octo_host_adaptive_leaves",
+]
+
+
+class OctoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class octo_leaf(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("ix", ctypes.c_int32), ("iy", ctypes.c_int32), ("iz", ctypes.c_int32)]
+
+
+class octo_opts(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("G", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("amc", ctypes.c_int32)]
+
+
+class octo_stats(ctypes.Structure):
+    _fields_ = [("total_mass", ctypes.c_double), ("net_force", ctypes.c_double * 3),
+                ("net_torque", ctypes.c_double * 3), ("force_scale", ctypes.c_double),
+                ("torque_scale", ctypes.c_double), ("n_leaf_cells", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
+                ("direct_pairs", ctypes.c_int64), ("device_ms", ctypes.c_double),
+                ("phase_ms", ctypes.c_double * 6)]
+
+    def as_dict(self):
+        F = np.array(self.net_force[:])
+        T = np.array(self.net_torque[:])
+        return dict(total_mass=self.total_mass, net_force=F, net_torque=T, force_scale=self.force_scale,
+                    torque_scale=self.torque_scale, n_leaf_cells=self.n_leaf_cells, m2l_pairs=self.m2l_pairs,
+                    direct_pairs=self.direct_pairs, device_ms=self.device_ms, phase_ms=list(self.phase_ms),
+                    force=float(np.linalg.norm(F) / self.force_scale) if self.force_scale else 0.0,
+                    torque=float(np.linalg.norm(T) / self.torque_scale) if self.torque_scale else 0.0)
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+DENSITY_FN = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                              ctypes.c_void_p)
+BOXMAX_FN = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+
+
+class octo_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liboctofmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2101_08226_amd.build` "
+                           "or __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    sig = {
+        "octo_ctx_create": [_I, _P, ctypes.POINTER(octo_allocator), ctypes.c_size_t, _PP],
+        "octo_ctx_destroy": [_P],
+        "octo_ctx_memory": [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+        "octo_ctx_set_profiling": [_P, _I],
+        "octo_tree_build": [_P, ctypes.POINTER(octo_leaf), _I64, _D, _I, _PP],
+        "octo_tree_build_uniform": [_P, _I, _D, _I, _PP],
+        "octo_tree_build_adaptive": [_P, DENSITY_FN, BOXMAX_FN, _P, _I, ctypes.c_double, _PP],
+        "octo_tree_set_density": [_P, _D, _I],
+        "octo_tree_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t)],
+        "octo_tree_leaves": [_P, ctypes.POINTER(octo_leaf)],
+        "octo_tree_destroy": [_P],
+        "octo_solve": [_P, _P, ctypes.POINTER(octo_opts), _D, _D, _I, ctypes.POINTER(octo_stats)],
+        "octo_solve_batch": [_P, _PP, ctypes.c_int32, ctypes.POINTER(octo_opts), ctypes.POINTER(_D),
+                             ctypes.POINTER(_D), _I, ctypes.POINTER(octo_stats)],
+        "octo_submit": [_P, _P, ctypes.POINTER(octo_opts), _D, _D, ctypes.POINTER(_I64)],
+        "octo_poll": [_P, _I64, ctypes.POINTER(_I)],
+        "octo_wait": [_P, _I64, ctypes.POINTER(octo_stats)],
+        "octo_host_stencil_sizes": [ctypes.c_double, ctypes.POINTER(ctypes.c_int32)],
+        "octo_host_layout": [ctypes.POINTER(octo_leaf), _I64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_I64)],
+        "octo_host_adaptive_leaves": [BOXMAX_FN, _P, _I, ctypes.c_double, ctypes.POINTER(octo_leaf), _I64,
+                                      ctypes.POINTER(_I64)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.octo_last_error.argtypes = []
+    L.octo_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int, allow=()):
+    if status != OCTO_OK and status not in allow:
+        raise OctoError(status, load_library().octo_last_error().decode())
+    return status
+
+
+# ---------------------------------------------------------------- C names
+
+def octo_last_error() -> str:
+    return load_library().octo_last_error().decode()
+
+
+def octo_ctx_create(device: int = 0, hip_stream: int = 0, alloc: Optional[octo_allocator] = None,
+                    hbm_budget: int = 0) -> int:
+    out = ctypes.c_void_p()
+    _check(load_library().octo_ctx_create(device, ctypes.c_void_p(hip_stream or None),
+                                          ctypes.byref(alloc) if alloc is not None else None, hbm_budget,
+                                          ctypes.byref(out)))
+    return out.value
+
+
+def octo_ctx_destroy(ctx: int) -> None:
+    _check(load_library().octo_ctx_destroy(ctx))
+
+
+def octo_ctx_set_profiling(ctx: int, on: bool) -> None:
+    _check(load_library().octo_ctx_set_profiling(ctx, int(bool(on))))
+
+
+def octo_ctx_memory(ctx: int):
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().octo_ctx_memory(ctx, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def _dptr(p: int):
+    return ctypes.cast(ctypes.c_void_p(p), _D)
+
+
+def octo_tree_build(ctx: int, leaves: np.ndarray, rho_ptr: int, rho_on_device: bool) -> int:
+    lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
+    out = ctypes.c_void_p()
+    _check(load_library().octo_tree_build(ctx, lv.ctypes.data_as(ctypes.POINTER(octo_leaf)), lv.shape[0],
+                                          _dptr(rho_ptr), int(rho_on_device), ctypes.byref(out)))
+    return out.value
+
+
+def octo_tree_build_uniform(ctx: int, level: int, rho_ptr: int, rho_on_device: bool) -> int:
+    out = ctypes.c_void_p()
+    _check(load_library().octo_tree_build_uniform(ctx, level, _dptr(rho_ptr), int(rho_on_device), ctypes.byref(out)))
+    return out.value
+
+
+def octo_tree_build_adaptive(ctx: int, field, max_level: int, threshold: float) -> int:
+    """`field` provides density(x, y, z) and boxmax(lo, hi) on numpy arrays."""
+    def dens(n, xyz, out, user):
+        a = np.ctypeslib.as_array(xyz, shape=(n, 3))
+        np.ctypeslib.as_array(out, shape=(n,))[:] = field.density(a[:, 0], a[:, 1], a[:, 2])
+
+    def bmax(n, lo, hi, out, user):
+        lo_a = np.ctypeslib.as_array(lo, shape=(n, 3))
+        hi_a = np.ctypeslib.as_array(hi, shape=(n, 3))
+        np.ctypeslib.as_array(out, shape=(n,))[:] = field.boxmax(lo_a, hi_a)
+
+    fd, fb = DENSITY_FN(dens), BOXMAX_FN(bmax)
+    out = ctypes.c_void_p()
+    _check(load_library().octo_tree_build_adaptive(ctx, fd, fb, None, max_level, float(threshold), ctypes.byref(out)))
+    return out.value
+
+
+def octo_tree_set_density(tree: int, rho_ptr: int, rho_on_device: bool) -> None:
+    _check(load_library().octo_tree_set_density(tree, _dptr(rho_ptr), int(rho_on_device)))
+
+
+def octo_tree_info(tree: int):
+    n, lv, b = _I64(), ctypes.c_int32(), ctypes.c_size_t()
+    _check(load_library().octo_tree_info(tree, ctypes.byref(n), ctypes.byref(lv), ctypes.byref(b)))
+    return n.value, lv.value, b.value
+
+
+def octo_tree_leaves(tree: int) -> np.ndarray:
+    n, _, _ = octo_tree_info(tree)
+    out = np.empty((n // 512, 4), dtype=np.int32)
+    _check(load_library().octo_tree_leaves(tree, out.ctypes.data_as(ctypes.POINTER(octo_leaf))))
+    return out
+
+
+def octo_tree_destroy(tree: int) -> None:
+    _check(load_library().octo_tree_destroy(tree))
+
+
+def make_opts(theta=0.5, G=1.0, precision=OCTO_FP64, amc=True) -> octo_opts:
+    return octo_opts(float(theta), float(G), int(precision), int(bool(amc)))
+
+
+def octo_solve(ctx: int, tree: int, opts: octo_opts, phi_ptr: int, g_ptr: int, out_on_device: bool,
+               want_stats: bool = True):
+    st = octo_stats()
+    _check(load_library().octo_solve(ctx, tree, ctypes.byref(opts), _dptr(phi_ptr), _dptr(g_ptr),
+                                     int(out_on_device), ctypes.byref(st) if want_stats else None))
+    return st if want_stats else None
+
+
+def octo_solve_batch(ctx: int, trees: Sequence[int], opts: octo_opts, phi_ptrs: Sequence[int],
+                     g_ptrs: Sequence[int], out_on_device: bool, want_stats: bool = True):
+    n = len(trees)
+    tr = (ctypes.c_void_p * n)(*trees)
+    ph = (_D * n)(*[_dptr(p) for p in phi_ptrs])
+    gg = (_D * n)(*[_dptr(p) for p in g_ptrs])
+    st = (octo_stats * n)()
+    _check(load_library().octo_solve_batch(ctx, tr, n, ctypes.byref(opts), ph, gg, int(out_on_device),
+                                           st if want_stats else None))
+    return list(st) if want_stats else None
+
+
+def octo_submit(ctx: int, tree: int, opts: octo_opts, phi_ptr: int, g_ptr: int) -> int:
+    t = _I64()
+    _check(load_library().octo_submit(ctx, tree, ctypes.byref(opts), _dptr(phi_ptr), _dptr(g_ptr), ctypes.byref(t)))
+    return t.value
+
+
+def octo_poll(ctx: int, ticket: int) -> bool:
+    d = _I()
+    s = _check(load_library().octo_poll(ctx, ticket, ctypes.byref(d)), allow=(OCTO_E_PENDING,))
+    return s == OCTO_OK and d.value == 1
+
+
+def octo_wait(ctx: int, ticket: int) -> octo_stats:
+    st = octo_stats()
+    _check(load_library().octo_wait(ctx, ticket, ctypes.byref(st)))
+    return st
+
+
+def octo_host_stencil_sizes(theta: float) -> np.ndarray:
+    out = np.zeros(24, dtype=np.int32)
+    _check(load_library().octo_host_stencil_sizes(float(theta), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return out
+
+
+def octo_host_layout(leaves) -> tuple:
+    lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
+    n = ctypes.c_int32()
+    out = np.zeros(30, dtype=np.int64)
+    _check(load_library().octo_host_layout(lv.ctypes.data_as(ctypes.POINTER(octo_leaf)), lv.shape[0],
+                                           ctypes.byref(n), out.ctypes.data_as(ctypes.POINTER(_I64))))
+    return n.value, out.reshape(10, 3)[: n.value]
+
+
+def octo_host_adaptive_leaves(field, max_level: int, threshold: float) -> np.ndarray:
+    def bmax(n, lo, hi, out, user):
+        lo_a = np.ctypeslib.as_array(lo, shape=(n, 3))
+        hi_a = np.ctypeslib.as_array(hi, shape=(n, 3))
+        np.ctypeslib.as_array(out, shape=(n,))[:] = field.boxmax(lo_a, hi_a)
+
+    fb = BOXMAX_FN(bmax)
+    n = _I64()
+    _check(load_library().octo_host_adaptive_leaves(fb, None, max_level, float(threshold), None, 0, ctypes.byref(n)))
+    out = np.empty((n.value, 4), dtype=np.int32)
+    _check(load_library().octo_host_adaptive_leaves(fb, None, max_level, float(threshold),
+                                                    out.ctypes.data_as(ctypes.POINTER(octo_leaf)), n.value,
+                                                    ctypes.byref(n)))
+    return out
+
+
+# ---------------------------------------------------------------- torch glue
+
+class Context:
+    """A library context on one GPU whose device memory comes from PyTorch's
+    caching allocator and whose launches go to a dedicated PyTorch stream."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the HIP library needs a ROCm device")
+        load_library()
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self._blocks = {}
+
+        def _alloc(nbytes, user):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            p = t.data_ptr()
+            self._blocks[p] = t
+            return p
+
+        def _free(ptr, user):
+            self._blocks.pop(ptr, None)
+
+        self._cb = (ALLOC_FN(_alloc), FREE_FN(_free))
+        self._alloc = octo_allocator(self._cb[0], self._cb[1], None)
+        self.handle = octo_ctx_create(device, self.stream.cuda_stream, self._alloc, hbm_budget)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            octo_ctx_destroy(self.handle)
+            self.handle = None
+
+    def memory(self):
+        return octo_ctx_memory(self.handle)
+
+    def set_profiling(self, on: bool) -> None:
+        octo_ctx_set_profiling(self.handle, on)
+
+    def uniform_tree(self, rho) -> "Tree":
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        n = rho.shape[0]
+        level = int(np.log2(n // 8))
+        assert rho.shape == (n, n, n) and (8 << level) == n
+        return Tree(self, octo_tree_build_uniform(self.handle, level, rho.ctypes.data, False), grid=n)
+
+    def tree(self, leaves, rho) -> "Tree":
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        return Tree(self, octo_tree_build(self.handle, leaves, rho.ctypes.data, False))
+
+    def adaptive_tree(self, field, max_level: int, threshold: float) -> "Tree":
+        return Tree(self, octo_tree_build_adaptive(self.handle, field, max_level, threshold))
+
+    def solve(self, tree: "Tree", theta=0.5, precision=OCTO_FP64, amc=True, G=1.0, out=None, stats=True):
+        """phi (n,) and g (3, n) as float64 tensors on the device, in the tree's
+        density layout, plus the solve statistics."""
+        torch = self.torch
+        n = tree.n_leaf_cells
+        if out is None:
+            phi = torch.empty(n, dtype=torch.float64, device=self.device)
+            g = torch.empty((3, n), dtype=torch.float64, device=self.device)
+        else:
+            phi, g = out
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        st = octo_solve(self.handle, tree.handle, make_opts(theta, G, precision, amc), phi.data_ptr(), g.data_ptr(),
+                        True, want_stats=stats)
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return phi, g, (st.as_dict() if st is not None else None)
+
+    def solve_batch(self, trees, theta=0.5, precision=OCTO_FP64, amc=True, G=1.0, outs=None, stats=True):
+        torch = self.torch
+        if outs is None:
+            outs = [(torch.empty(t.n_leaf_cells, dtype=torch.float64, device=self.device),
+                     torch.empty((3, t.n_leaf_cells), dtype=torch.float64, device=self.device)) for t in trees]
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        st = octo_solve_batch(self.handle, [t.handle for t in trees], make_opts(theta, G, precision, amc),
+                              [o[0].data_ptr() for o in outs], [o[1].data_ptr() for o in outs], True,
+                              want_stats=stats)
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return outs, ([s.as_dict() for s in st] if st is not None else None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    def __init__(self, ctx: Context, handle: int, grid: Optional[int] = None):
+        self.ctx = ctx
+        self.handle = handle
+        self.grid = grid
+        self.n_leaf_cells, self.n_levels, self.bytes = octo_tree_info(handle)
+
+    def leaves(self) -> np.ndarray:
+        return octo_tree_leaves(self.handle)
+
+    def set_density(self, rho) -> None:
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        octo_tree_set_density(self.handle, rho.ctypes.data, False)
+
+    def destroy(self):
+        if self.handle:
+            octo_tree_destroy(self.handle)
+            self.handle = None

@@ -1,0 +1,404 @@
+// Batched solves (many trees per launch), graph replay and asynchronous
+// requests merged into launch waves (continuous batching).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+
+#include "runtime.h"
+
+using namespace octo;
+
+namespace octo {
+
+namespace {
+__global__ void k_set_tree(TreeDesc *dst, TreeDesc v) { *dst = v; }
+
+uint64_t theta_bits(double t) {
+    uint64_t k;
+    memcpy(&k, &t, 8);
+    return k;
+}
+}  // namespace
+
+void drop_graphs(std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs) {
+    for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
+    graphs.clear();
+}
+
+void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs,
+              const std::vector<TreeDesc> &want, const octo_opts *o) {
+    // tree descriptors (outputs, G, correction switch) live in device memory
+    // and are refreshed only when they change
+    for (int i = 0; i < plan.n_trees; ++i) {
+        TreeDesc &cur = plan.trees_host[i];
+        if (memcmp(&cur, &want[i], sizeof(TreeDesc)) != 0) {
+            cur = want[i];
+            hipLaunchKernelGGL(k_set_tree, dim3(1), dim3(1), 0, ctx->stream, plan.d_trees + i, cur);
+        }
+    }
+    const StencilDevHolder &st = ctx->stencil(o->theta);
+    LaunchOpts lo;
+    lo.precision = o->precision;
+    if (ctx->profiling) {
+        lo.phase_events = ctx->phase_ev;
+        launch_solve(plan, st.dev, lo, ctx->stream);
+        return;
+    }
+    if (!ctx->use_graphs) {
+        launch_solve(plan, st.dev, lo, ctx->stream);
+        return;
+    }
+    const auto key = std::make_pair(theta_bits(o->theta), (int)o->precision);
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
+        hipGraph_t g = nullptr;
+        check_hip(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal), "graph capture");
+        try {
+            launch_solve(plan, st.dev, lo, ctx->capture);
+        } catch (...) {
+            hipStreamEndCapture(ctx->capture, &g);
+            if (g) hipGraphDestroy(g);
+            throw;
+        }
+        check_hip(hipStreamEndCapture(ctx->capture, &g), "graph capture");
+        hipGraphExec_t ex = nullptr;
+        hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        check_hip(e, "graph instantiate");
+        it = graphs.emplace(key, ex).first;
+    }
+    check_hip(hipGraphLaunch(it->second, ctx->stream), "graph launch");
+}
+
+// Concatenate the single-tree plans of several trees.
+static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, const std::vector<TreeDesc> &descs) {
+    auto bp = std::make_unique<BatchPlan>();
+    bp->sig.assign(trees, trees + n);
+    PlanHost &ph = bp->ph;
+    size_t max_lv = 0;
+    for (int i = 0; i < n; ++i) max_lv = std::max(max_lv, trees[i]->ph.interior.size());
+    ph.interior.resize(max_lv);
+    for (int i = 0; i < n; ++i) {
+        const PlanHost &t = trees[i]->ph;
+        const int base = (int)ph.levels.size();
+        for (LevelDesc d : t.levels) {
+            if (d.parent_ld >= 0) d.parent_ld += base;
+            if (d.child_ld >= 0) d.child_ld += base;
+            d.tree = i;
+            ph.levels.push_back(d);
+        }
+        ph.trees.push_back(descs[i]);
+        ph.tree_leaf_beg.push_back((int32_t)ph.leaf.size());
+        ph.tree_m2l_beg.push_back((int32_t)ph.m2l.size());
+        for (M2LItem m : t.m2l) {
+            m.ld += base;
+            ph.m2l.push_back(m);
+        }
+        for (LeafItem f : t.leaf) {
+            f.ld += base;
+            ph.leaf.push_back(f);
+        }
+        for (NodeItem q : t.p2m) {
+            q.ld += base;
+            ph.p2m.push_back(q);
+        }
+        for (size_t l = 0; l < t.interior.size(); ++l)
+            for (NodeItem q : t.interior[l]) {
+                q.ld += base;
+                ph.interior[l].push_back(q);
+            }
+    }
+    ph.tree_leaf_beg.push_back((int32_t)ph.leaf.size());
+    ph.tree_m2l_beg.push_back((int32_t)ph.m2l.size());
+    return bp;
+}
+
+static TreeDesc desc_for(octo_tree *t, double *phi, double *g, const octo_opts *o) {
+    TreeDesc d = t->ph.trees[0];
+    d.phi = phi;
+    d.g = g;
+    d.G = o->G;
+    d.amc = o->amc ? 1 : 0;
+    return d;
+}
+
+static void validate(const octo_opts *o) {
+    if (!o) fail(OCTO_E_INVALID, "opts is NULL");
+    if (!(o->theta >= 0.34 && o->theta < 1.0)) fail(OCTO_E_UNSUPPORTED, "theta must lie in [0.34, 1)");
+    if (o->precision != OCTO_FP64 && o->precision != OCTO_MIXED) fail(OCTO_E_UNSUPPORTED, "unknown precision");
+    if (!std::isfinite(o->G)) fail(OCTO_E_INVALID, "G not finite");
+}
+
+static void fill(const double *v, int64_t n_leaf_cells, double ms, octo_stats *st) {
+    memset(st->phase_ms, 0, sizeof st->phase_ms);
+    st->total_mass = v[0];
+    for (int k = 0; k < 3; ++k) {
+        st->net_force[k] = v[1 + k];
+        st->net_torque[k] = v[4 + k];
+    }
+    st->force_scale = v[7];
+    st->torque_scale = v[8];
+    st->n_leaf_cells = n_leaf_cells;
+    st->m2l_pairs = (int64_t)v[9];
+    st->direct_pairs = (int64_t)v[10];
+    st->device_ms = ms;
+}
+
+}  // namespace octo
+
+void octo_ctx::release_batch(BatchPlan *bp) {
+    if (!bp) return;
+    drop_graphs(bp->graphs);
+    if (bp->mem) dev_free(bp->mem, bp->bytes);
+    if (bp->staging) hipHostFree(bp->staging);
+    bp->mem = nullptr;
+    bp->staging = nullptr;
+}
+
+void octo_ctx::invalidate_batches() {
+    if (batch) {
+        hipStreamSynchronize(stream);
+        release_batch(batch.get());
+        batch.reset();
+    }
+}
+
+namespace octo {
+void set_error(const std::string &m);
+}
+
+template <typename F>
+static octo_status guard_b(F &&f) {
+    try {
+        f();
+        return OCTO_OK;
+    } catch (const Error &e) {
+        octo::set_error(e.msg);
+        return e.code;
+    } catch (const std::exception &e) {
+        octo::set_error(e.what());
+        return OCTO_E_INVALID;
+    }
+}
+
+// ------------------------------------------------------------------ waves
+
+static void retire_waves(octo_ctx *ctx) {
+    for (auto it = ctx->waves.begin(); it != ctx->waves.end();) {
+        Wave &w = it->second;
+        if (hipEventQuery(w.done) != hipSuccess) {
+            ++it;
+            continue;
+        }
+        const int nt = (int)w.tickets.size();
+        w.bp->stats.resize((size_t)nt * 12);
+        check_hip(hipMemcpy(w.bp->stats.data(), w.bp->plan.d_out, (size_t)nt * 12 * sizeof(double),
+                            hipMemcpyDeviceToHost),
+                  "wave stats");
+        for (int i = 0; i < nt; ++i) {
+            auto r = ctx->requests.find(w.tickets[i]);
+            if (r != ctx->requests.end()) r->second.done = true;
+        }
+        hipEventDestroy(w.done);
+        // keep the stats with the requests, release the device block
+        for (int i = 0; i < nt; ++i) {
+            auto r = ctx->requests.find(w.tickets[i]);
+            if (r != ctx->requests.end()) {
+                r->second.wave = -1;
+                memcpy(r->second.stats, w.bp->stats.data() + 12 * i, 12 * sizeof(double));
+            }
+        }
+        ctx->release_batch(w.bp.get());
+        it = ctx->waves.erase(it);
+    }
+}
+
+// Launch waves while fewer than max_inflight_waves are on the device: each
+// wave takes the pending requests with the first request's (theta,
+// precision), at most one request per tree.
+static void pump(octo_ctx *ctx) {
+    retire_waves(ctx);
+    while (!ctx->pending.empty() && (int)ctx->waves.size() < ctx->max_inflight_waves) {
+        const Request &first = ctx->requests.at(ctx->pending.front());
+        const double theta = first.opts.theta;
+        const int prec = first.opts.precision;
+        std::vector<octo_ticket> take;
+        std::set<octo_tree *> used;
+        std::deque<octo_ticket> rest;
+        for (octo_ticket t : ctx->pending) {
+            Request &r = ctx->requests.at(t);
+            if (r.opts.theta == theta && r.opts.precision == prec && !used.count(r.tree)) {
+                used.insert(r.tree);
+                take.push_back(t);
+            } else {
+                rest.push_back(t);
+            }
+        }
+        std::vector<octo_tree *> trees;
+        std::vector<TreeDesc> descs;
+        for (octo_ticket t : take) {
+            Request &r = ctx->requests.at(t);
+            trees.push_back(r.tree);
+            descs.push_back(desc_for(r.tree, r.phi, r.g, &r.opts));
+        }
+        auto bp = make_batch(trees.data(), (int)trees.size(), descs);
+        std::vector<char> img;
+        const size_t bytes = plan_layout(bp->ph, nullptr, bp->plan, img);
+        void *mem = nullptr;
+        try {
+            mem = ctx->dev_alloc(bytes);
+        } catch (const Error &) {
+            if (ctx->waves.empty()) throw;  // nothing will free memory
+            return;                         // retry when a wave retires
+        }
+        bp->mem = mem;
+        bp->bytes = bytes;
+        plan_layout(bp->ph, mem, bp->plan, img);
+        check_hip(hipHostMalloc(&bp->staging, img.size(), hipHostMallocDefault), "pinned staging");
+        memcpy(bp->staging, img.data(), img.size());
+        check_hip(hipMemcpyAsync(mem, bp->staging, img.size(), hipMemcpyHostToDevice, ctx->stream), "wave upload");
+        const StencilDevHolder &st = ctx->stencil(theta);
+        LaunchOpts lo;
+        lo.precision = prec;
+        launch_solve(bp->plan, st.dev, lo, ctx->stream);
+        Wave w;
+        check_hip(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "event");
+        check_hip(hipEventRecord(w.done, ctx->stream), "event");
+        w.tickets = take;
+        w.bp = std::move(bp);
+        const int id = ctx->next_wave++;
+        for (size_t i = 0; i < take.size(); ++i) {
+            Request &r = ctx->requests.at(take[i]);
+            r.wave = id;
+            r.index = (int)i;
+        }
+        ctx->waves.emplace(id, std::move(w));
+        ctx->pending.swap(rest);
+    }
+}
+
+extern "C" {
+
+octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, const octo_opts *opts,
+                             double *const *phi, double *const *g, int out_on_device, octo_stats *stats) {
+    return guard_b([&] {
+        if (!ctx || !trees || n <= 0 || !phi || !g) fail(OCTO_E_INVALID, "bad batch arguments");
+        validate(opts);
+        std::set<octo_tree *> seen;
+        for (int i = 0; i < n; ++i) {
+            if (!trees[i] || !phi[i] || !g[i]) fail(OCTO_E_INVALID, "NULL tree or output in batch");
+            if (trees[i]->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+            if (!seen.insert(trees[i]).second) fail(OCTO_E_INVALID, "a tree appears twice in one batch");
+        }
+        hipSetDevice(ctx->device);
+        std::vector<octo_tree *> sig(trees, trees + n);
+        if (!ctx->batch || ctx->batch->sig != sig) {
+            ctx->invalidate_batches();
+            std::vector<TreeDesc> descs;
+            for (int i = 0; i < n; ++i) descs.push_back(trees[i]->ph.trees[0]);
+            auto bp = make_batch(trees, n, descs);
+            const size_t bytes = plan_bytes(bp->ph);
+            bp->mem = ctx->dev_alloc(bytes);
+            bp->bytes = bytes;
+            plan_upload(bp->ph, bp->mem, bp->plan, ctx->stream);
+            ctx->batch = std::move(bp);
+        }
+        BatchPlan &bp = *ctx->batch;
+        std::vector<TreeDesc> want;
+        for (int i = 0; i < n; ++i) {
+            octo_tree *t = trees[i];
+            const int64_t m = t->layout.n_leaf_cells;
+            want.push_back(desc_for(t, out_on_device ? phi[i] : t->stage, out_on_device ? g[i] : t->stage + m, opts));
+        }
+        if (stats) check_hip(hipEventRecord(ctx->ev0, ctx->stream), "event");
+        run_plan(ctx, bp.plan, bp.graphs, want, opts);
+        if (stats) {
+            check_hip(hipEventRecord(ctx->ev1, ctx->stream), "event");
+            if ((size_t)n * 12 > ctx->h_stats_cap) fail(OCTO_E_INVALID, "batch too large for statistics");
+            check_hip(hipMemcpyAsync(ctx->h_stats, bp.plan.d_out, (size_t)n * 12 * sizeof(double),
+                                     hipMemcpyDeviceToHost, ctx->stream),
+                      "stats copy");
+        }
+        if (!out_on_device)
+            for (int i = 0; i < n; ++i) {
+                octo_tree *t = trees[i];
+                const int64_t m = t->layout.n_leaf_cells;
+                check_hip(hipMemcpyAsync(phi[i], t->stage, m * 8, hipMemcpyDeviceToHost, ctx->stream), "phi copy");
+                check_hip(hipMemcpyAsync(g[i], t->stage + m, 3 * m * 8, hipMemcpyDeviceToHost, ctx->stream),
+                          "g copy");
+            }
+        if (stats || !out_on_device) check_hip(hipStreamSynchronize(ctx->stream), "batch");
+        if (stats) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+            for (int i = 0; i < n; ++i) fill(ctx->h_stats + 12 * i, trees[i]->layout.n_leaf_cells, ms, &stats[i]);
+        }
+    });
+}
+
+octo_status octo_submit(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, double *phi_dev, double *g_dev,
+                        octo_ticket *ticket) {
+    return guard_b([&] {
+        if (!ctx || !tree || !phi_dev || !g_dev || !ticket) fail(OCTO_E_INVALID, "NULL argument");
+        if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+        validate(opts);
+        hipSetDevice(ctx->device);
+        Request r{};
+        r.ticket = ctx->next_ticket++;
+        r.tree = tree;
+        r.opts = *opts;
+        r.phi = phi_dev;
+        r.g = g_dev;
+        ctx->requests.emplace(r.ticket, r);
+        ctx->pending.push_back(r.ticket);
+        try {
+            pump(ctx);
+        } catch (...) {
+            ctx->pending.erase(std::remove(ctx->pending.begin(), ctx->pending.end(), r.ticket), ctx->pending.end());
+            ctx->requests.erase(r.ticket);
+            throw;
+        }
+        *ticket = r.ticket;
+    });
+}
+
+octo_status octo_poll(octo_ctx *ctx, octo_ticket ticket, int *done) {
+    return guard_b([&] {
+        if (!ctx || !done) fail(OCTO_E_INVALID, "NULL argument");
+        auto it = ctx->requests.find(ticket);
+        if (it == ctx->requests.end()) fail(OCTO_E_INVALID, "unknown ticket");
+        hipSetDevice(ctx->device);
+        pump(ctx);
+        *done = ctx->requests.at(ticket).done ? 1 : 0;
+        if (!*done) fail(OCTO_E_PENDING, "pending");
+    });
+}
+
+octo_status octo_wait(octo_ctx *ctx, octo_ticket ticket, octo_stats *stats) {
+    return guard_b([&] {
+        if (!ctx) fail(OCTO_E_INVALID, "NULL argument");
+        auto it = ctx->requests.find(ticket);
+        if (it == ctx->requests.end()) fail(OCTO_E_INVALID, "unknown ticket");
+        hipSetDevice(ctx->device);
+        while (!ctx->requests.at(ticket).done) {
+            pump(ctx);
+            Request &r = ctx->requests.at(ticket);
+            if (r.done) break;
+            if (r.wave >= 0) {
+                check_hip(hipEventSynchronize(ctx->waves.at(r.wave).done), "wait");
+            } else if (ctx->waves.empty() && !ctx->pending.empty()) {
+                pump(ctx);  // nothing in flight: the pending wave launches now
+            } else if (!ctx->waves.empty()) {
+                check_hip(hipEventSynchronize(ctx->waves.begin()->second.done), "wait");
+            }
+        }
+        Request &r = ctx->requests.at(ticket);
+        if (stats) fill(r.stats, r.tree->layout.n_leaf_cells, 0.0, stats);
+        ctx->requests.erase(ticket);
+    });
+}
+
+}  // extern "C"

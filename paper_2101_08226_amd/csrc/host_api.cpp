@@ -1,0 +1,73 @@
+// Host-only introspection entry points (include/octo_host.h).
+#include <algorithm>
+#include <cmath>
+
+#include "octo_host.h"
+#include "runtime.h"
+
+using namespace octo;
+
+namespace octo {
+void set_error(const std::string &m);
+}
+
+template <typename F>
+static octo_status guard_h(F &&f) {
+    try {
+        f();
+        return OCTO_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return OCTO_E_INVALID;
+    }
+}
+
+extern "C" {
+
+octo_status octo_host_stencil_sizes(double theta, int32_t *out) {
+    return guard_h([&] {
+        if (!out) fail(OCTO_E_INVALID, "out is NULL");
+        if (!(theta >= 0.34 && theta < 1.0)) fail(OCTO_E_UNSUPPORTED, "theta must lie in [0.34, 1)");
+        Stencil s = make_stencil(theta);
+        for (int p = 0; p < 8; ++p) {
+            out[p] = s.m2l_beg[p + 1] - s.m2l_beg[p];
+            out[8 + p] = s.near_beg[p + 1] - s.near_beg[p];
+            int reach = 0;
+            for (int k = s.leaf_beg[p]; k < s.leaf_beg[p + 1]; ++k) {
+                int v = s.leaf[k];
+                int dx = (int)(int8_t)(v & 255), dy = (int)(int8_t)((v >> 8) & 255), dz = (int)(int8_t)((v >> 16) & 255);
+                reach = std::max(reach, std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))));
+            }
+            out[16 + p] = reach;
+        }
+    });
+}
+
+octo_status octo_host_layout(const octo_leaf *leaves, int64_t n_leaves, int32_t *n_levels, int64_t *out) {
+    return guard_h([&] {
+        if (!n_levels || !out) fail(OCTO_E_INVALID, "NULL output");
+        Layout L = build_layout(leaves, n_leaves, -1);
+        *n_levels = L.n_levels;
+        for (int l = 0; l <= kMaxLevel; ++l) {
+            const bool have = l < L.n_levels;
+            out[3 * l] = have ? L.lv[l].n_nodes : 0;
+            out[3 * l + 1] = have ? L.lv[l].n_int : 0;
+            out[3 * l + 2] = have ? L.lv[l].n_rec - L.lv[l].n_int : 0;
+        }
+    });
+}
+
+octo_status octo_host_adaptive_leaves(octo_boxmax_fn boxmax, void *user, int max_level, double threshold,
+                                      octo_leaf *out, int64_t cap, int64_t *n) {
+    return guard_h([&] {
+        if (!n) fail(OCTO_E_INVALID, "n is NULL");
+        std::vector<octo_leaf> v = adaptive_leaves(boxmax, user, max_level, threshold);
+        *n = (int64_t)v.size();
+        if (out && cap >= (int64_t)v.size()) std::copy(v.begin(), v.end(), out);
+    });
+}
+
+}  // extern "C"

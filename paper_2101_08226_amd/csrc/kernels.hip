@@ -1,0 +1,736 @@
+// HIP kernels of the gravity solve for gfx950 (wave64).
+//
+// Method (Octo-Tiger, Sec. 2.2): leaf cells are point masses; multipoles
+// (mass, centre of mass, raw 2nd and 3rd moments) are composed upward; cells
+// of one level that are well separated while their parents are not interact
+// through a third-order multipole-to-local expansion plus the
+// angular-momentum correction; leaf pairs that are not covered that way are
+// summed directly; expansions are shifted downward and evaluated at the
+// leaves (phi, g = -grad phi).
+//
+// Work decomposition: one 64-lane wavefront = one parity class (64 cells) of
+// one 8^3 node, so every lane of a wavefront walks the same stencil of
+// neighbour offsets; work-group ids are remapped so that consecutive items
+// land on the same XCD (each XCD has its own L2).
+#include <hip/hip_runtime.h>
+
+#include "octo_internal.h"
+#include "runtime.h"
+
+namespace octo {
+
+namespace {
+
+constexpr int kXcd = 8;
+
+// blockIdx -> item: the hardware deals work-groups round-robin over the XCDs;
+// give each XCD a contiguous slice of the item list instead.
+__device__ inline int xcd_item(int n_items) {
+    const int b = blockIdx.x;
+    const int per = (n_items + kXcd - 1) / kXcd;
+    return (b % kXcd) * per + b / kXcd;
+}
+
+__device__ inline int grid_for_items(int n) { return n; }
+
+__device__ inline void local_xyz(int s, int &x, int &y, int &z) {
+    const int p = s >> 6, q = s & 63;
+    x = ((q >> 4) << 1) | (p >> 2);
+    y = (((q >> 2) & 3) << 1) | ((p >> 1) & 1);
+    z = ((q & 3) << 1) | (p & 1);
+}
+
+__device__ inline int store_idx(int x, int y, int z) {
+    return ((((x & 1) << 2) | ((y & 1) << 1) | (z & 1)) << 6) | (((x >> 1) << 4) | ((y >> 1) << 2) | (z >> 1));
+}
+
+__device__ inline double centre(int gi, double h) { return (gi + 0.5) * h - 0.5; }
+
+__device__ inline void unpack(int32_t off, int &dx, int &dy, int &dz) {
+    dx = (int)(int8_t)(off & 255);
+    dy = (int)(int8_t)((off >> 8) & 255);
+    dz = (int)(int8_t)((off >> 16) & 255);
+}
+
+__device__ inline int nbr_slot(int sx, int sy, int sz) {
+    return ((sx >> 3) + 1) * 9 + ((sy >> 3) + 1) * 3 + ((sz >> 3) + 1);
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// packed symmetric index helpers for 3rd-order tensors:
+// xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
+// sum_{bc} T_abc u_b u_c for each a
+__device__ inline void t3_uu(const double *T, double ux, double uy, double uz, double &ox, double &oy,
+                             double &oz) {
+    const double xx = ux * ux, yy = uy * uy, zz = uz * uz, xy = ux * uy, xz = ux * uz, yz = uy * uz;
+    ox = T[0] * xx + T[3] * yy + T[5] * zz + 2.0 * (T[1] * xy + T[2] * xz + T[4] * yz);
+    oy = T[1] * xx + T[6] * yy + T[8] * zz + 2.0 * (T[3] * xy + T[4] * xz + T[7] * yz);
+    oz = T[2] * xx + T[7] * yy + T[9] * zz + 2.0 * (T[4] * xy + T[5] * xz + T[8] * yz);
+}
+
+// traces t_a = T_abb
+__device__ inline void t3_trace(const double *T, double &tx, double &ty, double &tz) {
+    tx = T[0] + T[3] + T[5];
+    ty = T[1] + T[6] + T[8];
+    tz = T[2] + T[7] + T[9];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ P2M
+// Leaf cells become point masses m = rho h^3 at their centres; record leaves
+// also get their (trivial) multipole record.
+__global__ __launch_bounds__(256) void k_p2m(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ T,
+                                             const NodeItem *__restrict__ items, int n_items) {
+    const int it = blockIdx.x >> 1;
+    if (it >= n_items) return;
+    const NodeItem item = items[it];
+    const LevelDesc ld = L[item.ld];
+    const TreeDesc td = T[ld.tree];
+    const int node = item.node;
+    const int s = ((blockIdx.x & 1) << 8) | threadIdx.x;
+    int x, y, z;
+    local_xyz(s, x, y, z);
+    const double h = ld.h;
+    const int64_t off = ld.out_base[node] + x * td.sx + y * td.sy + z * td.sz;
+    const double m = td.rho[off] * (h * h * h);
+    const size_t ci = (size_t)node * kCells + s;
+    ld.mass[ci] = m;
+    if (node < ld.n_rec) {
+        const size_t S = (size_t)ld.n_rec * kCells;
+        ld.mp[ci] = centre(8 * ld.coord[3 * node] + x, h);
+        ld.mp[S + ci] = centre(8 * ld.coord[3 * node + 1] + y, h);
+        ld.mp[2 * S + ci] = centre(8 * ld.coord[3 * node + 2] + z, h);
+        for (int c = 3; c < kRec; ++c) ld.mp[c * S + ci] = 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ M2M
+// Parent multipole from its 8 children: mass, centre of mass, and the raw
+// 2nd/3rd moments about it (parallel-axis shifts; the children's dipoles
+// about their own centres of mass vanish).
+__global__ __launch_bounds__(256) void k_m2m(const LevelDesc *__restrict__ L, const NodeItem *__restrict__ items,
+                                             int n_items) {
+    const int it = blockIdx.x >> 1;
+    if (it >= n_items) return;
+    const NodeItem item = items[it];
+    const LevelDesc ld = L[item.ld];
+    const LevelDesc cl = L[ld.child_ld];
+    const int node = item.node;
+    const int s = ((blockIdx.x & 1) << 8) | threadIdx.x;
+    int x, y, z;
+    local_xyz(s, x, y, z);
+    const size_t CS = (size_t)cl.n_rec * kCells;
+    int cn[8], cs[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int cx = 2 * x + (c >> 2), cy = 2 * y + ((c >> 1) & 1), cz = 2 * z + (c & 1);
+        cn[c] = ld.child[node * 8 + ((cx >> 3) << 2) + ((cy >> 3) << 1) + (cz >> 3)];
+        cs[c] = store_idx(cx & 7, cy & 7, cz & 7);
+    }
+    auto child_com = [&](int c, double &zx, double &zy, double &zz) {
+        const size_t ci = (size_t)cn[c] * kCells + cs[c];
+        if (cn[c] < cl.n_rec) {
+            zx = cl.mp[ci];
+            zy = cl.mp[CS + ci];
+            zz = cl.mp[2 * CS + ci];
+        } else {
+            const int cx = 2 * x + (c >> 2), cy = 2 * y + ((c >> 1) & 1), cz = 2 * z + (c & 1);
+            const int ch = ld.child[node * 8 + ((cx >> 3) << 2) + ((cy >> 3) << 1) + (cz >> 3)];
+            zx = centre(8 * cl.coord[3 * ch] + (cx & 7), cl.h);
+            zy = centre(8 * cl.coord[3 * ch + 1] + (cy & 7), cl.h);
+            zz = centre(8 * cl.coord[3 * ch + 2] + (cz & 7), cl.h);
+        }
+    };
+    double m = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const double cm = cl.mass[(size_t)cn[c] * kCells + cs[c]];
+        double zx, zy, zz;
+        child_com(c, zx, zy, zz);
+        m += cm;
+        mx += cm * zx;
+        my += cm * zy;
+        mz += cm * zz;
+    }
+    double Zx, Zy, Zz;
+    if (m > 0.0) {
+        Zx = mx / m;
+        Zy = my / m;
+        Zz = mz / m;
+    } else {
+        Zx = centre(8 * ld.coord[3 * node] + x, ld.h);
+        Zy = centre(8 * ld.coord[3 * node + 1] + y, ld.h);
+        Zz = centre(8 * ld.coord[3 * node + 2] + z, ld.h);
+    }
+    double Q[6] = {0, 0, 0, 0, 0, 0};
+    double O[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c = 0; c < 8; ++c) {
+        const size_t ci = (size_t)cn[c] * kCells + cs[c];
+        const double cm = cl.mass[ci];
+        double zx, zy, zz;
+        child_com(c, zx, zy, zz);
+        const double sx = zx - Zx, sy = zy - Zy, sz = zz - Zz;
+        double q[6] = {0, 0, 0, 0, 0, 0}, o[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (cn[c] < cl.n_rec) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) q[k] = cl.mp[(3 + k) * CS + ci];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) o[k] = cl.mp[(9 + k) * CS + ci];
+        }
+        // second moments: q_ab + m s_a s_b
+        Q[0] += q[0] + cm * sx * sx;
+        Q[1] += q[1] + cm * sx * sy;
+        Q[2] += q[2] + cm * sx * sz;
+        Q[3] += q[3] + cm * sy * sy;
+        Q[4] += q[4] + cm * sy * sz;
+        Q[5] += q[5] + cm * sz * sz;
+        // third moments: o_abc + q_ab s_c + q_ac s_b + q_bc s_a + m s_a s_b s_c
+        // q packed: xx0 xy1 xz2 yy3 yz4 zz5
+        O[0] += o[0] + 3.0 * q[0] * sx + cm * sx * sx * sx;                      // xxx
+        O[1] += o[1] + q[0] * sy + 2.0 * q[1] * sx + cm * sx * sx * sy;          // xxy
+        O[2] += o[2] + q[0] * sz + 2.0 * q[2] * sx + cm * sx * sx * sz;          // xxz
+        O[3] += o[3] + q[3] * sx + 2.0 * q[1] * sy + cm * sx * sy * sy;          // xyy
+        O[4] += o[4] + q[1] * sz + q[2] * sy + q[4] * sx + cm * sx * sy * sz;    // xyz
+        O[5] += o[5] + q[5] * sx + 2.0 * q[2] * sz + cm * sx * sz * sz;          // xzz
+        O[6] += o[6] + 3.0 * q[3] * sy + cm * sy * sy * sy;                      // yyy
+        O[7] += o[7] + q[3] * sz + 2.0 * q[4] * sy + cm * sy * sy * sz;          // yyz
+        O[8] += o[8] + q[5] * sy + 2.0 * q[4] * sz + cm * sy * sz * sz;          // yzz
+        O[9] += o[9] + 3.0 * q[5] * sz + cm * sz * sz * sz;                      // zzz
+    }
+    const size_t pi = (size_t)node * kCells + s;
+    const size_t PS = (size_t)ld.n_rec * kCells;
+    ld.mass[pi] = m;
+    ld.mp[pi] = Zx;
+    ld.mp[PS + pi] = Zy;
+    ld.mp[2 * PS + pi] = Zz;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ld.mp[(3 + k) * PS + pi] = Q[k];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) ld.mp[(9 + k) * PS + pi] = O[k];
+}
+
+// ------------------------------------------------------------------ M2L
+// Multipole-to-local of one ordered pair A <- B (R = z_A - z_B), truncated
+// at total order 3 (L^(n) takes source moments of order <= 3 - n), with the
+// angular-momentum correction: C_A += -(1/6) [M3_B - (m_B/m_A) M3_A] : D4(R).
+// G is applied once at the end.
+struct Acc {
+    double L0, L1[3], L2[6], L3[10], C[3];
+};
+
+template <bool LEAF_TARGET>
+__device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB, const double *Q, const double *O,
+                                double mu, const double *OA, bool amc, Acc &a) {
+    const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
+    const double f0 = rsqrt(r2);
+    const double ir2 = f0 * f0;
+    const double f1 = -f0 * ir2;
+    const double f2 = -3.0 * f1 * ir2;
+    const double f3 = -5.0 * f2 * ir2;
+    // quadrupole contractions
+    const double QRx = Q[0] * Rx + Q[1] * Ry + Q[2] * Rz;
+    const double QRy = Q[1] * Rx + Q[3] * Ry + Q[4] * Rz;
+    const double QRz = Q[2] * Rx + Q[4] * Ry + Q[5] * Rz;
+    const double RQR = Rx * QRx + Ry * QRy + Rz * QRz;
+    const double trQ = Q[0] + Q[3] + Q[5];
+    // octupole contractions
+    double ORx, ORy, ORz;
+    t3_uu(O, Rx, Ry, Rz, ORx, ORy, ORz);
+    const double ORRR = Rx * ORx + Ry * ORy + Rz * ORz;
+    double tOx, tOy, tOz;
+    t3_trace(O, tOx, tOy, tOz);
+    const double tOR = tOx * Rx + tOy * Ry + tOz * Rz;
+    // L0 = -[m f0 + 1/2 (f2 RQR + f1 trQ) - 1/6 (f3 ORRR + 3 f2 tOR)]
+    a.L0 -= mB * f0 + 0.5 * (f2 * RQR + f1 * trQ) - (f3 * ORRR + 3.0 * f2 * tOR) * (1.0 / 6.0);
+    // L1_a = -[m f1 R_a + 1/2 (f3 R_a RQR + f2 (2 QR_a + R_a trQ))]
+    const double c1 = mB * f1 + 0.5 * (f3 * RQR + f2 * trQ);
+    a.L1[0] -= c1 * Rx + f2 * QRx;
+    a.L1[1] -= c1 * Ry + f2 * QRy;
+    a.L1[2] -= c1 * Rz + f2 * QRz;
+    if (!LEAF_TARGET) {
+        // L2_ab = -m (f2 R_a R_b + f1 d_ab)
+        const double m2 = mB * f2, m1 = mB * f1;
+        const double xx = Rx * Rx, yy = Ry * Ry, zz = Rz * Rz, xy = Rx * Ry, xz = Rx * Rz, yz = Ry * Rz;
+        a.L2[0] -= m2 * xx + m1;
+        a.L2[1] -= m2 * xy;
+        a.L2[2] -= m2 * xz;
+        a.L2[3] -= m2 * yy + m1;
+        a.L2[4] -= m2 * yz;
+        a.L2[5] -= m2 * zz + m1;
+        // L3_abc = -m (f3 R_a R_b R_c + f2 (d_ab R_c + d_ac R_b + d_bc R_a))
+        const double m3 = mB * f3;
+        const double m3x = m3 * Rx, m3y = m3 * Ry, m3z = m3 * Rz;
+        a.L3[0] -= m3x * xx + 3.0 * m2 * Rx;
+        a.L3[1] -= m3x * xy + m2 * Ry;
+        a.L3[2] -= m3x * xz + m2 * Rz;
+        a.L3[3] -= m3x * yy + m2 * Rx;
+        a.L3[4] -= m3x * yz;
+        a.L3[5] -= m3x * zz + m2 * Rx;
+        a.L3[6] -= m3y * yy + 3.0 * m2 * Ry;
+        a.L3[7] -= m3y * yz + m2 * Rz;
+        a.L3[8] -= m3z * yz + m2 * Ry;
+        a.L3[9] -= m3z * zz + 3.0 * m2 * Rz;
+    }
+    if (amc) {
+        // n = M3_B - mu M3_A; n : D4 = f4 R s + 3 f3 (v + R (t.R)) + 3 f2 t
+        double n[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) n[k] = O[k] - mu * OA[k];
+        const double f4 = -7.0 * f3 * ir2;
+        double vx, vy, vz, tx, ty, tz;
+        t3_uu(n, Rx, Ry, Rz, vx, vy, vz);
+        t3_trace(n, tx, ty, tz);
+        const double sv = vx * Rx + vy * Ry + vz * Rz;
+        const double tR = tx * Rx + ty * Ry + tz * Rz;
+        const double cR = f4 * sv + 3.0 * f3 * tR;
+        constexpr double k6 = 1.0 / 6.0;
+        a.C[0] -= k6 * (cR * Rx + 3.0 * (f3 * vx + f2 * tx));
+        a.C[1] -= k6 * (cR * Ry + 3.0 * (f3 * vy + f2 * ty));
+        a.C[2] -= k6 * (cR * Rz + 3.0 * (f3 * vz + f2 * tz));
+    }
+}
+
+template <bool LEAF_TARGET>
+__device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilDev &st, const M2LItem item,
+                         const int *s_nbr, int64_t *cnt_out) {
+    const int lane = threadIdx.x;
+    const int node = item.node, p = item.parity;
+    const int s = (p << 6) | lane;
+    int x, y, z;
+    local_xyz(s, x, y, z);
+    const size_t S = (size_t)ld.n_rec * kCells;
+    const size_t ti = (size_t)node * kCells + s;
+    const double zAx = ld.mp[ti], zAy = ld.mp[S + ti], zAz = ld.mp[2 * S + ti];
+    const double mA = ld.mass[ti];
+    double OA[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) OA[k] = ld.mp[(9 + k) * S + ti];
+    const bool amc = td.amc && mA > 0.0;
+    const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
+    Acc a;
+    a.L0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.L1[k] = a.C[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a.L2[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) a.L3[k] = 0.0;
+    int cnt = 0;
+    const int n_src_max = LEAF_TARGET ? ld.n_int : ld.n_rec;  // leaf <- leaf pairs are direct
+    if (ld.level == 0) {
+        // root: every other root cell is a candidate; multipole iff well separated
+        const int parts = LEAF_TARGET ? 1 : ld.n_parts;
+        const int k0 = kCells * item.chunk / parts, k1 = kCells * (item.chunk + 1) / parts;
+        for (int k = k0; k < k1; ++k) {
+            int bx, by, bz;
+            local_xyz(k, bx, by, bz);
+            const int dx = bx - x, dy = by - y, dz = bz - z;
+            const double d2 = (double)(dx * dx + dy * dy + dz * dz);
+            if (!(st.theta2 * d2 > 1.0) || 0 >= n_src_max) continue;
+            const size_t si = k;  // root node 0
+            const double mB = ld.mass[si];
+            double Q[6], O[10];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) Q[q] = ld.mp[(3 + q) * S + si];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) O[q] = ld.mp[(9 + q) * S + si];
+            m2l_pair<LEAF_TARGET>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
+                                  mB * imA, OA, amc, a);
+            ++cnt;
+        }
+    } else {
+        const int beg = st.m2l_beg[p], len = st.m2l_beg[p + 1] - beg;
+        const int parts = LEAF_TARGET ? 1 : ld.n_parts;
+        const int k0 = beg + len * item.chunk / parts, k1 = beg + len * (item.chunk + 1) / parts;
+        for (int k = k0; k < k1; ++k) {
+            int dx, dy, dz;
+            unpack(st.m2l[k], dx, dy, dz);
+            const int sx = x + dx, sy = y + dy, sz = z + dz;
+            const int nb = s_nbr[nbr_slot(sx, sy, sz)];
+            if (nb < 0 || nb >= n_src_max) continue;
+            const size_t si = (size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7);
+            const double mB = ld.mass[si];
+            double Q[6], O[10];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) Q[q] = ld.mp[(3 + q) * S + si];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) O[q] = ld.mp[(9 + q) * S + si];
+            m2l_pair<LEAF_TARGET>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
+                                  mB * imA, OA, amc, a);
+            ++cnt;
+        }
+    }
+    const double G = td.G;
+    if (LEAF_TARGET) {
+        const size_t LS = (size_t)(ld.n_rec - ld.n_int) * kCells;
+        const size_t li = (size_t)(node - ld.n_int) * kCells + s;
+        ld.lacc[li] = G * a.L0;
+        ld.lacc[LS + li] = G * a.L1[0];
+        ld.lacc[2 * LS + li] = G * a.L1[1];
+        ld.lacc[3 * LS + li] = G * a.L1[2];
+        ld.lacc[4 * LS + li] = G * a.C[0];
+        ld.lacc[5 * LS + li] = G * a.C[1];
+        ld.lacc[6 * LS + li] = G * a.C[2];
+    } else {
+        const size_t IS = (size_t)ld.n_int * kCells;
+        double *out = ld.loc + (size_t)item.chunk * kLoc * IS + (size_t)node * kCells + s;
+        out[0] = G * a.L0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[(1 + k) * IS] = G * a.L1[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) out[(4 + k) * IS] = G * a.L2[k];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) out[(10 + k) * IS] = G * a.L3[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[(20 + k) * IS] = G * a.C[k];
+    }
+    const int tot = wave_sum(cnt);
+    if (lane == 0) *cnt_out = tot;
+}
+
+__global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ T,
+                                            const M2LItem *__restrict__ items, int n_items, StencilDev st,
+                                            int64_t *__restrict__ cnt) {
+    const int it = xcd_item(n_items);
+    if (it >= n_items) return;
+    const M2LItem item = items[it];
+    const LevelDesc ld = L[item.ld];
+    const TreeDesc td = T[ld.tree];
+    __shared__ int s_nbr[27];
+    if (threadIdx.x < 27) s_nbr[threadIdx.x] = ld.nbr[item.node * 27 + threadIdx.x];
+    __syncthreads();
+    if (item.node < ld.n_int)
+        m2l_item<false>(ld, td, st, item, s_nbr, cnt + it);
+    else
+        m2l_item<true>(ld, td, st, item, s_nbr, cnt + it);
+}
+
+// ------------------------------------------------------------------ L2L
+// Interior cells: sum the partial locals, then add the parent's expansion
+// shifted to this cell's centre of mass (Taylor shift of the order-3 local
+// polynomial; the correction C is a uniform acceleration and is inherited).
+__global__ __launch_bounds__(256) void k_l2l(const LevelDesc *__restrict__ L, const NodeItem *__restrict__ items,
+                                             int n_items) {
+    const int it = blockIdx.x >> 1;
+    if (it >= n_items) return;
+    const NodeItem item = items[it];
+    const LevelDesc ld = L[item.ld];
+    const int node = item.node;
+    const int s = ((blockIdx.x & 1) << 8) | threadIdx.x;
+    const size_t IS = (size_t)ld.n_int * kCells;
+    const size_t ci = (size_t)node * kCells + s;
+    double v[kLoc];
+#pragma unroll
+    for (int c = 0; c < kLoc; ++c) v[c] = ld.loc[c * IS + ci];
+    for (int part = 1; part < ld.n_parts; ++part) {
+        const double *src = ld.loc + (size_t)part * kLoc * IS + ci;
+#pragma unroll
+        for (int c = 0; c < kLoc; ++c) v[c] += src[c * IS];
+    }
+    if (ld.parent_ld >= 0) {
+        const LevelDesc pl = L[ld.parent_ld];
+        int x, y, z;
+        local_xyz(s, x, y, z);
+        const int pn = ld.parent[node];
+        const int ps = store_idx(4 * (ld.coord[3 * node] & 1) + (x >> 1), 4 * (ld.coord[3 * node + 1] & 1) + (y >> 1),
+                                 4 * (ld.coord[3 * node + 2] & 1) + (z >> 1));
+        const size_t pi = (size_t)pn * kCells + ps;
+        const size_t PIS = (size_t)pl.n_int * kCells, PRS = (size_t)pl.n_rec * kCells;
+        const size_t RS = (size_t)ld.n_rec * kCells;
+        const double dx = ld.mp[ci] - pl.mp[pi], dy = ld.mp[RS + ci] - pl.mp[PRS + pi],
+                     dz = ld.mp[2 * RS + ci] - pl.mp[2 * PRS + pi];
+        double P[kLoc];
+#pragma unroll
+        for (int c = 0; c < kLoc; ++c) P[c] = pl.loc[c * PIS + pi];
+        const double *P2 = P + 4, *P3 = P + 10;
+        double Tx, Ty, Tz;  // sum_bc L3_abc d_b d_c
+        t3_uu(P3, dx, dy, dz, Tx, Ty, Tz);
+        const double L2dx = P2[0] * dx + P2[1] * dy + P2[2] * dz;
+        const double L2dy = P2[1] * dx + P2[3] * dy + P2[4] * dz;
+        const double L2dz = P2[2] * dx + P2[4] * dy + P2[5] * dz;
+        v[0] += P[0] + P[1] * dx + P[2] * dy + P[3] * dz + 0.5 * (L2dx * dx + L2dy * dy + L2dz * dz) +
+                (Tx * dx + Ty * dy + Tz * dz) * (1.0 / 6.0);
+        v[1] += P[1] + L2dx + 0.5 * Tx;
+        v[2] += P[2] + L2dy + 0.5 * Ty;
+        v[3] += P[3] + L2dz + 0.5 * Tz;
+        // L2_ab += sum_c L3_abc d_c
+        v[4] += P2[0] + P3[0] * dx + P3[1] * dy + P3[2] * dz;  // xx
+        v[5] += P2[1] + P3[1] * dx + P3[3] * dy + P3[4] * dz;  // xy
+        v[6] += P2[2] + P3[2] * dx + P3[4] * dy + P3[5] * dz;  // xz
+        v[7] += P2[3] + P3[3] * dx + P3[6] * dy + P3[7] * dz;  // yy
+        v[8] += P2[4] + P3[4] * dx + P3[7] * dy + P3[8] * dz;  // yz
+        v[9] += P2[5] + P3[5] * dx + P3[8] * dy + P3[9] * dz;  // zz
+#pragma unroll
+        for (int c = 10; c < kLoc; ++c) v[c] += P[c];
+    }
+#pragma unroll
+    for (int c = 0; c < kLoc; ++c) ld.loc[c * IS + ci] = v[c];
+}
+
+// ------------------------------------------------------------------ leaves
+// Per leaf cell: direct point-mass sums over same-level leaf partners (the
+// stencil of parents that are not well separated), over the children of
+// nearby interior cells and over nearby coarser leaves (properly nested AMR
+// boundaries), plus the parent's expansion shifted to the cell centre and
+// the cell's own multipole-to-local sums; writes phi and g = -grad phi and
+// per-wavefront sums for the net force and torque.
+__device__ inline void direct_add(double Rx, double Ry, double Rz, double m, double &phi, double &gx, double &gy,
+                                  double &gz) {
+    const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
+    const double ir = rsqrt(r2);
+    const double mir = m * ir;
+    const double mir3 = mir * ir * ir;
+    phi -= mir;
+    gx -= mir3 * Rx;
+    gy -= mir3 * Ry;
+    gz -= mir3 * Rz;
+}
+
+__global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ T,
+                                             const LeafItem *__restrict__ items, int n_items, StencilDev st,
+                                             double *__restrict__ stat, int64_t *__restrict__ cnt_out) {
+    const int it = xcd_item(n_items);
+    if (it >= n_items) return;
+    const LeafItem item = items[it];
+    const LevelDesc ld = L[item.ld];
+    const TreeDesc td = T[ld.tree];
+    const int lane = threadIdx.x;
+    const int node = item.node, p = item.parity;
+    __shared__ int s_nbr[27];
+    __shared__ int s_pnbr[27];
+    if (threadIdx.x < 27) {
+        s_nbr[threadIdx.x] = ld.nbr[node * 27 + threadIdx.x];
+        if (ld.parent_ld >= 0) s_pnbr[threadIdx.x] = L[ld.parent_ld].nbr[ld.parent[node] * 27 + threadIdx.x];
+    }
+    __syncthreads();
+    const int s = (p << 6) | lane;
+    int x, y, z;
+    local_xyz(s, x, y, z);
+    const double h = ld.h;
+    const int gx0 = 8 * ld.coord[3 * node], gy0 = 8 * ld.coord[3 * node + 1], gz0 = 8 * ld.coord[3 * node + 2];
+    const double cx = centre(gx0 + x, h), cy = centre(gy0 + y, h), cz = centre(gz0 + z, h);
+    int cnt = 0;
+
+    // same-level leaf partners: phi = -(1/h) sum m w0, g = (1/h^2) sum m w1
+    double sp = 0.0, sgx = 0.0, sgy = 0.0, sgz = 0.0;
+    if (ld.level == 0) {
+        for (int k = 0; k < kCells; ++k) {
+            if (k == s) continue;
+            int bx, by, bz;
+            local_xyz(k, bx, by, bz);
+            const double dx = bx - x, dy = by - y, dz = bz - z;
+            const double w0 = rsqrt(dx * dx + dy * dy + dz * dz);
+            const double m = ld.mass[k];
+            const double mw0 = m * w0, mw3 = mw0 * w0 * w0;
+            sp += mw0;
+            sgx += mw3 * dx;
+            sgy += mw3 * dy;
+            sgz += mw3 * dz;
+            ++cnt;
+        }
+    } else {
+        const int beg = st.leaf_beg[p], end = st.leaf_beg[p + 1];
+        for (int k = beg; k < end; ++k) {
+            int dx, dy, dz;
+            unpack(st.leaf[k], dx, dy, dz);
+            const int sx = x + dx, sy = y + dy, sz = z + dz;
+            const int nb = s_nbr[nbr_slot(sx, sy, sz)];
+            if (nb < ld.n_int) continue;  // absent (nb < 0) or interior
+            const double m = ld.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)];
+            const double *w = st.leaf_w + 4 * k;
+            sp += m * w[0];
+            sgx += m * w[1];
+            sgy += m * w[2];
+            sgz += m * w[3];
+            ++cnt;
+        }
+    }
+    const double ih = 1.0 / h;
+    double phi = -sp * ih;
+    double gx = sgx * ih * ih, gy = sgy * ih * ih, gz = sgz * ih * ih;
+
+    // cross-level pairs at AMR boundaries (direct point masses)
+    if (item.flags & kLeafX1) {
+        // interior cells B of this level, near (not well separated, parents not): sum over B's children
+        const LevelDesc cl = L[ld.child_ld >= 0 ? ld.child_ld : item.ld];
+        const int beg = st.near_beg[p], end = st.near_beg[p + 1];
+        for (int k = beg; k < end; ++k) {
+            int dx, dy, dz;
+            unpack(st.nearo[k], dx, dy, dz);
+            const int sx = x + dx, sy = y + dy, sz = z + dz;
+            const int nb = s_nbr[nbr_slot(sx, sy, sz)];
+            if (nb < 0 || nb >= ld.n_int) continue;
+            const int bx = sx & 7, by = sy & 7, bz = sz & 7;
+            for (int c = 0; c < 8; ++c) {
+                const int ox = c >> 2, oy = (c >> 1) & 1, oz = c & 1;
+                const int ux = 2 * bx + ox, uy = 2 * by + oy, uz = 2 * bz + oz;
+                const int ch = ld.child[nb * 8 + ((ux >> 3) << 2) + ((uy >> 3) << 1) + (uz >> 3)];
+                const double m = cl.mass[(size_t)ch * kCells + store_idx(ux & 7, uy & 7, uz & 7)];
+                // R = z_A - z_b = (h/2) (1/2 - o - 2 d) per axis
+                const double hh = 0.5 * h;
+                direct_add(hh * (0.5 - ox - 2.0 * dx), hh * (0.5 - oy - 2.0 * dy), hh * (0.5 - oz - 2.0 * dz), m,
+                           phi, gx, gy, gz);
+                ++cnt;
+            }
+        }
+    }
+    if ((item.flags & kLeafX2) && ld.parent_ld >= 0) {
+        // leaves B one level up, near the parent cell P (not well separated, parents not)
+        const LevelDesc pl = L[ld.parent_ld];
+        const int px = 4 * (ld.coord[3 * node] & 1) + (x >> 1), py = 4 * (ld.coord[3 * node + 1] & 1) + (y >> 1),
+                  pz = 4 * (ld.coord[3 * node + 2] & 1) + (z >> 1);
+        const int pp = ((px & 1) << 2) | ((py & 1) << 1) | (pz & 1);
+        const int beg = st.near_beg[pp], end = st.near_beg[pp + 1];
+        for (int k = beg; k < end; ++k) {
+            int dx, dy, dz;
+            unpack(st.nearo[k], dx, dy, dz);
+            const int sx = px + dx, sy = py + dy, sz = pz + dz;
+            const int nb = s_pnbr[nbr_slot(sx, sy, sz)];
+            if (nb < pl.n_int) continue;  // absent or interior
+            const double m = pl.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)];
+            // R = z_a - z_B = h (o - 1/2 - 2 d), o = own index bit
+            direct_add(h * ((x & 1) - 0.5 - 2.0 * dx), h * ((y & 1) - 0.5 - 2.0 * dy), h * ((z & 1) - 0.5 - 2.0 * dz),
+                       m, phi, gx, gy, gz);
+            ++cnt;
+        }
+    }
+    phi *= td.G;
+    gx *= td.G;
+    gy *= td.G;
+    gz *= td.G;
+
+    // own multipole-to-local sums (record leaves)
+    if (item.flags & kLeafLacc) {
+        const size_t LS = (size_t)(ld.n_rec - ld.n_int) * kCells;
+        const size_t li = (size_t)(node - ld.n_int) * kCells + s;
+        phi += ld.lacc[li];
+        gx += -ld.lacc[LS + li] + ld.lacc[4 * LS + li];
+        gy += -ld.lacc[2 * LS + li] + ld.lacc[5 * LS + li];
+        gz += -ld.lacc[3 * LS + li] + ld.lacc[6 * LS + li];
+    }
+    // parent expansion shifted to the cell centre, evaluated there
+    if (ld.parent_ld >= 0) {
+        const LevelDesc pl = L[ld.parent_ld];
+        const int pn = ld.parent[node];
+        const int ps = store_idx(4 * (ld.coord[3 * node] & 1) + (x >> 1), 4 * (ld.coord[3 * node + 1] & 1) + (y >> 1),
+                                 4 * (ld.coord[3 * node + 2] & 1) + (z >> 1));
+        const size_t pi = (size_t)pn * kCells + ps;
+        const size_t PIS = (size_t)pl.n_int * kCells, PRS = (size_t)pl.n_rec * kCells;
+        const double dx = cx - pl.mp[pi], dy = cy - pl.mp[PRS + pi], dz = cz - pl.mp[2 * PRS + pi];
+        double P[kLoc];
+#pragma unroll
+        for (int c = 0; c < kLoc; ++c) P[c] = pl.loc[c * PIS + pi];
+        const double *P2 = P + 4, *P3 = P + 10;
+        double Tx, Ty, Tz;
+        t3_uu(P3, dx, dy, dz, Tx, Ty, Tz);
+        const double L2dx = P2[0] * dx + P2[1] * dy + P2[2] * dz;
+        const double L2dy = P2[1] * dx + P2[3] * dy + P2[4] * dz;
+        const double L2dz = P2[2] * dx + P2[4] * dy + P2[5] * dz;
+        phi += P[0] + P[1] * dx + P[2] * dy + P[3] * dz + 0.5 * (L2dx * dx + L2dy * dy + L2dz * dz) +
+               (Tx * dx + Ty * dy + Tz * dz) * (1.0 / 6.0);
+        gx += -(P[1] + L2dx + 0.5 * Tx) + P[20];
+        gy += -(P[2] + L2dy + 0.5 * Ty) + P[21];
+        gz += -(P[3] + L2dz + 0.5 * Tz) + P[22];
+    }
+    const int64_t o = ld.out_base[node] + x * td.sx + y * td.sy + z * td.sz;
+    td.phi[o] = phi;
+    td.g[o] = gx;
+    td.g[td.n_leaf_cells + o] = gy;
+    td.g[2 * td.n_leaf_cells + o] = gz;
+
+    // per-wavefront partial sums for the diagnostics
+    const double m = ld.mass[(size_t)node * kCells + s];
+    const double fx = m * gx, fy = m * gy, fz = m * gz;
+    const double gn = sqrt(gx * gx + gy * gy + gz * gz);
+    const double xn = sqrt(cx * cx + cy * cy + cz * cz);
+    double v[kStat] = {m, fx, fy, fz, cy * fz - cz * fy, cz * fx - cx * fz, cx * fy - cy * fx, m * gn, xn * m * gn};
+#pragma unroll
+    for (int k = 0; k < kStat; ++k) v[k] = wave_sum(v[k]);
+    const int tot = wave_sum(cnt);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kStat; ++k) stat[(size_t)it * kStat + k] = v[k];
+        cnt_out[it] = tot;
+    }
+}
+
+// ------------------------------------------------------------------ stats
+// One work-group per tree: fixed-order sums of the per-wavefront partials.
+__global__ __launch_bounds__(256) void k_stats(const int32_t *__restrict__ leaf_beg,
+                                               const int32_t *__restrict__ m2l_beg, const double *__restrict__ stat,
+                                               const int64_t *__restrict__ leaf_cnt,
+                                               const int64_t *__restrict__ m2l_cnt, double *__restrict__ out) {
+    const int t = blockIdx.x;
+    __shared__ double sh[256];
+    __shared__ long long shc[256];
+    const int lb = leaf_beg[t], le = leaf_beg[t + 1];
+    for (int k = 0; k < kStat + 2; ++k) {
+        double acc = 0.0;
+        long long c = 0;
+        if (k < kStat) {
+            for (int i = lb + threadIdx.x; i < le; i += 256) acc += stat[(size_t)i * kStat + k];
+        } else if (k == kStat) {
+            for (int i = m2l_beg[t] + threadIdx.x; i < m2l_beg[t + 1]; i += 256) c += m2l_cnt[i];
+        } else {
+            for (int i = lb + threadIdx.x; i < le; i += 256) c += leaf_cnt[i];
+        }
+        sh[threadIdx.x] = acc;
+        shc[threadIdx.x] = c;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                sh[threadIdx.x] += sh[threadIdx.x + w];
+                shc[threadIdx.x] += shc[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[t * 12 + k] = k < kStat ? sh[0] : (double)shc[0];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ launch
+
+void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipStream_t s) {
+    auto mark = [&](int i) {
+        if (o.phase_events) check_hip(hipEventRecord(o.phase_events[i], s), "phase event");
+    };
+    mark(0);
+    if (p.n_p2m) hipLaunchKernelGGL(k_p2m, dim3(2 * p.n_p2m), dim3(256), 0, s, p.d_levels, p.d_trees, p.d_p2m, p.n_p2m);
+    mark(1);
+    for (int l = p.n_levels_max - 1; l >= 0; --l) {
+        const int n = p.n_interior[l];
+        if (n) hipLaunchKernelGGL(k_m2m, dim3(2 * n), dim3(256), 0, s, p.d_levels, p.d_interior + p.interior_off[l], n);
+    }
+    mark(2);
+    if (p.n_m2l) {
+        const int grid = ((p.n_m2l + kXcd - 1) / kXcd) * kXcd;
+        hipLaunchKernelGGL(k_m2l, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st,
+                           p.d_m2l_cnt);
+    }
+    mark(3);
+    for (int l = 0; l < p.n_levels_max; ++l) {
+        const int n = p.n_interior[l];
+        if (n) hipLaunchKernelGGL(k_l2l, dim3(2 * n), dim3(256), 0, s, p.d_levels, p.d_interior + p.interior_off[l], n);
+    }
+    mark(4);
+    if (p.n_leaf) {
+        const int grid = ((p.n_leaf + kXcd - 1) / kXcd) * kXcd;
+        hipLaunchKernelGGL(k_leaf, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st, p.d_stat,
+                           p.d_leaf_cnt);
+    }
+    mark(5);
+    hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(256), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg, p.d_stat,
+                       p.d_leaf_cnt, p.d_m2l_cnt, p.d_out);
+    mark(6);
+    check_hip(hipGetLastError(), "kernel launch");
+}
+
+}  // namespace octo

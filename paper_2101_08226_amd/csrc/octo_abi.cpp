@@ -1,0 +1,511 @@
+// C-ABI of the library: contexts, trees, solves, batches and asynchronous
+// requests.  Every entry point converts C++ failures into an octo_status and a
+// thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <cstdlib>
+#include <string>
+
+#include "runtime.h"
+
+using namespace octo;
+
+namespace {
+
+thread_local std::string g_err;
+
+octo_status ok() { return OCTO_OK; }
+
+}  // namespace
+
+namespace octo {
+void set_error(const std::string &m) { g_err = m; }
+}  // namespace octo
+
+namespace {
+
+template <typename F>
+octo_status guard(F &&f) {
+    try {
+        f();
+        return ok();
+    } catch (const Error &e) {
+        g_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host out of memory";
+        return OCTO_E_BUDGET;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return OCTO_E_INVALID;
+    } catch (...) {
+        g_err = "unknown error";
+        return OCTO_E_INVALID;
+    }
+}
+
+inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        hipGetDevice(&prev);
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        hipGetDevice(&cur);
+        if (prev >= 0 && cur != prev) hipSetDevice(prev);
+    }
+};
+
+int n_parts_for(int n_int) {
+    if (n_int <= 0) return 1;
+    int p = 256 / (8 * n_int);
+    return std::max(1, std::min(32, p));
+}
+
+// Allocate the tree's data block and build its single-tree plan.
+void finish_tree(octo_tree *t, const double *rho, int rho_on_device) {
+    octo_ctx *ctx = t->ctx;
+    Layout &L = t->layout;
+    const int nl = L.n_levels;
+    // data block: per level tables and fields, then rho and output staging
+    size_t bytes = 0;
+    std::vector<size_t> off_nbr(nl), off_child(nl), off_parent(nl), off_coord(nl), off_out(nl), off_mass(nl),
+        off_mp(nl), off_loc(nl), off_lacc(nl);
+    std::vector<int> parts(nl);
+    for (int l = 0; l < nl; ++l) {
+        const HostLevel &h = L.lv[l];
+        parts[l] = n_parts_for(h.n_int);
+        off_nbr[l] = bytes;
+        bytes += al(h.nbr.size() * 4);
+        off_child[l] = bytes;
+        bytes += al(h.child.size() * 4);
+        off_parent[l] = bytes;
+        bytes += al(h.parent.size() * 4);
+        off_coord[l] = bytes;
+        bytes += al(h.coord.size() * 4);
+        off_out[l] = bytes;
+        bytes += al(h.out_base.size() * 8);
+        off_mass[l] = bytes;
+        bytes += al((size_t)h.n_nodes * kCells * 8);
+        off_mp[l] = bytes;
+        bytes += al((size_t)kRec * h.n_rec * kCells * 8);
+        off_loc[l] = bytes;
+        bytes += al((size_t)parts[l] * kLoc * h.n_int * kCells * 8);
+        off_lacc[l] = bytes;
+        bytes += al((size_t)kLacc * (h.n_rec - h.n_int) * kCells * 8);
+    }
+    const size_t off_rho = bytes;
+    bytes += al((size_t)L.n_leaf_cells * 8);
+    const size_t off_stage = bytes;
+    bytes += al((size_t)L.n_leaf_cells * 8 * 4);
+
+    // plan (host)
+    PlanHost &ph = t->ph;
+    ph = PlanHost{};
+    ph.interior.resize(nl);
+    for (int l = 0; l < nl; ++l) {
+        const HostLevel &h = L.lv[l];
+        for (int n = h.n_int; n < h.n_nodes; ++n) ph.p2m.push_back(NodeItem{l, n});
+        for (int n = 0; n < h.n_int; ++n) ph.interior[l].push_back(NodeItem{l, n});
+        for (int n = 0; n < h.n_int; ++n)
+            for (int c = 0; c < parts[l]; ++c)
+                for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, c});
+        for (int n = h.n_int; n < h.n_rec; ++n)
+            for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, 0});
+        for (int n = h.n_int; n < h.n_nodes; ++n)
+            for (int p = 0; p < 8; ++p) ph.leaf.push_back(LeafItem{l, n, p, h.flags[n]});
+    }
+    ph.tree_leaf_beg = {0, (int32_t)ph.leaf.size()};
+    ph.tree_m2l_beg = {0, (int32_t)ph.m2l.size()};
+    const size_t pbytes0 = 0;
+    (void)pbytes0;
+
+    // allocate everything in one block
+    ph.levels.resize(nl);
+    ph.trees.resize(1);
+    const size_t plan_sz = plan_bytes(ph);
+    const size_t total = al(bytes) + plan_sz;
+    void *mem = ctx->dev_alloc(total);
+    t->data.ptr = mem;
+    t->data.bytes = total;
+    t->bytes = total;
+    char *base = (char *)mem;
+    hipStream_t s = ctx->stream;
+    auto up = [&](size_t off, const void *src, size_t n) {
+        if (n) check_hip(hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s), "tree upload");
+    };
+    for (int l = 0; l < nl; ++l) {
+        const HostLevel &h = L.lv[l];
+        up(off_nbr[l], h.nbr.data(), h.nbr.size() * 4);
+        up(off_child[l], h.child.data(), h.child.size() * 4);
+        up(off_parent[l], h.parent.data(), h.parent.size() * 4);
+        up(off_coord[l], h.coord.data(), h.coord.size() * 4);
+        up(off_out[l], h.out_base.data(), h.out_base.size() * 8);
+        LevelDesc &d = ph.levels[l];
+        d.level = l;
+        d.n_nodes = h.n_nodes;
+        d.n_int = h.n_int;
+        d.n_rec = h.n_rec;
+        d.parent_ld = l > 0 ? l - 1 : -1;
+        d.child_ld = (h.n_int > 0 && l + 1 < nl) ? l + 1 : -1;
+        d.n_parts = parts[l];
+        d.tree = 0;
+        d.h = 1.0 / (double)(8 << l);
+        d.nbr = (const int32_t *)(base + off_nbr[l]);
+        d.child = (const int32_t *)(base + off_child[l]);
+        d.parent = (const int32_t *)(base + off_parent[l]);
+        d.coord = (const int32_t *)(base + off_coord[l]);
+        d.out_base = (const int64_t *)(base + off_out[l]);
+        d.mass = (double *)(base + off_mass[l]);
+        d.mp = (double *)(base + off_mp[l]);
+        d.loc = (double *)(base + off_loc[l]);
+        d.lacc = (double *)(base + off_lacc[l]);
+    }
+    t->rho = (double *)(base + off_rho);
+    t->stage = (double *)(base + off_stage);
+    TreeDesc &td = ph.trees[0];
+    td = TreeDesc{};
+    td.rho = t->rho;
+    td.phi = t->stage;
+    td.g = t->stage + L.n_leaf_cells;
+    td.n_leaf_cells = L.n_leaf_cells;
+    td.sx = L.sx;
+    td.sy = L.sy;
+    td.sz = L.sz;
+    td.G = 1.0;
+    td.amc = 1;
+    check_hip(hipMemcpyAsync(t->rho, rho, (size_t)L.n_leaf_cells * 8,
+                             rho_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
+              "density upload");
+    plan_upload(ph, base + al(bytes), t->plan, s);  // synchronises the stream
+}
+
+void check_density_host(const double *rho, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!(rho[i] >= 0.0) || !std::isfinite(rho[i]))
+            fail(OCTO_E_INVALID, "density negative or not finite at cell " + std::to_string(i));
+}
+
+void validate_opts(const octo_opts *o) {
+    if (!o) fail(OCTO_E_INVALID, "opts is NULL");
+    if (!(o->theta >= 0.34 && o->theta < 1.0)) fail(OCTO_E_UNSUPPORTED, "theta must lie in [0.34, 1)");
+    if (o->precision != OCTO_FP64 && o->precision != OCTO_MIXED) fail(OCTO_E_UNSUPPORTED, "unknown precision");
+    if (!std::isfinite(o->G)) fail(OCTO_E_INVALID, "G not finite");
+}
+
+void fill_stats(const double *v, int64_t n_leaf_cells, double ms, octo_stats *st) {
+    memset(st->phase_ms, 0, sizeof st->phase_ms);
+    st->total_mass = v[0];
+    for (int k = 0; k < 3; ++k) {
+        st->net_force[k] = v[1 + k];
+        st->net_torque[k] = v[4 + k];
+    }
+    st->force_scale = v[7];
+    st->torque_scale = v[8];
+    st->n_leaf_cells = n_leaf_cells;
+    st->m2l_pairs = (int64_t)v[9];
+    st->direct_pairs = (int64_t)v[10];
+    st->device_ms = ms;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ctx
+
+void *octo_ctx::dev_alloc(size_t bytes) {
+    if (budget && in_use + bytes > budget)
+        fail(OCTO_E_BUDGET, "HBM budget exceeded (" + std::to_string(in_use + bytes) + " > " + std::to_string(budget) + ")");
+    void *p = nullptr;
+    if (has_alloc) {
+        p = alloc.alloc(bytes, alloc.user);
+        if (!p) fail(OCTO_E_BUDGET, "allocator returned NULL");
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) fail(OCTO_E_BUDGET, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    in_use += bytes;
+    return p;
+}
+
+void octo_ctx::dev_free(void *p, size_t bytes) {
+    if (!p) return;
+    if (has_alloc)
+        alloc.free(p, alloc.user);
+    else
+        hipFree(p);
+    in_use -= bytes;
+}
+
+const StencilDevHolder &octo_ctx::stencil(double theta) {
+    uint64_t k;
+    memcpy(&k, &theta, 8);
+    auto it = stencils.find(k);
+    if (it != stencils.end()) return *it->second;
+    auto h = std::make_unique<StencilDevHolder>();
+    h->host = make_stencil(theta);
+    const Stencil &S = h->host;
+    size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_w.size() * 8);
+    void *mem = nullptr;
+    check_hip(hipMalloc(&mem, b), "stencil alloc");
+    h->block.ptr = mem;
+    h->block.bytes = b;
+    char *base = (char *)mem;
+    size_t off = 0;
+    auto put = [&](const void *src, size_t n) {
+        void *dst = base + off;
+        if (n) check_hip(hipMemcpy(dst, src, n, hipMemcpyHostToDevice), "stencil upload");
+        off += al(n);
+        return dst;
+    };
+    h->dev.m2l = (const int32_t *)put(S.m2l.data(), S.m2l.size() * 4);
+    h->dev.nearo = (const int32_t *)put(S.nearo.data(), S.nearo.size() * 4);
+    h->dev.leaf = (const int32_t *)put(S.leaf.data(), S.leaf.size() * 4);
+    h->dev.leaf_w = (const double *)put(S.leaf_w.data(), S.leaf_w.size() * 8);
+    for (int p = 0; p < 9; ++p) {
+        h->dev.m2l_beg[p] = S.m2l_beg[p];
+        h->dev.near_beg[p] = S.near_beg[p];
+        h->dev.leaf_beg[p] = S.leaf_beg[p];
+    }
+    h->dev.theta2 = theta * theta;
+    auto &ref = *h;
+    stencils.emplace(k, std::move(h));
+    return ref;
+}
+
+extern "C" {
+
+const char *octo_last_error(void) { return g_err.c_str(); }
+
+octo_status octo_ctx_create(int device, void *hip_stream, const octo_allocator *alloc, size_t hbm_budget,
+                            octo_ctx **out) {
+    return guard([&] {
+        if (!out) fail(OCTO_E_INVALID, "out is NULL");
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+            fail(OCTO_E_DEVICE, "no HIP device " + std::to_string(device));
+        DeviceGuard dg(device);
+        auto *c = new octo_ctx();
+        c->device = device;
+        c->budget = hbm_budget;
+        if (alloc && alloc->alloc && alloc->free) {
+            c->has_alloc = true;
+            c->alloc = *alloc;
+        }
+        if (hip_stream) {
+            c->stream = (hipStream_t)hip_stream;
+        } else {
+            check_hip(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "stream create");
+            c->own_stream = true;
+        }
+        check_hip(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking), "stream create");
+        if (const char *e = getenv("OCTO_GRAPHS")) c->use_graphs = atoi(e) != 0;
+        check_hip(hipEventCreate(&c->ev0), "event");
+        for (int i = 0; i < 7; ++i) check_hip(hipEventCreate(&c->phase_ev[i]), "event");
+        check_hip(hipEventCreate(&c->ev1), "event");
+        c->h_stats_cap = 12 * 1024;
+        check_hip(hipHostMalloc((void **)&c->h_stats, c->h_stats_cap * sizeof(double), hipHostMallocDefault),
+                  "pinned stats");
+        *out = c;
+    });
+}
+
+octo_status octo_ctx_destroy(octo_ctx *ctx) {
+    return guard([&] {
+        if (!ctx) return;
+        if (ctx->n_trees > 0) fail(OCTO_E_STATE, "context still owns trees");
+        DeviceGuard dg(ctx->device);
+        hipStreamSynchronize(ctx->stream);
+        ctx->invalidate_batches();
+        for (auto &kv : ctx->stencils) hipFree(kv.second->block.ptr);
+        hipStreamDestroy(ctx->capture);
+        hipEventDestroy(ctx->ev0);
+        for (int i = 0; i < 7; ++i) hipEventDestroy(ctx->phase_ev[i]);
+        hipEventDestroy(ctx->ev1);
+        hipHostFree(ctx->h_stats);
+        if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+        delete ctx;
+    });
+}
+
+octo_status octo_ctx_set_profiling(octo_ctx *ctx, int on) {
+    return guard([&] {
+        if (!ctx) fail(OCTO_E_INVALID, "ctx is NULL");
+        ctx->profiling = on != 0;
+    });
+}
+
+octo_status octo_ctx_memory(const octo_ctx *ctx, size_t *bytes_in_use, size_t *budget) {
+    return guard([&] {
+        if (!ctx) fail(OCTO_E_INVALID, "ctx is NULL");
+        if (bytes_in_use) *bytes_in_use = ctx->in_use;
+        if (budget) *budget = ctx->budget;
+    });
+}
+
+// ------------------------------------------------------------------ trees
+
+static octo_status make_tree(octo_ctx *ctx, const octo_leaf *leaves, int64_t n, int grid_level, const double *rho,
+                             int rho_on_device, octo_tree **out) {
+    return guard([&] {
+        if (!ctx || !out || !rho) fail(OCTO_E_INVALID, "NULL argument");
+        DeviceGuard dg(ctx->device);
+        auto t = std::make_unique<octo_tree>();
+        t->ctx = ctx;
+        t->layout = build_layout(leaves, n, grid_level);
+        if (!rho_on_device) check_density_host(rho, t->layout.n_leaf_cells);
+        finish_tree(t.get(), rho, rho_on_device);
+        ctx->n_trees++;
+        *out = t.release();
+    });
+}
+
+octo_status octo_tree_build(octo_ctx *ctx, const octo_leaf *leaves, int64_t n_leaves, const double *rho,
+                            int rho_on_device, octo_tree **out) {
+    return make_tree(ctx, leaves, n_leaves, -1, rho, rho_on_device, out);
+}
+
+octo_status octo_tree_build_uniform(octo_ctx *ctx, int level, const double *rho, int rho_on_device,
+                                    octo_tree **out) {
+    if (level < 0 || level > 6) {
+        g_err = "uniform level must lie in [0, 6]";
+        return OCTO_E_INVALID;
+    }
+    const int m = 1 << level;
+    std::vector<octo_leaf> lv;
+    lv.reserve((size_t)m * m * m);
+    for (int x = 0; x < m; ++x)
+        for (int y = 0; y < m; ++y)
+            for (int z = 0; z < m; ++z) lv.push_back(octo_leaf{level, x, y, z});
+    return make_tree(ctx, lv.data(), (int64_t)lv.size(), level, rho, rho_on_device, out);
+}
+
+octo_status octo_tree_build_adaptive(octo_ctx *ctx, octo_density_fn density, octo_boxmax_fn boxmax, void *user,
+                                     int max_level, double threshold, octo_tree **out) {
+    std::vector<octo_leaf> lv;
+    std::vector<double> rho;
+    octo_status st = guard([&] {
+        if (!ctx || !out || !density || !boxmax) fail(OCTO_E_INVALID, "NULL argument");
+        if (!std::isfinite(threshold)) fail(OCTO_E_INVALID, "threshold not finite");
+        lv = adaptive_leaves(boxmax, user, max_level, threshold);
+        rho.resize(lv.size() * 512);
+        std::vector<double> xyz(3 * 512 * 64);
+        for (size_t b = 0; b < lv.size(); b += 64) {
+            const size_t e = std::min(lv.size(), b + 64);
+            size_t k = 0;
+            for (size_t i = b; i < e; ++i) {
+                const octo_leaf &f = lv[i];
+                const double h = 1.0 / (double)(8 << f.level);
+                for (int x = 0; x < 8; ++x)
+                    for (int y = 0; y < 8; ++y)
+                        for (int z = 0; z < 8; ++z) {
+                            xyz[3 * k] = (8 * f.ix + x + 0.5) * h - 0.5;
+                            xyz[3 * k + 1] = (8 * f.iy + y + 0.5) * h - 0.5;
+                            xyz[3 * k + 2] = (8 * f.iz + z + 0.5) * h - 0.5;
+                            ++k;
+                        }
+            }
+            density((int64_t)k, xyz.data(), rho.data() + b * 512, user);
+        }
+    });
+    if (st != OCTO_OK) return st;
+    return make_tree(ctx, lv.data(), (int64_t)lv.size(), -1, rho.data(), 0, out);
+}
+
+octo_status octo_tree_set_density(octo_tree *t, const double *rho, int rho_on_device) {
+    return guard([&] {
+        if (!t || !rho) fail(OCTO_E_INVALID, "NULL argument");
+        DeviceGuard dg(t->ctx->device);
+        if (!rho_on_device) check_density_host(rho, t->layout.n_leaf_cells);
+        check_hip(hipMemcpyAsync(t->rho, rho, (size_t)t->layout.n_leaf_cells * 8,
+                                 rho_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, t->ctx->stream),
+                  "density upload");
+        if (!rho_on_device) check_hip(hipStreamSynchronize(t->ctx->stream), "density upload");
+    });
+}
+
+octo_status octo_tree_info(const octo_tree *t, int64_t *n_leaf_cells, int32_t *n_levels, size_t *bytes) {
+    return guard([&] {
+        if (!t) fail(OCTO_E_INVALID, "tree is NULL");
+        if (n_leaf_cells) *n_leaf_cells = t->layout.n_leaf_cells;
+        if (n_levels) *n_levels = t->layout.n_levels;
+        if (bytes) *bytes = t->bytes;
+    });
+}
+
+octo_status octo_tree_leaves(const octo_tree *t, octo_leaf *out) {
+    return guard([&] {
+        if (!t || !out) fail(OCTO_E_INVALID, "NULL argument");
+        std::copy(t->layout.leaves.begin(), t->layout.leaves.end(), out);
+    });
+}
+
+octo_status octo_tree_destroy(octo_tree *t) {
+    return guard([&] {
+        if (!t) return;
+        DeviceGuard dg(t->ctx->device);
+        for (auto &kv : t->ctx->requests)
+            if (kv.second.tree == t && !kv.second.done)
+                fail(OCTO_E_STATE, "tree has an unfinished request");
+        hipStreamSynchronize(t->ctx->stream);
+        if (t->ctx->batch &&
+            std::find(t->ctx->batch->sig.begin(), t->ctx->batch->sig.end(), t) != t->ctx->batch->sig.end())
+            t->ctx->invalidate_batches();
+        drop_graphs(t->graphs);
+        t->ctx->dev_free(t->data.ptr, t->data.bytes);
+        t->ctx->n_trees--;
+        delete t;
+    });
+}
+
+// ------------------------------------------------------------------ solve
+
+octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, double *phi, double *g,
+                       int out_on_device, octo_stats *stats) {
+    return guard([&] {
+        if (!ctx || !tree) fail(OCTO_E_INVALID, "NULL argument");
+        if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+        validate_opts(opts);
+        if (!phi || !g) fail(OCTO_E_INVALID, "NULL output");
+        DeviceGuard dg(ctx->device);
+        const int64_t n = tree->layout.n_leaf_cells;
+        std::vector<TreeDesc> want = tree->plan.trees_host;
+        want[0].phi = out_on_device ? phi : tree->stage;
+        want[0].g = out_on_device ? g : tree->stage + n;
+        want[0].G = opts->G;
+        want[0].amc = opts->amc ? 1 : 0;
+        if (stats) check_hip(hipEventRecord(ctx->ev0, ctx->stream), "event");
+        run_plan(ctx, tree->plan, tree->graphs, want, opts);
+        if (stats) {
+            check_hip(hipEventRecord(ctx->ev1, ctx->stream), "event");
+            check_hip(hipMemcpyAsync(ctx->h_stats, tree->plan.d_out, 12 * sizeof(double), hipMemcpyDeviceToHost,
+                                     ctx->stream),
+                      "stats copy");
+        }
+        if (!out_on_device) {
+            check_hip(hipMemcpyAsync(phi, tree->stage, n * 8, hipMemcpyDeviceToHost, ctx->stream), "phi copy");
+            check_hip(hipMemcpyAsync(g, tree->stage + n, 3 * n * 8, hipMemcpyDeviceToHost, ctx->stream), "g copy");
+        }
+        if (stats || !out_on_device) check_hip(hipStreamSynchronize(ctx->stream), "solve");
+        if (stats) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+            fill_stats(ctx->h_stats, n, ms, stats);
+            if (ctx->profiling)
+                for (int i = 0; i < 6; ++i) {
+                    float pm = 0.f;
+                    hipEventElapsedTime(&pm, ctx->phase_ev[i], ctx->phase_ev[i + 1]);
+                    stats->phase_ms[i] = pm;
+                }
+        }
+    });
+}
+
+}  // extern "C"

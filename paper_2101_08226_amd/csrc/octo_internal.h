@@ -1,0 +1,106 @@
+// Internal data layout shared by the host runtime and the HIP kernels.
+//
+// Device layout of one tree (all arrays in HBM, owned by the tree):
+//  * Per level l, nodes are numbered [0, n_int) interior, [n_int, n_rec) leaf
+//    nodes that touch an interior node of their level ("record leaves": they
+//    take part in multipole interactions), [n_rec, n_nodes) other leaves;
+//    each group is in Morton order.
+//  * Cells inside a node are stored parity-major: storage index
+//    s = parity * 64 + q with parity = (x&1)<<2 | (y&1)<<1 | (z&1) and
+//    q = (x>>1)<<4 | (y>>1)<<2 | (z>>1) for local cell (x, y, z).  One
+//    64-lane wavefront holds one parity class of one node, so all its lanes
+//    share one interaction stencil.
+//  * Per-cell fields are structure-of-arrays: component c of node n cell s
+//    lives at base[c * (count * 512) + n * 512 + s].
+#pragma once
+
+#include <cstdint>
+
+#ifndef __HIPCC__
+#ifndef __host__
+#define __host__
+#define __device__
+#endif
+#endif
+
+namespace octo {
+
+constexpr int kCells = 512;
+constexpr int kMaxLevel = 9;  // deepest supported level (finest cells 1/4096)
+
+// multipole record of a cell (besides its mass): centre of mass (3), raw
+// second moments (6: xx xy xz yy yz zz), raw third moments (10: xxx xxy xxz
+// xyy xyz xzz yyy yyz yzz zzz), all about the centre of mass
+constexpr int kRec = 19;
+// local expansion of an interior cell: L0, L1 (3), L2 (6), L3 (10) and the
+// angular-momentum correction C (3), same packing as the moments
+constexpr int kLoc = 23;
+// multipole-to-local accumulators of a record leaf: L0, L1 (3), C (3)
+constexpr int kLacc = 7;
+// per leaf work item partial sums: M, F (3), T (3), S_F, S_T
+constexpr int kStat = 9;
+
+struct LevelDesc {
+    int32_t level, n_nodes, n_int, n_rec;
+    int32_t parent_ld;  // descriptor of level - 1 of the same tree (-1 at the root)
+    int32_t child_ld;   // descriptor of level + 1 (-1 if the level has no interior nodes)
+    int32_t n_parts;    // slots of partial interior locals (chunked multipole work)
+    int32_t tree;       // index of the tree descriptor
+    double h;           // cell width
+    const int32_t *nbr;       // n_nodes * 27: same-level neighbour node (dx,dy,dz) at (dx+1)*9+(dy+1)*3+dz+1, -1 = none
+    const int32_t *child;     // n_int * 8: child node at level + 1, child (cx,cy,cz) at cx*4+cy*2+cz
+    const int32_t *parent;    // n_nodes: parent node at level - 1 (-1 at the root)
+    const int32_t *coord;     // n_nodes * 3: node index at this level
+    const int64_t *out_base;  // n_nodes: caller-layout offset of local cell (0,0,0) (leaf nodes), -1 otherwise
+    double *mass;             // n_nodes * 512
+    double *mp;               // kRec * n_rec * 512
+    double *loc;              // n_parts * kLoc * n_int * 512 (slot-major)
+    double *lacc;             // kLacc * (n_rec - n_int) * 512
+};
+
+struct TreeDesc {
+    const double *rho;  // caller layout
+    double *phi;        // caller layout, set per solve
+    double *g;          // 3 x n_leaf_cells, set per solve
+    int64_t n_leaf_cells;
+    int64_t sx, sy, sz;  // caller-layout strides of local cell (x, y, z)
+    double G;
+    int32_t amc;
+    int32_t pad;
+};
+
+// one wavefront of multipole-to-local work: 64 target cells of one parity
+// class of one node, stencil entries [len*chunk/n_parts, len*(chunk+1)/n_parts)
+struct M2LItem {
+    int32_t ld, node, parity, chunk;
+};
+
+enum : int32_t { kLeafX1 = 1, kLeafX2 = 2, kLeafLacc = 4 };
+
+// one wavefront of leaf work: 64 leaf cells of one parity class of one node
+struct LeafItem {
+    int32_t ld, node, parity, flags;
+};
+
+struct NodeItem {
+    int32_t ld, node;
+};
+
+// interaction stencils for one opening angle (levels >= 1), per parity class;
+// offsets packed as (dx & 255) | (dy & 255) << 8 | (dz & 255) << 16
+struct StencilDev {
+    const int32_t *m2l;    // well separated, parents not
+    const int32_t *nearo;  // not well separated, parents not, d != 0
+    const int32_t *leaf;   // m2l followed by near, with weights
+    const double *leaf_w;  // 4 per leaf entry: 1/|d|, d/|d|^3
+    int32_t m2l_beg[9];
+    int32_t near_beg[9];
+    int32_t leaf_beg[9];
+    double theta2;
+};
+
+__host__ __device__ inline int32_t pack_off(int dx, int dy, int dz) {
+    return (dx & 255) | ((dy & 255) << 8) | ((dz & 255) << 16);
+}
+
+}  // namespace octo

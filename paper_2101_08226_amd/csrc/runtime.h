@@ -1,0 +1,213 @@
+// Host runtime: tree layout, interaction stencils, solve plans and launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "octo.h"
+#include "octo_internal.h"
+
+namespace octo {
+
+// error carrying an octo_status across the C++ side of the library
+struct Error {
+    octo_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(octo_status code, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+
+// ---------------------------------------------------------------- layout
+
+struct HostLevel {
+    int n_nodes = 0, n_int = 0, n_rec = 0;
+    std::vector<int32_t> nbr, child, parent, coord;
+    std::vector<int64_t> out_base;
+    std::vector<int32_t> flags;  // kLeaf* flags per node (leaf nodes)
+};
+
+struct Layout {
+    int n_levels = 0;
+    int64_t n_leaf_cells = 0;
+    int64_t sx = 64, sy = 8, sz = 1;
+    std::vector<HostLevel> lv;
+    std::vector<octo_leaf> leaves;  // caller order
+};
+
+// Validate a leaf list (tiling, nesting) and lay the tree out level by level.
+// grid_level >= 0: uniform grid layout of 8 * 2^grid_level cells per axis for
+// the caller's arrays; otherwise leaf-list layout.
+Layout build_layout(const octo_leaf *leaves, int64_t n, int grid_level);
+
+// Leaves of the adaptive tree of a density field (refinement + nesting).
+std::vector<octo_leaf> adaptive_leaves(octo_boxmax_fn boxmax, void *user, int max_level, double threshold);
+
+// ---------------------------------------------------------------- stencils
+
+struct Stencil {
+    double theta = 0;
+    std::vector<int32_t> m2l, nearo, leaf;
+    std::vector<double> leaf_w;
+    int m2l_beg[9], near_beg[9], leaf_beg[9];
+};
+
+Stencil make_stencil(double theta);
+
+// ---------------------------------------------------------------- plans
+
+// Host description of the work of one or more trees (concatenated), uploaded
+// into one device buffer.
+struct PlanHost {
+    std::vector<LevelDesc> levels;
+    std::vector<TreeDesc> trees;
+    std::vector<M2LItem> m2l;
+    std::vector<LeafItem> leaf;
+    std::vector<NodeItem> p2m;
+    // interior nodes by level index (level l of every tree)
+    std::vector<std::vector<NodeItem>> interior;
+    std::vector<int32_t> tree_leaf_beg, tree_m2l_beg;  // per tree, +1 sentinel
+};
+
+struct DeviceBlock {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Plan {
+    int n_trees = 0, n_levels_max = 0;
+    int n_m2l = 0, n_leaf = 0, n_p2m = 0;
+    std::vector<int> n_interior;        // per level index
+    std::vector<size_t> interior_off;   // element offset into d_interior per level index
+    LevelDesc *d_levels = nullptr;
+    TreeDesc *d_trees = nullptr;
+    M2LItem *d_m2l = nullptr;
+    LeafItem *d_leaf = nullptr;
+    NodeItem *d_p2m = nullptr;
+    NodeItem *d_interior = nullptr;
+    int32_t *d_tree_leaf_beg = nullptr, *d_tree_m2l_beg = nullptr;
+    double *d_stat = nullptr;      // n_leaf * kStat
+    int64_t *d_leaf_cnt = nullptr;  // n_leaf
+    int64_t *d_m2l_cnt = nullptr;   // n_m2l
+    double *d_out = nullptr;        // n_trees * 12: stats per tree
+    DeviceBlock block;
+    std::vector<TreeDesc> trees_host;  // current tree descriptors (outputs, G, amc)
+};
+
+size_t plan_bytes(const PlanHost &ph);
+size_t plan_layout(const PlanHost &ph, void *dev, Plan &plan, std::vector<char> &image);
+void plan_upload(const PlanHost &ph, void *dev, Plan &plan, hipStream_t s);
+
+struct StencilDevHolder {
+    Stencil host;
+    StencilDev dev;
+    DeviceBlock block;
+};
+
+// ---------------------------------------------------------------- launches
+
+struct LaunchOpts {
+    int precision = OCTO_FP64;
+    hipEvent_t *phase_events = nullptr;  // 7 events around the 6 phases, or NULL
+};
+
+// enqueue one full solve of a plan on stream s
+void launch_solve(const Plan &plan, const StencilDev &st, const LaunchOpts &o, hipStream_t s);
+
+}  // namespace octo
+
+// ---------------------------------------------------------------- objects
+
+namespace octo {
+// a concatenated plan of several trees with its device block and graphs
+struct BatchPlan {
+    std::vector<octo_tree *> sig;
+    PlanHost ph;
+    Plan plan;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    std::map<std::pair<uint64_t, int>, hipGraphExec_t> graphs;  // (theta bits, precision)
+    void *staging = nullptr;  // pinned upload image (asynchronous waves)
+    std::vector<double> stats;  // per tree, 12 values, after completion
+};
+
+// an asynchronous request
+struct Request {
+    octo_ticket ticket;
+    octo_tree *tree;
+    octo_opts opts;
+    double *phi, *g;
+    int wave = -1;
+    bool done = false;
+    int index = 0;  // position in its wave
+    double stats[12] = {0};
+};
+
+struct Wave {
+    std::vector<octo_ticket> tickets;
+    std::unique_ptr<BatchPlan> bp;
+    hipEvent_t done = nullptr;
+    bool finished = false;
+};
+}  // namespace octo
+
+struct octo_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool has_alloc = false;
+    octo_allocator alloc{};
+    size_t budget = 0, in_use = 0;
+    int n_trees = 0;
+    std::map<uint64_t, std::unique_ptr<octo::StencilDevHolder>> stencils;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t capture = nullptr;  // private stream for graph capture
+    bool use_graphs = true;
+    bool profiling = false;
+    hipEvent_t phase_ev[7] = {};
+    double *h_stats = nullptr;  // pinned host staging for stats
+    size_t h_stats_cap = 0;
+    // last batch signature (octo_solve_batch)
+    std::unique_ptr<octo::BatchPlan> batch;
+    void *batch_mem = nullptr;
+    size_t batch_bytes = 0;
+    // asynchronous requests
+    octo_ticket next_ticket = 1;
+    std::map<octo_ticket, octo::Request> requests;
+    std::deque<octo_ticket> pending;
+    std::map<int, octo::Wave> waves;
+    int next_wave = 0;
+    int max_inflight_waves = 2;
+
+    void *dev_alloc(size_t bytes);
+    void dev_free(void *p, size_t bytes);
+    const octo::StencilDevHolder &stencil(double theta);
+    void invalidate_batches();
+    void release_batch(octo::BatchPlan *bp);
+};
+
+struct octo_tree {
+    octo_ctx *ctx = nullptr;
+    octo::Layout layout;
+    octo::PlanHost ph;    // single-tree plan (host copy)
+    octo::Plan plan;      // single-tree plan (device)
+    octo::DeviceBlock data;  // tables + fields
+    double *rho = nullptr;
+    double *stage = nullptr;  // device staging of phi, g for host outputs
+    size_t bytes = 0;
+    std::map<std::pair<uint64_t, int>, hipGraphExec_t> graphs;  // (theta bits, precision)
+};
+
+namespace octo {
+// launch a plan through a cached graph (captured on first use) or directly
+void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs,
+              const std::vector<TreeDesc> &want, const octo_opts *o);
+void drop_graphs(std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs);
+}  // namespace octo

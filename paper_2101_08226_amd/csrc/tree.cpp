@@ -1,0 +1,395 @@
+// Host side of the octree: validation and layout of a leaf list, adaptive
+// refinement from a density field, interaction stencils and work plans.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+#include <unordered_set>
+
+#include "runtime.h"
+
+namespace octo {
+
+void fail(octo_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char *what) {
+    if (e != hipSuccess) fail(OCTO_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+inline uint64_t key(int l, int x, int y, int z) {
+    return ((uint64_t)l << 60) | ((uint64_t)x << 40) | ((uint64_t)y << 20) | (uint64_t)z;
+}
+
+inline uint64_t morton(int x, int y, int z) {
+    uint64_t m = 0;
+    for (int b = 0; b < 20; ++b) {
+        m |= (uint64_t)((x >> b) & 1) << (3 * b + 2);
+        m |= (uint64_t)((y >> b) & 1) << (3 * b + 1);
+        m |= (uint64_t)((z >> b) & 1) << (3 * b);
+    }
+    return m;
+}
+
+struct Node {
+    int l, x, y, z;
+    bool leaf;
+    int64_t leaf_index;  // caller order, -1 for interior
+    int idx = -1;        // index within its level after sorting
+};
+
+}  // namespace
+
+Layout build_layout(const octo_leaf *leaves, int64_t n, int grid_level) {
+    if (n <= 0 || !leaves) fail(OCTO_E_INVALID, "empty leaf list");
+    std::vector<Node> nodes;
+    nodes.reserve((size_t)n * 8 / 7 + 8);
+    std::unordered_map<uint64_t, int> at;
+    at.reserve((size_t)n * 2);
+    int deepest = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const octo_leaf &f = leaves[k];
+        if (f.level < 0 || f.level > kMaxLevel) fail(OCTO_E_INVALID, "leaf " + std::to_string(k) + ": level out of range");
+        int m = 1 << f.level;
+        if (f.ix < 0 || f.iy < 0 || f.iz < 0 || f.ix >= m || f.iy >= m || f.iz >= m)
+            fail(OCTO_E_INVALID, "leaf " + std::to_string(k) + ": index out of range");
+        uint64_t kk = key(f.level, f.ix, f.iy, f.iz);
+        if (at.count(kk)) fail(OCTO_E_INVALID, "leaf " + std::to_string(k) + ": duplicate");
+        at[kk] = (int)nodes.size();
+        nodes.push_back(Node{f.level, f.ix, f.iy, f.iz, true, k});
+        deepest = std::max(deepest, f.level);
+    }
+    // ancestors
+    for (int64_t k = 0; k < n; ++k) {
+        Node f = nodes[k];
+        int x = f.x, y = f.y, z = f.z;
+        for (int l = f.l - 1; l >= 0; --l) {
+            x >>= 1;
+            y >>= 1;
+            z >>= 1;
+            auto it = at.find(key(l, x, y, z));
+            if (it != at.end()) {
+                if (nodes[it->second].leaf)
+                    fail(OCTO_E_INVALID, "leaf " + std::to_string(k) + " lies inside another leaf");
+                break;
+            }
+            at[key(l, x, y, z)] = (int)nodes.size();
+            nodes.push_back(Node{l, x, y, z, false, -1});
+        }
+    }
+    if (!at.count(key(0, 0, 0, 0))) fail(OCTO_E_INVALID, "no root");
+    auto find = [&](int l, int x, int y, int z) -> int {
+        if (l < 0) return -1;
+        int m = 1 << l;
+        if (x < 0 || y < 0 || z < 0 || x >= m || y >= m || z >= m) return -1;
+        auto it = at.find(key(l, x, y, z));
+        return it == at.end() ? -1 : it->second;
+    };
+    // every interior node has its 8 children
+    for (const Node &p : nodes) {
+        if (p.leaf) continue;
+        for (int c = 0; c < 8; ++c)
+            if (find(p.l + 1, 2 * p.x + (c >> 2), 2 * p.y + ((c >> 1) & 1), 2 * p.z + (c & 1)) < 0)
+                fail(OCTO_E_INVALID, "the leaves leave a gap below node (" + std::to_string(p.l) + "," +
+                                         std::to_string(p.x) + "," + std::to_string(p.y) + "," + std::to_string(p.z) +
+                                         ")");
+    }
+    // proper nesting: no leaf touches an interior node one level finer
+    for (const Node &a : nodes) {
+        if (!a.leaf) continue;
+        for (int o = 0; o < 27; ++o) {
+            int dx = o / 9 - 1, dy = (o / 3) % 3 - 1, dz = o % 3 - 1;
+            if (!dx && !dy && !dz) continue;
+            int b = find(a.l, a.x + dx, a.y + dy, a.z + dz);
+            if (b < 0 || nodes[b].leaf) continue;
+            const Node &p = nodes[b];
+            // children of p on the faces/edges/corner towards a
+            for (int c = 0; c < 8; ++c) {
+                int cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
+                if ((dx > 0 && cx) || (dx < 0 && !cx) || (dy > 0 && cy) || (dy < 0 && !cy) || (dz > 0 && cz) ||
+                    (dz < 0 && !cz))
+                    continue;
+                int q = find(p.l + 1, 2 * p.x + cx, 2 * p.y + cy, 2 * p.z + cz);
+                if (!nodes[q].leaf) fail(OCTO_E_INVALID, "leaves are not properly nested (2:1 balance)");
+            }
+        }
+    }
+
+    Layout L;
+    L.n_levels = deepest + 1;
+    L.leaves.assign(leaves, leaves + n);
+    L.n_leaf_cells = n * 512;
+    L.lv.resize(L.n_levels);
+    std::vector<std::vector<int>> per(L.n_levels);
+    for (int i = 0; i < (int)nodes.size(); ++i) per[nodes[i].l].push_back(i);
+    // classification: interior, record leaf (touches an interior node of its level), other leaf
+    std::vector<int> cls(nodes.size());
+    for (int i = 0; i < (int)nodes.size(); ++i) {
+        const Node &a = nodes[i];
+        if (!a.leaf) {
+            cls[i] = 0;
+            continue;
+        }
+        bool rec = false;
+        for (int o = 0; o < 27 && !rec; ++o) {
+            int b = find(a.l, a.x + o / 9 - 1, a.y + (o / 3) % 3 - 1, a.z + o % 3 - 1);
+            if (b >= 0 && !nodes[b].leaf) rec = true;
+        }
+        cls[i] = rec ? 1 : 2;
+    }
+    for (int l = 0; l < L.n_levels; ++l) {
+        auto &v = per[l];
+        std::sort(v.begin(), v.end(), [&](int a, int b) {
+            if (cls[a] != cls[b]) return cls[a] < cls[b];
+            return morton(nodes[a].x, nodes[a].y, nodes[a].z) < morton(nodes[b].x, nodes[b].y, nodes[b].z);
+        });
+        HostLevel &h = L.lv[l];
+        h.n_nodes = (int)v.size();
+        h.n_int = (int)std::count_if(v.begin(), v.end(), [&](int a) { return cls[a] == 0; });
+        h.n_rec = h.n_int + (int)std::count_if(v.begin(), v.end(), [&](int a) { return cls[a] == 1; });
+        for (int k = 0; k < h.n_nodes; ++k) nodes[v[k]].idx = k;
+    }
+    const int64_t gn = grid_level >= 0 ? (int64_t)8 << grid_level : 0;
+    if (grid_level >= 0) {
+        L.sx = gn * gn;
+        L.sy = gn;
+        L.sz = 1;
+    }
+    for (int l = 0; l < L.n_levels; ++l) {
+        HostLevel &h = L.lv[l];
+        auto &v = per[l];
+        h.nbr.assign((size_t)h.n_nodes * 27, -1);
+        h.child.assign((size_t)h.n_int * 8, -1);
+        h.parent.assign(h.n_nodes, -1);
+        h.coord.assign((size_t)h.n_nodes * 3, 0);
+        h.out_base.assign(h.n_nodes, -1);
+        h.flags.assign(h.n_nodes, 0);
+        for (int k = 0; k < h.n_nodes; ++k) {
+            const Node &a = nodes[v[k]];
+            h.coord[3 * k] = a.x;
+            h.coord[3 * k + 1] = a.y;
+            h.coord[3 * k + 2] = a.z;
+            for (int o = 0; o < 27; ++o) {
+                int b = find(l, a.x + o / 9 - 1, a.y + (o / 3) % 3 - 1, a.z + o % 3 - 1);
+                h.nbr[27 * k + o] = b < 0 ? -1 : nodes[b].idx;
+            }
+            if (l > 0) h.parent[k] = nodes[find(l - 1, a.x >> 1, a.y >> 1, a.z >> 1)].idx;
+            if (!a.leaf) {
+                for (int c = 0; c < 8; ++c)
+                    h.child[8 * k + c] =
+                        nodes[find(l + 1, 2 * a.x + (c >> 2), 2 * a.y + ((c >> 1) & 1), 2 * a.z + (c & 1))].idx;
+            } else {
+                if (grid_level >= 0)
+                    h.out_base[k] = ((int64_t)8 * a.x * gn + 8 * a.y) * gn + 8 * a.z;
+                else
+                    h.out_base[k] = a.leaf_index * 512;
+                int32_t f = 0;
+                if (k < h.n_rec) f |= kLeafX1 | kLeafLacc;
+                if (l > 0) {
+                    const Node &p = nodes[find(l - 1, a.x >> 1, a.y >> 1, a.z >> 1)];
+                    for (int o = 0; o < 27; ++o) {
+                        int b = find(l - 1, p.x + o / 9 - 1, p.y + (o / 3) % 3 - 1, p.z + o % 3 - 1);
+                        if (b >= 0 && nodes[b].leaf) f |= kLeafX2;
+                    }
+                }
+                h.flags[k] = f;
+            }
+        }
+    }
+    return L;
+}
+
+std::vector<octo_leaf> adaptive_leaves(octo_boxmax_fn boxmax, void *user, int max_level, double threshold) {
+    if (!boxmax) fail(OCTO_E_INVALID, "no boxmax callback");
+    if (max_level < 0 || max_level > kMaxLevel) fail(OCTO_E_INVALID, "max_level out of range");
+    std::vector<std::unordered_set<uint64_t>> interior(max_level + 1);
+    std::vector<std::array<int, 3>> cur{{0, 0, 0}};
+    for (int l = 0; l < max_level && !cur.empty(); ++l) {
+        double w = 1.0 / (double)(1 << l);
+        std::vector<double> lo(3 * cur.size()), hi(3 * cur.size()), bm(cur.size());
+        for (size_t i = 0; i < cur.size(); ++i)
+            for (int d = 0; d < 3; ++d) {
+                lo[3 * i + d] = cur[i][d] * w - 0.5;
+                hi[3 * i + d] = lo[3 * i + d] + w;
+            }
+        boxmax((int64_t)cur.size(), lo.data(), hi.data(), bm.data(), user);
+        std::vector<std::array<int, 3>> nxt;
+        for (size_t i = 0; i < cur.size(); ++i) {
+            if (!(bm[i] > threshold)) continue;
+            interior[l].insert(key(l, cur[i][0], cur[i][1], cur[i][2]));
+            for (int c = 0; c < 8; ++c)
+                nxt.push_back({2 * cur[i][0] + (c >> 2), 2 * cur[i][1] + ((c >> 1) & 1), 2 * cur[i][2] + (c & 1)});
+        }
+        cur.swap(nxt);
+    }
+    auto exists = [&](int l, int x, int y, int z) {
+        int m = 1 << l;
+        if (x < 0 || y < 0 || z < 0 || x >= m || y >= m || z >= m) return false;
+        if (l == 0) return true;
+        return interior[l - 1].count(key(l - 1, x >> 1, y >> 1, z >> 1)) > 0;
+    };
+    // proper nesting: refine every leaf that touches an interior node one level finer
+    for (bool changed = true; changed;) {
+        changed = false;
+        for (int l = max_level - 1; l >= 0; --l) {
+            std::vector<uint64_t> add;
+            for (uint64_t k : interior[l + 1]) {
+                int x = (int)((k >> 40) & 0xFFFFF), y = (int)((k >> 20) & 0xFFFFF), z = (int)(k & 0xFFFFF);
+                for (int o = 0; o < 27; ++o) {
+                    int nx = x + o / 9 - 1, ny = y + (o / 3) % 3 - 1, nz = z + o % 3 - 1;
+                    if (nx < 0 || ny < 0 || nz < 0) continue;
+                    int px = nx >> 1, py = ny >> 1, pz = nz >> 1;
+                    if (!exists(l, px, py, pz)) continue;
+                    uint64_t pk = key(l, px, py, pz);
+                    if (!interior[l].count(pk)) add.push_back(pk);
+                }
+            }
+            for (uint64_t k : add)
+                if (interior[l].insert(k).second) changed = true;
+        }
+    }
+    std::vector<octo_leaf> out;
+    for (int l = 0; l <= max_level; ++l) {
+        std::vector<std::array<int, 3>> nodes;
+        if (l == 0)
+            nodes.push_back({0, 0, 0});
+        else
+            for (uint64_t k : interior[l - 1]) {
+                int x = (int)((k >> 40) & 0xFFFFF), y = (int)((k >> 20) & 0xFFFFF), z = (int)(k & 0xFFFFF);
+                for (int c = 0; c < 8; ++c) nodes.push_back({2 * x + (c >> 2), 2 * y + ((c >> 1) & 1), 2 * z + (c & 1)});
+            }
+        for (auto &a : nodes)
+            if (!interior[l].count(key(l, a[0], a[1], a[2]))) out.push_back(octo_leaf{l, a[0], a[1], a[2]});
+    }
+    std::sort(out.begin(), out.end(), [](const octo_leaf &a, const octo_leaf &b) {
+        if (a.level != b.level) return a.level < b.level;
+        if (a.ix != b.ix) return a.ix < b.ix;
+        if (a.iy != b.iy) return a.iy < b.iy;
+        return a.iz < b.iz;
+    });
+    return out;
+}
+
+// Stencils of one opening angle for levels >= 1.  For a cell of parity p
+// (its index modulo 2 per axis) and an offset d to another cell of the same
+// level, the parents' offset is floor((p + d) / 2).  Multipole partners are
+// well separated with parents that are not; near partners are neither (d != 0).
+Stencil make_stencil(double theta) {
+    Stencil s;
+    s.theta = theta;
+    const double t2 = theta * theta;
+    auto fdiv2 = [](int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); };
+    std::vector<std::array<int, 3>> m2l[8], nr[8];
+    for (int p = 0; p < 8; ++p) {
+        int px = p >> 2, py = (p >> 1) & 1, pz = p & 1;
+        for (int dx = -7; dx <= 7; ++dx)
+            for (int dy = -7; dy <= 7; ++dy)
+                for (int dz = -7; dz <= 7; ++dz) {
+                    int Dx = fdiv2(px + dx), Dy = fdiv2(py + dy), Dz = fdiv2(pz + dz);
+                    double d2 = (double)(dx * dx + dy * dy + dz * dz);
+                    double D2 = (double)(Dx * Dx + Dy * Dy + Dz * Dz);
+                    if (t2 * D2 > 1.0) continue;  // parents well separated
+                    if (std::abs(dx) > 5 || std::abs(dy) > 5 || std::abs(dz) > 5)
+                        fail(OCTO_E_UNSUPPORTED, "stencil reach above 5 cells");
+                    if (t2 * d2 > 1.0)
+                        m2l[p].push_back({dx, dy, dz});
+                    else if (dx || dy || dz)
+                        nr[p].push_back({dx, dy, dz});
+                }
+    }
+    for (int p = 0; p < 8; ++p) {
+        s.m2l_beg[p] = (int)s.m2l.size();
+        for (auto &d : m2l[p]) s.m2l.push_back(pack_off(d[0], d[1], d[2]));
+        s.near_beg[p] = (int)s.nearo.size();
+        for (auto &d : nr[p]) s.nearo.push_back(pack_off(d[0], d[1], d[2]));
+        s.leaf_beg[p] = (int)s.leaf.size();
+        for (int pass = 0; pass < 2; ++pass)
+            for (auto &d : (pass == 0 ? m2l[p] : nr[p])) {
+                s.leaf.push_back(pack_off(d[0], d[1], d[2]));
+                double r = std::sqrt((double)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+                double w0 = 1.0 / r;
+                double w3 = w0 * w0 * w0;
+                s.leaf_w.push_back(w0);
+                s.leaf_w.push_back(d[0] * w3);
+                s.leaf_w.push_back(d[1] * w3);
+                s.leaf_w.push_back(d[2] * w3);
+            }
+    }
+    s.m2l_beg[8] = (int)s.m2l.size();
+    s.near_beg[8] = (int)s.nearo.size();
+    s.leaf_beg[8] = (int)s.leaf.size();
+    return s;
+}
+
+// ---------------------------------------------------------------- plans
+
+namespace {
+inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t plan_bytes(const PlanHost &ph) {
+    Plan p;
+    std::vector<char> img;
+    return plan_layout(ph, nullptr, p, img);
+}
+
+// Lay the plan out in a device block starting at `dev`: set the Plan's device
+// pointers and write the part that must be uploaded (descriptors and work
+// items) into `image`; the per-item partial sums follow it.  Returns the
+// total size of the block.
+size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &image) {
+    char *base = (char *)dev;
+    size_t off = 0;
+    image.clear();
+    auto put = [&](const void *src, size_t bytes) -> void * {
+        void *dst = base + off;
+        size_t n = al(bytes);
+        image.resize(off + n, 0);
+        if (bytes) memcpy(image.data() + off, src, bytes);
+        off += n;
+        return dst;
+    };
+    auto reserve = [&](size_t bytes) -> void * {
+        void *dst = base + off;
+        off += al(bytes);
+        return dst;
+    };
+    p.n_trees = (int)ph.trees.size();
+    p.n_m2l = (int)ph.m2l.size();
+    p.n_leaf = (int)ph.leaf.size();
+    p.n_p2m = (int)ph.p2m.size();
+    p.n_levels_max = (int)ph.interior.size();
+    p.d_levels = (LevelDesc *)put(ph.levels.data(), ph.levels.size() * sizeof(LevelDesc));
+    p.d_trees = (TreeDesc *)put(ph.trees.data(), ph.trees.size() * sizeof(TreeDesc));
+    p.d_m2l = (M2LItem *)put(ph.m2l.data(), ph.m2l.size() * sizeof(M2LItem));
+    p.d_leaf = (LeafItem *)put(ph.leaf.data(), ph.leaf.size() * sizeof(LeafItem));
+    p.d_p2m = (NodeItem *)put(ph.p2m.data(), ph.p2m.size() * sizeof(NodeItem));
+    std::vector<NodeItem> all;
+    p.n_interior.clear();
+    p.interior_off.clear();
+    for (auto &v : ph.interior) {
+        p.interior_off.push_back(all.size());
+        p.n_interior.push_back((int)v.size());
+        all.insert(all.end(), v.begin(), v.end());
+    }
+    p.d_interior = (NodeItem *)put(all.data(), all.size() * sizeof(NodeItem));
+    p.d_tree_leaf_beg = (int32_t *)put(ph.tree_leaf_beg.data(), ph.tree_leaf_beg.size() * sizeof(int32_t));
+    p.d_tree_m2l_beg = (int32_t *)put(ph.tree_m2l_beg.data(), ph.tree_m2l_beg.size() * sizeof(int32_t));
+    p.d_stat = (double *)reserve(ph.leaf.size() * kStat * sizeof(double));
+    p.d_leaf_cnt = (int64_t *)reserve(ph.leaf.size() * sizeof(int64_t));
+    p.d_m2l_cnt = (int64_t *)reserve(ph.m2l.size() * sizeof(int64_t));
+    p.d_out = (double *)reserve(ph.trees.size() * 12 * sizeof(double));
+    p.trees_host = ph.trees;
+    return off;
+}
+
+// Synchronous upload (tree and batch set-up).
+void plan_upload(const PlanHost &ph, void *dev, Plan &p, hipStream_t s) {
+    std::vector<char> img;
+    plan_layout(ph, dev, p, img);
+    check_hip(hipMemcpyAsync(dev, img.data(), img.size(), hipMemcpyHostToDevice, s), "plan upload");
+    check_hip(hipStreamSynchronize(s), "plan upload");
+}
+
+}  // namespace octo

@@ -1,0 +1,213 @@
+"""GPU parity of the HIP library against the CPU oracle (FP64).
+
+Bar (FP64): e_phi = max_i |dphi_i| / |phi_i| <= 1e-12 (phi < 0 everywhere)
+and e_g = max_i |dg_i| / max_i |g_i| <= 1e-12 (normwise, g -> 0 near centres).
+Pair counts are integers and must match the oracle's recursion exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2101_08226_amd as lib
+import workloads as w
+from helpers import random_amr_leaves
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def errs(phi, g, phi_ref, g_ref):
+    e_phi = float(np.max(np.abs(phi - phi_ref) / np.abs(phi_ref)))
+    e_g = float(np.max(np.abs(g - g_ref)) / np.max(np.abs(g_ref)))
+    return e_phi, e_g
+
+
+def gpu_solve(ctx, tree, **kw):
+    phi, g, st = ctx.solve(tree, **kw)
+    return phi.cpu().numpy(), g.cpu().numpy(), st
+
+
+def check_counts(st, t_orc):
+    m2l, direct, ll = t_orc.last_counts(split=True)
+    assert st["m2l_pairs"] == m2l - ll
+    assert st["direct_pairs"] == direct + ll
+
+
+def uniform_case(ctx, rho, theta, amc=True, counts=True):
+    n = rho.shape[0]
+    level = int(np.log2(n // 8))
+    say(f"uniform n={n} theta={theta} amc={amc}")
+    tree = ctx.uniform_tree(rho)
+    phi, g, st = gpu_solve(ctx, tree, theta=theta, amc=amc)
+    tree.destroy()
+    t = oracle.Tree(w.uniform_leaves(level), w.grid_to_leaves(rho))
+    p_ref, g_ref = t.solve(theta=theta, amc=amc)
+    phi_l = w.grid_to_leaves(phi.reshape(n, n, n)).ravel()
+    g_l = np.stack([w.grid_to_leaves(g[a].reshape(n, n, n)).ravel() for a in range(3)])
+    e = errs(phi_l, g_l, p_ref, g_ref)
+    say(f"  e_phi={e[0]:.2e} e_g={e[1]:.2e} torque={st['torque']:.2e} force={st['force']:.2e}")
+    if counts:
+        check_counts(st, t)
+    return e, st
+
+
+def test_single_leaf(ctx):
+    rho = np.random.default_rng(1).uniform(0.5, 2.0, (8, 8, 8))
+    e, st = uniform_case(ctx, rho, 0.5)
+    assert e[0] <= TOL and e[1] <= TOL
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.34])
+def test_c1_noisy_sphere_16(ctx, theta):
+    e, st = uniform_case(ctx, w.noisy_sphere_16(), theta)
+    assert e[0] <= TOL and e[1] <= TOL
+    assert st["torque"] < 1e-13 and st["force"] < 1e-13
+
+
+@pytest.mark.parametrize("amc", [True, False])
+def test_uniform_32_random(ctx, amc):
+    rho = np.random.default_rng(2).uniform(0.0, 1.0, (32, 32, 32))
+    e, st = uniform_case(ctx, rho, 0.5, amc=amc)
+    assert e[0] <= TOL and e[1] <= TOL
+    if amc:
+        assert st["torque"] < 1e-13
+    else:
+        assert st["torque"] > 1e-10
+
+
+def test_uniform_64_binary_polytrope(ctx):
+    rho = w.uniform_grid(w.binary_polytrope(0.12, 0.10, 0.35, 0.7), 3)
+    e, st = uniform_case(ctx, rho, 0.5)
+    assert e[0] <= TOL and e[1] <= TOL
+    assert st["torque"] < 1e-13
+
+
+@pytest.mark.parametrize("seed,max_level", [(21, 2), (22, 3), (23, 3)])
+def test_adaptive_random(ctx, seed, max_level):
+    leaves, f = random_amr_leaves(seed, max_level=max_level, n_stars=2)
+    say(f"adaptive seed={seed} max_level={max_level} leaves={len(leaves)}")
+    tree = ctx.adaptive_tree(f, max_level, 1e-4)
+    assert np.array_equal(tree.leaves(), leaves)
+    for theta in (0.5, 0.34):
+        phi, g, st = gpu_solve(ctx, tree, theta=theta)
+        t = oracle.Tree(leaves, w.leaf_density(f, leaves))
+        p_ref, g_ref = t.solve(theta=theta)
+        e = errs(phi, g, p_ref, g_ref)
+        say(f"  theta={theta} e_phi={e[0]:.2e} e_g={e[1]:.2e} torque={st['torque']:.2e}")
+        assert e[0] <= TOL and e[1] <= TOL
+        check_counts(st, t)
+        assert st["torque"] < 1e-13 and st["force"] < 1e-13
+    tree.destroy()
+
+
+def test_explicit_leaf_order(ctx):
+    """octo_tree_build keeps the caller's leaf order (shuffled here)."""
+    leaves, f = random_amr_leaves(31, max_level=2, n_stars=1)
+    perm = np.random.default_rng(31).permutation(len(leaves))
+    lv = leaves[perm]
+    rho = w.leaf_density(f, lv)
+    say(f"explicit leaves={len(lv)}")
+    tree = ctx.tree(lv, rho)
+    phi, g, st = gpu_solve(ctx, tree)
+    tree.destroy()
+    p_ref, g_ref = oracle.Tree(lv, rho).solve()
+    e = errs(phi, g, p_ref, g_ref)
+    assert e[0] <= TOL and e[1] <= TOL
+
+
+def test_batch_and_async_equal_single(ctx):
+    rng = np.random.default_rng(4)
+    grids = [rng.uniform(0.1, 1.0, (n, n, n)) for n in (16, 32, 16)]
+    trees = [ctx.uniform_tree(r) for r in grids]
+    say("batch of 3 trees")
+    single = [gpu_solve(ctx, t)[:2] for t in trees]
+    outs, sts = ctx.solve_batch(trees)
+    for (p, g), (ps, gs) in zip(outs, single):
+        assert np.array_equal(p.cpu().numpy(), ps) and np.array_equal(g.cpu().numpy(), gs)
+    outs2, _ = ctx.solve_batch(trees)  # graph replay
+    for (p, g), (ps, gs) in zip(outs2, single):
+        assert np.array_equal(p.cpu().numpy(), ps) and np.array_equal(g.cpu().numpy(), gs)
+    say("async requests")
+    import torch
+
+    res = []
+    for t in trees + trees[:1]:
+        phi = torch.empty(t.n_leaf_cells, dtype=torch.float64, device="cuda")
+        g = torch.empty((3, t.n_leaf_cells), dtype=torch.float64, device="cuda")
+        tk = lib.octo_submit(ctx.handle, t.handle, lib.make_opts(), phi.data_ptr(), g.data_ptr())
+        res.append((tk, phi, g))
+    for i, (tk, phi, g) in enumerate(res):
+        st = lib.octo_wait(ctx.handle, tk)
+        ps, gs = single[i % 3]
+        assert np.array_equal(phi.cpu().numpy(), ps) and np.array_equal(g.cpu().numpy(), gs)
+        assert st.n_leaf_cells == phi.numel()
+    for t in trees:
+        t.destroy()
+
+
+def test_errors(ctx):
+    rho = np.ones((16, 16, 16))
+    tree = ctx.uniform_tree(rho)
+    with pytest.raises(lib.OctoError, match="UNSUPPORTED"):
+        ctx.solve(tree, theta=0.2)
+    with pytest.raises(lib.OctoError, match="UNSUPPORTED"):
+        ctx.solve(tree, theta=1.0)
+    tree.destroy()
+    bad = rho.copy()
+    bad[1, 2, 3] = -1.0
+    with pytest.raises(lib.OctoError, match="INVALID"):
+        ctx.uniform_tree(bad)
+    with pytest.raises(lib.OctoError, match="INVALID"):
+        ctx.tree(w.uniform_leaves(1)[:7], np.ones((7, 512)))
+
+
+def test_budget_admission():
+    c = lib.Context(0, hbm_budget=64 << 20)
+    try:
+        t = c.uniform_tree(np.ones((32, 32, 32)))
+        with pytest.raises(lib.OctoError, match="BUDGET"):
+            c.uniform_tree(np.ones((128, 128, 128)))
+        used, budget = c.memory()
+        assert used <= budget
+        t.destroy()
+    finally:
+        c.close()
+
+
+def test_c2_full_size_sampled(ctx):
+    """128^3 binary polytrope (16^3 sub-grids), the benchmark's workload:
+    every output against the oracle's sampled solve at 400 cells, plus the
+    invariants over all cells."""
+    rho = w.uniform_grid(w.binary_polytrope_128(), 4)
+    say("c2 128^3 full solve")
+    tree = ctx.uniform_tree(rho)
+    phi, g, st = gpu_solve(ctx, tree, theta=0.5)
+    tree.destroy()
+    n = 128
+    rng = np.random.default_rng(7)
+    sel = rng.choice(n ** 3, 400, replace=False)
+    from helpers import grid_ids
+
+    ids = grid_ids(4, sel)
+    t = oracle.Tree(w.uniform_leaves(4), w.grid_to_leaves(rho))
+    p_ref, g_ref = t.solve(theta=0.5, sample=ids)
+    e_phi = float(np.max(np.abs(phi[sel] - p_ref) / np.abs(p_ref)))
+    e_g = float(np.max(np.abs(g[:, sel] - g_ref)) / np.max(np.abs(g_ref)))
+    say(f"  e_phi={e_phi:.2e} e_g={e_g:.2e} torque={st['torque']:.2e} pairs={st['m2l_pairs']} {st['direct_pairs']}")
+    assert e_phi <= TOL and e_g <= TOL
+    assert st["torque"] < 1e-13 and st["force"] < 1e-13
+    assert st["m2l_pairs"] == 64121280 and st["direct_pairs"] == 534396416
