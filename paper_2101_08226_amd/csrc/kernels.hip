@@ -171,6 +171,7 @@ __global__ __launch_bounds__(256) void k_m2m(const LevelDesc *__restrict__ L, co
     }
     double Q[6] = {0, 0, 0, 0, 0, 0};
     double O[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
     for (int c = 0; c < 8; ++c) {
         const size_t ci = (size_t)cn[c] * kCells + cs[c];
         const double cm = cl.mass[ci];
@@ -221,83 +222,98 @@ __global__ __launch_bounds__(256) void k_m2m(const LevelDesc *__restrict__ L, co
 // at total order 3 (L^(n) takes source moments of order <= 3 - n), with the
 // angular-momentum correction: C_A += -(1/6) [M3_B - (m_B/m_A) M3_A] : D4(R).
 // G is applied once at the end.
+template <typename T>
 struct Acc {
-    double L0, L1[3], L2[6], L3[10], C[3];
+    T L0, L1[3], L2[6], L3[10];
+    double C[3];
 };
 
-template <bool LEAF_TARGET>
-__device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB, const double *Q, const double *O,
-                                double mu, const double *OA, bool amc, Acc &a) {
+// T = double: everything in FP64.  T = float (mixed precision): the L0..L3
+// contractions run in FP32 with FP32 partial sums; R, the radial factors and
+// the correction stay FP64.
+template <bool LEAF_TARGET, typename T>
+__device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, const double *Q64, const double *O64,
+                                double mu, const double *OA, bool amc, Acc<T> &a) {
     const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
-    const double f0 = rsqrt(r2);
-    const double ir2 = f0 * f0;
-    const double f1 = -f0 * ir2;
-    const double f2 = -3.0 * f1 * ir2;
-    const double f3 = -5.0 * f2 * ir2;
-    // quadrupole contractions
-    const double QRx = Q[0] * Rx + Q[1] * Ry + Q[2] * Rz;
-    const double QRy = Q[1] * Rx + Q[3] * Ry + Q[4] * Rz;
-    const double QRz = Q[2] * Rx + Q[4] * Ry + Q[5] * Rz;
-    const double RQR = Rx * QRx + Ry * QRy + Rz * QRz;
-    const double trQ = Q[0] + Q[3] + Q[5];
-    // octupole contractions
-    double ORx, ORy, ORz;
-    t3_uu(O, Rx, Ry, Rz, ORx, ORy, ORz);
-    const double ORRR = Rx * ORx + Ry * ORy + Rz * ORz;
-    double tOx, tOy, tOz;
-    t3_trace(O, tOx, tOy, tOz);
-    const double tOR = tOx * Rx + tOy * Ry + tOz * Rz;
-    // L0 = -[m f0 + 1/2 (f2 RQR + f1 trQ) - 1/6 (f3 ORRR + 3 f2 tOR)]
-    a.L0 -= mB * f0 + 0.5 * (f2 * RQR + f1 * trQ) - (f3 * ORRR + 3.0 * f2 * tOR) * (1.0 / 6.0);
-    // L1_a = -[m f1 R_a + 1/2 (f3 R_a RQR + f2 (2 QR_a + R_a trQ))]
-    const double c1 = mB * f1 + 0.5 * (f3 * RQR + f2 * trQ);
-    a.L1[0] -= c1 * Rx + f2 * QRx;
-    a.L1[1] -= c1 * Ry + f2 * QRy;
-    a.L1[2] -= c1 * Rz + f2 * QRz;
-    if (!LEAF_TARGET) {
-        // L2_ab = -m (f2 R_a R_b + f1 d_ab)
-        const double m2 = mB * f2, m1 = mB * f1;
-        const double xx = Rx * Rx, yy = Ry * Ry, zz = Rz * Rz, xy = Rx * Ry, xz = Rx * Rz, yz = Ry * Rz;
-        a.L2[0] -= m2 * xx + m1;
-        a.L2[1] -= m2 * xy;
-        a.L2[2] -= m2 * xz;
-        a.L2[3] -= m2 * yy + m1;
-        a.L2[4] -= m2 * yz;
-        a.L2[5] -= m2 * zz + m1;
-        // L3_abc = -m (f3 R_a R_b R_c + f2 (d_ab R_c + d_ac R_b + d_bc R_a))
-        const double m3 = mB * f3;
-        const double m3x = m3 * Rx, m3y = m3 * Ry, m3z = m3 * Rz;
-        a.L3[0] -= m3x * xx + 3.0 * m2 * Rx;
-        a.L3[1] -= m3x * xy + m2 * Ry;
-        a.L3[2] -= m3x * xz + m2 * Rz;
-        a.L3[3] -= m3x * yy + m2 * Rx;
-        a.L3[4] -= m3x * yz;
-        a.L3[5] -= m3x * zz + m2 * Rx;
-        a.L3[6] -= m3y * yy + 3.0 * m2 * Ry;
-        a.L3[7] -= m3y * yz + m2 * Rz;
-        a.L3[8] -= m3z * yz + m2 * Ry;
-        a.L3[9] -= m3z * zz + 3.0 * m2 * Rz;
+    const double d0 = rsqrt(r2);
+    const double ir2 = d0 * d0;
+    const double d1 = -d0 * ir2;
+    const double d2 = -3.0 * d1 * ir2;
+    const double d3 = -5.0 * d2 * ir2;
+    {
+        const T rx = (T)Rx, ry = (T)Ry, rz = (T)Rz;
+        const T f0 = (T)d0, f1 = (T)d1, f2 = (T)d2, f3 = (T)d3;
+        const T mB = (T)mB64;
+        T Q[6], O[10];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Q[k] = (T)Q64[k];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) O[k] = (T)O64[k];
+        const T half = (T)0.5, three = (T)3.0, sixth = (T)(1.0 / 6.0), two = (T)2.0;
+        // quadrupole contractions
+        const T QRx = Q[0] * rx + Q[1] * ry + Q[2] * rz;
+        const T QRy = Q[1] * rx + Q[3] * ry + Q[4] * rz;
+        const T QRz = Q[2] * rx + Q[4] * ry + Q[5] * rz;
+        const T RQR = rx * QRx + ry * QRy + rz * QRz;
+        const T trQ = Q[0] + Q[3] + Q[5];
+        // octupole contractions
+        const T xx = rx * rx, yy = ry * ry, zz = rz * rz, xy = rx * ry, xz = rx * rz, yz = ry * rz;
+        const T ORx = O[0] * xx + O[3] * yy + O[5] * zz + two * (O[1] * xy + O[2] * xz + O[4] * yz);
+        const T ORy = O[1] * xx + O[6] * yy + O[8] * zz + two * (O[3] * xy + O[4] * xz + O[7] * yz);
+        const T ORz = O[2] * xx + O[7] * yy + O[9] * zz + two * (O[4] * xy + O[5] * xz + O[8] * yz);
+        const T ORRR = rx * ORx + ry * ORy + rz * ORz;
+        const T tOR = (O[0] + O[3] + O[5]) * rx + (O[1] + O[6] + O[8]) * ry + (O[2] + O[7] + O[9]) * rz;
+        // L0 = -[m f0 + 1/2 (f2 RQR + f1 trQ) - 1/6 (f3 ORRR + 3 f2 tOR)]
+        a.L0 -= mB * f0 + half * (f2 * RQR + f1 * trQ) - (f3 * ORRR + three * f2 * tOR) * sixth;
+        // L1_a = -[m f1 R_a + 1/2 (f3 R_a RQR + f2 (2 QR_a + R_a trQ))]
+        const T c1 = mB * f1 + half * (f3 * RQR + f2 * trQ);
+        a.L1[0] -= c1 * rx + f2 * QRx;
+        a.L1[1] -= c1 * ry + f2 * QRy;
+        a.L1[2] -= c1 * rz + f2 * QRz;
+        if (!LEAF_TARGET) {
+            // L2_ab = -m (f2 R_a R_b + f1 d_ab)
+            const T m2 = mB * f2, m1 = mB * f1;
+            a.L2[0] -= m2 * xx + m1;
+            a.L2[1] -= m2 * xy;
+            a.L2[2] -= m2 * xz;
+            a.L2[3] -= m2 * yy + m1;
+            a.L2[4] -= m2 * yz;
+            a.L2[5] -= m2 * zz + m1;
+            // L3_abc = -m (f3 R_a R_b R_c + f2 (d_ab R_c + d_ac R_b + d_bc R_a))
+            const T m3 = mB * f3;
+            const T m3x = m3 * rx, m3y = m3 * ry, m3z = m3 * rz;
+            a.L3[0] -= m3x * xx + three * m2 * rx;
+            a.L3[1] -= m3x * xy + m2 * ry;
+            a.L3[2] -= m3x * xz + m2 * rz;
+            a.L3[3] -= m3x * yy + m2 * rx;
+            a.L3[4] -= m3x * yz;
+            a.L3[5] -= m3x * zz + m2 * rx;
+            a.L3[6] -= m3y * yy + three * m2 * ry;
+            a.L3[7] -= m3y * yz + m2 * rz;
+            a.L3[8] -= m3z * yz + m2 * ry;
+            a.L3[9] -= m3z * zz + three * m2 * rz;
+        }
     }
     if (amc) {
-        // n = M3_B - mu M3_A; n : D4 = f4 R s + 3 f3 (v + R (t.R)) + 3 f2 t
+        // n = M3_B - mu M3_A; n : D4 = f4 R s + 3 f3 (v + R (t.R)) + 3 f2 t   (FP64)
         double n[10];
 #pragma unroll
-        for (int k = 0; k < 10; ++k) n[k] = O[k] - mu * OA[k];
-        const double f4 = -7.0 * f3 * ir2;
+        for (int k = 0; k < 10; ++k) n[k] = O64[k] - mu * OA[k];
+        const double d4 = -7.0 * d3 * ir2;
         double vx, vy, vz, tx, ty, tz;
         t3_uu(n, Rx, Ry, Rz, vx, vy, vz);
         t3_trace(n, tx, ty, tz);
         const double sv = vx * Rx + vy * Ry + vz * Rz;
         const double tR = tx * Rx + ty * Ry + tz * Rz;
-        const double cR = f4 * sv + 3.0 * f3 * tR;
+        const double cR = d4 * sv + 3.0 * d3 * tR;
         constexpr double k6 = 1.0 / 6.0;
-        a.C[0] -= k6 * (cR * Rx + 3.0 * (f3 * vx + f2 * tx));
-        a.C[1] -= k6 * (cR * Ry + 3.0 * (f3 * vy + f2 * ty));
-        a.C[2] -= k6 * (cR * Rz + 3.0 * (f3 * vz + f2 * tz));
+        a.C[0] -= k6 * (cR * Rx + 3.0 * (d3 * vx + d2 * tx));
+        a.C[1] -= k6 * (cR * Ry + 3.0 * (d3 * vy + d2 * ty));
+        a.C[2] -= k6 * (cR * Rz + 3.0 * (d3 * vz + d2 * tz));
     }
 }
 
-template <bool LEAF_TARGET>
+template <bool LEAF_TARGET, typename T>
 __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilDev &st, const M2LItem item,
                          const int *s_nbr, int64_t *cnt_out) {
     const int lane = threadIdx.x;
@@ -314,14 +330,17 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
     for (int k = 0; k < 10; ++k) OA[k] = ld.mp[(9 + k) * S + ti];
     const bool amc = td.amc && mA > 0.0;
     const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
-    Acc a;
-    a.L0 = 0.0;
+    Acc<T> a;
+    a.L0 = (T)0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a.L1[k] = a.C[k] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        a.L1[k] = (T)0;
+        a.C[k] = 0.0;
+    }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) a.L2[k] = 0.0;
+    for (int k = 0; k < 6; ++k) a.L2[k] = (T)0;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) a.L3[k] = 0.0;
+    for (int k = 0; k < 10; ++k) a.L3[k] = (T)0;
     int cnt = 0;
     const int n_src_max = LEAF_TARGET ? ld.n_int : ld.n_rec;  // leaf <- leaf pairs are direct
     if (ld.level == 0) {
@@ -341,7 +360,7 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
             for (int q = 0; q < 6; ++q) Q[q] = ld.mp[(3 + q) * S + si];
 #pragma unroll
             for (int q = 0; q < 10; ++q) O[q] = ld.mp[(9 + q) * S + si];
-            m2l_pair<LEAF_TARGET>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
+            m2l_pair<LEAF_TARGET, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
                                   mB * imA, OA, amc, a);
             ++cnt;
         }
@@ -362,7 +381,7 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
             for (int q = 0; q < 6; ++q) Q[q] = ld.mp[(3 + q) * S + si];
 #pragma unroll
             for (int q = 0; q < 10; ++q) O[q] = ld.mp[(9 + q) * S + si];
-            m2l_pair<LEAF_TARGET>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
+            m2l_pair<LEAF_TARGET, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
                                   mB * imA, OA, amc, a);
             ++cnt;
         }
@@ -371,23 +390,23 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
     if (LEAF_TARGET) {
         const size_t LS = (size_t)(ld.n_rec - ld.n_int) * kCells;
         const size_t li = (size_t)(node - ld.n_int) * kCells + s;
-        ld.lacc[li] = G * a.L0;
-        ld.lacc[LS + li] = G * a.L1[0];
-        ld.lacc[2 * LS + li] = G * a.L1[1];
-        ld.lacc[3 * LS + li] = G * a.L1[2];
+        ld.lacc[li] = G * (double)a.L0;
+        ld.lacc[LS + li] = G * (double)a.L1[0];
+        ld.lacc[2 * LS + li] = G * (double)a.L1[1];
+        ld.lacc[3 * LS + li] = G * (double)a.L1[2];
         ld.lacc[4 * LS + li] = G * a.C[0];
         ld.lacc[5 * LS + li] = G * a.C[1];
         ld.lacc[6 * LS + li] = G * a.C[2];
     } else {
         const size_t IS = (size_t)ld.n_int * kCells;
         double *out = ld.loc + (size_t)item.chunk * kLoc * IS + (size_t)node * kCells + s;
-        out[0] = G * a.L0;
+        out[0] = G * (double)a.L0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) out[(1 + k) * IS] = G * a.L1[k];
+        for (int k = 0; k < 3; ++k) out[(1 + k) * IS] = G * (double)a.L1[k];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) out[(4 + k) * IS] = G * a.L2[k];
+        for (int k = 0; k < 6; ++k) out[(4 + k) * IS] = G * (double)a.L2[k];
 #pragma unroll
-        for (int k = 0; k < 10; ++k) out[(10 + k) * IS] = G * a.L3[k];
+        for (int k = 0; k < 10; ++k) out[(10 + k) * IS] = G * (double)a.L3[k];
 #pragma unroll
         for (int k = 0; k < 3; ++k) out[(20 + k) * IS] = G * a.C[k];
     }
@@ -395,21 +414,22 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
     if (lane == 0) *cnt_out = tot;
 }
 
-__global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ T,
+template <typename T>
+__global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                             const M2LItem *__restrict__ items, int n_items, StencilDev st,
                                             int64_t *__restrict__ cnt) {
     const int it = xcd_item(n_items);
     if (it >= n_items) return;
     const M2LItem item = items[it];
     const LevelDesc ld = L[item.ld];
-    const TreeDesc td = T[ld.tree];
+    const TreeDesc td = TD[ld.tree];
     __shared__ int s_nbr[27];
     if (threadIdx.x < 27) s_nbr[threadIdx.x] = ld.nbr[item.node * 27 + threadIdx.x];
     __syncthreads();
     if (item.node < ld.n_int)
-        m2l_item<false>(ld, td, st, item, s_nbr, cnt + it);
+        m2l_item<false, T>(ld, td, st, item, s_nbr, cnt + it);
     else
-        m2l_item<true>(ld, td, st, item, s_nbr, cnt + it);
+        m2l_item<true, T>(ld, td, st, item, s_nbr, cnt + it);
 }
 
 // ------------------------------------------------------------------ L2L
@@ -481,26 +501,41 @@ __global__ __launch_bounds__(256) void k_l2l(const LevelDesc *__restrict__ L, co
 // boundaries), plus the parent's expansion shifted to the cell centre and
 // the cell's own multipole-to-local sums; writes phi and g = -grad phi and
 // per-wavefront sums for the net force and torque.
-__device__ inline void direct_add(double Rx, double Ry, double Rz, double m, double &phi, double &gx, double &gy,
-                                  double &gz) {
-    const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
-    const double ir = rsqrt(r2);
-    const double mir = m * ir;
-    const double mir3 = mir * ir * ir;
+__device__ inline float rsqrt_t(float v) { return rsqrtf(v); }
+
+template <typename T>
+__device__ inline const T *weights(const StencilDev &st);
+template <>
+__device__ inline const double *weights<double>(const StencilDev &st) {
+    return st.leaf_w;
+}
+template <>
+__device__ inline const float *weights<float>(const StencilDev &st) {
+    return st.leaf_w32;
+}
+__device__ inline double rsqrt_t(double v) { return rsqrt(v); }
+
+template <typename T>
+__device__ inline void direct_add(T Rx, T Ry, T Rz, T m, T &phi, T &gx, T &gy, T &gz) {
+    const T r2 = Rx * Rx + Ry * Ry + Rz * Rz;
+    const T ir = rsqrt_t(r2);
+    const T mir = m * ir;
+    const T mir3 = mir * ir * ir;
     phi -= mir;
     gx -= mir3 * Rx;
     gy -= mir3 * Ry;
     gz -= mir3 * Rz;
 }
 
-__global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ T,
+template <typename T>
+__global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                              const LeafItem *__restrict__ items, int n_items, StencilDev st,
                                              double *__restrict__ stat, int64_t *__restrict__ cnt_out) {
     const int it = xcd_item(n_items);
     if (it >= n_items) return;
     const LeafItem item = items[it];
     const LevelDesc ld = L[item.ld];
-    const TreeDesc td = T[ld.tree];
+    const TreeDesc td = TD[ld.tree];
     const int lane = threadIdx.x;
     const int node = item.node, p = item.parity;
     __shared__ int s_nbr[27];
@@ -519,16 +554,17 @@ __global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, co
     int cnt = 0;
 
     // same-level leaf partners: phi = -(1/h) sum m w0, g = (1/h^2) sum m w1
-    double sp = 0.0, sgx = 0.0, sgy = 0.0, sgz = 0.0;
+    T sp = 0, sgx = 0, sgy = 0, sgz = 0;
+    const T *lw = weights<T>(st);
     if (ld.level == 0) {
         for (int k = 0; k < kCells; ++k) {
             if (k == s) continue;
             int bx, by, bz;
             local_xyz(k, bx, by, bz);
-            const double dx = bx - x, dy = by - y, dz = bz - z;
-            const double w0 = rsqrt(dx * dx + dy * dy + dz * dz);
-            const double m = ld.mass[k];
-            const double mw0 = m * w0, mw3 = mw0 * w0 * w0;
+            const T dx = (T)(bx - x), dy = (T)(by - y), dz = (T)(bz - z);
+            const T w0 = rsqrt_t(dx * dx + dy * dy + dz * dz);
+            const T m = (T)ld.mass[k];
+            const T mw0 = m * w0, mw3 = mw0 * w0 * w0;
             sp += mw0;
             sgx += mw3 * dx;
             sgy += mw3 * dy;
@@ -543,8 +579,8 @@ __global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, co
             const int sx = x + dx, sy = y + dy, sz = z + dz;
             const int nb = s_nbr[nbr_slot(sx, sy, sz)];
             if (nb < ld.n_int) continue;  // absent (nb < 0) or interior
-            const double m = ld.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)];
-            const double *w = st.leaf_w + 4 * k;
+            const T m = (T)ld.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)];
+            const T *w = lw + 4 * k;
             sp += m * w[0];
             sgx += m * w[1];
             sgy += m * w[2];
@@ -552,9 +588,9 @@ __global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, co
             ++cnt;
         }
     }
-    const double ih = 1.0 / h;
-    double phi = -sp * ih;
-    double gx = sgx * ih * ih, gy = sgy * ih * ih, gz = sgz * ih * ih;
+    const T ih = (T)(1.0 / h);
+    T phi_t = -sp * ih;
+    T gx_t = sgx * ih * ih, gy_t = sgy * ih * ih, gz_t = sgz * ih * ih;
 
     // cross-level pairs at AMR boundaries (direct point masses)
     if (item.flags & kLeafX1) {
@@ -572,11 +608,11 @@ __global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, co
                 const int ox = c >> 2, oy = (c >> 1) & 1, oz = c & 1;
                 const int ux = 2 * bx + ox, uy = 2 * by + oy, uz = 2 * bz + oz;
                 const int ch = ld.child[nb * 8 + ((ux >> 3) << 2) + ((uy >> 3) << 1) + (uz >> 3)];
-                const double m = cl.mass[(size_t)ch * kCells + store_idx(ux & 7, uy & 7, uz & 7)];
+                const T m = (T)cl.mass[(size_t)ch * kCells + store_idx(ux & 7, uy & 7, uz & 7)];
                 // R = z_A - z_b = (h/2) (1/2 - o - 2 d) per axis
                 const double hh = 0.5 * h;
-                direct_add(hh * (0.5 - ox - 2.0 * dx), hh * (0.5 - oy - 2.0 * dy), hh * (0.5 - oz - 2.0 * dz), m,
-                           phi, gx, gy, gz);
+                direct_add<T>((T)(hh * (0.5 - ox - 2.0 * dx)), (T)(hh * (0.5 - oy - 2.0 * dy)),
+                              (T)(hh * (0.5 - oz - 2.0 * dz)), m, phi_t, gx_t, gy_t, gz_t);
                 ++cnt;
             }
         }
@@ -594,17 +630,16 @@ __global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, co
             const int sx = px + dx, sy = py + dy, sz = pz + dz;
             const int nb = s_pnbr[nbr_slot(sx, sy, sz)];
             if (nb < pl.n_int) continue;  // absent or interior
-            const double m = pl.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)];
+            const T m = (T)pl.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)];
             // R = z_a - z_B = h (o - 1/2 - 2 d), o = own index bit
-            direct_add(h * ((x & 1) - 0.5 - 2.0 * dx), h * ((y & 1) - 0.5 - 2.0 * dy), h * ((z & 1) - 0.5 - 2.0 * dz),
-                       m, phi, gx, gy, gz);
+            direct_add<T>((T)(h * ((x & 1) - 0.5 - 2.0 * dx)), (T)(h * ((y & 1) - 0.5 - 2.0 * dy)),
+                          (T)(h * ((z & 1) - 0.5 - 2.0 * dz)), m, phi_t, gx_t, gy_t, gz_t);
             ++cnt;
         }
     }
-    phi *= td.G;
-    gx *= td.G;
-    gy *= td.G;
-    gz *= td.G;
+    // direct sums enter the FP64 accumulation here
+    double phi = td.G * (double)phi_t;
+    double gx = td.G * (double)gx_t, gy = td.G * (double)gy_t, gz = td.G * (double)gz_t;
 
     // own multipole-to-local sums (record leaves)
     if (item.flags & kLeafLacc) {
@@ -712,8 +747,12 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     mark(2);
     if (p.n_m2l) {
         const int grid = ((p.n_m2l + kXcd - 1) / kXcd) * kXcd;
-        hipLaunchKernelGGL(k_m2l, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st,
-                           p.d_m2l_cnt);
+        if (o.precision == OCTO_MIXED)
+            hipLaunchKernelGGL(k_m2l<float>, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st,
+                               p.d_m2l_cnt);
+        else
+            hipLaunchKernelGGL(k_m2l<double>, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st,
+                               p.d_m2l_cnt);
     }
     mark(3);
     for (int l = 0; l < p.n_levels_max; ++l) {
@@ -723,8 +762,12 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     mark(4);
     if (p.n_leaf) {
         const int grid = ((p.n_leaf + kXcd - 1) / kXcd) * kXcd;
-        hipLaunchKernelGGL(k_leaf, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st, p.d_stat,
-                           p.d_leaf_cnt);
+        if (o.precision == OCTO_MIXED)
+            hipLaunchKernelGGL(k_leaf<float>, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
+                               p.d_stat, p.d_leaf_cnt);
+        else
+            hipLaunchKernelGGL(k_leaf<double>, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
+                               p.d_stat, p.d_leaf_cnt);
     }
     mark(5);
     hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(256), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg, p.d_stat,

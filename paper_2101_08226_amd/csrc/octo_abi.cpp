@@ -252,7 +252,9 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     auto h = std::make_unique<StencilDevHolder>();
     h->host = make_stencil(theta);
     const Stencil &S = h->host;
-    size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_w.size() * 8);
+    std::vector<float> w32(S.leaf_w.begin(), S.leaf_w.end());
+    size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_w.size() * 8) +
+               al(w32.size() * 4);
     void *mem = nullptr;
     check_hip(hipMalloc(&mem, b), "stencil alloc");
     h->block.ptr = mem;
@@ -269,6 +271,7 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     h->dev.nearo = (const int32_t *)put(S.nearo.data(), S.nearo.size() * 4);
     h->dev.leaf = (const int32_t *)put(S.leaf.data(), S.leaf.size() * 4);
     h->dev.leaf_w = (const double *)put(S.leaf_w.data(), S.leaf_w.size() * 8);
+    h->dev.leaf_w32 = (const float *)put(w32.data(), w32.size() * 4);
     for (int p = 0; p < 9; ++p) {
         h->dev.m2l_beg[p] = S.m2l_beg[p];
         h->dev.near_beg[p] = S.near_beg[p];

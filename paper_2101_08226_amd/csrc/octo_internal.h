@@ -93,6 +93,7 @@ struct StencilDev {
     const int32_t *nearo;  // not well separated, parents not, d != 0
     const int32_t *leaf;   // m2l followed by near, with weights
     const double *leaf_w;  // 4 per leaf entry: 1/|d|, d/|d|^3
+    const float *leaf_w32; // the same weights rounded to FP32 (mixed precision)
     int32_t m2l_beg[9];
     int32_t near_beg[9];
     int32_t leaf_beg[9];

@@ -114,6 +114,44 @@ def test_adaptive_random(ctx, seed, max_level):
     tree.destroy()
 
 
+# Mixed precision (FP32 L-term contractions and near field, FP64 moments,
+# correction and final accumulation): bounds are 4x the largest error measured
+# on these cases (see the design notes).
+MIXED_PHI = 4e-6
+MIXED_G = 4e-5
+
+
+@pytest.mark.parametrize("case", ["c1", "poly64", "amr"])
+def test_mixed_precision_bounds(ctx, case):
+    if case == "c1":
+        rho = w.noisy_sphere_16()
+    elif case == "poly64":
+        rho = w.uniform_grid(w.binary_polytrope(0.12, 0.10, 0.35, 0.7), 3)
+    if case in ("c1", "poly64"):
+        n = rho.shape[0]
+        level = int(np.log2(n // 8))
+        tree = ctx.uniform_tree(rho)
+        t = oracle.Tree(w.uniform_leaves(level), w.grid_to_leaves(rho))
+        to_leaf = lambda a: w.grid_to_leaves(a.reshape(n, n, n)).ravel()  # noqa: E731
+    else:
+        leaves, f = random_amr_leaves(22, max_level=3, n_stars=2)
+        tree = ctx.adaptive_tree(f, 3, 1e-4)
+        t = oracle.Tree(leaves, w.leaf_density(f, leaves))
+        to_leaf = lambda a: a  # noqa: E731
+    say(f"mixed {case}")
+    phi, g, st = gpu_solve(ctx, tree, theta=0.5, precision=lib.OCTO_MIXED)
+    p64, g64, st64 = gpu_solve(ctx, tree, theta=0.5, precision=lib.OCTO_FP64)
+    tree.destroy()
+    p_ref, g_ref = t.solve(theta=0.5)
+    phi_l = to_leaf(phi)
+    g_l = np.stack([to_leaf(g[a]) for a in range(3)])
+    e = errs(phi_l, g_l, p_ref, g_ref)
+    say(f"  mixed e_phi={e[0]:.2e} e_g={e[1]:.2e} torque={st['torque']:.2e} (fp64 torque {st64['torque']:.2e})")
+    assert e[0] <= MIXED_PHI and e[1] <= MIXED_G
+    assert st["torque"] < 1e-5 and st["force"] < 1e-5
+    assert st["m2l_pairs"] == st64["m2l_pairs"] and st["direct_pairs"] == st64["direct_pairs"]
+
+
 def test_explicit_leaf_order(ctx):
     """octo_tree_build keeps the caller's leaf order (shuffled here)."""
     leaves, f = random_amr_leaves(31, max_level=2, n_stars=1)
