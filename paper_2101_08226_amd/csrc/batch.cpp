@@ -93,6 +93,11 @@ static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, con
         ph.trees.push_back(descs[i]);
         ph.tree_leaf_beg.push_back((int32_t)ph.leaf.size());
         ph.tree_m2l_beg.push_back((int32_t)ph.m2l.size());
+        ph.tree_m2ln_beg.push_back((int32_t)ph.m2l_nodes.size());
+        for (NodeItem q : t.m2l_nodes) {
+            q.ld += base;
+            ph.m2l_nodes.push_back(q);
+        }
         for (M2LItem m : t.m2l) {
             m.ld += base;
             ph.m2l.push_back(m);
@@ -113,6 +118,7 @@ static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, con
     }
     ph.tree_leaf_beg.push_back((int32_t)ph.leaf.size());
     ph.tree_m2l_beg.push_back((int32_t)ph.m2l.size());
+    ph.tree_m2ln_beg.push_back((int32_t)ph.m2l_nodes.size());
     return bp;
 }
 

@@ -432,6 +432,124 @@ __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, con
         m2l_item<true, T>(ld, td, st, item, s_nbr, cnt + it);
 }
 
+
+// Multipole-to-local for all 512 cells of one interior node, with the source
+// halo staged in LDS one parity class at a time: the cells of one parity class
+// within 5 cells of the node form a 9x9x9 lattice (20 FP64 values each,
+// 117 KB); every wavefront (one target parity class) walks the part of its
+// stencil whose sources fall in the staged class.
+template <typename T>
+__global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
+                                                 const NodeItem *__restrict__ items, int n_items, StencilDev st,
+                                                 int64_t *__restrict__ cnt_out) {
+    const int it = xcd_item(n_items);
+    if (it >= n_items) return;
+    const NodeItem item = items[it];
+    const LevelDesc ld = L[item.ld];
+    const TreeDesc td = TD[ld.tree];
+    const int node = item.node;
+    __shared__ double2 s_src[10][729];
+    __shared__ int s_nbr[27];
+    __shared__ int s_cnt[8];
+    const int tid = threadIdx.x;
+    const int p = tid >> 6, lane = tid & 63;
+    if (tid < 27) s_nbr[tid] = ld.nbr[node * 27 + tid];
+    const int s = tid;  // parity-major storage: wavefront p holds class p
+    int x, y, z;
+    local_xyz(s, x, y, z);
+    const size_t S = (size_t)ld.n_rec * kCells;
+    const size_t ti = (size_t)node * kCells + s;
+    const double zAx = ld.mp[ti], zAy = ld.mp[S + ti], zAz = ld.mp[2 * S + ti];
+    const double mA = ld.mass[ti];
+    double OA[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) OA[k] = ld.mp[(9 + k) * S + ti];
+    const bool amc = td.amc && mA > 0.0;
+    const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
+    Acc<T> a;
+    a.L0 = (T)0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a.L1[k] = (T)0;
+        a.C[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a.L2[k] = (T)0;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) a.L3[k] = (T)0;
+    int cnt = 0;
+    __syncthreads();
+    for (int q = 0; q < 8; ++q) {
+        const int qx = q >> 2, qy = (q >> 1) & 1, qz = q & 1;
+        // stage source class q: lattice index i in [0,9) <-> local coordinate 2i - 4 - parity
+        for (int c = tid; c < 729; c += 512) {
+            const int ix = c / 81, iy = (c / 9) % 9, iz = c % 9;
+            const int sx = 2 * ix - 4 - qx, sy = 2 * iy - 4 - qy, sz = 2 * iz - 4 - qz;
+            const int nb = s_nbr[nbr_slot(sx, sy, sz)];
+            double v[20];
+            if (nb >= 0 && nb < ld.n_rec) {
+                const size_t si = (size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7);
+                v[0] = ld.mass[si];
+#pragma unroll
+                for (int k = 0; k < kRec; ++k) v[1 + k] = ld.mp[k * S + si];
+            } else {
+                v[0] = -1.0;  // no source cell here
+#pragma unroll
+                for (int k = 1; k < 20; ++k) v[k] = 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 10; ++k) s_src[k][c] = make_double2(v[2 * k], v[2 * k + 1]);
+        }
+        __syncthreads();
+        const int beg = st.m2l_src_beg[p * 9 + q], end = st.m2l_src_beg[p * 9 + q + 1];
+        for (int k = beg; k < end; ++k) {
+            int dx, dy, dz;
+            unpack(st.m2l_src[k], dx, dy, dz);
+            const int h = (((x + dx + 5) >> 1) * 9 + ((y + dy + 5) >> 1)) * 9 + ((z + dz + 5) >> 1);
+            const double2 e0 = s_src[0][h];
+            if (e0.x < 0.0) continue;
+            const double2 e1 = s_src[1][h];
+            double Q[6], O[10];
+            const double2 e2 = s_src[2][h], e3 = s_src[3][h], e4 = s_src[4][h];
+            Q[0] = e2.x;
+            Q[1] = e2.y;
+            Q[2] = e3.x;
+            Q[3] = e3.y;
+            Q[4] = e4.x;
+            Q[5] = e4.y;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                const double2 e = s_src[5 + j][h];
+                O[2 * j] = e.x;
+                O[2 * j + 1] = e.y;
+            }
+            m2l_pair<false, T>(zAx - e0.y, zAy - e1.x, zAz - e1.y, e0.x, Q, O, e0.x * imA, OA, amc, a);
+            ++cnt;
+        }
+        __syncthreads();
+    }
+    const double G = td.G;
+    const size_t IS = (size_t)ld.n_int * kCells;
+    double *out = ld.loc + (size_t)node * kCells + s;
+    out[0] = G * (double)a.L0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[(1 + k) * IS] = G * (double)a.L1[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) out[(4 + k) * IS] = G * (double)a.L2[k];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) out[(10 + k) * IS] = G * (double)a.L3[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[(20 + k) * IS] = G * a.C[k];
+    const int tot = wave_sum(cnt);
+    if (lane == 0) s_cnt[p] = tot;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t sum = 0;
+        for (int k = 0; k < 8; ++k) sum += s_cnt[k];
+        cnt_out[it] = sum;
+    }
+}
+
 // ------------------------------------------------------------------ L2L
 // Interior cells: sum the partial locals, then add the parent's expansion
 // shifted to this cell's centre of mass (Taylor shift of the order-3 local
@@ -699,8 +817,9 @@ __global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, co
 // ------------------------------------------------------------------ stats
 // One work-group per tree: fixed-order sums of the per-wavefront partials.
 __global__ __launch_bounds__(256) void k_stats(const int32_t *__restrict__ leaf_beg,
-                                               const int32_t *__restrict__ m2l_beg, const double *__restrict__ stat,
-                                               const int64_t *__restrict__ leaf_cnt,
+                                               const int32_t *__restrict__ m2l_beg,
+                                               const int32_t *__restrict__ m2ln_beg, int n_m2l,
+                                               const double *__restrict__ stat, const int64_t *__restrict__ leaf_cnt,
                                                const int64_t *__restrict__ m2l_cnt, double *__restrict__ out) {
     const int t = blockIdx.x;
     __shared__ double sh[256];
@@ -713,6 +832,7 @@ __global__ __launch_bounds__(256) void k_stats(const int32_t *__restrict__ leaf_
             for (int i = lb + threadIdx.x; i < le; i += 256) acc += stat[(size_t)i * kStat + k];
         } else if (k == kStat) {
             for (int i = m2l_beg[t] + threadIdx.x; i < m2l_beg[t + 1]; i += 256) c += m2l_cnt[i];
+            for (int i = m2ln_beg[t] + threadIdx.x; i < m2ln_beg[t + 1]; i += 256) c += m2l_cnt[n_m2l + i];
         } else {
             for (int i = lb + threadIdx.x; i < le; i += 256) c += leaf_cnt[i];
         }
@@ -754,6 +874,15 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
             hipLaunchKernelGGL(k_m2l<double>, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st,
                                p.d_m2l_cnt);
     }
+    if (p.n_m2l_nodes) {
+        const int grid = ((p.n_m2l_nodes + kXcd - 1) / kXcd) * kXcd;
+        if (o.precision == OCTO_MIXED)
+            hipLaunchKernelGGL(k_m2l_lds<float>, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes,
+                               p.n_m2l_nodes, st, p.d_m2l_cnt + p.n_m2l);
+        else
+            hipLaunchKernelGGL(k_m2l_lds<double>, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes,
+                               p.n_m2l_nodes, st, p.d_m2l_cnt + p.n_m2l);
+    }
     mark(3);
     for (int l = 0; l < p.n_levels_max; ++l) {
         const int n = p.n_interior[l];
@@ -770,8 +899,8 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
                                p.d_stat, p.d_leaf_cnt);
     }
     mark(5);
-    hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(256), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg, p.d_stat,
-                       p.d_leaf_cnt, p.d_m2l_cnt, p.d_out);
+    hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(256), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg,
+                       p.d_tree_m2ln_beg, p.n_m2l, p.d_stat, p.d_leaf_cnt, p.d_m2l_cnt, p.d_out);
     mark(6);
     check_hip(hipGetLastError(), "kernel launch");
 }

@@ -111,13 +111,24 @@ void finish_tree(octo_tree *t, const double *rho, int rho_on_device) {
     PlanHost &ph = t->ph;
     ph = PlanHost{};
     ph.interior.resize(nl);
+    // interior nodes of levels with many nodes take the LDS-staged multipole
+    // kernel (one work-group per node); the root and sparse levels use the
+    // chunked per-wavefront kernel so that the chip still fills
+    const char *mode = getenv("OCTO_M2L");
+    const bool lds = !(mode && std::string(mode) == "global");
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
         for (int n = h.n_int; n < h.n_nodes; ++n) ph.p2m.push_back(NodeItem{l, n});
         for (int n = 0; n < h.n_int; ++n) ph.interior[l].push_back(NodeItem{l, n});
-        for (int n = 0; n < h.n_int; ++n)
+        const bool use_lds = lds && l >= 1 && parts[l] == 1;
+        for (int n = 0; n < h.n_int; ++n) {
+            if (use_lds) {
+                ph.m2l_nodes.push_back(NodeItem{l, n});
+                continue;
+            }
             for (int c = 0; c < parts[l]; ++c)
                 for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, c});
+        }
         for (int n = h.n_int; n < h.n_rec; ++n)
             for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, 0});
         for (int n = h.n_int; n < h.n_nodes; ++n)
@@ -125,6 +136,7 @@ void finish_tree(octo_tree *t, const double *rho, int rho_on_device) {
     }
     ph.tree_leaf_beg = {0, (int32_t)ph.leaf.size()};
     ph.tree_m2l_beg = {0, (int32_t)ph.m2l.size()};
+    ph.tree_m2ln_beg = {0, (int32_t)ph.m2l_nodes.size()};
     const size_t pbytes0 = 0;
     (void)pbytes0;
 
@@ -254,7 +266,7 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     const Stencil &S = h->host;
     std::vector<float> w32(S.leaf_w.begin(), S.leaf_w.end());
     size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_w.size() * 8) +
-               al(w32.size() * 4);
+               al(w32.size() * 4) + al(S.m2l_src.size() * 4);
     void *mem = nullptr;
     check_hip(hipMalloc(&mem, b), "stencil alloc");
     h->block.ptr = mem;
@@ -272,6 +284,8 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     h->dev.leaf = (const int32_t *)put(S.leaf.data(), S.leaf.size() * 4);
     h->dev.leaf_w = (const double *)put(S.leaf_w.data(), S.leaf_w.size() * 8);
     h->dev.leaf_w32 = (const float *)put(w32.data(), w32.size() * 4);
+    h->dev.m2l_src = (const int32_t *)put(S.m2l_src.data(), S.m2l_src.size() * 4);
+    for (int k = 0; k < 73; ++k) h->dev.m2l_src_beg[k] = S.m2l_src_beg[k];
     for (int p = 0; p < 9; ++p) {
         h->dev.m2l_beg[p] = S.m2l_beg[p];
         h->dev.near_beg[p] = S.near_beg[p];

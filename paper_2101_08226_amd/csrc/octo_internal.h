@@ -94,9 +94,11 @@ struct StencilDev {
     const int32_t *leaf;   // m2l followed by near, with weights
     const double *leaf_w;  // 4 per leaf entry: 1/|d|, d/|d|^3
     const float *leaf_w32; // the same weights rounded to FP32 (mixed precision)
+    const int32_t *m2l_src;  // m2l entries regrouped by source parity class
     int32_t m2l_beg[9];
     int32_t near_beg[9];
     int32_t leaf_beg[9];
+    int32_t m2l_src_beg[73];  // target class p, source class q: [p*9+q, p*9+q+1)
     double theta2;
 };
 

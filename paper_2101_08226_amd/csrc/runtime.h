@@ -54,9 +54,10 @@ std::vector<octo_leaf> adaptive_leaves(octo_boxmax_fn boxmax, void *user, int ma
 
 struct Stencil {
     double theta = 0;
-    std::vector<int32_t> m2l, nearo, leaf;
+    std::vector<int32_t> m2l, nearo, leaf, m2l_src;
     std::vector<double> leaf_w;
     int m2l_beg[9], near_beg[9], leaf_beg[9];
+    int m2l_src_beg[73];
 };
 
 Stencil make_stencil(double theta);
@@ -71,9 +72,10 @@ struct PlanHost {
     std::vector<M2LItem> m2l;
     std::vector<LeafItem> leaf;
     std::vector<NodeItem> p2m;
+    std::vector<NodeItem> m2l_nodes;  // interior nodes served by the LDS-staged kernel
     // interior nodes by level index (level l of every tree)
     std::vector<std::vector<NodeItem>> interior;
-    std::vector<int32_t> tree_leaf_beg, tree_m2l_beg;  // per tree, +1 sentinel
+    std::vector<int32_t> tree_leaf_beg, tree_m2l_beg, tree_m2ln_beg;  // per tree, +1 sentinel
 };
 
 struct DeviceBlock {
@@ -83,7 +85,7 @@ struct DeviceBlock {
 
 struct Plan {
     int n_trees = 0, n_levels_max = 0;
-    int n_m2l = 0, n_leaf = 0, n_p2m = 0;
+    int n_m2l = 0, n_leaf = 0, n_p2m = 0, n_m2l_nodes = 0;
     std::vector<int> n_interior;        // per level index
     std::vector<size_t> interior_off;   // element offset into d_interior per level index
     LevelDesc *d_levels = nullptr;
@@ -91,11 +93,12 @@ struct Plan {
     M2LItem *d_m2l = nullptr;
     LeafItem *d_leaf = nullptr;
     NodeItem *d_p2m = nullptr;
+    NodeItem *d_m2l_nodes = nullptr;
     NodeItem *d_interior = nullptr;
-    int32_t *d_tree_leaf_beg = nullptr, *d_tree_m2l_beg = nullptr;
+    int32_t *d_tree_leaf_beg = nullptr, *d_tree_m2l_beg = nullptr, *d_tree_m2ln_beg = nullptr;
     double *d_stat = nullptr;      // n_leaf * kStat
     int64_t *d_leaf_cnt = nullptr;  // n_leaf
-    int64_t *d_m2l_cnt = nullptr;   // n_m2l
+    int64_t *d_m2l_cnt = nullptr;   // n_m2l + n_m2l_nodes
     double *d_out = nullptr;        // n_trees * 12: stats per tree
     DeviceBlock block;
     std::vector<TreeDesc> trees_host;  // current tree descriptors (outputs, G, amc)

@@ -319,6 +319,19 @@ Stencil make_stencil(double theta) {
     s.m2l_beg[8] = (int)s.m2l.size();
     s.near_beg[8] = (int)s.nearo.size();
     s.leaf_beg[8] = (int)s.leaf.size();
+    // the same multipole entries grouped by the parity class of the source cell
+    for (int p = 0; p < 8; ++p) {
+        int px = p >> 2, py = (p >> 1) & 1, pz = p & 1;
+        for (int q = 0; q < 8; ++q) {
+            s.m2l_src_beg[p * 9 + q] = (int)s.m2l_src.size();
+            for (auto &d : m2l[p]) {
+                int qq = (((px + d[0]) & 1) << 2) | (((py + d[1]) & 1) << 1) | ((pz + d[2]) & 1);
+                if (qq == q) s.m2l_src.push_back(pack_off(d[0], d[1], d[2]));
+            }
+        }
+        s.m2l_src_beg[p * 9 + 8] = (int)s.m2l_src.size();
+    }
+    s.m2l_src_beg[72] = (int)s.m2l_src.size();
     return s;
 }
 
@@ -359,12 +372,14 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
     p.n_m2l = (int)ph.m2l.size();
     p.n_leaf = (int)ph.leaf.size();
     p.n_p2m = (int)ph.p2m.size();
+    p.n_m2l_nodes = (int)ph.m2l_nodes.size();
     p.n_levels_max = (int)ph.interior.size();
     p.d_levels = (LevelDesc *)put(ph.levels.data(), ph.levels.size() * sizeof(LevelDesc));
     p.d_trees = (TreeDesc *)put(ph.trees.data(), ph.trees.size() * sizeof(TreeDesc));
     p.d_m2l = (M2LItem *)put(ph.m2l.data(), ph.m2l.size() * sizeof(M2LItem));
     p.d_leaf = (LeafItem *)put(ph.leaf.data(), ph.leaf.size() * sizeof(LeafItem));
     p.d_p2m = (NodeItem *)put(ph.p2m.data(), ph.p2m.size() * sizeof(NodeItem));
+    p.d_m2l_nodes = (NodeItem *)put(ph.m2l_nodes.data(), ph.m2l_nodes.size() * sizeof(NodeItem));
     std::vector<NodeItem> all;
     p.n_interior.clear();
     p.interior_off.clear();
@@ -376,9 +391,10 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
     p.d_interior = (NodeItem *)put(all.data(), all.size() * sizeof(NodeItem));
     p.d_tree_leaf_beg = (int32_t *)put(ph.tree_leaf_beg.data(), ph.tree_leaf_beg.size() * sizeof(int32_t));
     p.d_tree_m2l_beg = (int32_t *)put(ph.tree_m2l_beg.data(), ph.tree_m2l_beg.size() * sizeof(int32_t));
+    p.d_tree_m2ln_beg = (int32_t *)put(ph.tree_m2ln_beg.data(), ph.tree_m2ln_beg.size() * sizeof(int32_t));
     p.d_stat = (double *)reserve(ph.leaf.size() * kStat * sizeof(double));
     p.d_leaf_cnt = (int64_t *)reserve(ph.leaf.size() * sizeof(int64_t));
-    p.d_m2l_cnt = (int64_t *)reserve(ph.m2l.size() * sizeof(int64_t));
+    p.d_m2l_cnt = (int64_t *)reserve((ph.m2l.size() + ph.m2l_nodes.size()) * sizeof(int64_t));
     p.d_out = (double *)reserve(ph.trees.size() * 12 * sizeof(double));
     p.trees_host = ph.trees;
     return off;
