@@ -646,24 +646,36 @@ __device__ inline void direct_add(T Rx, T Ry, T Rz, T m, T &phi, T &gx, T &gy, T
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
-                                             const LeafItem *__restrict__ items, int n_items, StencilDev st,
-                                             double *__restrict__ stat, int64_t *__restrict__ cnt_out) {
+__global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
+                                              const LeafItem *__restrict__ items, int n_items, StencilDev st,
+                                              double *__restrict__ stat, int64_t *__restrict__ cnt_out) {
     const int it = xcd_item(n_items);
     if (it >= n_items) return;
     const LeafItem item = items[it];
     const LevelDesc ld = L[item.ld];
     const TreeDesc td = TD[ld.tree];
-    const int lane = threadIdx.x;
-    const int node = item.node, p = item.parity;
+    const int tid = threadIdx.x;
+    const int p = tid >> 6, lane = tid & 63;
+    const int node = item.node;
+    // masses of the 18^3 cells within 5 cells of this node; -1 where the cell
+    // is not a leaf of this level (absent or interior)
+    __shared__ T s_m[18 * 18 * 18];
     __shared__ int s_nbr[27];
     __shared__ int s_pnbr[27];
-    if (threadIdx.x < 27) {
-        s_nbr[threadIdx.x] = ld.nbr[node * 27 + threadIdx.x];
-        if (ld.parent_ld >= 0) s_pnbr[threadIdx.x] = L[ld.parent_ld].nbr[ld.parent[node] * 27 + threadIdx.x];
+    if (tid < 27) {
+        s_nbr[tid] = ld.nbr[node * 27 + tid];
+        if (ld.parent_ld >= 0) s_pnbr[tid] = L[ld.parent_ld].nbr[ld.parent[node] * 27 + tid];
     }
     __syncthreads();
-    const int s = (p << 6) | lane;
+    if (ld.level > 0) {
+        for (int c = tid; c < 18 * 18 * 18; c += 512) {
+            const int sx = c / 324 - 5, sy = (c / 18) % 18 - 5, sz = c % 18 - 5;
+            const int nb = s_nbr[nbr_slot(sx, sy, sz)];
+            s_m[c] = nb >= ld.n_int ? (T)ld.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)] : (T)-1;
+        }
+    }
+    __syncthreads();
+    const int s = tid;  // parity-major storage: wavefront p holds class p
     int x, y, z;
     local_xyz(s, x, y, z);
     const double h = ld.h;
@@ -690,14 +702,11 @@ __global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, co
             ++cnt;
         }
     } else {
+        const int base = ((x + 5) * 18 + (y + 5)) * 18 + (z + 5);
         const int beg = st.leaf_beg[p], end = st.leaf_beg[p + 1];
         for (int k = beg; k < end; ++k) {
-            int dx, dy, dz;
-            unpack(st.leaf[k], dx, dy, dz);
-            const int sx = x + dx, sy = y + dy, sz = z + dz;
-            const int nb = s_nbr[nbr_slot(sx, sy, sz)];
-            if (nb < ld.n_int) continue;  // absent (nb < 0) or interior
-            const T m = (T)ld.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)];
+            const T m = s_m[base + st.leaf_hoff[k]];
+            if (m < (T)0) continue;
             const T *w = lw + 4 * k;
             sp += m * w[0];
             sgx += m * w[1];
@@ -808,9 +817,10 @@ __global__ __launch_bounds__(64) void k_leaf(const LevelDesc *__restrict__ L, co
     for (int k = 0; k < kStat; ++k) v[k] = wave_sum(v[k]);
     const int tot = wave_sum(cnt);
     if (lane == 0) {
+        const size_t wi = (size_t)it * 8 + p;
 #pragma unroll
-        for (int k = 0; k < kStat; ++k) stat[(size_t)it * kStat + k] = v[k];
-        cnt_out[it] = tot;
+        for (int k = 0; k < kStat; ++k) stat[wi * kStat + k] = v[k];
+        cnt_out[wi] = tot;
     }
 }
 
@@ -824,7 +834,7 @@ __global__ __launch_bounds__(256) void k_stats(const int32_t *__restrict__ leaf_
     const int t = blockIdx.x;
     __shared__ double sh[256];
     __shared__ long long shc[256];
-    const int lb = leaf_beg[t], le = leaf_beg[t + 1];
+    const int lb = 8 * leaf_beg[t], le = 8 * leaf_beg[t + 1];
     for (int k = 0; k < kStat + 2; ++k) {
         double acc = 0.0;
         long long c = 0;
@@ -892,10 +902,10 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     if (p.n_leaf) {
         const int grid = ((p.n_leaf + kXcd - 1) / kXcd) * kXcd;
         if (o.precision == OCTO_MIXED)
-            hipLaunchKernelGGL(k_leaf<float>, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
+            hipLaunchKernelGGL(k_leaf<float>, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
                                p.d_stat, p.d_leaf_cnt);
         else
-            hipLaunchKernelGGL(k_leaf<double>, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
+            hipLaunchKernelGGL(k_leaf<double>, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
                                p.d_stat, p.d_leaf_cnt);
     }
     mark(5);

@@ -131,8 +131,7 @@ void finish_tree(octo_tree *t, const double *rho, int rho_on_device) {
         }
         for (int n = h.n_int; n < h.n_rec; ++n)
             for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, 0});
-        for (int n = h.n_int; n < h.n_nodes; ++n)
-            for (int p = 0; p < 8; ++p) ph.leaf.push_back(LeafItem{l, n, p, h.flags[n]});
+        for (int n = h.n_int; n < h.n_nodes; ++n) ph.leaf.push_back(LeafItem{l, n, 0, h.flags[n]});
     }
     ph.tree_leaf_beg = {0, (int32_t)ph.leaf.size()};
     ph.tree_m2l_beg = {0, (int32_t)ph.m2l.size()};
@@ -266,7 +265,7 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     const Stencil &S = h->host;
     std::vector<float> w32(S.leaf_w.begin(), S.leaf_w.end());
     size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_w.size() * 8) +
-               al(w32.size() * 4) + al(S.m2l_src.size() * 4);
+               al(w32.size() * 4) + al(S.m2l_src.size() * 4) + al(S.leaf_hoff.size() * 4);
     void *mem = nullptr;
     check_hip(hipMalloc(&mem, b), "stencil alloc");
     h->block.ptr = mem;
@@ -285,6 +284,7 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     h->dev.leaf_w = (const double *)put(S.leaf_w.data(), S.leaf_w.size() * 8);
     h->dev.leaf_w32 = (const float *)put(w32.data(), w32.size() * 4);
     h->dev.m2l_src = (const int32_t *)put(S.m2l_src.data(), S.m2l_src.size() * 4);
+    h->dev.leaf_hoff = (const int32_t *)put(S.leaf_hoff.data(), S.leaf_hoff.size() * 4);
     for (int k = 0; k < 73; ++k) h->dev.m2l_src_beg[k] = S.m2l_src_beg[k];
     for (int p = 0; p < 9; ++p) {
         h->dev.m2l_beg[p] = S.m2l_beg[p];

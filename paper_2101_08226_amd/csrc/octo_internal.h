@@ -77,9 +77,10 @@ struct M2LItem {
 
 enum : int32_t { kLeafX1 = 1, kLeafX2 = 2, kLeafLacc = 4 };
 
-// one wavefront of leaf work: 64 leaf cells of one parity class of one node
+// one work-group of leaf work: the 512 cells of one leaf node (8 wavefronts,
+// one per parity class)
 struct LeafItem {
-    int32_t ld, node, parity, flags;
+    int32_t ld, node, pad, flags;
 };
 
 struct NodeItem {
@@ -95,6 +96,7 @@ struct StencilDev {
     const double *leaf_w;  // 4 per leaf entry: 1/|d|, d/|d|^3
     const float *leaf_w32; // the same weights rounded to FP32 (mixed precision)
     const int32_t *m2l_src;  // m2l entries regrouped by source parity class
+    const int32_t *leaf_hoff;  // leaf entries as offsets in an 18^3 halo: (dx*18 + dy)*18 + dz
     int32_t m2l_beg[9];
     int32_t near_beg[9];
     int32_t leaf_beg[9];

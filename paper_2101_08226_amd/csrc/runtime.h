@@ -54,7 +54,7 @@ std::vector<octo_leaf> adaptive_leaves(octo_boxmax_fn boxmax, void *user, int ma
 
 struct Stencil {
     double theta = 0;
-    std::vector<int32_t> m2l, nearo, leaf, m2l_src;
+    std::vector<int32_t> m2l, nearo, leaf, m2l_src, leaf_hoff;
     std::vector<double> leaf_w;
     int m2l_beg[9], near_beg[9], leaf_beg[9];
     int m2l_src_beg[73];
@@ -96,8 +96,8 @@ struct Plan {
     NodeItem *d_m2l_nodes = nullptr;
     NodeItem *d_interior = nullptr;
     int32_t *d_tree_leaf_beg = nullptr, *d_tree_m2l_beg = nullptr, *d_tree_m2ln_beg = nullptr;
-    double *d_stat = nullptr;      // n_leaf * kStat
-    int64_t *d_leaf_cnt = nullptr;  // n_leaf
+    double *d_stat = nullptr;      // 8 * n_leaf * kStat (per wavefront)
+    int64_t *d_leaf_cnt = nullptr;  // 8 * n_leaf
     int64_t *d_m2l_cnt = nullptr;   // n_m2l + n_m2l_nodes
     double *d_out = nullptr;        // n_trees * 12: stats per tree
     DeviceBlock block;

@@ -307,6 +307,7 @@ Stencil make_stencil(double theta) {
         for (int pass = 0; pass < 2; ++pass)
             for (auto &d : (pass == 0 ? m2l[p] : nr[p])) {
                 s.leaf.push_back(pack_off(d[0], d[1], d[2]));
+                s.leaf_hoff.push_back((d[0] * 18 + d[1]) * 18 + d[2]);
                 double r = std::sqrt((double)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
                 double w0 = 1.0 / r;
                 double w3 = w0 * w0 * w0;
@@ -392,8 +393,8 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
     p.d_tree_leaf_beg = (int32_t *)put(ph.tree_leaf_beg.data(), ph.tree_leaf_beg.size() * sizeof(int32_t));
     p.d_tree_m2l_beg = (int32_t *)put(ph.tree_m2l_beg.data(), ph.tree_m2l_beg.size() * sizeof(int32_t));
     p.d_tree_m2ln_beg = (int32_t *)put(ph.tree_m2ln_beg.data(), ph.tree_m2ln_beg.size() * sizeof(int32_t));
-    p.d_stat = (double *)reserve(ph.leaf.size() * kStat * sizeof(double));
-    p.d_leaf_cnt = (int64_t *)reserve(ph.leaf.size() * sizeof(int64_t));
+    p.d_stat = (double *)reserve(8 * ph.leaf.size() * kStat * sizeof(double));
+    p.d_leaf_cnt = (int64_t *)reserve(8 * ph.leaf.size() * sizeof(int64_t));
     p.d_m2l_cnt = (int64_t *)reserve((ph.m2l.size() + ph.m2l_nodes.size()) * sizeof(int64_t));
     p.d_out = (double *)reserve(ph.trees.size() * 12 * sizeof(double));
     p.trees_host = ph.trees;
