@@ -32,9 +32,9 @@ METRIC = "FMM cells solved/s (FP64 vs mixed, 1 GPU); p50/p99 served solve latenc
 
 # Algorithmic FP64 operations per ordered multipole-to-local pair with an
 # interior target and the correction on: adds, multiplies and rsqrt count as
-# one, a fused multiply-add as two (189 for the L0..L3 terms, 109 for the
+# one, a fused multiply-add as two (188 for R and the L0..L3 terms, 109 for the
 # correction); the accounting is in the design notes.
-M2L_FLOPS_PER_PAIR = 298
+M2L_FLOPS_PER_PAIR = 297
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector
 PHASES = ["p2m", "m2m", "m2l", "l2l", "leaf", "stats"]
