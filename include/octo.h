@@ -188,6 +188,17 @@ octo_status octo_tree_destroy(octo_tree *tree);
 octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, double *phi, double *g,
                        int out_on_device, octo_stats *stats);
 
+/* Autotune the tree's multipole work shape for these options: for every level
+ * with interior nodes, time the multipole-interaction phase with each
+ * candidate (one LDS-staged work-group per node, or one wavefront per parity
+ * class with 1, 2, 4, ... stencil chunks) and keep the fastest, level by
+ * level.  Runs several solves (outputs into the tree's own staging memory)
+ * and rebuilds the tree's work plan (device memory for the plan is
+ * reallocated).  choice: NULL or n_levels entries: -1 = no interior nodes,
+ * 0 = LDS-staged, k > 0 = per-wavefront with k chunks.  Results of later
+ * solves are identical to within rounding of the summation order. */
+octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, int32_t *choice);
+
 /* Solve n independent trees with one launch per phase of the method, all
  * trees together (the phases are captured once into a HIP graph per batch
  * signature and replayed).  phi[i], g[i] as in octo_solve for trees[i];

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "OCTO_OK", 1: "OCTO_E_INVALID", 2: "OCTO_E_DEVICE", 3: "OCTO_
 EXPORTS = [
     "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_tree_build", "octo_tree_build_uniform",
     "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
-    "octo_solve", "octo_solve_batch", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
+    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
     "octo_host_stencil_sizes", "octo_host_layout", "octo_host_adaptive_leaves",
 ]
 
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_tree_leaves": [_P, ctypes.POINTER(octo_leaf)],
         "octo_tree_destroy": [_P],
         "octo_solve": [_P, _P, ctypes.POINTER(octo_opts), _D, _D, _I, ctypes.POINTER(octo_stats)],
+        "octo_tree_autotune": [_P, _P, ctypes.POINTER(octo_opts), ctypes.POINTER(ctypes.c_int32)],
         "octo_solve_batch": [_P, _PP, ctypes.c_int32, ctypes.POINTER(octo_opts), ctypes.POINTER(_D),
                              ctypes.POINTER(_D), _I, ctypes.POINTER(octo_stats)],
         "octo_submit": [_P, _P, ctypes.POINTER(octo_opts), _D, _D, ctypes.POINTER(_I64)],
@@ -229,6 +230,13 @@ def octo_solve(ctx: int, tree: int, opts: octo_opts, phi_ptr: int, g_ptr: int, o
     _check(load_library().octo_solve(ctx, tree, ctypes.byref(opts), _dptr(phi_ptr), _dptr(g_ptr),
                                      int(out_on_device), ctypes.byref(st) if want_stats else None))
     return st if want_stats else None
+
+
+def octo_tree_autotune(ctx: int, tree: int, opts: octo_opts) -> list:
+    _, nl, _ = octo_tree_info(tree)
+    out = (ctypes.c_int32 * nl)()
+    _check(load_library().octo_tree_autotune(ctx, tree, ctypes.byref(opts), out))
+    return list(out)
 
 
 def octo_solve_batch(ctx: int, trees: Sequence[int], opts: octo_opts, phi_ptrs: Sequence[int],
@@ -391,6 +399,11 @@ class Tree:
 
     def leaves(self) -> np.ndarray:
         return octo_tree_leaves(self.handle)
+
+    def autotune(self, theta=0.5, precision=OCTO_FP64, amc=True, G=1.0) -> list:
+        """Pick the multipole work shape per level by timing; returns the choice
+        per level (-1 none, 0 LDS-staged, k chunks)."""
+        return octo_tree_autotune(self.ctx.handle, self.handle, make_opts(theta, G, precision, amc))
 
     def set_density(self, rho) -> None:
         rho = np.ascontiguousarray(rho, dtype=np.float64)

@@ -64,25 +64,32 @@ struct DeviceGuard {
     }
 };
 
-int n_parts_for(int n_int) {
+int n_parts_for(int n_int, int target) {
     if (n_int <= 0) return 1;
-    int p = 256 / (8 * n_int);
+    int p = target / (8 * n_int);
     return std::max(1, std::min(32, p));
 }
 
-// Allocate the tree's data block and build its single-tree plan.
-void finish_tree(octo_tree *t, const double *rho, int rho_on_device) {
+// Allocate the tree's data block (tables and fields), upload tables and
+// density, and fill the level and tree descriptors of its plan.
+void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
     octo_ctx *ctx = t->ctx;
     Layout &L = t->layout;
     const int nl = L.n_levels;
-    // data block: per level tables and fields, then rho and output staging
     size_t bytes = 0;
     std::vector<size_t> off_nbr(nl), off_child(nl), off_parent(nl), off_coord(nl), off_out(nl), off_mass(nl),
         off_mp(nl), off_loc(nl), off_lacc(nl);
-    std::vector<int> parts(nl);
+    t->parts_alloc.assign(nl, 1);
+    t->parts.assign(nl, 1);
+    t->m2l_lds.assign(nl, 0);
+    const char *mode = getenv("OCTO_M2L");
+    const bool lds = !(mode && std::string(mode) == "global");
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
-        parts[l] = n_parts_for(h.n_int);
+        t->parts_alloc[l] = n_parts_for(h.n_int, 1024);
+        t->parts[l] = n_parts_for(h.n_int, 256);
+        // dense levels take the LDS-staged kernel (one work-group per node)
+        t->m2l_lds[l] = (lds && l >= 1 && t->parts[l] == 1) ? 1 : 0;
         off_nbr[l] = bytes;
         bytes += al(h.nbr.size() * 4);
         off_child[l] = bytes;
@@ -98,7 +105,7 @@ void finish_tree(octo_tree *t, const double *rho, int rho_on_device) {
         off_mp[l] = bytes;
         bytes += al((size_t)kRec * h.n_rec * kCells * 8);
         off_loc[l] = bytes;
-        bytes += al((size_t)parts[l] * kLoc * h.n_int * kCells * 8);
+        bytes += al((size_t)t->parts_alloc[l] * kLoc * h.n_int * kCells * 8);
         off_lacc[l] = bytes;
         bytes += al((size_t)kLacc * (h.n_rec - h.n_int) * kCells * 8);
     }
@@ -106,53 +113,18 @@ void finish_tree(octo_tree *t, const double *rho, int rho_on_device) {
     bytes += al((size_t)L.n_leaf_cells * 8);
     const size_t off_stage = bytes;
     bytes += al((size_t)L.n_leaf_cells * 8 * 4);
-
-    // plan (host)
-    PlanHost &ph = t->ph;
-    ph = PlanHost{};
-    ph.interior.resize(nl);
-    // interior nodes of levels with many nodes take the LDS-staged multipole
-    // kernel (one work-group per node); the root and sparse levels use the
-    // chunked per-wavefront kernel so that the chip still fills
-    const char *mode = getenv("OCTO_M2L");
-    const bool lds = !(mode && std::string(mode) == "global");
-    for (int l = 0; l < nl; ++l) {
-        const HostLevel &h = L.lv[l];
-        for (int n = h.n_int; n < h.n_nodes; ++n) ph.p2m.push_back(NodeItem{l, n});
-        for (int n = 0; n < h.n_int; ++n) ph.interior[l].push_back(NodeItem{l, n});
-        const bool use_lds = lds && l >= 1 && parts[l] == 1;
-        for (int n = 0; n < h.n_int; ++n) {
-            if (use_lds) {
-                ph.m2l_nodes.push_back(NodeItem{l, n});
-                continue;
-            }
-            for (int c = 0; c < parts[l]; ++c)
-                for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, c});
-        }
-        for (int n = h.n_int; n < h.n_rec; ++n)
-            for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, 0});
-        for (int n = h.n_int; n < h.n_nodes; ++n) ph.leaf.push_back(LeafItem{l, n, 0, h.flags[n]});
-    }
-    ph.tree_leaf_beg = {0, (int32_t)ph.leaf.size()};
-    ph.tree_m2l_beg = {0, (int32_t)ph.m2l.size()};
-    ph.tree_m2ln_beg = {0, (int32_t)ph.m2l_nodes.size()};
-    const size_t pbytes0 = 0;
-    (void)pbytes0;
-
-    // allocate everything in one block
-    ph.levels.resize(nl);
-    ph.trees.resize(1);
-    const size_t plan_sz = plan_bytes(ph);
-    const size_t total = al(bytes) + plan_sz;
-    void *mem = ctx->dev_alloc(total);
+    void *mem = ctx->dev_alloc(bytes);
     t->data.ptr = mem;
-    t->data.bytes = total;
-    t->bytes = total;
+    t->data.bytes = bytes;
     char *base = (char *)mem;
     hipStream_t s = ctx->stream;
     auto up = [&](size_t off, const void *src, size_t n) {
         if (n) check_hip(hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s), "tree upload");
     };
+    PlanHost &ph = t->ph;
+    ph = PlanHost{};
+    ph.levels.resize(nl);
+    ph.trees.resize(1);
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
         up(off_nbr[l], h.nbr.data(), h.nbr.size() * 4);
@@ -167,7 +139,7 @@ void finish_tree(octo_tree *t, const double *rho, int rho_on_device) {
         d.n_rec = h.n_rec;
         d.parent_ld = l > 0 ? l - 1 : -1;
         d.child_ld = (h.n_int > 0 && l + 1 < nl) ? l + 1 : -1;
-        d.n_parts = parts[l];
+        d.n_parts = t->parts[l];
         d.tree = 0;
         d.h = 1.0 / (double)(8 << l);
         d.nbr = (const int32_t *)(base + off_nbr[l]);
@@ -196,7 +168,71 @@ void finish_tree(octo_tree *t, const double *rho, int rho_on_device) {
     check_hip(hipMemcpyAsync(t->rho, rho, (size_t)L.n_leaf_cells * 8,
                              rho_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
               "density upload");
-    plan_upload(ph, base + al(bytes), t->plan, s);  // synchronises the stream
+    check_hip(hipStreamSynchronize(s), "tree upload");
+}
+
+}  // namespace
+
+namespace octo {
+// (Re)build the tree's single-tree plan from its per-level choices: multipole
+// kernel (LDS-staged per node, or chunked per wavefront with `parts` slots).
+void build_tree_plan(octo_tree *t) {
+    octo_ctx *ctx = t->ctx;
+    const Layout &L = t->layout;
+    const int nl = L.n_levels;
+    PlanHost &ph = t->ph;
+    ph.m2l.clear();
+    ph.m2l_nodes.clear();
+    ph.leaf.clear();
+    ph.p2m.clear();
+    ph.interior.assign(nl, {});
+    for (int l = 0; l < nl; ++l) {
+        const HostLevel &h = L.lv[l];
+        ph.levels[l].n_parts = t->m2l_lds[l] ? 1 : t->parts[l];
+        for (int n = h.n_int; n < h.n_nodes; ++n) ph.p2m.push_back(NodeItem{l, n});
+        for (int n = 0; n < h.n_int; ++n) ph.interior[l].push_back(NodeItem{l, n});
+        for (int n = 0; n < h.n_int; ++n) {
+            if (t->m2l_lds[l]) {
+                ph.m2l_nodes.push_back(NodeItem{l, n});
+                continue;
+            }
+            for (int c = 0; c < t->parts[l]; ++c)
+                for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, c});
+        }
+        for (int n = h.n_int; n < h.n_rec; ++n)
+            for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, 0});
+        for (int n = h.n_int; n < h.n_nodes; ++n) ph.leaf.push_back(LeafItem{l, n, 0, h.flags[n]});
+    }
+    ph.tree_leaf_beg = {0, (int32_t)ph.leaf.size()};
+    ph.tree_m2l_beg = {0, (int32_t)ph.m2l.size()};
+    ph.tree_m2ln_beg = {0, (int32_t)ph.m2l_nodes.size()};
+    const size_t bytes = plan_bytes(ph);
+    void *mem = ctx->dev_alloc(bytes);
+    const TreeDesc keep = t->plan.trees_host.empty() ? ph.trees[0] : t->plan.trees_host[0];
+    if (t->plan_block.ptr) {
+        check_hip(hipStreamSynchronize(ctx->stream), "plan rebuild");
+        ctx->dev_free(t->plan_block.ptr, t->plan_block.bytes);
+    }
+    t->plan_block.ptr = mem;
+    t->plan_block.bytes = bytes;
+    ph.trees[0] = keep;
+    plan_upload(ph, mem, t->plan, ctx->stream);
+    drop_graphs(t->graphs);
+    t->bytes = t->data.bytes + bytes;
+}
+}  // namespace octo
+
+namespace {
+
+void finish_tree(octo_tree *t, const double *rho, int rho_on_device) {
+    alloc_tree(t, rho, rho_on_device);
+    try {
+        build_tree_plan(t);
+    } catch (...) {
+        t->ctx->dev_free(t->data.ptr, t->data.bytes);
+        t->data.ptr = nullptr;
+        throw;
+    }
 }
 
 void check_density_host(const double *rho, int64_t n) {
@@ -477,6 +513,7 @@ octo_status octo_tree_destroy(octo_tree *t) {
             t->ctx->invalidate_batches();
         drop_graphs(t->graphs);
         t->ctx->dev_free(t->data.ptr, t->data.bytes);
+        t->ctx->dev_free(t->plan_block.ptr, t->plan_block.bytes);
         t->ctx->n_trees--;
         delete t;
     });
@@ -522,6 +559,71 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
                     stats->phase_ms[i] = pm;
                 }
         }
+    });
+}
+
+// Autotuner: for each level with interior nodes, time the multipole phase
+// with each candidate work shape (LDS-staged per node, or per wavefront with
+// 1..parts_alloc stencil chunks) and keep the fastest, level by level.
+octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, int32_t *choice) {
+    return guard([&] {
+        if (!ctx || !tree) fail(OCTO_E_INVALID, "NULL argument");
+        if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+        validate_opts(opts);
+        DeviceGuard dg(ctx->device);
+        if (ctx->batch &&
+            std::find(ctx->batch->sig.begin(), ctx->batch->sig.end(), tree) != ctx->batch->sig.end())
+            ctx->invalidate_batches();
+        const bool prof = ctx->profiling;
+        ctx->profiling = true;
+        const int64_t n = tree->layout.n_leaf_cells;
+        auto measure = [&]() {
+            std::vector<TreeDesc> want = tree->plan.trees_host;
+            want[0].phi = tree->stage;
+            want[0].g = tree->stage + n;
+            want[0].G = opts->G;
+            want[0].amc = opts->amc ? 1 : 0;
+            double best = 1e30;
+            for (int rep = 0; rep < 4; ++rep) {
+                run_plan(ctx, tree->plan, tree->graphs, want, opts);
+                check_hip(hipStreamSynchronize(ctx->stream), "autotune");
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, ctx->phase_ev[2], ctx->phase_ev[3]);
+                if (rep > 0) best = std::min(best, (double)ms);  // first run warms up
+            }
+            return best;
+        };
+        const int nl = tree->layout.n_levels;
+        try {
+            for (int l = 0; l < nl; ++l) {
+                if (tree->layout.lv[l].n_int == 0) continue;
+                std::vector<std::pair<int, int>> cand;  // (lds, parts)
+                if (l >= 1) cand.push_back({1, 1});
+                for (int p = 1; p <= tree->parts_alloc[l]; p *= 2) cand.push_back({0, p});
+                double best = 1e30;
+                std::pair<int, int> pick{tree->m2l_lds[l], tree->parts[l]};
+                for (auto c : cand) {
+                    tree->m2l_lds[l] = c.first;
+                    tree->parts[l] = c.second;
+                    build_tree_plan(tree);
+                    const double ms = measure();
+                    if (ms < best) {
+                        best = ms;
+                        pick = c;
+                    }
+                }
+                tree->m2l_lds[l] = pick.first;
+                tree->parts[l] = pick.second;
+            }
+            build_tree_plan(tree);
+        } catch (...) {
+            ctx->profiling = prof;
+            throw;
+        }
+        ctx->profiling = prof;
+        if (choice)
+            for (int l = 0; l < nl; ++l)
+                choice[l] = tree->layout.lv[l].n_int == 0 ? -1 : (tree->m2l_lds[l] ? 0 : tree->parts[l]);
     });
 }
 

@@ -201,7 +201,9 @@ struct octo_tree {
     octo::Layout layout;
     octo::PlanHost ph;    // single-tree plan (host copy)
     octo::Plan plan;      // single-tree plan (device)
-    octo::DeviceBlock data;  // tables + fields
+    octo::DeviceBlock data;        // tables + fields
+    octo::DeviceBlock plan_block;  // work plan
+    std::vector<int> parts_alloc, parts, m2l_lds;  // per level: multipole work choices
     double *rho = nullptr;
     double *stage = nullptr;  // device staging of phi, g for host outputs
     size_t bytes = 0;
@@ -213,4 +215,5 @@ namespace octo {
 void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs,
               const std::vector<TreeDesc> &want, const octo_opts *o);
 void drop_graphs(std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs);
+void build_tree_plan(octo_tree *t);
 }  // namespace octo

@@ -249,3 +249,69 @@ def test_c2_full_size_sampled(ctx):
     assert e_phi <= TOL and e_g <= TOL
     assert st["torque"] < 1e-13 and st["force"] < 1e-13
     assert st["m2l_pairs"] == 64121280 and st["direct_pairs"] == 534396416
+
+
+def test_c3_adaptive_full_size_sampled(ctx):
+    """The c2 field refined adaptively to level 6 (7736 leaf sub-grids, 3.96M
+    leaf cells): sampled cells against the oracle, leaf list identical to the
+    oracle's builder, invariants over all cells."""
+    f = w.binary_polytrope_128()
+    say("c3 adaptive level 6 build")
+    tree = ctx.adaptive_tree(f, 6, 1e-4)
+    lv = tree.leaves()
+    assert np.array_equal(lv, oracle.build_adaptive_leaves(f.boxmax, 6, 1e-4))
+    say(f"c3 solve leaves={len(lv)}")
+    for prec in (lib.OCTO_FP64, lib.OCTO_MIXED):
+        phi, g, st = gpu_solve(ctx, tree, theta=0.5, precision=prec)
+        rng = np.random.default_rng(8)
+        # half the samples in the stars (levels 5-6), half anywhere
+        fine = np.nonzero(np.repeat(lv[:, 0] >= 5, 512))[0]
+        sel = np.concatenate([rng.choice(fine, 200, replace=False), rng.choice(tree.n_leaf_cells, 200, replace=False)])
+        if prec == lib.OCTO_FP64:
+            t = oracle.Tree(lv, w.leaf_density(f, lv))
+            p_ref, g_ref = t.solve(theta=0.5, sample=sel)
+        e_phi = float(np.max(np.abs(phi[sel] - p_ref) / np.abs(p_ref)))
+        e_g = float(np.max(np.abs(g[:, sel] - g_ref)) / np.max(np.abs(g_ref)))
+        say(f"  prec={prec} e_phi={e_phi:.2e} e_g={e_g:.2e} torque={st['torque']:.2e} force={st['force']:.2e}")
+        if prec == lib.OCTO_FP64:
+            assert e_phi <= TOL and e_g <= TOL
+            assert st["torque"] < 1e-13 and st["force"] < 1e-13
+        else:
+            assert e_phi <= MIXED_PHI and e_g <= MIXED_G
+    tree.destroy()
+
+
+def test_batch_mixed_sizes_and_precision(ctx):
+    """Trees of different depths in one batch (levels 0-3 and adaptive): every
+    result bitwise equal to its single solve, in both precisions."""
+    rng = np.random.default_rng(9)
+    trees = [ctx.uniform_tree(rng.uniform(0.1, 1.0, (n, n, n))) for n in (8, 64, 16)]
+    leaves, f = random_amr_leaves(24, max_level=3, n_stars=1)
+    trees.append(ctx.adaptive_tree(f, 3, 1e-4))
+    for prec in (lib.OCTO_FP64, lib.OCTO_MIXED):
+        say(f"batch sizes prec={prec}")
+        single = [gpu_solve(ctx, t, precision=prec)[:2] for t in trees]
+        outs, sts = ctx.solve_batch(trees, precision=prec)
+        for (p, g), (ps, gs) in zip(outs, single):
+            assert np.array_equal(p.cpu().numpy(), ps) and np.array_equal(g.cpu().numpy(), gs)
+    for t in trees:
+        t.destroy()
+
+
+def test_autotune_keeps_parity(ctx):
+    """The autotuner changes only the work shape: results stay at parity."""
+    rho = w.uniform_grid(w.binary_polytrope(0.12, 0.10, 0.35, 0.7), 3)
+    tree = ctx.uniform_tree(rho)
+    say("autotune 64^3")
+    choice = tree.autotune(theta=0.5)
+    say(f"  choice per level: {choice}")
+    assert len(choice) == 4 and choice[-1] == -1 and all(c >= 0 for c in choice[:-1])
+    phi, g, st = gpu_solve(ctx, tree, theta=0.5)
+    tree.destroy()
+    t = oracle.Tree(w.uniform_leaves(3), w.grid_to_leaves(rho))
+    p_ref, g_ref = t.solve(theta=0.5)
+    phi_l = w.grid_to_leaves(phi.reshape(64, 64, 64)).ravel()
+    g_l = np.stack([w.grid_to_leaves(g[a].reshape(64, 64, 64)).ravel() for a in range(3)])
+    e = errs(phi_l, g_l, p_ref, g_ref)
+    assert e[0] <= TOL and e[1] <= TOL
+    check_counts(st, t)
