@@ -452,7 +452,8 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     __shared__ int s_nbr[27];
     __shared__ int s_cnt[8];
     const int tid = threadIdx.x;
-    const int p = tid >> 6, lane = tid & 63;
+    // wave-uniform (one wavefront per parity class): keep it in a scalar register
+    const int p = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     if (tid < 27) s_nbr[tid] = ld.nbr[node * 27 + tid];
     const int s = tid;  // parity-major storage: wavefront p holds class p
     int x, y, z;
@@ -655,7 +656,8 @@ __global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, c
     const LevelDesc ld = L[item.ld];
     const TreeDesc td = TD[ld.tree];
     const int tid = threadIdx.x;
-    const int p = tid >> 6, lane = tid & 63;
+    // wave-uniform (one wavefront per parity class): keep it in a scalar register
+    const int p = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int node = item.node;
     // masses of the 18^3 cells within 5 cells of this node; -1 where the cell
     // is not a leaf of this level (absent or interior)
@@ -816,48 +818,68 @@ __global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, c
 #pragma unroll
     for (int k = 0; k < kStat; ++k) v[k] = wave_sum(v[k]);
     const int tot = wave_sum(cnt);
+    __shared__ double s_v[8][kStat];
+    __shared__ int s_c[8];
     if (lane == 0) {
-        const size_t wi = (size_t)it * 8 + p;
 #pragma unroll
-        for (int k = 0; k < kStat; ++k) stat[wi * kStat + k] = v[k];
-        cnt_out[wi] = tot;
+        for (int k = 0; k < kStat; ++k) s_v[p][k] = v[k];
+        s_c[p] = tot;
+    }
+    __syncthreads();
+    if (tid < kStat) {
+        double acc = 0.0;
+        for (int w = 0; w < 8; ++w) acc += s_v[w][tid];
+        stat[(size_t)it * kStat + tid] = acc;
+    } else if (tid == kStat) {
+        int64_t c = 0;
+        for (int w = 0; w < 8; ++w) c += s_c[w];
+        cnt_out[it] = c;
     }
 }
 
 // ------------------------------------------------------------------ stats
-// One work-group per tree: fixed-order sums of the per-wavefront partials.
-__global__ __launch_bounds__(256) void k_stats(const int32_t *__restrict__ leaf_beg,
-                                               const int32_t *__restrict__ m2l_beg,
-                                               const int32_t *__restrict__ m2ln_beg, int n_m2l,
-                                               const double *__restrict__ stat, const int64_t *__restrict__ leaf_cnt,
-                                               const int64_t *__restrict__ m2l_cnt, double *__restrict__ out) {
+// One work-group per tree: fixed-order sums of the per-node partials (each
+// thread a fixed strided subset, then a fixed-shape tree in LDS).
+__global__ __launch_bounds__(1024) void k_stats(const int32_t *__restrict__ leaf_beg,
+                                                const int32_t *__restrict__ m2l_beg,
+                                                const int32_t *__restrict__ m2ln_beg, int n_m2l,
+                                                const double *__restrict__ stat, const int64_t *__restrict__ leaf_cnt,
+                                                const int64_t *__restrict__ m2l_cnt, double *__restrict__ out) {
     const int t = blockIdx.x;
-    __shared__ double sh[256];
-    __shared__ long long shc[256];
-    const int lb = 8 * leaf_beg[t], le = 8 * leaf_beg[t + 1];
-    for (int k = 0; k < kStat + 2; ++k) {
-        double acc = 0.0;
-        long long c = 0;
-        if (k < kStat) {
-            for (int i = lb + threadIdx.x; i < le; i += 256) acc += stat[(size_t)i * kStat + k];
-        } else if (k == kStat) {
-            for (int i = m2l_beg[t] + threadIdx.x; i < m2l_beg[t + 1]; i += 256) c += m2l_cnt[i];
-            for (int i = m2ln_beg[t] + threadIdx.x; i < m2ln_beg[t + 1]; i += 256) c += m2l_cnt[n_m2l + i];
-        } else {
-            for (int i = lb + threadIdx.x; i < le; i += 256) c += leaf_cnt[i];
-        }
-        sh[threadIdx.x] = acc;
-        shc[threadIdx.x] = c;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w) {
-                sh[threadIdx.x] += sh[threadIdx.x + w];
-                shc[threadIdx.x] += shc[threadIdx.x + w];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[t * 12 + k] = k < kStat ? sh[0] : (double)shc[0];
-        __syncthreads();
+    constexpr int NT = 1024;
+    __shared__ double sh[kStat][NT / 64];
+    __shared__ long long shc[2][NT / 64];
+    double acc[kStat];
+#pragma unroll
+    for (int k = 0; k < kStat; ++k) acc[k] = 0.0;
+    long long c_m2l = 0, c_dir = 0;
+    for (int i = leaf_beg[t] + threadIdx.x; i < leaf_beg[t + 1]; i += NT) {
+#pragma unroll
+        for (int k = 0; k < kStat; ++k) acc[k] += stat[(size_t)i * kStat + k];
+        c_dir += leaf_cnt[i];
+    }
+    for (int i = m2l_beg[t] + threadIdx.x; i < m2l_beg[t + 1]; i += NT) c_m2l += m2l_cnt[i];
+    for (int i = m2ln_beg[t] + threadIdx.x; i < m2ln_beg[t + 1]; i += NT) c_m2l += m2l_cnt[n_m2l + i];
+#pragma unroll
+    for (int k = 0; k < kStat; ++k) acc[k] = wave_sum(acc[k]);
+    c_m2l = wave_sum(c_m2l);
+    c_dir = wave_sum(c_dir);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < kStat; ++k) sh[k][wv] = acc[k];
+        shc[0][wv] = c_m2l;
+        shc[1][wv] = c_dir;
+    }
+    __syncthreads();
+    if (threadIdx.x < kStat) {
+        double v = 0.0;
+        for (int w = 0; w < NT / 64; ++w) v += sh[threadIdx.x][w];
+        out[t * 12 + threadIdx.x] = v;
+    } else if (threadIdx.x < kStat + 2) {
+        long long v = 0;
+        for (int w = 0; w < NT / 64; ++w) v += shc[threadIdx.x - kStat][w];
+        out[t * 12 + (threadIdx.x == kStat ? kStat : kStat + 1)] = (double)v;
     }
 }
 
@@ -909,7 +931,7 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
                                p.d_stat, p.d_leaf_cnt);
     }
     mark(5);
-    hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(256), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg,
+    hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(1024), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg,
                        p.d_tree_m2ln_beg, p.n_m2l, p.d_stat, p.d_leaf_cnt, p.d_m2l_cnt, p.d_out);
     mark(6);
     check_hip(hipGetLastError(), "kernel launch");

@@ -96,8 +96,8 @@ struct Plan {
     NodeItem *d_m2l_nodes = nullptr;
     NodeItem *d_interior = nullptr;
     int32_t *d_tree_leaf_beg = nullptr, *d_tree_m2l_beg = nullptr, *d_tree_m2ln_beg = nullptr;
-    double *d_stat = nullptr;      // 8 * n_leaf * kStat (per wavefront)
-    int64_t *d_leaf_cnt = nullptr;  // 8 * n_leaf
+    double *d_stat = nullptr;      // n_leaf * kStat (per leaf node)
+    int64_t *d_leaf_cnt = nullptr;  // n_leaf
     int64_t *d_m2l_cnt = nullptr;   // n_m2l + n_m2l_nodes
     double *d_out = nullptr;        // n_trees * 12: stats per tree
     DeviceBlock block;

@@ -393,8 +393,8 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
     p.d_tree_leaf_beg = (int32_t *)put(ph.tree_leaf_beg.data(), ph.tree_leaf_beg.size() * sizeof(int32_t));
     p.d_tree_m2l_beg = (int32_t *)put(ph.tree_m2l_beg.data(), ph.tree_m2l_beg.size() * sizeof(int32_t));
     p.d_tree_m2ln_beg = (int32_t *)put(ph.tree_m2ln_beg.data(), ph.tree_m2ln_beg.size() * sizeof(int32_t));
-    p.d_stat = (double *)reserve(8 * ph.leaf.size() * kStat * sizeof(double));
-    p.d_leaf_cnt = (int64_t *)reserve(8 * ph.leaf.size() * sizeof(int64_t));
+    p.d_stat = (double *)reserve(ph.leaf.size() * kStat * sizeof(double));
+    p.d_leaf_cnt = (int64_t *)reserve(ph.leaf.size() * sizeof(int64_t));
     p.d_m2l_cnt = (int64_t *)reserve((ph.m2l.size() + ph.m2l_nodes.size()) * sizeof(int64_t));
     p.d_out = (double *)reserve(ph.trees.size() * 12 * sizeof(double));
     p.trees_host = ph.trees;
