@@ -190,12 +190,14 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
 
 /* Autotune the tree's multipole work shape for these options: for every level
  * with interior nodes, time the multipole-interaction phase with each
- * candidate (one LDS-staged work-group per node, or one wavefront per parity
- * class with 1, 2, 4, ... stencil chunks) and keep the fastest, level by
+ * candidate (LDS-staged work-groups per node and group of source parity
+ * classes, 1, 2, 4 or 8 groups; or one wavefront per target parity class with
+ * 1, 2, 4, ... stencil chunks) and keep the fastest, level by
  * level.  Runs several solves (outputs into the tree's own staging memory)
  * and rebuilds the tree's work plan (device memory for the plan is
  * reallocated).  choice: NULL or n_levels entries: -1 = no interior nodes,
- * 0 = LDS-staged, k > 0 = per-wavefront with k chunks.  Results of later
+ * -(k+1) = LDS-staged with the source classes split into k groups, k > 0 =
+ * per-wavefront with k stencil chunks.  Results of later
  * solves are identical to within rounding of the summation order. */
 octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, int32_t *choice);
 

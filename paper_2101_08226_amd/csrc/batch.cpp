@@ -94,7 +94,7 @@ static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, con
         ph.tree_leaf_beg.push_back((int32_t)ph.leaf.size());
         ph.tree_m2l_beg.push_back((int32_t)ph.m2l.size());
         ph.tree_m2ln_beg.push_back((int32_t)ph.m2l_nodes.size());
-        for (NodeItem q : t.m2l_nodes) {
+        for (M2LItem q : t.m2l_nodes) {
             q.ld += base;
             ph.m2l_nodes.push_back(q);
         }

@@ -440,11 +440,11 @@ __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, con
 // stencil whose sources fall in the staged class.
 template <typename T>
 __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
-                                                 const NodeItem *__restrict__ items, int n_items, StencilDev st,
+                                                 const M2LItem *__restrict__ items, int n_items, StencilDev st,
                                                  int64_t *__restrict__ cnt_out) {
     const int it = xcd_item(n_items);
     if (it >= n_items) return;
-    const NodeItem item = items[it];
+    const M2LItem item = items[it];
     const LevelDesc ld = L[item.ld];
     const TreeDesc td = TD[ld.tree];
     const int node = item.node;
@@ -480,7 +480,10 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     for (int k = 0; k < 10; ++k) a.L3[k] = (T)0;
     int cnt = 0;
     __syncthreads();
-    for (int q = 0; q < 8; ++q) {
+    // this item's share of the source parity classes; its partial locals go
+    // to slot `chunk` and are summed by the downward pass
+    const int q0 = 8 * item.chunk / ld.n_parts, q1 = 8 * (item.chunk + 1) / ld.n_parts;
+    for (int q = q0; q < q1; ++q) {
         const int qx = q >> 2, qy = (q >> 1) & 1, qz = q & 1;
         // stage source class q: lattice index i in [0,9) <-> local coordinate 2i - 4 - parity
         for (int c = tid; c < 729; c += 512) {
@@ -531,7 +534,7 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     }
     const double G = td.G;
     const size_t IS = (size_t)ld.n_int * kCells;
-    double *out = ld.loc + (size_t)node * kCells + s;
+    double *out = ld.loc + (size_t)item.chunk * kLoc * IS + (size_t)node * kCells + s;
     out[0] = G * (double)a.L0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) out[(1 + k) * IS] = G * (double)a.L1[k];
@@ -551,12 +554,30 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     }
 }
 
+// ------------------------------------------------------------------ partial slots
+// Sum the partial-locals slots of one level into slot 0, one thread per
+// (cell, component) (coarse levels, where few cells have many slots).
+__global__ __launch_bounds__(256) void k_sum_parts(const LevelDesc *__restrict__ L, const NodeItem *__restrict__ items,
+                                                   int n_items) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_items * kCells * kLoc) return;
+    const int it = i / (kCells * kLoc), r = i % (kCells * kLoc);
+    const int c = r / kCells, cell = r % kCells;
+    const NodeItem item = items[it];
+    const LevelDesc ld = L[item.ld];
+    const size_t IS = (size_t)ld.n_int * kCells;
+    double *dst = ld.loc + c * IS + (size_t)item.node * kCells + cell;
+    double v = *dst;
+    for (int part = 1; part < ld.n_parts; ++part) v += dst[(size_t)part * kLoc * IS];
+    *dst = v;
+}
+
 // ------------------------------------------------------------------ L2L
 // Interior cells: sum the partial locals, then add the parent's expansion
 // shifted to this cell's centre of mass (Taylor shift of the order-3 local
 // polynomial; the correction C is a uniform acceleration and is inherited).
 __global__ __launch_bounds__(256) void k_l2l(const LevelDesc *__restrict__ L, const NodeItem *__restrict__ items,
-                                             int n_items) {
+                                             int n_items, int parts_done) {
     const int it = blockIdx.x >> 1;
     if (it >= n_items) return;
     const NodeItem item = items[it];
@@ -568,7 +589,7 @@ __global__ __launch_bounds__(256) void k_l2l(const LevelDesc *__restrict__ L, co
     double v[kLoc];
 #pragma unroll
     for (int c = 0; c < kLoc; ++c) v[c] = ld.loc[c * IS + ci];
-    for (int part = 1; part < ld.n_parts; ++part) {
+    for (int part = 1; part < (parts_done ? 1 : ld.n_parts); ++part) {
         const double *src = ld.loc + (size_t)part * kLoc * IS + ci;
 #pragma unroll
         for (int c = 0; c < kLoc; ++c) v[c] += src[c * IS];
@@ -706,16 +727,48 @@ __global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, c
     } else {
         const int base = ((x + 5) * 18 + (y + 5)) * 18 + (z + 5);
         const int beg = st.leaf_beg[p], end = st.leaf_beg[p + 1];
-        for (int k = beg; k < end; ++k) {
-            const T m = s_m[base + st.leaf_hoff[k]];
-            if (m < (T)0) continue;
-            const T *w = lw + 4 * k;
-            sp += m * w[0];
-            sgx += m * w[1];
-            sgy += m * w[2];
-            sgz += m * w[3];
-            ++cnt;
+        // blocks of 8 stencil entries: 8 LDS reads in flight, weights and
+        // offsets as scalar loads, absent partners (-1) masked arithmetically
+        T sp2 = 0, sgx2 = 0, sgy2 = 0, sgz2 = 0;
+        int k = beg;
+        for (; k + 8 <= end; k += 8) {
+            T m[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) m[u] = s_m[base + st.leaf_hoff[k + u]];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const T *w = lw + 4 * (k + u);
+                const bool ok = m[u] >= (T)0;
+                const T mm = ok ? m[u] : (T)0;
+                cnt += ok ? 1 : 0;
+                if (u & 1) {
+                    sp2 += mm * w[0];
+                    sgx2 += mm * w[1];
+                    sgy2 += mm * w[2];
+                    sgz2 += mm * w[3];
+                } else {
+                    sp += mm * w[0];
+                    sgx += mm * w[1];
+                    sgy += mm * w[2];
+                    sgz += mm * w[3];
+                }
+            }
         }
+        for (; k < end; ++k) {
+            const T m = s_m[base + st.leaf_hoff[k]];
+            const bool ok = m >= (T)0;
+            const T mm = ok ? m : (T)0;
+            cnt += ok ? 1 : 0;
+            const T *w = lw + 4 * k;
+            sp += mm * w[0];
+            sgx += mm * w[1];
+            sgy += mm * w[2];
+            sgz += mm * w[3];
+        }
+        sp += sp2;
+        sgx += sgx2;
+        sgy += sgy2;
+        sgz += sgz2;
     }
     const T ih = (T)(1.0 / h);
     T phi_t = -sp * ih;
@@ -918,7 +971,14 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     mark(3);
     for (int l = 0; l < p.n_levels_max; ++l) {
         const int n = p.n_interior[l];
-        if (n) hipLaunchKernelGGL(k_l2l, dim3(2 * n), dim3(256), 0, s, p.d_levels, p.d_interior + p.interior_off[l], n);
+        if (!n) continue;
+        // levels with few nodes sum their many partial slots in a separate wide pass
+        const bool wide = p.sum_parts_level.size() > (size_t)l && p.sum_parts_level[l];
+        if (wide)
+            hipLaunchKernelGGL(k_sum_parts, dim3((n * kCells * kLoc + 255) / 256), dim3(256), 0, s, p.d_levels,
+                               p.d_interior + p.interior_off[l], n);
+        hipLaunchKernelGGL(k_l2l, dim3(2 * n), dim3(256), 0, s, p.d_levels, p.d_interior + p.interior_off[l], n,
+                           wide ? 1 : 0);
     }
     mark(4);
     if (p.n_leaf) {

@@ -86,10 +86,12 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
     const bool lds = !(mode && std::string(mode) == "global");
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
-        t->parts_alloc[l] = n_parts_for(h.n_int, 1024);
+        t->parts_alloc[l] = std::max(n_parts_for(h.n_int, 1024), l >= 1 ? 4 : 1);
         t->parts[l] = n_parts_for(h.n_int, 256);
-        // dense levels take the LDS-staged kernel (one work-group per node)
+        // dense levels take the LDS-staged kernel: one work-group per (node,
+        // half of the source parity classes)
         t->m2l_lds[l] = (lds && l >= 1 && t->parts[l] == 1) ? 1 : 0;
+        if (t->m2l_lds[l]) t->parts[l] = 2;
         off_nbr[l] = bytes;
         bytes += al(h.nbr.size() * 4);
         off_child[l] = bytes;
@@ -188,12 +190,12 @@ void build_tree_plan(octo_tree *t) {
     ph.interior.assign(nl, {});
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
-        ph.levels[l].n_parts = t->m2l_lds[l] ? 1 : t->parts[l];
+        ph.levels[l].n_parts = t->parts[l];
         for (int n = h.n_int; n < h.n_nodes; ++n) ph.p2m.push_back(NodeItem{l, n});
         for (int n = 0; n < h.n_int; ++n) ph.interior[l].push_back(NodeItem{l, n});
         for (int n = 0; n < h.n_int; ++n) {
             if (t->m2l_lds[l]) {
-                ph.m2l_nodes.push_back(NodeItem{l, n});
+                for (int c = 0; c < t->parts[l]; ++c) ph.m2l_nodes.push_back(M2LItem{l, n, 0, c});
                 continue;
             }
             for (int c = 0; c < t->parts[l]; ++c)
@@ -598,7 +600,8 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
             for (int l = 0; l < nl; ++l) {
                 if (tree->layout.lv[l].n_int == 0) continue;
                 std::vector<std::pair<int, int>> cand;  // (lds, parts)
-                if (l >= 1) cand.push_back({1, 1});
+                if (l >= 1)
+                    for (int p = 1; p <= std::min(8, tree->parts_alloc[l]); p *= 2) cand.push_back({1, p});
                 for (int p = 1; p <= tree->parts_alloc[l]; p *= 2) cand.push_back({0, p});
                 double best = 1e30;
                 std::pair<int, int> pick{tree->m2l_lds[l], tree->parts[l]};
@@ -623,7 +626,7 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
         ctx->profiling = prof;
         if (choice)
             for (int l = 0; l < nl; ++l)
-                choice[l] = tree->layout.lv[l].n_int == 0 ? -1 : (tree->m2l_lds[l] ? 0 : tree->parts[l]);
+                choice[l] = tree->layout.lv[l].n_int == 0 ? -1 : (tree->m2l_lds[l] ? -tree->parts[l] - 1 : tree->parts[l]);
     });
 }
 

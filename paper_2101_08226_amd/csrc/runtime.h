@@ -72,7 +72,7 @@ struct PlanHost {
     std::vector<M2LItem> m2l;
     std::vector<LeafItem> leaf;
     std::vector<NodeItem> p2m;
-    std::vector<NodeItem> m2l_nodes;  // interior nodes served by the LDS-staged kernel
+    std::vector<M2LItem> m2l_nodes;  // (node, source-class group) items of the LDS-staged kernel
     // interior nodes by level index (level l of every tree)
     std::vector<std::vector<NodeItem>> interior;
     std::vector<int32_t> tree_leaf_beg, tree_m2l_beg, tree_m2ln_beg;  // per tree, +1 sentinel
@@ -93,7 +93,8 @@ struct Plan {
     M2LItem *d_m2l = nullptr;
     LeafItem *d_leaf = nullptr;
     NodeItem *d_p2m = nullptr;
-    NodeItem *d_m2l_nodes = nullptr;
+    M2LItem *d_m2l_nodes = nullptr;
+    std::vector<char> sum_parts_level;  // per level index: partial slots summed in a separate wide pass
     NodeItem *d_interior = nullptr;
     int32_t *d_tree_leaf_beg = nullptr, *d_tree_m2l_beg = nullptr, *d_tree_m2ln_beg = nullptr;
     double *d_stat = nullptr;      // n_leaf * kStat (per leaf node)

@@ -380,7 +380,7 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
     p.d_m2l = (M2LItem *)put(ph.m2l.data(), ph.m2l.size() * sizeof(M2LItem));
     p.d_leaf = (LeafItem *)put(ph.leaf.data(), ph.leaf.size() * sizeof(LeafItem));
     p.d_p2m = (NodeItem *)put(ph.p2m.data(), ph.p2m.size() * sizeof(NodeItem));
-    p.d_m2l_nodes = (NodeItem *)put(ph.m2l_nodes.data(), ph.m2l_nodes.size() * sizeof(NodeItem));
+    p.d_m2l_nodes = (M2LItem *)put(ph.m2l_nodes.data(), ph.m2l_nodes.size() * sizeof(M2LItem));
     std::vector<NodeItem> all;
     p.n_interior.clear();
     p.interior_off.clear();
@@ -390,6 +390,13 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
         all.insert(all.end(), v.begin(), v.end());
     }
     p.d_interior = (NodeItem *)put(all.data(), all.size() * sizeof(NodeItem));
+    // coarse levels (few interior nodes, many partial slots): separate wide sum
+    p.sum_parts_level.assign(ph.interior.size(), 0);
+    for (size_t l = 0; l < ph.interior.size(); ++l) {
+        int max_parts = 1;
+        for (const NodeItem &q : ph.interior[l]) max_parts = std::max(max_parts, ph.levels[q.ld].n_parts);
+        p.sum_parts_level[l] = (max_parts > 4) ? 1 : 0;
+    }
     p.d_tree_leaf_beg = (int32_t *)put(ph.tree_leaf_beg.data(), ph.tree_leaf_beg.size() * sizeof(int32_t));
     p.d_tree_m2l_beg = (int32_t *)put(ph.tree_m2l_beg.data(), ph.tree_m2l_beg.size() * sizeof(int32_t));
     p.d_tree_m2ln_beg = (int32_t *)put(ph.tree_m2ln_beg.data(), ph.tree_m2ln_beg.size() * sizeof(int32_t));
