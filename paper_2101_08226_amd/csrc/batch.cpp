@@ -29,7 +29,7 @@ void drop_graphs(std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs) {
 }
 
 void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs,
-              const std::vector<TreeDesc> &want, const octo_opts *o) {
+              const std::vector<TreeDesc> &want, const octo_opts *o, bool count) {
     // tree descriptors (outputs, G, correction switch) live in device memory
     // and are refreshed only when they change
     for (int i = 0; i < plan.n_trees; ++i) {
@@ -42,16 +42,22 @@ void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipG
     const StencilDevHolder &st = ctx->stencil(o->theta);
     LaunchOpts lo;
     lo.precision = o->precision;
+    lo.count = count;
+    lo.fork = ctx->fork_ev;
+    lo.join = ctx->join_ev;
     if (ctx->profiling) {
         lo.phase_events = ctx->phase_ev;
+        lo.aux = ctx->aux;
         launch_solve(plan, st.dev, lo, ctx->stream);
         return;
     }
     if (!ctx->use_graphs) {
+        lo.aux = ctx->aux;
         launch_solve(plan, st.dev, lo, ctx->stream);
         return;
     }
-    const auto key = std::make_pair(theta_bits(o->theta), (int)o->precision);
+    lo.aux = ctx->capture_aux;
+    const auto key = std::make_pair(theta_bits(o->theta), (int)o->precision * 2 + (count ? 1 : 0));
     auto it = graphs.find(key);
     if (it == graphs.end()) {
         hipGraph_t g = nullptr;
@@ -269,6 +275,9 @@ static void pump(octo_ctx *ctx) {
         const StencilDevHolder &st = ctx->stencil(theta);
         LaunchOpts lo;
         lo.precision = prec;
+        lo.aux = ctx->aux;
+        lo.fork = ctx->fork_ev;
+        lo.join = ctx->join_ev;
         launch_solve(bp->plan, st.dev, lo, ctx->stream);
         Wave w;
         check_hip(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "event");
@@ -320,7 +329,7 @@ octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, 
             want.push_back(desc_for(t, out_on_device ? phi[i] : t->stage, out_on_device ? g[i] : t->stage + m, opts));
         }
         if (stats) check_hip(hipEventRecord(ctx->ev0, ctx->stream), "event");
-        run_plan(ctx, bp.plan, bp.graphs, want, opts);
+        run_plan(ctx, bp.plan, bp.graphs, want, opts, stats != nullptr);
         if (stats) {
             check_hip(hipEventRecord(ctx->ev1, ctx->stream), "event");
             if ((size_t)n * 12 > ctx->h_stats_cap) fail(OCTO_E_INVALID, "batch too large for statistics");

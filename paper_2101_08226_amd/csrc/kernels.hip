@@ -222,11 +222,53 @@ __global__ __launch_bounds__(256) void k_m2m(const LevelDesc *__restrict__ L, co
 // at total order 3 (L^(n) takes source moments of order <= 3 - n), with the
 // angular-momentum correction: C_A += -(1/6) [M3_B - (m_B/m_A) M3_A] : D4(R).
 // G is applied once at the end.
+// Accumulators of one target: L0, L1 directly; L2 and L3 as the sums
+// T2 = sum m f2 R R, s1 = sum m f1, T3 = sum m f3 R R R, U = sum m f2 R, from
+// which L2 = -(T2 + s1 I) and L3 = -(T3 + sym(I U)) are formed once at the
+// end (finish_l2_l3); C is the correction.
 template <typename T>
 struct Acc {
-    T L0, L1[3], L2[6], L3[10];
+    T L0, L1[3], L2[6], L3[10], s1, U[3];
     double C[3];
 };
+
+template <typename T>
+__device__ inline void acc_zero(Acc<T> &a) {
+    a.L0 = (T)0;
+    a.s1 = (T)0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a.L1[k] = (T)0;
+        a.U[k] = (T)0;
+        a.C[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a.L2[k] = (T)0;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) a.L3[k] = (T)0;
+}
+
+// L2 = -(T2 + s1 I); L3_abc = -(T3_abc + d_ab U_c + d_ac U_b + d_bc U_a)
+template <typename T>
+__device__ inline void finish_l2_l3(Acc<T> &a) {
+    a.L2[0] = -(a.L2[0] + a.s1);
+    a.L2[1] = -a.L2[1];
+    a.L2[2] = -a.L2[2];
+    a.L2[3] = -(a.L2[3] + a.s1);
+    a.L2[4] = -a.L2[4];
+    a.L2[5] = -(a.L2[5] + a.s1);
+    const T three = (T)3;
+    a.L3[0] = -(a.L3[0] + three * a.U[0]);
+    a.L3[1] = -(a.L3[1] + a.U[1]);
+    a.L3[2] = -(a.L3[2] + a.U[2]);
+    a.L3[3] = -(a.L3[3] + a.U[0]);
+    a.L3[4] = -a.L3[4];
+    a.L3[5] = -(a.L3[5] + a.U[0]);
+    a.L3[6] = -(a.L3[6] + three * a.U[1]);
+    a.L3[7] = -(a.L3[7] + a.U[2]);
+    a.L3[8] = -(a.L3[8] + a.U[1]);
+    a.L3[9] = -(a.L3[9] + three * a.U[2]);
+}
 
 // T = double: everything in FP64.  T = float (mixed precision): the L0..L3
 // contractions run in FP32 with FP32 partial sums; R, the radial factors and
@@ -271,27 +313,32 @@ __device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, co
         a.L1[1] -= c1 * ry + f2 * QRy;
         a.L1[2] -= c1 * rz + f2 * QRz;
         if (!LEAF_TARGET) {
-            // L2_ab = -m (f2 R_a R_b + f1 d_ab)
-            const T m2 = mB * f2, m1 = mB * f1;
-            a.L2[0] -= m2 * xx + m1;
-            a.L2[1] -= m2 * xy;
-            a.L2[2] -= m2 * xz;
-            a.L2[3] -= m2 * yy + m1;
-            a.L2[4] -= m2 * yz;
-            a.L2[5] -= m2 * zz + m1;
-            // L3_abc = -m (f3 R_a R_b R_c + f2 (d_ab R_c + d_ac R_b + d_bc R_a))
+            // L2_ab = -m (f2 R_a R_b + f1 d_ab): raw sums T2 (in L2) and s1
+            const T m2 = mB * f2;
+            a.s1 += mB * f1;
+            a.L2[0] += m2 * xx;
+            a.L2[1] += m2 * xy;
+            a.L2[2] += m2 * xz;
+            a.L2[3] += m2 * yy;
+            a.L2[4] += m2 * yz;
+            a.L2[5] += m2 * zz;
+            // L3_abc = -m (f3 R_a R_b R_c + f2 (d_ab R_c + d_ac R_b + d_bc R_a)):
+            // raw sums T3 (in L3) and U = sum m f2 R
             const T m3 = mB * f3;
             const T m3x = m3 * rx, m3y = m3 * ry, m3z = m3 * rz;
-            a.L3[0] -= m3x * xx + three * m2 * rx;
-            a.L3[1] -= m3x * xy + m2 * ry;
-            a.L3[2] -= m3x * xz + m2 * rz;
-            a.L3[3] -= m3x * yy + m2 * rx;
-            a.L3[4] -= m3x * yz;
-            a.L3[5] -= m3x * zz + m2 * rx;
-            a.L3[6] -= m3y * yy + three * m2 * ry;
-            a.L3[7] -= m3y * yz + m2 * rz;
-            a.L3[8] -= m3z * yz + m2 * ry;
-            a.L3[9] -= m3z * zz + three * m2 * rz;
+            a.U[0] += m2 * rx;
+            a.U[1] += m2 * ry;
+            a.U[2] += m2 * rz;
+            a.L3[0] += m3x * xx;
+            a.L3[1] += m3x * xy;
+            a.L3[2] += m3x * xz;
+            a.L3[3] += m3x * yy;
+            a.L3[4] += m3x * yz;
+            a.L3[5] += m3x * zz;
+            a.L3[6] += m3y * yy;
+            a.L3[7] += m3y * yz;
+            a.L3[8] += m3z * yz;
+            a.L3[9] += m3z * zz;
         }
     }
     if (amc) {
@@ -331,16 +378,7 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
     const bool amc = td.amc && mA > 0.0;
     const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
     Acc<T> a;
-    a.L0 = (T)0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        a.L1[k] = (T)0;
-        a.C[k] = 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) a.L2[k] = (T)0;
-#pragma unroll
-    for (int k = 0; k < 10; ++k) a.L3[k] = (T)0;
+    acc_zero(a);
     int cnt = 0;
     const int n_src_max = LEAF_TARGET ? ld.n_int : ld.n_rec;  // leaf <- leaf pairs are direct
     if (ld.level == 0) {
@@ -398,6 +436,7 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
         ld.lacc[5 * LS + li] = G * a.C[1];
         ld.lacc[6 * LS + li] = G * a.C[2];
     } else {
+        finish_l2_l3(a);
         const size_t IS = (size_t)ld.n_int * kCells;
         double *out = ld.loc + (size_t)item.chunk * kLoc * IS + (size_t)node * kCells + s;
         out[0] = G * (double)a.L0;
@@ -448,7 +487,10 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     const LevelDesc ld = L[item.ld];
     const TreeDesc td = TD[ld.tree];
     const int node = item.node;
-    __shared__ double2 s_src[10][729];
+    // halo of one source class: 9x9x9 lattice, rows padded to 12 so that the
+    // 8 lanes of each 16-byte LDS read phase hit distinct banks
+    constexpr int HY = 12, HX = 9 * 12, HN = 9 * 9 * 12;
+    __shared__ double2 s_src[10][HN];
     __shared__ int s_nbr[27];
     __shared__ int s_cnt[8];
     const int tid = threadIdx.x;
@@ -468,16 +510,7 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     const bool amc = td.amc && mA > 0.0;
     const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
     Acc<T> a;
-    a.L0 = (T)0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        a.L1[k] = (T)0;
-        a.C[k] = 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) a.L2[k] = (T)0;
-#pragma unroll
-    for (int k = 0; k < 10; ++k) a.L3[k] = (T)0;
+    acc_zero(a);
     int cnt = 0;
     __syncthreads();
     // this item's share of the source parity classes; its partial locals go
@@ -486,8 +519,9 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     for (int q = q0; q < q1; ++q) {
         const int qx = q >> 2, qy = (q >> 1) & 1, qz = q & 1;
         // stage source class q: lattice index i in [0,9) <-> local coordinate 2i - 4 - parity
-        for (int c = tid; c < 729; c += 512) {
-            const int ix = c / 81, iy = (c / 9) % 9, iz = c % 9;
+        for (int cc = tid; cc < 729; cc += 512) {
+            const int ix = cc / 81, iy = (cc / 9) % 9, iz = cc % 9;
+            const int c = ix * HX + iy * HY + iz;
             const int sx = 2 * ix - 4 - qx, sy = 2 * iy - 4 - qy, sz = 2 * iz - 4 - qz;
             const int nb = s_nbr[nbr_slot(sx, sy, sz)];
             double v[20];
@@ -509,7 +543,7 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
         for (int k = beg; k < end; ++k) {
             int dx, dy, dz;
             unpack(st.m2l_src[k], dx, dy, dz);
-            const int h = (((x + dx + 5) >> 1) * 9 + ((y + dy + 5) >> 1)) * 9 + ((z + dz + 5) >> 1);
+            const int h = ((x + dx + 5) >> 1) * HX + ((y + dy + 5) >> 1) * HY + ((z + dz + 5) >> 1);
             const double2 e0 = s_src[0][h];
             if (e0.x < 0.0) continue;
             const double2 e1 = s_src[1][h];
@@ -533,6 +567,7 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
         __syncthreads();
     }
     const double G = td.G;
+    finish_l2_l3(a);
     const size_t IS = (size_t)ld.n_int * kCells;
     double *out = ld.loc + (size_t)item.chunk * kLoc * IS + (size_t)node * kCells + s;
     out[0] = G * (double)a.L0;
@@ -667,7 +702,10 @@ __device__ inline void direct_add(T Rx, T Ry, T Rz, T m, T &phi, T &gx, T &gy, T
     gz -= mir3 * Rz;
 }
 
-template <typename T>
+// COUNT: count the evaluated pairs (solves that report statistics); without
+// it absent partners are stored as zero masses and the loop is unmasked
+// (identical results: adding 0 * w changes nothing).
+template <typename T, bool COUNT>
 __global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                               const LeafItem *__restrict__ items, int n_items, StencilDev st,
                                               double *__restrict__ stat, int64_t *__restrict__ cnt_out) {
@@ -694,7 +732,8 @@ __global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, c
         for (int c = tid; c < 18 * 18 * 18; c += 512) {
             const int sx = c / 324 - 5, sy = (c / 18) % 18 - 5, sz = c % 18 - 5;
             const int nb = s_nbr[nbr_slot(sx, sy, sz)];
-            s_m[c] = nb >= ld.n_int ? (T)ld.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)] : (T)-1;
+            s_m[c] = nb >= ld.n_int ? (T)ld.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)]
+                                    : (T)(COUNT ? -1 : 0);
         }
     }
     __syncthreads();
@@ -738,9 +777,12 @@ __global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, c
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const T *w = lw + 4 * (k + u);
-                const bool ok = m[u] >= (T)0;
-                const T mm = ok ? m[u] : (T)0;
-                cnt += ok ? 1 : 0;
+                T mm = m[u];
+                if (COUNT) {
+                    const bool ok = m[u] >= (T)0;
+                    mm = ok ? m[u] : (T)0;
+                    cnt += ok ? 1 : 0;
+                }
                 if (u & 1) {
                     sp2 += mm * w[0];
                     sgx2 += mm * w[1];
@@ -756,9 +798,12 @@ __global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, c
         }
         for (; k < end; ++k) {
             const T m = s_m[base + st.leaf_hoff[k]];
-            const bool ok = m >= (T)0;
-            const T mm = ok ? m : (T)0;
-            cnt += ok ? 1 : 0;
+            T mm = m;
+            if (COUNT) {
+                const bool ok = m >= (T)0;
+                mm = ok ? m : (T)0;
+                cnt += ok ? 1 : 0;
+            }
             const T *w = lw + 4 * k;
             sp += mm * w[0];
             sgx += mm * w[1];
@@ -950,15 +995,24 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
         if (n) hipLaunchKernelGGL(k_m2m, dim3(2 * n), dim3(256), 0, s, p.d_levels, p.d_interior + p.interior_off[l], n);
     }
     mark(2);
+    // the per-wavefront multipole items (root, sparse levels, leaf targets)
+    // run on the auxiliary stream, concurrently with the LDS-staged kernel
+    const bool fork = o.aux && p.n_m2l && p.n_m2l_nodes;
+    hipStream_t sm = fork ? o.aux : s;
+    if (fork) {
+        check_hip(hipEventRecord(o.fork, s), "fork");
+        check_hip(hipStreamWaitEvent(o.aux, o.fork, 0), "fork");
+    }
     if (p.n_m2l) {
         const int grid = ((p.n_m2l + kXcd - 1) / kXcd) * kXcd;
         if (o.precision == OCTO_MIXED)
-            hipLaunchKernelGGL(k_m2l<float>, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st,
+            hipLaunchKernelGGL(k_m2l<float>, dim3(grid), dim3(64), 0, sm, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st,
                                p.d_m2l_cnt);
         else
-            hipLaunchKernelGGL(k_m2l<double>, dim3(grid), dim3(64), 0, s, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st,
+            hipLaunchKernelGGL(k_m2l<double>, dim3(grid), dim3(64), 0, sm, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st,
                                p.d_m2l_cnt);
     }
+    if (fork) check_hip(hipEventRecord(o.join, o.aux), "join");
     if (p.n_m2l_nodes) {
         const int grid = ((p.n_m2l_nodes + kXcd - 1) / kXcd) * kXcd;
         if (o.precision == OCTO_MIXED)
@@ -968,6 +1022,7 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
             hipLaunchKernelGGL(k_m2l_lds<double>, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes,
                                p.n_m2l_nodes, st, p.d_m2l_cnt + p.n_m2l);
     }
+    if (fork) check_hip(hipStreamWaitEvent(s, o.join, 0), "join");
     mark(3);
     for (int l = 0; l < p.n_levels_max; ++l) {
         const int n = p.n_interior[l];
@@ -983,12 +1038,10 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     mark(4);
     if (p.n_leaf) {
         const int grid = ((p.n_leaf + kXcd - 1) / kXcd) * kXcd;
-        if (o.precision == OCTO_MIXED)
-            hipLaunchKernelGGL(k_leaf<float>, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
-                               p.d_stat, p.d_leaf_cnt);
-        else
-            hipLaunchKernelGGL(k_leaf<double>, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
-                               p.d_stat, p.d_leaf_cnt);
+        auto leaf = o.precision == OCTO_MIXED ? (o.count ? k_leaf<float, true> : k_leaf<float, false>)
+                                              : (o.count ? k_leaf<double, true> : k_leaf<double, false>);
+        hipLaunchKernelGGL(leaf, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st, p.d_stat,
+                           p.d_leaf_cnt);
     }
     mark(5);
     hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(1024), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg,

@@ -361,6 +361,10 @@ octo_status octo_ctx_create(int device, void *hip_stream, const octo_allocator *
             c->own_stream = true;
         }
         check_hip(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking), "stream create");
+        check_hip(hipStreamCreateWithFlags(&c->capture_aux, hipStreamNonBlocking), "stream create");
+        check_hip(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking), "stream create");
+        check_hip(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming), "event");
+        check_hip(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming), "event");
         if (const char *e = getenv("OCTO_GRAPHS")) c->use_graphs = atoi(e) != 0;
         check_hip(hipEventCreate(&c->ev0), "event");
         for (int i = 0; i < 7; ++i) check_hip(hipEventCreate(&c->phase_ev[i]), "event");
@@ -381,6 +385,11 @@ octo_status octo_ctx_destroy(octo_ctx *ctx) {
         ctx->invalidate_batches();
         for (auto &kv : ctx->stencils) hipFree(kv.second->block.ptr);
         hipStreamDestroy(ctx->capture);
+        hipStreamDestroy(ctx->capture_aux);
+        hipStreamSynchronize(ctx->aux);
+        hipStreamDestroy(ctx->aux);
+        hipEventDestroy(ctx->fork_ev);
+        hipEventDestroy(ctx->join_ev);
         hipEventDestroy(ctx->ev0);
         for (int i = 0; i < 7; ++i) hipEventDestroy(ctx->phase_ev[i]);
         hipEventDestroy(ctx->ev1);
@@ -538,7 +547,7 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
         want[0].G = opts->G;
         want[0].amc = opts->amc ? 1 : 0;
         if (stats) check_hip(hipEventRecord(ctx->ev0, ctx->stream), "event");
-        run_plan(ctx, tree->plan, tree->graphs, want, opts);
+        run_plan(ctx, tree->plan, tree->graphs, want, opts, stats != nullptr);
         if (stats) {
             check_hip(hipEventRecord(ctx->ev1, ctx->stream), "event");
             check_hip(hipMemcpyAsync(ctx->h_stats, tree->plan.d_out, 12 * sizeof(double), hipMemcpyDeviceToHost,
@@ -587,7 +596,7 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
             want[0].amc = opts->amc ? 1 : 0;
             double best = 1e30;
             for (int rep = 0; rep < 4; ++rep) {
-                run_plan(ctx, tree->plan, tree->graphs, want, opts);
+                run_plan(ctx, tree->plan, tree->graphs, want, opts, false);
                 check_hip(hipStreamSynchronize(ctx->stream), "autotune");
                 float ms = 0.f;
                 hipEventElapsedTime(&ms, ctx->phase_ev[2], ctx->phase_ev[3]);

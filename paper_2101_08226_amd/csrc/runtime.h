@@ -119,7 +119,10 @@ struct StencilDevHolder {
 
 struct LaunchOpts {
     int precision = OCTO_FP64;
+    bool count = true;                   // count evaluated pairs (statistics)
     hipEvent_t *phase_events = nullptr;  // 7 events around the 6 phases, or NULL
+    hipStream_t aux = nullptr;           // second stream for concurrent multipole work, or NULL
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 // enqueue one full solve of a plan on stream s
@@ -173,6 +176,8 @@ struct octo_ctx {
     std::map<uint64_t, std::unique_ptr<octo::StencilDevHolder>> stencils;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipStream_t capture = nullptr;  // private stream for graph capture
+    hipStream_t aux = nullptr, capture_aux = nullptr;  // second streams (direct launches, capture)
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     bool use_graphs = true;
     bool profiling = false;
     hipEvent_t phase_ev[7] = {};
@@ -214,7 +219,7 @@ struct octo_tree {
 namespace octo {
 // launch a plan through a cached graph (captured on first use) or directly
 void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs,
-              const std::vector<TreeDesc> &want, const octo_opts *o);
+              const std::vector<TreeDesc> &want, const octo_opts *o, bool count = true);
 void drop_graphs(std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs);
 void build_tree_plan(octo_tree *t);
 }  // namespace octo

@@ -395,7 +395,7 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
     for (size_t l = 0; l < ph.interior.size(); ++l) {
         int max_parts = 1;
         for (const NodeItem &q : ph.interior[l]) max_parts = std::max(max_parts, ph.levels[q.ld].n_parts);
-        p.sum_parts_level[l] = (max_parts > 4) ? 1 : 0;
+        p.sum_parts_level[l] = (max_parts > 1 && ph.interior[l].size() <= 128) ? 1 : 0;
     }
     p.d_tree_leaf_beg = (int32_t *)put(ph.tree_leaf_beg.data(), ph.tree_leaf_beg.size() * sizeof(int32_t));
     p.d_tree_m2l_beg = (int32_t *)put(ph.tree_m2l_beg.data(), ph.tree_m2l_beg.size() * sizeof(int32_t));
