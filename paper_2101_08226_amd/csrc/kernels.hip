@@ -518,34 +518,49 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     const int q0 = 8 * item.chunk / ld.n_parts, q1 = 8 * (item.chunk + 1) / ld.n_parts;
     for (int q = q0; q < q1; ++q) {
         const int qx = q >> 2, qy = (q >> 1) & 1, qz = q & 1;
-        // stage source class q: lattice index i in [0,9) <-> local coordinate 2i - 4 - parity
-        for (int cc = tid; cc < 729; cc += 512) {
+        // stage source class q: lattice index i in [0,9) <-> local coordinate
+        // 2i - 4 - parity; both cells of this thread are loaded before either
+        // is stored so that all 40 loads are in flight together.  Cells that
+        // are not sources get mass -0.0 (counted as absent, contributes
+        // exact zeros) and a far-away centre.
+        double v[2][20];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int cc = tid + 512 * u;
             const int ix = cc / 81, iy = (cc / 9) % 9, iz = cc % 9;
-            const int c = ix * HX + iy * HY + iz;
             const int sx = 2 * ix - 4 - qx, sy = 2 * iy - 4 - qy, sz = 2 * iz - 4 - qz;
-            const int nb = s_nbr[nbr_slot(sx, sy, sz)];
-            double v[20];
+            const int nb = cc < 729 ? s_nbr[nbr_slot(sx, sy, sz)] : -1;
             if (nb >= 0 && nb < ld.n_rec) {
                 const size_t si = (size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7);
-                v[0] = ld.mass[si];
+                v[u][0] = ld.mass[si];
 #pragma unroll
-                for (int k = 0; k < kRec; ++k) v[1 + k] = ld.mp[k * S + si];
+                for (int k = 0; k < kRec; ++k) v[u][1 + k] = ld.mp[k * S + si];
             } else {
-                v[0] = -1.0;  // no source cell here
+                v[u][0] = -0.0;
+                v[u][1] = v[u][2] = v[u][3] = 1.0e3;
 #pragma unroll
-                for (int k = 1; k < 20; ++k) v[k] = 0.0;
+                for (int k = 4; k < 20; ++k) v[u][k] = 0.0;
             }
+        }
 #pragma unroll
-            for (int k = 0; k < 10; ++k) s_src[k][c] = make_double2(v[2 * k], v[2 * k + 1]);
+        for (int u = 0; u < 2; ++u) {
+            const int cc = tid + 512 * u;
+            if (cc < 729) {
+                const int ix = cc / 81, iy = (cc / 9) % 9, iz = cc % 9;
+                const int c = ix * HX + iy * HY + iz;
+#pragma unroll
+                for (int k = 0; k < 10; ++k) s_src[k][c] = make_double2(v[u][2 * k], v[u][2 * k + 1]);
+            }
         }
         __syncthreads();
         const int beg = st.m2l_src_beg[p * 9 + q], end = st.m2l_src_beg[p * 9 + q + 1];
+#pragma unroll 2
         for (int k = beg; k < end; ++k) {
             int dx, dy, dz;
             unpack(st.m2l_src[k], dx, dy, dz);
             const int h = ((x + dx + 5) >> 1) * HX + ((y + dy + 5) >> 1) * HY + ((z + dz + 5) >> 1);
             const double2 e0 = s_src[0][h];
-            if (e0.x < 0.0) continue;
+            cnt += signbit(e0.x) ? 0 : 1;  // absent sources carry -0.0
             const double2 e1 = s_src[1][h];
             double Q[6], O[10];
             const double2 e2 = s_src[2][h], e3 = s_src[3][h], e4 = s_src[4][h];
@@ -562,7 +577,6 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
                 O[2 * j + 1] = e.y;
             }
             m2l_pair<false, T>(zAx - e0.y, zAy - e1.x, zAz - e1.y, e0.x, Q, O, e0.x * imA, OA, amc, a);
-            ++cnt;
         }
         __syncthreads();
     }
@@ -729,12 +743,20 @@ __global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, c
     }
     __syncthreads();
     if (ld.level > 0) {
-        for (int c = tid; c < 18 * 18 * 18; c += 512) {
+        // all 12 loads of this thread in flight before any store
+        constexpr int NH = 18 * 18 * 18, NU = (NH + 511) / 512;
+        T v[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int c = tid + 512 * u;
             const int sx = c / 324 - 5, sy = (c / 18) % 18 - 5, sz = c % 18 - 5;
-            const int nb = s_nbr[nbr_slot(sx, sy, sz)];
-            s_m[c] = nb >= ld.n_int ? (T)ld.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)]
-                                    : (T)(COUNT ? -1 : 0);
+            const int nb = c < NH ? s_nbr[nbr_slot(sx, sy, sz)] : -1;
+            v[u] = nb >= ld.n_int ? (T)ld.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)]
+                                  : (T)(COUNT ? -1 : 0);
         }
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+            if (tid + 512 * u < NH) s_m[tid + 512 * u] = v[u];
     }
     __syncthreads();
     const int s = tid;  // parity-major storage: wavefront p holds class p
