@@ -37,7 +37,7 @@ METRIC = "FMM cells solved/s (FP64 vs mixed, 1 GPU); p50/p99 served solve latenc
 M2L_FLOPS_PER_PAIR = 297
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector
-PHASES = ["p2m", "m2m", "m2l", "l2l", "leaf", "stats"]
+PHASES = ["p2m", "near", "m2m", "m2l", "l2l", "l2p", "stats"]
 
 
 def parse():
@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=400, help="c5: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="c5: arrivals per second (0: 0.8 x measured saturation)")
     ap.add_argument("--budget-gib", type=float, default=16.0, help="c5: HBM budget of the server context")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes (counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -70,7 +72,7 @@ def timed(step, sync, steps, warmup):
 
 def phase_times(lib, ctx, solve_once, n=5):
     ctx.set_profiling(True)
-    acc = np.zeros(6)
+    acc = np.zeros(7)
     for _ in range(n):
         acc += np.array(solve_once().phase_ms[:])
     ctx.set_profiling(False)
@@ -117,6 +119,16 @@ def main():
         sys.exit(2)
     import torch
 
+    if a.copy_probe:
+        n = a.copy_probe // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(1, a.steps)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8, "copies": max(1, a.steps)}))
+        return
+
     import paper_2101_08226_amd as lib
     import workloads as w
 
@@ -159,7 +171,7 @@ def main():
                          "m2l_pairs": int(r["stats"]["m2l_pairs"]), "direct_pairs": int(r["stats"]["direct_pairs"])}
         out["torque"] = r["stats"]["torque"]
         out["force"] = r["stats"]["force"]
-        rl = roofline_m2l(r["stats"]["m2l_pairs"], r["phases"][2], main_p)
+        rl = roofline_m2l(r["stats"]["m2l_pairs"], r["phases"][3], main_p)
         rl["phase_ms"] = {k: round(v, 4) for k, v in zip(PHASES, r["phases"])}
         out["roofline"] = rl
         if "mixed" in res and main_p == "fp64":

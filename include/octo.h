@@ -105,13 +105,14 @@ typedef struct {
     int64_t m2l_pairs;
     int64_t direct_pairs;
     double device_ms;
-    /* per-phase device time (ms) when profiling is on (octo_ctx_set_profiling):
-     * [0] leaf masses (P2M), [1] upward pass (M2M, all levels), [2] multipole
-     * interactions (M2L with the correction, all levels), [3] downward pass
-     * (L2L, interior levels), [4] leaf kernel (near field, cross-level pairs,
-     * final shift, potential and acceleration), [5] statistics reduction;
-     * zeros otherwise */
-    double phase_ms[6];
+    /* per-phase device time (ms) when profiling is on (octo_ctx_set_profiling;
+     * the phases then run one after the other): [0] leaf masses (P2M),
+     * [1] near field (same-level and cross-level direct pairs), [2] upward
+     * pass (M2M, all levels), [3] multipole interactions (M2L with the
+     * correction, all levels), [4] downward pass (L2L, interior levels),
+     * [5] leaves (final shift, potential and acceleration), [6] statistics
+     * reduction; zeros otherwise */
+    double phase_ms[7];
 } octo_stats;
 
 /* Density at n points: xyz is 3n doubles (x0,y0,z0,x1,...), rho_out n doubles. */

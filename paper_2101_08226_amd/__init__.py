@@ -54,7 +54,7 @@ class octo_stats(ctypes.Structure):
                 ("net_torque", ctypes.c_double * 3), ("force_scale", ctypes.c_double),
                 ("torque_scale", ctypes.c_double), ("n_leaf_cells", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
                 ("direct_pairs", ctypes.c_int64), ("device_ms", ctypes.c_double),
-                ("phase_ms", ctypes.c_double * 6)]
+                ("phase_ms", ctypes.c_double * 7)]
 
     def as_dict(self):
         F = np.array(self.net_force[:])

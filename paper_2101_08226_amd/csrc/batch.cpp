@@ -45,18 +45,22 @@ void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipG
     lo.count = count;
     lo.fork = ctx->fork_ev;
     lo.join = ctx->join_ev;
+    lo.fork_near = ctx->fork_near_ev;
+    lo.join_near = ctx->join_near_ev;
     if (ctx->profiling) {
+        // phases are timed one after the other: no concurrent streams
         lo.phase_events = ctx->phase_ev;
-        lo.aux = ctx->aux;
         launch_solve(plan, st.dev, lo, ctx->stream);
         return;
     }
     if (!ctx->use_graphs) {
         lo.aux = ctx->aux;
+        lo.aux_near = ctx->aux_near;
         launch_solve(plan, st.dev, lo, ctx->stream);
         return;
     }
     lo.aux = ctx->capture_aux;
+    lo.aux_near = ctx->capture_near;
     const auto key = std::make_pair(theta_bits(o->theta), (int)o->precision * 2 + (count ? 1 : 0));
     auto it = graphs.find(key);
     if (it == graphs.end()) {
@@ -278,6 +282,9 @@ static void pump(octo_ctx *ctx) {
         lo.aux = ctx->aux;
         lo.fork = ctx->fork_ev;
         lo.join = ctx->join_ev;
+        lo.aux_near = ctx->aux_near;
+        lo.fork_near = ctx->fork_near_ev;
+        lo.join_near = ctx->join_near_ev;
         launch_solve(bp->plan, st.dev, lo, ctx->stream);
         Wave w;
         check_hip(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "event");

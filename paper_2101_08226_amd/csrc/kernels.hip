@@ -720,9 +720,9 @@ __device__ inline void direct_add(T Rx, T Ry, T Rz, T m, T &phi, T &gx, T &gy, T
 // it absent partners are stored as zero masses and the loop is unmasked
 // (identical results: adding 0 * w changes nothing).
 template <typename T, bool COUNT>
-__global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
+__global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                               const LeafItem *__restrict__ items, int n_items, StencilDev st,
-                                              double *__restrict__ stat, int64_t *__restrict__ cnt_out) {
+                                              int64_t *__restrict__ cnt_out) {
     const int it = xcd_item(n_items);
     if (it >= n_items) return;
     const LeafItem item = items[it];
@@ -886,9 +886,53 @@ __global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, c
             ++cnt;
         }
     }
-    // direct sums enter the FP64 accumulation here
-    double phi = td.G * (double)phi_t;
-    double gx = td.G * (double)gx_t, gy = td.G * (double)gy_t, gz = td.G * (double)gz_t;
+    // direct sums enter the FP64 accumulation: phi and g of this cell's
+    // direct partners, G applied
+    const size_t NS = (size_t)(ld.n_nodes - ld.n_int) * kCells;
+    const size_t ni = (size_t)(node - ld.n_int) * kCells + s;
+    ld.nf[ni] = td.G * (double)phi_t;
+    ld.nf[NS + ni] = td.G * (double)gx_t;
+    ld.nf[2 * NS + ni] = td.G * (double)gy_t;
+    ld.nf[3 * NS + ni] = td.G * (double)gz_t;
+    if (COUNT) {
+        const int tot = wave_sum(cnt);
+        __shared__ int s_c[8];
+        if (lane == 0) s_c[p] = tot;
+        __syncthreads();
+        if (tid == 0) {
+            int64_t c = 0;
+            for (int w = 0; w < 8; ++w) c += s_c[w];
+            cnt_out[it] = c;
+        }
+    }
+}
+
+// Leaf cells, after the downward pass: the direct sums from the near-field
+// kernel, the cell's own multipole-to-local sums (record leaves) and the
+// parent's expansion shifted to the cell centre give phi and g = -grad phi,
+// written in the caller's layout, plus per-node partial sums of the
+// diagnostics.
+__global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
+                                             const LeafItem *__restrict__ items, int n_items,
+                                             double *__restrict__ stat) {
+    const int it = xcd_item(n_items);
+    if (it >= n_items) return;
+    const LeafItem item = items[it];
+    const LevelDesc ld = L[item.ld];
+    const TreeDesc td = TD[ld.tree];
+    const int tid = threadIdx.x;
+    const int p = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int node = item.node;
+    const int s = tid;
+    int x, y, z;
+    local_xyz(s, x, y, z);
+    const double h = ld.h;
+    const int gx0 = 8 * ld.coord[3 * node], gy0 = 8 * ld.coord[3 * node + 1], gz0 = 8 * ld.coord[3 * node + 2];
+    const double cx = centre(gx0 + x, h), cy = centre(gy0 + y, h), cz = centre(gz0 + z, h);
+    const size_t NS = (size_t)(ld.n_nodes - ld.n_int) * kCells;
+    const size_t ni = (size_t)(node - ld.n_int) * kCells + s;
+    double phi = ld.nf[ni];
+    double gx = ld.nf[NS + ni], gy = ld.nf[2 * NS + ni], gz = ld.nf[3 * NS + ni];
 
     // own multipole-to-local sums (record leaves)
     if (item.flags & kLeafLacc) {
@@ -937,23 +981,16 @@ __global__ __launch_bounds__(512) void k_leaf(const LevelDesc *__restrict__ L, c
     double v[kStat] = {m, fx, fy, fz, cy * fz - cz * fy, cz * fx - cx * fz, cx * fy - cy * fx, m * gn, xn * m * gn};
 #pragma unroll
     for (int k = 0; k < kStat; ++k) v[k] = wave_sum(v[k]);
-    const int tot = wave_sum(cnt);
     __shared__ double s_v[8][kStat];
-    __shared__ int s_c[8];
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < kStat; ++k) s_v[p][k] = v[k];
-        s_c[p] = tot;
     }
     __syncthreads();
     if (tid < kStat) {
         double acc = 0.0;
         for (int w = 0; w < 8; ++w) acc += s_v[w][tid];
         stat[(size_t)it * kStat + tid] = acc;
-    } else if (tid == kStat) {
-        int64_t c = 0;
-        for (int w = 0; w < 8; ++w) c += s_c[w];
-        cnt_out[it] = c;
     }
 }
 
@@ -1012,11 +1049,28 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     mark(0);
     if (p.n_p2m) hipLaunchKernelGGL(k_p2m, dim3(2 * p.n_p2m), dim3(256), 0, s, p.d_levels, p.d_trees, p.d_p2m, p.n_p2m);
     mark(1);
+    // the near field needs only the leaf masses: it runs on its own stream,
+    // concurrently with the upward pass, the multipole phase and the downward pass
+    const bool near_fork = o.aux_near && p.n_leaf;
+    hipStream_t sn = near_fork ? o.aux_near : s;
+    if (near_fork) {
+        check_hip(hipEventRecord(o.fork_near, s), "fork");
+        check_hip(hipStreamWaitEvent(o.aux_near, o.fork_near, 0), "fork");
+    }
+    if (p.n_leaf) {
+        const int grid = ((p.n_leaf + kXcd - 1) / kXcd) * kXcd;
+        auto near = o.precision == OCTO_MIXED ? (o.count ? k_near<float, true> : k_near<float, false>)
+                                              : (o.count ? k_near<double, true> : k_near<double, false>);
+        hipLaunchKernelGGL(near, dim3(grid), dim3(512), 0, sn, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
+                           p.d_leaf_cnt);
+    }
+    if (near_fork) check_hip(hipEventRecord(o.join_near, o.aux_near), "join");
+    mark(2);
     for (int l = p.n_levels_max - 1; l >= 0; --l) {
         const int n = p.n_interior[l];
         if (n) hipLaunchKernelGGL(k_m2m, dim3(2 * n), dim3(256), 0, s, p.d_levels, p.d_interior + p.interior_off[l], n);
     }
-    mark(2);
+    mark(3);
     // the per-wavefront multipole items (root, sparse levels, leaf targets)
     // run on the auxiliary stream, concurrently with the LDS-staged kernel
     const bool fork = o.aux && p.n_m2l && p.n_m2l_nodes;
@@ -1045,7 +1099,7 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
                                p.n_m2l_nodes, st, p.d_m2l_cnt + p.n_m2l);
     }
     if (fork) check_hip(hipStreamWaitEvent(s, o.join, 0), "join");
-    mark(3);
+    mark(4);
     for (int l = 0; l < p.n_levels_max; ++l) {
         const int n = p.n_interior[l];
         if (!n) continue;
@@ -1057,18 +1111,16 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
         hipLaunchKernelGGL(k_l2l, dim3(2 * n), dim3(256), 0, s, p.d_levels, p.d_interior + p.interior_off[l], n,
                            wide ? 1 : 0);
     }
-    mark(4);
+    mark(5);
+    if (near_fork) check_hip(hipStreamWaitEvent(s, o.join_near, 0), "join");
     if (p.n_leaf) {
         const int grid = ((p.n_leaf + kXcd - 1) / kXcd) * kXcd;
-        auto leaf = o.precision == OCTO_MIXED ? (o.count ? k_leaf<float, true> : k_leaf<float, false>)
-                                              : (o.count ? k_leaf<double, true> : k_leaf<double, false>);
-        hipLaunchKernelGGL(leaf, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st, p.d_stat,
-                           p.d_leaf_cnt);
+        hipLaunchKernelGGL(k_l2p, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, p.d_stat);
     }
-    mark(5);
+    mark(6);
     hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(1024), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg,
                        p.d_tree_m2ln_beg, p.n_m2l, p.d_stat, p.d_leaf_cnt, p.d_m2l_cnt, p.d_out);
-    mark(6);
+    mark(7);
     check_hip(hipGetLastError(), "kernel launch");
 }
 

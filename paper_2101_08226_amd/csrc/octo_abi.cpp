@@ -78,7 +78,7 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
     const int nl = L.n_levels;
     size_t bytes = 0;
     std::vector<size_t> off_nbr(nl), off_child(nl), off_parent(nl), off_coord(nl), off_out(nl), off_mass(nl),
-        off_mp(nl), off_loc(nl), off_lacc(nl);
+        off_mp(nl), off_loc(nl), off_lacc(nl), off_nf(nl);
     t->parts_alloc.assign(nl, 1);
     t->parts.assign(nl, 1);
     t->m2l_lds.assign(nl, 0);
@@ -110,6 +110,8 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
         bytes += al((size_t)t->parts_alloc[l] * kLoc * h.n_int * kCells * 8);
         off_lacc[l] = bytes;
         bytes += al((size_t)kLacc * (h.n_rec - h.n_int) * kCells * 8);
+        off_nf[l] = bytes;
+        bytes += al((size_t)4 * (h.n_nodes - h.n_int) * kCells * 8);
     }
     const size_t off_rho = bytes;
     bytes += al((size_t)L.n_leaf_cells * 8);
@@ -153,6 +155,7 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
         d.mp = (double *)(base + off_mp[l]);
         d.loc = (double *)(base + off_loc[l]);
         d.lacc = (double *)(base + off_lacc[l]);
+        d.nf = (double *)(base + off_nf[l]);
     }
     t->rho = (double *)(base + off_rho);
     t->stage = (double *)(base + off_stage);
@@ -365,9 +368,13 @@ octo_status octo_ctx_create(int device, void *hip_stream, const octo_allocator *
         check_hip(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking), "stream create");
         check_hip(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming), "event");
         check_hip(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming), "event");
+        check_hip(hipStreamCreateWithFlags(&c->aux_near, hipStreamNonBlocking), "stream create");
+        check_hip(hipStreamCreateWithFlags(&c->capture_near, hipStreamNonBlocking), "stream create");
+        check_hip(hipEventCreateWithFlags(&c->fork_near_ev, hipEventDisableTiming), "event");
+        check_hip(hipEventCreateWithFlags(&c->join_near_ev, hipEventDisableTiming), "event");
         if (const char *e = getenv("OCTO_GRAPHS")) c->use_graphs = atoi(e) != 0;
         check_hip(hipEventCreate(&c->ev0), "event");
-        for (int i = 0; i < 7; ++i) check_hip(hipEventCreate(&c->phase_ev[i]), "event");
+        for (int i = 0; i < 8; ++i) check_hip(hipEventCreate(&c->phase_ev[i]), "event");
         check_hip(hipEventCreate(&c->ev1), "event");
         c->h_stats_cap = 12 * 1024;
         check_hip(hipHostMalloc((void **)&c->h_stats, c->h_stats_cap * sizeof(double), hipHostMallocDefault),
@@ -390,8 +397,13 @@ octo_status octo_ctx_destroy(octo_ctx *ctx) {
         hipStreamDestroy(ctx->aux);
         hipEventDestroy(ctx->fork_ev);
         hipEventDestroy(ctx->join_ev);
+        hipStreamSynchronize(ctx->aux_near);
+        hipStreamDestroy(ctx->aux_near);
+        hipStreamDestroy(ctx->capture_near);
+        hipEventDestroy(ctx->fork_near_ev);
+        hipEventDestroy(ctx->join_near_ev);
         hipEventDestroy(ctx->ev0);
-        for (int i = 0; i < 7; ++i) hipEventDestroy(ctx->phase_ev[i]);
+        for (int i = 0; i < 8; ++i) hipEventDestroy(ctx->phase_ev[i]);
         hipEventDestroy(ctx->ev1);
         hipHostFree(ctx->h_stats);
         if (ctx->own_stream) hipStreamDestroy(ctx->stream);
@@ -564,7 +576,7 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
             hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
             fill_stats(ctx->h_stats, n, ms, stats);
             if (ctx->profiling)
-                for (int i = 0; i < 6; ++i) {
+                for (int i = 0; i < 7; ++i) {
                     float pm = 0.f;
                     hipEventElapsedTime(&pm, ctx->phase_ev[i], ctx->phase_ev[i + 1]);
                     stats->phase_ms[i] = pm;
@@ -599,7 +611,7 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
                 run_plan(ctx, tree->plan, tree->graphs, want, opts, false);
                 check_hip(hipStreamSynchronize(ctx->stream), "autotune");
                 float ms = 0.f;
-                hipEventElapsedTime(&ms, ctx->phase_ev[2], ctx->phase_ev[3]);
+                hipEventElapsedTime(&ms, ctx->phase_ev[3], ctx->phase_ev[4]);
                 if (rep > 0) best = std::min(best, (double)ms);  // first run warms up
             }
             return best;

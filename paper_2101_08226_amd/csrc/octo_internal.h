@@ -56,6 +56,7 @@ struct LevelDesc {
     double *mp;               // kRec * n_rec * 512
     double *loc;              // n_parts * kLoc * n_int * 512 (slot-major)
     double *lacc;             // kLacc * (n_rec - n_int) * 512
+    double *nf;               // 4 * (n_nodes - n_int) * 512: direct-sum phi, g of leaf cells
 };
 
 struct TreeDesc {

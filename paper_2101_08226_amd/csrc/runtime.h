@@ -120,9 +120,11 @@ struct StencilDevHolder {
 struct LaunchOpts {
     int precision = OCTO_FP64;
     bool count = true;                   // count evaluated pairs (statistics)
-    hipEvent_t *phase_events = nullptr;  // 7 events around the 6 phases, or NULL
+    hipEvent_t *phase_events = nullptr;  // 8 events around the 7 phases, or NULL
     hipStream_t aux = nullptr;           // second stream for concurrent multipole work, or NULL
     hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t aux_near = nullptr;      // third stream for the near field, or NULL
+    hipEvent_t fork_near = nullptr, join_near = nullptr;
 };
 
 // enqueue one full solve of a plan on stream s
@@ -178,9 +180,11 @@ struct octo_ctx {
     hipStream_t capture = nullptr;  // private stream for graph capture
     hipStream_t aux = nullptr, capture_aux = nullptr;  // second streams (direct launches, capture)
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    hipStream_t aux_near = nullptr, capture_near = nullptr;  // near-field streams
+    hipEvent_t fork_near_ev = nullptr, join_near_ev = nullptr;
     bool use_graphs = true;
     bool profiling = false;
-    hipEvent_t phase_ev[7] = {};
+    hipEvent_t phase_ev[8] = {};
     double *h_stats = nullptr;  // pinned host staging for stats
     size_t h_stats_cap = 0;
     // last batch signature (octo_solve_batch)
