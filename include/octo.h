@@ -210,6 +210,27 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
 octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, const octo_opts *opts,
                              double *const *phi, double *const *g, int out_on_device, octo_stats *stats);
 
+/* ---- coupling to the hydrodynamic update -------------------------------- */
+
+/* Gravity source terms of the hydrodynamic update (Sec. 2.3, source vector S,
+ * with the right-hand sides of the momentum and energy equations of Sec. 2.1)
+ * at every leaf cell, x being the cell centre:
+ *   src_s = rho g + Omega x s                                  (3 x n)
+ *   src_e = 1/2 (phi drho/dt - rho dphi/dt) + rho Omega . (x x g)   (n)
+ * omega: 3 doubles, host memory (the grid's rotation vector).  rho, phi,
+ * drho_dt, dphi_dt: n doubles; s, g: 3 x n component-major; outputs likewise;
+ * all device pointers in the tree's density layout, n = leaf cells.  drho_dt
+ * and dphi_dt may be NULL (taken as zero).  Stream-ordered on the context
+ * stream (returns once enqueued).  Errors: OCTO_E_INVALID, OCTO_E_STATE. */
+octo_status octo_gravity_sources(octo_ctx *ctx, octo_tree *tree, const double *omega, const double *rho,
+                                 const double *s, const double *phi, const double *g, const double *drho_dt,
+                                 const double *dphi_dt, double *src_s, double *src_e);
+/* Energy update after a potential solve (Sec. 2.3):
+ * E += 1/2 rho (phi_before - phi_after), elementwise over the tree's n leaf
+ * cells; device pointers, stream-ordered on the context stream. */
+octo_status octo_energy_update(octo_ctx *ctx, octo_tree *tree, const double *rho, const double *phi_before,
+                               const double *phi_after, double *E);
+
 /* ---- asynchronous requests (continuous batching) ------------------------ */
 
 typedef int64_t octo_ticket;

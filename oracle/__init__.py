@@ -18,6 +18,7 @@ import numpy as np
 
 from .build import LIB_PATH, build  # noqa: F401
 from .adaptive import build_adaptive_leaves, is_balanced  # noqa: F401
+from . import coupling  # noqa: F401
 
 _lib = None
 

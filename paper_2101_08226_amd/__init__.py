@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "OCTO_OK", 1: "OCTO_E_INVALID", 2: "OCTO_E_DEVICE", 3: "OCTO_
 EXPORTS = [
     "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_tree_build", "octo_tree_build_uniform",
     "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
-    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
+    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_gravity_sources", "octo_energy_update", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
     "octo_host_stencil_sizes", "octo_host_layout", "octo_host_adaptive_leaves",
 ]
 
@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_solve_batch": [_P, _PP, ctypes.c_int32, ctypes.POINTER(octo_opts), ctypes.POINTER(_D),
                              ctypes.POINTER(_D), _I, ctypes.POINTER(octo_stats)],
         "octo_submit": [_P, _P, ctypes.POINTER(octo_opts), _D, _D, ctypes.POINTER(_I64)],
+        "octo_gravity_sources": [_P, _P, _D, _D, _D, _D, _D, _D, _D, _D, _D],
+        "octo_energy_update": [_P, _P, _D, _D, _D, _D],
         "octo_poll": [_P, _I64, ctypes.POINTER(_I)],
         "octo_wait": [_P, _I64, ctypes.POINTER(octo_stats)],
         "octo_host_stencil_sizes": [ctypes.c_double, ctypes.POINTER(ctypes.c_int32)],
@@ -251,6 +253,17 @@ def octo_solve_batch(ctx: int, trees: Sequence[int], opts: octo_opts, phi_ptrs: 
     return list(st) if want_stats else None
 
 
+def octo_gravity_sources(ctx: int, tree: int, omega, rho: int, s: int, phi: int, g: int, drho_dt: int,
+                         dphi_dt: int, src_s: int, src_e: int) -> None:
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    _check(load_library().octo_gravity_sources(ctx, tree, om.ctypes.data_as(_D), _dptr(rho), _dptr(s), _dptr(phi),
+                                               _dptr(g), _dptr(drho_dt), _dptr(dphi_dt), _dptr(src_s), _dptr(src_e)))
+
+
+def octo_energy_update(ctx: int, tree: int, rho: int, phi_before: int, phi_after: int, E: int) -> None:
+    _check(load_library().octo_energy_update(ctx, tree, _dptr(rho), _dptr(phi_before), _dptr(phi_after), _dptr(E)))
+
+
 def octo_submit(ctx: int, tree: int, opts: octo_opts, phi_ptr: int, g_ptr: int) -> int:
     t = _I64()
     _check(load_library().octo_submit(ctx, tree, ctypes.byref(opts), _dptr(phi_ptr), _dptr(g_ptr), ctypes.byref(t)))
@@ -382,6 +395,27 @@ class Context:
                               want_stats=stats)
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return outs, ([s.as_dict() for s in st] if st is not None else None)
+
+    def gravity_sources(self, tree: "Tree", omega, rho, s, phi, g, drho_dt=None, dphi_dt=None):
+        """Source terms (src_s (3, n), src_e (n)) from device tensors in the
+        tree's layout."""
+        torch = self.torch
+        n = tree.n_leaf_cells
+        src_s = torch.empty((3, n), dtype=torch.float64, device=self.device)
+        src_e = torch.empty(n, dtype=torch.float64, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        octo_gravity_sources(self.handle, tree.handle, omega, rho.data_ptr(), s.data_ptr(), phi.data_ptr(),
+                             g.data_ptr(), drho_dt.data_ptr() if drho_dt is not None else 0,
+                             dphi_dt.data_ptr() if dphi_dt is not None else 0, src_s.data_ptr(), src_e.data_ptr())
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return src_s, src_e
+
+    def energy_update(self, tree: "Tree", rho, phi_before, phi_after, E) -> None:
+        torch = self.torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        octo_energy_update(self.handle, tree.handle, rho.data_ptr(), phi_before.data_ptr(), phi_after.data_ptr(),
+                           E.data_ptr())
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
     def __del__(self):
         try:

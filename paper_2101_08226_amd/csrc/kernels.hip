@@ -1125,3 +1125,69 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
 }
 
 }  // namespace octo
+
+namespace octo {
+
+// ------------------------------------------------------------------ coupling
+// Gravity source terms of the hydrodynamic update (Sec. 2.3, source vector S
+// with the right-hand sides of the momentum and energy equations, Sec. 2.1):
+//   S_s = rho g + Omega x s
+//   S_E = 1/2 (phi drho/dt - rho dphi/dt) + rho Omega . (x x g)
+// for every leaf cell (x = cell centre), arrays in the caller's layout.
+__global__ __launch_bounds__(512) void k_sources(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
+                                                 const LeafItem *__restrict__ items, int n_items, double ox, double oy,
+                                                 double oz, const double *__restrict__ rho, const double *__restrict__ sv,
+                                                 const double *__restrict__ phi, const double *__restrict__ g,
+                                                 const double *__restrict__ drho, const double *__restrict__ dphi,
+                                                 double *__restrict__ src_s, double *__restrict__ src_e) {
+    const int it = blockIdx.x;
+    if (it >= n_items) return;
+    const LeafItem item = items[it];
+    const LevelDesc ld = L[item.ld];
+    const TreeDesc td = TD[ld.tree];
+    const int node = item.node;
+    const int s = threadIdx.x;
+    int x, y, z;
+    local_xyz(s, x, y, z);
+    const double h = ld.h;
+    const double cx = centre(8 * ld.coord[3 * node] + x, h), cy = centre(8 * ld.coord[3 * node + 1] + y, h),
+                 cz = centre(8 * ld.coord[3 * node + 2] + z, h);
+    const int64_t n = td.n_leaf_cells;
+    const int64_t o = ld.out_base[node] + x * td.sx + y * td.sy + z * td.sz;
+    const double r = rho[o], gx = g[o], gy = g[n + o], gz = g[2 * n + o];
+    const double sx = sv[o], sy = sv[n + o], sz = sv[2 * n + o];
+    src_s[o] = r * gx + (oy * sz - oz * sy);
+    src_s[n + o] = r * gy + (oz * sx - ox * sz);
+    src_s[2 * n + o] = r * gz + (ox * sy - oy * sx);
+    const double dr = drho ? drho[o] : 0.0, dp = dphi ? dphi[o] : 0.0;
+    // x cross g
+    const double xgx = cy * gz - cz * gy, xgy = cz * gx - cx * gz, xgz = cx * gy - cy * gx;
+    src_e[o] = 0.5 * (phi[o] * dr - r * dp) + r * (ox * xgx + oy * xgy + oz * xgz);
+}
+
+// Energy update after a potential solve (Sec. 2.3): E += 1/2 rho (phi_before - phi_after).
+__global__ __launch_bounds__(256) void k_energy_update(int64_t n, const double *__restrict__ rho,
+                                                       const double *__restrict__ before,
+                                                       const double *__restrict__ after, double *__restrict__ E) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) E[i] += 0.5 * rho[i] * (before[i] - after[i]);
+}
+
+void launch_sources(const Plan &p, const double omega[3], const double *rho, const double *s, const double *phi,
+                    const double *g, const double *drho, const double *dphi, double *src_s, double *src_e,
+                    hipStream_t st) {
+    if (!p.n_leaf) return;
+    hipLaunchKernelGGL(k_sources, dim3(p.n_leaf), dim3(512), 0, st, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf,
+                       omega[0], omega[1], omega[2], rho, s, phi, g, drho, dphi, src_s, src_e);
+    check_hip(hipGetLastError(), "sources launch");
+}
+
+void launch_energy_update(int64_t n, const double *rho, const double *before, const double *after, double *E,
+                          hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_energy_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, rho, before, after,
+                       E);
+    check_hip(hipGetLastError(), "energy update launch");
+}
+
+}  // namespace octo

@@ -585,6 +585,30 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
     });
 }
 
+octo_status octo_gravity_sources(octo_ctx *ctx, octo_tree *tree, const double *omega, const double *rho,
+                                 const double *s, const double *phi, const double *g, const double *drho_dt,
+                                 const double *dphi_dt, double *src_s, double *src_e) {
+    return guard([&] {
+        if (!ctx || !tree || !omega || !rho || !s || !phi || !g || !src_s || !src_e)
+            fail(OCTO_E_INVALID, "NULL argument");
+        if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(omega[k])) fail(OCTO_E_INVALID, "omega not finite");
+        DeviceGuard dg(ctx->device);
+        launch_sources(tree->plan, omega, rho, s, phi, g, drho_dt, dphi_dt, src_s, src_e, ctx->stream);
+    });
+}
+
+octo_status octo_energy_update(octo_ctx *ctx, octo_tree *tree, const double *rho, const double *phi_before,
+                               const double *phi_after, double *E) {
+    return guard([&] {
+        if (!ctx || !tree || !rho || !phi_before || !phi_after || !E) fail(OCTO_E_INVALID, "NULL argument");
+        if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+        DeviceGuard dg(ctx->device);
+        launch_energy_update(tree->layout.n_leaf_cells, rho, phi_before, phi_after, E, ctx->stream);
+    });
+}
+
 // Autotuner: for each level with interior nodes, time the multipole phase
 // with each candidate work shape (LDS-staged per node, or per wavefront with
 // 1..parts_alloc stencil chunks) and keep the fastest, level by level.

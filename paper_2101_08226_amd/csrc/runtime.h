@@ -129,6 +129,12 @@ struct LaunchOpts {
 
 // enqueue one full solve of a plan on stream s
 void launch_solve(const Plan &plan, const StencilDev &st, const LaunchOpts &o, hipStream_t s);
+// coupling of the solve to the hydrodynamic update (single-tree plans)
+void launch_sources(const Plan &p, const double omega[3], const double *rho, const double *s, const double *phi,
+                    const double *g, const double *drho, const double *dphi, double *src_s, double *src_e,
+                    hipStream_t st);
+void launch_energy_update(int64_t n, const double *rho, const double *before, const double *after, double *E,
+                          hipStream_t st);
 
 }  // namespace octo
 

@@ -315,3 +315,40 @@ def test_autotune_keeps_parity(ctx):
     e = errs(phi_l, g_l, p_ref, g_ref)
     assert e[0] <= TOL and e[1] <= TOL
     check_counts(st, t)
+
+
+def test_coupling_kernels(ctx):
+    """Gravity source terms and energy update on the device equal the oracle's
+    definitions (elementwise, FP64)."""
+    import torch
+
+    leaves, f = random_amr_leaves(43, max_level=3, n_stars=2)
+    tree = ctx.adaptive_tree(f, 3, 1e-4)
+    lv = tree.leaves()
+    rho_h = w.leaf_density(f, lv).ravel()
+    rng = np.random.default_rng(43)
+    n = rho_h.size
+    s_h = rng.standard_normal((3, n))
+    drho_h = rng.standard_normal(n)
+    dphi_h = rng.standard_normal(n)
+    say("coupling kernels")
+    phi, g, _ = ctx.solve(tree)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    rho, s, drho, dphi = dev(rho_h), dev(s_h), dev(drho_h), dev(dphi_h)
+    omega = np.array([0.1, 0.2, 0.9])
+    src_s, src_e = ctx.gravity_sources(tree, omega, rho, s, phi, g, drho, dphi)
+    x, _ = oracle.Tree(lv, rho_h.reshape(-1, 512)).leaf_cells()
+    ref_s, ref_e = oracle.coupling.gravity_sources(omega, x, rho_h, s_h, phi.cpu().numpy(), g.cpu().numpy(), drho_h,
+                                                   dphi_h)
+    assert np.max(np.abs(src_s.cpu().numpy() - ref_s)) <= 1e-14 * np.max(np.abs(ref_s))
+    assert np.max(np.abs(src_e.cpu().numpy() - ref_e)) <= 1e-14 * np.max(np.abs(ref_e))
+    src_s0, src_e0 = ctx.gravity_sources(tree, omega, rho, s, phi, g)  # NULL time derivatives
+    ref_s0, ref_e0 = oracle.coupling.gravity_sources(omega, x, rho_h, s_h, phi.cpu().numpy(), g.cpu().numpy())
+    assert np.max(np.abs(src_e0.cpu().numpy() - ref_e0)) <= 1e-14 * np.max(np.abs(ref_e0))
+    E = dev(rng.uniform(1, 2, n))
+    E_h = E.cpu().numpy()
+    pb = dev(-rng.uniform(1, 2, n))
+    ctx.energy_update(tree, rho, pb, phi, E)
+    ref = oracle.coupling.energy_update(E_h, rho_h, pb.cpu().numpy(), phi.cpu().numpy())
+    assert np.max(np.abs(E.cpu().numpy() - ref)) <= 1e-15 * np.max(np.abs(ref))
+    tree.destroy()

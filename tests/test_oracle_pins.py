@@ -437,3 +437,52 @@ def test_uniform_sphere_residuals_against_paper_table():
             peak = 10 ** edges[np.argmax(hist)]
             assert 1e-5 <= peak <= 1e-3
     assert means[0.35] < means[0.5]
+
+
+# --------------------------------------------------------------------------
+# coupling to the hydrodynamic update (Sec. 2.3)
+# --------------------------------------------------------------------------
+
+def test_coupling_sources_cancel_globally():
+    """With phi, dphi/dt and g from a symmetric pair sum (the direct N^2 sum),
+    the source terms integrate to zero: sum rho g = 0 (action = reaction),
+    sum (phi drho/dt - rho dphi/dt) = 0 (K_ij = K_ji), and
+    sum rho Omega.(x cross g) = Omega . (net torque) = 0 (central forces).
+    A sign error in any of the terms breaks one of these."""
+    rng = np.random.default_rng(41)
+    leaves, f = random_amr_leaves(41, max_level=2, n_stars=1)
+    rho = w.leaf_density(f, leaves).ravel()
+    drho = rng.standard_normal(rho.size) * rho
+    t = oracle.Tree(leaves, rho.reshape(-1, 512))
+    x, m = t.leaf_cells()
+    vol = m / rho
+    phi, g = oracle.direct(x, m)
+    dphi, _ = oracle.direct(x, drho * vol)
+    omega = np.array([0.3, -0.2, 1.1])
+    s = rng.standard_normal((3, rho.size))
+    S_s, S_E = oracle.coupling.gravity_sources(omega, x, rho, s, phi, g, drho, dphi)
+    S_s0, S_E0 = oracle.coupling.gravity_sources(np.zeros(3), x, rho, np.zeros_like(s), phi, g, drho, dphi)
+    scale_f = np.sum(vol * rho * np.linalg.norm(g, axis=0))
+    assert np.linalg.norm((vol * S_s0).sum(1)) < 1e-13 * scale_f
+    scale_e = np.sum(vol * (np.abs(phi * drho) + np.abs(rho * dphi)))
+    assert abs((vol * S_E0).sum()) < 1e-13 * scale_e
+    rot = (vol * (S_E - S_E0)).sum()
+    scale_r = np.linalg.norm(omega) * np.sum(vol * rho * np.linalg.norm(x, axis=0) * np.linalg.norm(g, axis=0))
+    assert abs(rot) < 1e-13 * scale_r
+    # the rotation term of the momentum source is Omega x s exactly
+    assert np.allclose(S_s - S_s0, np.cross(omega[:, None], s, axis=0), rtol=0, atol=1e-15 * np.abs(s).max())
+    # with the multipole solve the same cancellations hold to rounding (momentum and torque conserved)
+    p_f, g_f = t.solve()
+    S_sf, S_Ef = oracle.coupling.gravity_sources(omega, x, rho, np.zeros_like(s), p_f, g_f)
+    assert np.linalg.norm((vol * S_sf).sum(1)) < 1e-13 * scale_f
+    assert abs((vol * S_Ef).sum()) < 1e-13 * scale_r
+
+
+def test_energy_update_conserves_total_energy():
+    """E + 1/2 rho phi is unchanged by a potential update (Sec. 2.3)."""
+    rng = np.random.default_rng(42)
+    rho = rng.uniform(0.1, 1.0, 1000)
+    E = rng.uniform(1.0, 2.0, 1000)
+    pb, pa = -rng.uniform(1, 2, 1000), -rng.uniform(1, 2, 1000)
+    E2 = oracle.coupling.energy_update(E, rho, pb, pa)
+    assert np.allclose(E2 + 0.5 * rho * pa, E + 0.5 * rho * pb, rtol=1e-15, atol=0)
