@@ -486,3 +486,20 @@ def test_energy_update_conserves_total_energy():
     pb, pa = -rng.uniform(1, 2, 1000), -rng.uniform(1, 2, 1000)
     E2 = oracle.coupling.energy_update(E, rho, pb, pa)
     assert np.allclose(E2 + 0.5 * rho * pa, E + 0.5 * rho * pb, rtol=1e-15, atol=0)
+
+
+def test_coupling_rotation_term_is_power_of_the_torque():
+    """The rotation part of the energy source integrates to Omega . T with T the
+    gravitational torque diagnostic sum x cross rho g (Sec. 4); with the
+    correction off T != 0, which fixes the term's sign and orientation."""
+    leaves, f = random_amr_leaves(44, max_level=2, n_stars=2)
+    rho = w.leaf_density(f, leaves).ravel()
+    t = oracle.Tree(leaves, rho.reshape(-1, 512))
+    x, m = t.leaf_cells()
+    vol = m / rho
+    phi, g = t.solve(amc=False)
+    omega = np.array([0.4, -0.7, 0.2])
+    _, S_E = oracle.coupling.gravity_sources(omega, x, rho, np.zeros_like(g), phi, g)
+    T = oracle.stats(x, m, g)["T"]
+    assert np.linalg.norm(T) > 0
+    assert abs((vol * S_E).sum() - omega @ T) < 1e-12 * abs(omega @ T)
