@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision field")
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
-    ap.add_argument("--requests", type=int, default=400, help="c5: number of requests")
+    ap.add_argument("--requests", type=int, default=2000, help="c5: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="c5: arrivals per second (0: 0.8 x measured saturation)")
     ap.add_argument("--budget-gib", type=float, default=16.0, help="c5: HBM budget of the server context")
     ap.add_argument("--copy-probe", type=int, default=0,
