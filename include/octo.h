@@ -6,7 +6,7 @@
  * Momentum Correction").
  *
  * Problem solved (Sec. 2.1, Poisson equation and g = -grad phi; code units
- * with G = 1, Sec. 2.9; isolated boundaries, Sec. 2.6): every leaf cell of the
+ * with G = 1, Sec. 2.8; isolated boundaries, Sec. 2.5): every leaf cell of the
  * octree is a point mass m = rho h^3 at its centre; the library returns, for
  * each leaf cell, the potential phi and the acceleration g = -grad phi of all
  * other cells, computed by the multipole method with opening angle theta.
@@ -15,7 +15,7 @@
  * (level 0) has 8^3 cells of width 1/8; a sub-grid at level l with index
  * (ix, iy, iz) in [0, 2^l)^3 covers cells of width h = 1/(8 * 2^l) whose
  * global indices are 8*(ix, iy, iz) + [0, 8)^3; the centre of global cell i
- * is -1/2 + (i + 1/2) h (Sec. 2.4 octree, Sec. 3.2 level numbering).
+ * is -1/2 + (i + 1/2) h (Sec. 2.4 octree, Sec. 3.3 level numbering).
  *
  * Memory: "host" pointers are ordinary CPU memory, "device" pointers are HIP
  * device memory on the context's device.  The library never keeps a caller
@@ -74,7 +74,7 @@ enum { OCTO_FP64 = 0, OCTO_MIXED = 1 };
  *   dx/|x_A - x_B| < theta on geometric centres (Sec. 2.2), evaluated as
  *   (theta*theta)*|i_A - i_B|^2 > 1 on integer cell indices in IEEE double.
  *   Must lie in [0.34, 1): 0.34 is the paper's minimum for 8^3 sub-grids.
- * G: gravitational constant (1 in code units, Sec. 2.9).
+ * G: gravitational constant (1 in code units, Sec. 2.8).
  * precision: OCTO_FP64 computes everything in double precision;
  *   OCTO_MIXED evaluates the bulk of the multipole-to-local and near-field
  *   terms in single precision with single-precision partial sums, keeping the
@@ -157,7 +157,7 @@ octo_status octo_tree_build(octo_ctx *ctx, const octo_leaf *leaves, int64_t n_le
  * octo_solve use this same grid layout.  Errors as octo_tree_build. */
 octo_status octo_tree_build_uniform(octo_ctx *ctx, int level, const double *rho, int rho_on_device,
                                     octo_tree **out);
-/* Adaptive tree from a density field (Sec. 2.8, fixed-threshold form):
+/* Adaptive tree from a density field (Sec. 2.7, fixed-threshold form):
  * starting from the root, a node at level < max_level is refined when
  * boxmax over its cube exceeds `threshold`; nodes are then refined until the
  * tree is properly nested.  The density is evaluated at every leaf-cell

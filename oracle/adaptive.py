@@ -4,7 +4,7 @@ Sec. 2.4: every node of the octree carries one 8x8x8 sub-grid and is either a
 leaf or refined into 8 children, and the sub-grids are properly nested: across
 any sub-grid boundary (faces, edges and corners) the refinement level changes
 by at most one.  Refinement here follows the density criterion used for the
-binary runs (Sec. 2.8) in a fixed-threshold form: a node at level l < max_level
+binary runs (Sec. 2.7) in a fixed-threshold form: a node at level l < max_level
 is refined when the maximum density over its cube exceeds the threshold; nodes
 are then refined further until the nesting rule holds.  The balanced tree is
 the smallest one containing the density refinement, so it does not depend on

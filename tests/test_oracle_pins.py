@@ -397,7 +397,7 @@ def test_adaptive_builder_properties():
 
 @pytest.mark.slow
 def test_uniform_sphere_residuals_against_paper_table():
-    """Sec. 3.3: sphere of radius 0.25 and mass 1 on a 64^3 grid.
+    """Sec. 3.4: sphere of radius 0.25 and mass 1 on a 64^3 grid.
 
     Reading: the paper's grid voxelisation is unspecified, so the density is
     sampled at cell centres and renormalised to total mass 1.  The mean residual

@@ -6,15 +6,15 @@ potentials for closed-form checks.  It contains none of the multipole method's
 arithmetic and is shared by the HIP path, the CPU oracle, the tests and the
 benchmark.
 
-Coordinates are the unit box [-1/2, 1/2]^3 with G = 1 (paper Sec. 2.9, code
+Coordinates are the unit box [-1/2, 1/2]^3 with G = 1 (paper Sec. 2.8, code
 units).  All evaluations use only +, -, *, / and sqrt so that the same inputs
 give bit-identical densities regardless of how the points are batched.
 
 Workload shapes follow the paper's gravity tests:
   * uniform static sphere, radius 0.25, total mass 1, ambient 1e-10
-    (Sec. 3.3, "Uniform Static Sphere");
+    (Sec. 3.4, "Uniform Static Sphere");
   * n = 3/2 polytropes evaluated per cell from the Lane-Emden solution
-    (Sec. 3.4, "Stationary Star", polytropic EoS p = K rho^(1+1/n) of Sec. 2.1).
+    (Sec. 3.5, "Stationary Star", polytropic EoS p = K rho^(1+1/n) of Sec. 2.1).
 """
 from __future__ import annotations
 
@@ -176,7 +176,7 @@ class Polytropes(Field):
 @dataclass
 class UniformSphere(Field):
     """Static sphere of radius a and total mass M centred at the origin
-    (Sec. 3.3: a = 0.25, M = 1, ambient density 1e-10)."""
+    (Sec. 3.4: a = 0.25, M = 1, ambient density 1e-10)."""
 
     radius: float = 0.25
     total_mass: float = 1.0
