@@ -45,6 +45,9 @@ def lib():
         L.orc_solve.restype = ctypes.c_int
         L.orc_solve.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _D, _I64,
                                 ctypes.c_int64, ctypes.c_int, _D, _D]
+        L.orc_solve_source.restype = ctypes.c_int
+        L.orc_solve_source.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _D, _D, _I64,
+                                       ctypes.c_int64, ctypes.c_int, _D]
         L.orc_cell_moments.restype = ctypes.c_int
         L.orc_cell_moments.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D]
         L.orc_leaf_cells.argtypes = [_P, _D, _D]
@@ -122,6 +125,28 @@ class Tree:
             raise RuntimeError(f"orc_solve failed ({rc})")
         return phi, g
 
+    def solve_source(self, src, theta=0.5, G=1.0, kernel=None, sample=None, threads=0):
+        """Potential of a second, signed source `src` (same layout as the
+        density, e.g. a density rate) expanded about the density's centres of
+        mass with the density's interaction lists; returns it at every leaf
+        cell or at the sampled ids.  No correction (it acts on forces)."""
+        mode, coef = _kernel(kernel)
+        src = np.ascontiguousarray(np.asarray(src, dtype=np.float64).reshape(-1, 512))
+        assert src.shape == self.rho.shape
+        if sample is None:
+            n = self.n_cells
+            sp, ns = ctypes.cast(None, _I64), 0
+        else:
+            sample = np.ascontiguousarray(sample, dtype=np.int64)
+            n = sample.shape[0]
+            sp, ns = sample.ctypes.data_as(_I64), n
+        phi = np.empty(n)
+        rc = lib().orc_solve_source(self._h, float(theta), float(G), mode, _dp(coef), _dp(src), sp, ns, int(threads),
+                                    _dp(phi))
+        if rc != 0:
+            raise RuntimeError(f"orc_solve_source failed ({rc})")
+        return phi
+
     def last_counts(self, split=False):
         """(multipole pairs, direct pairs) of the last solve, ordered pairs;
         with split=True also the multipole pairs between two leaf cells."""
@@ -130,10 +155,10 @@ class Tree:
         return (int(out[0]), int(out[1]), int(out[2])) if split else (int(out[0]), int(out[1]))
 
     def cell_moments(self, level, gx, gy, gz):
-        out = np.empty(40)
+        out = np.empty(43)
         if lib().orc_cell_moments(self._h, level, gx, gy, gz, _dp(out)) != 0:
             raise KeyError((level, gx, gy, gz))
-        return dict(m=out[0], z=out[1:4].copy(), M2=out[4:13].reshape(3, 3).copy(),
+        return dict(m=out[0], z=out[1:4].copy(), M1=out[40:43].copy(), M2=out[4:13].reshape(3, 3).copy(),
                     M3=out[13:40].reshape(3, 3, 3).copy())
 
     def leaf_cells(self):

@@ -28,7 +28,12 @@
  *     removes the pair torque while keeping the pair forces equal and
  *     opposite;
  *   - downward pass: the expansion of each child is derived from its parent's
- *     (Sec. 2.2); leaves evaluate phi and g = -grad phi (Sec. 2.1).
+ *     (Sec. 2.2); leaves evaluate phi and g = -grad phi (Sec. 2.1);
+ *   - the time derivative of the potential (Sec. 2.1: the energy equation's
+ *     gravity source uses it, computed by the same FMM with the density rate
+ *     as source): a second, signed source is expanded about the density's
+ *     centres of mass (so it has a dipole) and goes through the same
+ *     interaction lists; orc_solve_source.
  *
  * Readings where the paper is silent are listed in the design notes; the ones
  * this file relies on: expansion order p = 3; expansion centres are centres of
@@ -52,6 +57,9 @@
 
 typedef struct {
     double m, z[3];
+    double M1[3]; /* dipole about z: zero for the density (z is its centre of
+                     mass), nonzero for a second source expanded about the
+                     density's centres */
     double M2[3][3];
     double M3[3][3][3];
     double L0, L1[3], L2[3][3], L3[3][3][3], C[3];
@@ -424,46 +432,87 @@ static void p2m(otree *t, cref a) {
     double h = cell_width(n->level);
     c->m = n->rho[a.loc] * h * h * h;
     for (int d = 0; d < 3; ++d) c->z[d] = centre(n->level, g[d]);
+    memset(c->M1, 0, sizeof c->M1);
     memset(c->M2, 0, sizeof c->M2);
     memset(c->M3, 0, sizeof c->M3);
 }
 
+/* Raw moments (orders 0-3) of the children's multipoles about the point z:
+ * each child's moments about its own centre z_c are shifted by s = z_c - z
+ * (binomial expansion of (x - z)^n = ((x - z_c) + s)^n). */
+static void compose(const ocell *const ch[8], const double z[3], ocell *p) {
+    p->m = 0.0;
+    memset(p->M1, 0, sizeof p->M1);
+    memset(p->M2, 0, sizeof p->M2);
+    memset(p->M3, 0, sizeof p->M3);
+    for (int k = 0; k < 8; ++k) {
+        const ocell *c = ch[k];
+        double s[3];
+        for (int d = 0; d < 3; ++d) s[d] = c->z[d] - z[d];
+        p->m += c->m;
+        for (int i = 0; i < 3; ++i) {
+            p->M1[i] += c->M1[i] + c->m * s[i];
+            for (int j = 0; j < 3; ++j) {
+                p->M2[i][j] += c->M2[i][j] + c->M1[i] * s[j] + c->M1[j] * s[i] + c->m * s[i] * s[j];
+                for (int l = 0; l < 3; ++l)
+                    p->M3[i][j][l] += c->M3[i][j][l] + c->M2[i][j] * s[l] + c->M2[i][l] * s[j] + c->M2[j][l] * s[i] +
+                                      c->M1[i] * s[j] * s[l] + c->M1[j] * s[i] * s[l] + c->M1[l] * s[i] * s[j] +
+                                      c->m * s[i] * s[j] * s[l];
+            }
+        }
+    }
+}
+
 /* Compose a cell's multipole from its 8 children: total mass, centre of mass,
- * and raw second and third moments about that centre (parallel-axis shifts of
- * the children's moments; the children's dipoles about their own centres of
- * mass vanish). */
+ * and raw second and third moments about that centre (the children's dipoles
+ * about their own centres of mass vanish, and so does the parent's about its
+ * own: it is set to zero rather than left at its rounding residue). */
 static void m2m(otree *t, cref a) {
     cref ch[8];
     children(t, a, ch);
     ocell *p = C(t, a);
+    const ocell *cc[8];
     double m = 0.0, mz[3] = {0, 0, 0};
     for (int k = 0; k < 8; ++k) {
-        const ocell *c = C(t, ch[k]);
-        m += c->m;
-        for (int d = 0; d < 3; ++d) mz[d] += c->m * c->z[d];
+        cc[k] = C(t, ch[k]);
+        m += cc[k]->m;
+        for (int d = 0; d < 3; ++d) mz[d] += cc[k]->m * cc[k]->z[d];
     }
-    p->m = m;
+    double z[3];
     if (m > 0.0) {
-        for (int d = 0; d < 3; ++d) p->z[d] = mz[d] / m;
+        for (int d = 0; d < 3; ++d) z[d] = mz[d] / m;
     } else {
         int g[3];
         gidx(t, a, g);
-        for (int d = 0; d < 3; ++d) p->z[d] = centre(t->nodes[a.node].level, g[d]);
+        for (int d = 0; d < 3; ++d) z[d] = centre(t->nodes[a.node].level, g[d]);
     }
-    memset(p->M2, 0, sizeof p->M2);
-    memset(p->M3, 0, sizeof p->M3);
-    for (int k = 0; k < 8; ++k) {
-        const ocell *c = C(t, ch[k]);
-        double s[3];
-        for (int d = 0; d < 3; ++d) s[d] = c->z[d] - p->z[d];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                p->M2[i][j] += c->M2[i][j] + c->m * s[i] * s[j];
-                for (int l = 0; l < 3; ++l)
-                    p->M3[i][j][l] += c->M3[i][j][l] + c->M2[i][j] * s[l] + c->M2[i][l] * s[j] + c->M2[j][l] * s[i] +
-                                      c->m * s[i] * s[j] * s[l];
-            }
-    }
+    compose(cc, z, p);
+    for (int d = 0; d < 3; ++d) p->z[d] = z[d];
+    memset(p->M1, 0, sizeof p->M1);
+}
+
+/* Second source (a density rate): leaf cells are point sources s h^3 at
+ * their centres (which are also the density's centres of mass). */
+static void p2m_src(otree *t, cref a, const double *src) {
+    const onode *n = &t->nodes[a.node];
+    ocell *c = C(t, a);
+    double h = cell_width(n->level);
+    c->m = src[(size_t)n->out * 512 + a.loc] * h * h * h;
+    memset(c->M1, 0, sizeof c->M1);
+    memset(c->M2, 0, sizeof c->M2);
+    memset(c->M3, 0, sizeof c->M3);
+}
+
+/* Second source, interior cells: moments of orders 0-3 about the density's
+ * centre of mass z (already in the cell), dipole included. */
+static void m2m_src(otree *t, cref a) {
+    cref ch[8];
+    children(t, a, ch);
+    ocell *p = C(t, a);
+    const ocell *cc[8];
+    for (int k = 0; k < 8; ++k) cc[k] = C(t, ch[k]);
+    double z[3] = {p->z[0], p->z[1], p->z[2]};
+    compose(cc, z, p);
 }
 
 /* Multipole-to-local: the Taylor expansion about z_A of the potential of
@@ -476,20 +525,27 @@ static void m2l_cells(const ocell *A, const ocell *B, const oparams *p, double *
     dtens D;
     dtensors(p, R, &D);
     const double G = p->G;
-    double q2 = 0.0, q3 = 0.0;
-    for (int a = 0; a < 3; ++a)
+    /* L^(n) = -G sum_{k <= 3-n} ((-1)^k / k!) M^(k)_B : D^(n+k) */
+    double q1 = 0.0, q2 = 0.0, q3 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        q1 += B->M1[a] * D.d1[a];
         for (int b = 0; b < 3; ++b) {
             q2 += B->M2[a][b] * D.d2[a][b];
             for (int c = 0; c < 3; ++c) q3 += B->M3[a][b][c] * D.d3[a][b][c];
         }
-    *L0 += -G * (B->m * D.d0 + 0.5 * q2 - q3 / 6.0);
+    }
+    *L0 += -G * (B->m * D.d0 - q1 + 0.5 * q2 - q3 / 6.0);
     for (int a = 0; a < 3; ++a) {
-        double s = 0.0;
-        for (int b = 0; b < 3; ++b)
-            for (int c = 0; c < 3; ++c) s += B->M2[b][c] * D.d3[a][b][c];
-        L1[a] += -G * (B->m * D.d1[a] + 0.5 * s);
+        double s1 = 0.0, s = 0.0;
         for (int b = 0; b < 3; ++b) {
-            L2[a][b] += -G * B->m * D.d2[a][b];
+            s1 += B->M1[b] * D.d2[a][b];
+            for (int c = 0; c < 3; ++c) s += B->M2[b][c] * D.d3[a][b][c];
+        }
+        L1[a] += -G * (B->m * D.d1[a] - s1 + 0.5 * s);
+        for (int b = 0; b < 3; ++b) {
+            double s2 = 0.0;
+            for (int c = 0; c < 3; ++c) s2 += B->M1[c] * D.d3[a][b][c];
+            L2[a][b] += -G * (B->m * D.d2[a][b] - s2);
             for (int c = 0; c < 3; ++c) L3[a][b][c] += -G * B->m * D.d3[a][b][c];
         }
     }
@@ -639,11 +695,9 @@ static void mark_up(otree *t, int node, int loc) {
  * interaction recursion to targets on their ancestor chains.
  * phi: n_out, g: 3 x n_out (SoA), where n_out = nleaves*512 (full) or nsample.
  * Returns 0 on success. */
-int orc_solve(otree *t, double theta, double G, int amc, int mode, const double *coef, const int64_t *sample,
-              int64_t nsample, int nthreads, double *phi, double *g) {
-    if (!t || t->err[0]) return 1;
-    oparams p;
-    init_params(&p, theta, G, amc, mode, coef);
+static int solve_impl(otree *t, const oparams *pp, const double *src, const int64_t *sample, int64_t nsample,
+                      int nthreads, double *phi, double *g) {
+    oparams p = *pp;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -694,6 +748,21 @@ int orc_solve(otree *t, double theta, double G, int amc, int mode, const double 
             for (int i = 0; i < 512; ++i) m2m(t, (cref){id, i});
         }
     }
+    /* a second source: its moments about the density's expansion centres */
+    if (src) {
+#pragma omp parallel for schedule(static)
+        for (int id = 0; id < t->nnodes; ++id)
+            if (t->nodes[id].leaf)
+                for (int i = 0; i < 512; ++i) p2m_src(t, (cref){id, i}, src);
+        for (int l = t->nlev - 2; l >= 0; --l) {
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < cnt[l]; ++k) {
+                int id = lev[l][k];
+                if (t->nodes[id].leaf) continue;
+                for (int i = 0; i < 512; ++i) m2m_src(t, (cref){id, i});
+            }
+        }
+    }
     /* interactions: all ordered pairs of distinct root cells are candidates */
     int root = lut_get(t, 0, 0, 0, 0);
     ocount *counts = (ocount *)calloc(512, sizeof(ocount));
@@ -735,7 +804,8 @@ int orc_solve(otree *t, double theta, double G, int amc, int mode, const double 
         int64_t gid = sample ? sample[s] : s;
         const ocell *c = &t->nodes[t->leaf_node[gid / 512]].cell[gid % 512];
         phi[s] = c->L0;
-        for (int d = 0; d < 3; ++d) g[d * nout + s] = -c->L1[d] + c->C[d];
+        if (g)
+            for (int d = 0; d < 3; ++d) g[d * nout + s] = -c->L1[d] + c->C[d];
     }
     for (int l = 0; l < OMAXLEV; ++l) free(lev[l]);
     free(lev);
@@ -743,8 +813,34 @@ int orc_solve(otree *t, double theta, double G, int amc, int mode, const double 
     return 0;
 }
 
+int orc_solve(otree *t, double theta, double G, int amc, int mode, const double *coef, const int64_t *sample,
+              int64_t nsample, int nthreads, double *phi, double *g) {
+    if (!t || t->err[0]) return 1;
+    oparams p;
+    init_params(&p, theta, G, amc, mode, coef);
+    return solve_impl(t, &p, NULL, sample, nsample, nthreads, phi, g);
+}
+
+/* The potential of a second, signed source s (a density rate, per leaf cell in
+ * the same layout as the density) with the density's tree, interaction lists
+ * and expansion centres: the FMM applied to the time derivative of the density
+ * gives the time derivative of the potential (Sec. 2.1, the energy equation's
+ * source term).  With the same centres the discrete operator is the same
+ * symmetric matrix as for the density, so sum_i (phi_i s_i - rho_i dphi_i) h_i^3
+ * vanishes up to rounding.  Only the potential is returned; the correction
+ * (which acts on forces) is not applied.  The tree's moments afterwards are
+ * those of s. */
+int orc_solve_source(otree *t, double theta, double G, int mode, const double *coef, const double *src,
+                     const int64_t *sample, int64_t nsample, int nthreads, double *phi) {
+    if (!t || t->err[0] || !src) return 1;
+    oparams p;
+    init_params(&p, theta, G, 0, mode, coef);
+    return solve_impl(t, &p, src, sample, nsample, nthreads, phi, NULL);
+}
+
 /* Moments of cell (level, global index) after the last solve:
- * out[0] = m, out[1..3] = z, out[4..12] = M2 (row-major), out[13..39] = M3. */
+ * out[0] = m, out[1..3] = z, out[4..12] = M2 (row-major), out[13..39] = M3,
+ * out[40..42] = M1. */
 int orc_cell_moments(const otree *t, int level, int gx, int gy, int gz, double *out) {
     int id = lut_get(t, level, gx >> 3, gy >> 3, gz >> 3);
     if (id < 0) return 1;
@@ -753,6 +849,7 @@ int orc_cell_moments(const otree *t, int level, int gx, int gy, int gz, double *
     for (int d = 0; d < 3; ++d) out[1 + d] = c->z[d];
     memcpy(out + 4, c->M2, 9 * sizeof(double));
     memcpy(out + 13, c->M3, 27 * sizeof(double));
+    memcpy(out + 40, c->M1, 3 * sizeof(double));
     return 0;
 }
 

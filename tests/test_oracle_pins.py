@@ -505,3 +505,76 @@ def test_coupling_rotation_term_is_power_of_the_torque():
     tol = 1e-13 * np.linalg.norm(omega) * st["ST"]  # rounding of two sums with heavy cancellation
     assert abs(omega @ T) > 1e4 * tol  # the uncorrected torque is resolved
     assert abs((vol * S_E).sum() - omega @ T) < tol
+
+
+# --------------------------------------------------------------------------
+# time derivative of the potential (Sec. 2.1: the FMM applied to the density
+# rate, expanded about the density's centres of mass)
+# --------------------------------------------------------------------------
+
+def _source_case(seed, max_level=2, n_stars=2):
+    leaves, f = random_amr_leaves(seed, max_level=max_level, n_stars=n_stars)
+    rng = np.random.default_rng(seed)
+    rho = w.leaf_density(f, leaves) + 1e-3 * rng.uniform(size=(len(leaves), 512))
+    src = rng.standard_normal(rho.shape) * rho  # a signed density rate
+    return leaves, rho, src
+
+
+def test_source_solve_cubic_kernel_is_exact():
+    """For a cubic kernel a third-order expansion of the signed source about
+    the density's centres (where its dipole does not vanish) is exact, so the
+    result equals brute force; a dropped or mis-signed dipole term in the
+    upward shift or in the multipole-to-local step fails this."""
+    leaves, rho, src = _source_case(51)
+    t = oracle.Tree(leaves, rho)
+    rng = np.random.default_rng(51)
+    coef = rng.standard_normal(20)
+    x, m = t.leaf_cells()
+    vol = m / rho.ravel()
+    for theta in (0.5, 0.34):
+        dphi = t.solve_source(src, theta=theta, kernel=coef)
+        pr, _ = poly_direct(coef, x, src.ravel() * vol)
+        assert np.max(np.abs(dphi - pr)) / np.max(np.abs(pr)) < 1e-11
+    # the expansion centres are the density's: interior cells carry a dipole
+    dip = [t.cell_moments(0, i, j, k) for i in range(8) for j in range(8) for k in range(8)]
+    m_max = max(abs(mo["m"]) for mo in dip)
+    assert max(np.linalg.norm(mo["M1"]) for mo in dip) > 1e-3 * m_max / 8
+
+
+def test_source_solve_energy_terms_cancel():
+    """sum_i (phi_i mdot_i - m_i dphi_i) = 0: the density and its rate go
+    through the same symmetric discrete operator (Sec. 2.1), although each
+    solve differs from the exact N^2 sum at truncation level."""
+    leaves, rho, src = _source_case(52)
+    t = oracle.Tree(leaves, rho)
+    x, m = t.leaf_cells()
+    md = src.ravel() * (m / rho.ravel())
+    for theta in (0.5, 0.34):
+        phi, _ = t.solve(theta=theta)
+        dphi = t.solve_source(src, theta=theta)
+        scale = np.sum(np.abs(phi * md)) + np.sum(np.abs(m * dphi))
+        assert abs(np.dot(phi, md) - np.dot(m, dphi)) < 1e-14 * scale
+        dd, _ = oracle.direct(x, md)
+        trunc = np.max(np.abs(dphi - dd)) / np.max(np.abs(dd))
+        assert 1e-9 < trunc < 1e-2  # not a direct sum in disguise
+
+
+def test_source_solve_special_cases():
+    """src = rho gives phi; the constant kernel counts every pair once; a
+    power-of-two scaling is exact; a sampled solve equals the full one."""
+    leaves, rho, src = _source_case(53, n_stars=1)
+    t = oracle.Tree(leaves, rho)
+    phi, _ = t.solve()
+    same = t.solve_source(rho)
+    assert np.max(np.abs(same - phi)) < 1e-13 * np.max(np.abs(phi))
+    coef = np.zeros(20)
+    coef[0] = 1.0
+    x, m = t.leaf_cells()
+    md = src.ravel() * (m / rho.ravel())
+    for theta in (0.5, 0.9):
+        c = t.solve_source(src, theta=theta, kernel=coef)
+        assert np.max(np.abs(c + (md.sum() - md))) < 1e-12 * np.abs(md).sum()
+    d1 = t.solve_source(src)
+    assert np.array_equal(t.solve_source(4.0 * src), 4.0 * d1)
+    sample = np.random.default_rng(5).choice(d1.size, 300, replace=False)
+    assert np.array_equal(t.solve_source(src, sample=sample), d1[sample])
