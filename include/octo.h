@@ -210,6 +210,27 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
 octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, const octo_opts *opts,
                              double *const *phi, double *const *g, int out_on_device, octo_stats *stats);
 
+/* ---- time derivative of the potential ----------------------------------- */
+
+/* dphi/dt from the density rate drho/dt (Sec. 2.1: the energy equation's
+ * gravity source 1/2 (phi drho/dt - rho dphi/dt) is evaluated with dphi/dt
+ * from the same multipole method, the density rate taking the place of the
+ * density).  The rate is expanded about the centres of mass of the tree's
+ * current density (so its cells carry a dipole) and goes through the same
+ * interaction lists; the discrete operator is then the one octo_solve
+ * applies to the density, which is symmetric, so for phi from octo_solve
+ * with the same options sum_i (phi_i drho_i - rho_i dphi_i) h_i^3 vanishes up
+ * to rounding.
+ * drho_dt: device, n doubles in the tree's density layout (n = leaf cells),
+ * any sign; dphi_dt: device output, same layout.  opts->theta, G and
+ * precision apply; opts->amc is ignored (the correction acts on forces).
+ * The call recomputes the density's moments, so it may come before or after
+ * octo_solve; it uses the tree's scratch, so calls on one tree are ordered by
+ * the context stream.  Stream-ordered (returns once enqueued).
+ * Errors: OCTO_E_INVALID (NULL pointer, bad options), OCTO_E_STATE. */
+octo_status octo_solve_dphidt(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, const double *drho_dt,
+                              double *dphi_dt);
+
 /* ---- coupling to the hydrodynamic update -------------------------------- */
 
 /* Gravity source terms of the hydrodynamic update (Sec. 2.3, source vector S,

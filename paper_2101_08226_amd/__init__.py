@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "OCTO_OK", 1: "OCTO_E_INVALID", 2: "OCTO_E_DEVICE", 3: "OCTO_
 EXPORTS = [
     "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_tree_build", "octo_tree_build_uniform",
     "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
-    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_gravity_sources", "octo_energy_update", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
+    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
     "octo_host_stencil_sizes", "octo_host_layout", "octo_host_adaptive_leaves",
 ]
 
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_solve_batch": [_P, _PP, ctypes.c_int32, ctypes.POINTER(octo_opts), ctypes.POINTER(_D),
                              ctypes.POINTER(_D), _I, ctypes.POINTER(octo_stats)],
         "octo_submit": [_P, _P, ctypes.POINTER(octo_opts), _D, _D, ctypes.POINTER(_I64)],
+        "octo_solve_dphidt": [_P, _P, ctypes.POINTER(octo_opts), _D, _D],
         "octo_gravity_sources": [_P, _P, _D, _D, _D, _D, _D, _D, _D, _D, _D],
         "octo_energy_update": [_P, _P, _D, _D, _D, _D],
         "octo_poll": [_P, _I64, ctypes.POINTER(_I)],
@@ -251,6 +252,10 @@ def octo_solve_batch(ctx: int, trees: Sequence[int], opts: octo_opts, phi_ptrs: 
     _check(load_library().octo_solve_batch(ctx, tr, n, ctypes.byref(opts), ph, gg, int(out_on_device),
                                            st if want_stats else None))
     return list(st) if want_stats else None
+
+
+def octo_solve_dphidt(ctx: int, tree: int, opts: octo_opts, drho_dt: int, dphi_dt: int) -> None:
+    _check(load_library().octo_solve_dphidt(ctx, tree, ctypes.byref(opts), _dptr(drho_dt), _dptr(dphi_dt)))
 
 
 def octo_gravity_sources(ctx: int, tree: int, omega, rho: int, s: int, phi: int, g: int, drho_dt: int,
@@ -395,6 +400,19 @@ class Context:
                               want_stats=stats)
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return outs, ([s.as_dict() for s in st] if st is not None else None)
+
+    def solve_dphidt(self, tree: "Tree", drho_dt, theta=0.5, precision=OCTO_FP64, G=1.0, out=None):
+        """dphi/dt (n,) on the device from the density rate drho_dt (a float64
+        device tensor in the tree's density layout)."""
+        torch = self.torch
+        n = tree.n_leaf_cells
+        assert drho_dt.dtype == torch.float64 and drho_dt.is_contiguous() and drho_dt.numel() == n
+        dphi = torch.empty(n, dtype=torch.float64, device=self.device) if out is None else out
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        octo_solve_dphidt(self.handle, tree.handle, make_opts(theta, G, precision, False), drho_dt.data_ptr(),
+                          dphi.data_ptr())
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return dphi
 
     def gravity_sources(self, tree: "Tree", omega, rho, s, phi, g, drho_dt=None, dphi_dt=None):
         """Source terms (src_s (3, n), src_e (n)) from device tensors in the

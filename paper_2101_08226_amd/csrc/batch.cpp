@@ -29,7 +29,7 @@ void drop_graphs(std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs) {
 }
 
 void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs,
-              const std::vector<TreeDesc> &want, const octo_opts *o, bool count) {
+              const std::vector<TreeDesc> &want, const octo_opts *o, bool count, bool source) {
     // tree descriptors (outputs, G, correction switch) live in device memory
     // and are refreshed only when they change
     for (int i = 0; i < plan.n_trees; ++i) {
@@ -43,6 +43,7 @@ void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipG
     LaunchOpts lo;
     lo.precision = o->precision;
     lo.count = count;
+    lo.source = source;
     lo.fork = ctx->fork_ev;
     lo.join = ctx->join_ev;
     lo.fork_near = ctx->fork_near_ev;
@@ -61,7 +62,8 @@ void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipG
     }
     lo.aux = ctx->capture_aux;
     lo.aux_near = ctx->capture_near;
-    const auto key = std::make_pair(theta_bits(o->theta), (int)o->precision * 2 + (count ? 1 : 0));
+    const auto key =
+        std::make_pair(theta_bits(o->theta), (int)o->precision * 4 + (source ? 2 : 0) + (count ? 1 : 0));
     auto it = graphs.find(key);
     if (it == graphs.end()) {
         hipGraph_t g = nullptr;

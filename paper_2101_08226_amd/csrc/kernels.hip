@@ -85,7 +85,10 @@ __device__ inline void t3_trace(const double *T, double &tx, double &ty, double 
 
 // ------------------------------------------------------------------ P2M
 // Leaf cells become point masses m = rho h^3 at their centres; record leaves
-// also get their (trivial) multipole record.
+// also get their (trivial) multipole record.  SRC: the second source (a
+// density rate) instead of the density; its leaf cells are point sources at
+// the same centres, with zero dipole.
+template <bool SRC>
 __global__ __launch_bounds__(256) void k_p2m(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ T,
                                              const NodeItem *__restrict__ items, int n_items) {
     const int it = blockIdx.x >> 1;
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(256) void k_p2m(const LevelDesc *__restrict__ L, co
     local_xyz(s, x, y, z);
     const double h = ld.h;
     const int64_t off = ld.out_base[node] + x * td.sx + y * td.sy + z * td.sz;
-    const double m = td.rho[off] * (h * h * h);
+    const double m = (SRC ? td.src : td.rho)[off] * (h * h * h);
     const size_t ci = (size_t)node * kCells + s;
     ld.mass[ci] = m;
     if (node < ld.n_rec) {
@@ -108,6 +111,8 @@ __global__ __launch_bounds__(256) void k_p2m(const LevelDesc *__restrict__ L, co
         ld.mp[S + ci] = centre(8 * ld.coord[3 * node + 1] + y, h);
         ld.mp[2 * S + ci] = centre(8 * ld.coord[3 * node + 2] + z, h);
         for (int c = 3; c < kRec; ++c) ld.mp[c * S + ci] = 0.0;
+        if (SRC)
+            for (int c = 0; c < 3; ++c) ld.dip[c * S + ci] = 0.0;
     }
 }
 
@@ -217,6 +222,86 @@ __global__ __launch_bounds__(256) void k_m2m(const LevelDesc *__restrict__ L, co
     for (int k = 0; k < 10; ++k) ld.mp[(9 + k) * PS + pi] = O[k];
 }
 
+// Second source: moments of orders 0-3 of the children's second-source
+// multipoles about the parent's density centre of mass (written by k_m2m),
+// where the dipole does not vanish: with s = z_c - Z,
+//   M1 += d + m s,  M2_ab += q_ab + d_a s_b + d_b s_a + m s_a s_b,
+//   M3_abc += o_abc + (q_ab s_c + q_ac s_b + q_bc s_a)
+//            + (d_a s_b s_c + d_b s_a s_c + d_c s_a s_b) + m s_a s_b s_c.
+__global__ __launch_bounds__(256) void k_m2m_src(const LevelDesc *__restrict__ L, const NodeItem *__restrict__ items,
+                                                 int n_items) {
+    const int it = blockIdx.x >> 1;
+    if (it >= n_items) return;
+    const NodeItem item = items[it];
+    const LevelDesc ld = L[item.ld];
+    const LevelDesc cl = L[ld.child_ld];
+    const int node = item.node;
+    const int s = ((blockIdx.x & 1) << 8) | threadIdx.x;
+    int x, y, z;
+    local_xyz(s, x, y, z);
+    const size_t CS = (size_t)cl.n_rec * kCells;
+    const size_t pi = (size_t)node * kCells + s;
+    const size_t PS = (size_t)ld.n_rec * kCells;
+    const double Zx = ld.mp[pi], Zy = ld.mp[PS + pi], Zz = ld.mp[2 * PS + pi];
+    double m = 0.0, D[3] = {0, 0, 0};
+    double Q[6] = {0, 0, 0, 0, 0, 0};
+    double O[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+    for (int c = 0; c < 8; ++c) {
+        const int cx = 2 * x + (c >> 2), cy = 2 * y + ((c >> 1) & 1), cz = 2 * z + (c & 1);
+        const int cn = ld.child[node * 8 + ((cx >> 3) << 2) + ((cy >> 3) << 1) + (cz >> 3)];
+        const size_t ci = (size_t)cn * kCells + store_idx(cx & 7, cy & 7, cz & 7);
+        const double cm = cl.mass[ci];
+        double zx, zy, zz;
+        double d[3] = {0, 0, 0}, q[6] = {0, 0, 0, 0, 0, 0}, o[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (cn < cl.n_rec) {
+            zx = cl.mp[ci];
+            zy = cl.mp[CS + ci];
+            zz = cl.mp[2 * CS + ci];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) d[k] = cl.dip[k * CS + ci];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) q[k] = cl.mp[(3 + k) * CS + ci];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) o[k] = cl.mp[(9 + k) * CS + ci];
+        } else {
+            zx = centre(8 * cl.coord[3 * cn] + (cx & 7), cl.h);
+            zy = centre(8 * cl.coord[3 * cn + 1] + (cy & 7), cl.h);
+            zz = centre(8 * cl.coord[3 * cn + 2] + (cz & 7), cl.h);
+        }
+        const double sx = zx - Zx, sy = zy - Zy, sz = zz - Zz;
+        m += cm;
+        D[0] += d[0] + cm * sx;
+        D[1] += d[1] + cm * sy;
+        D[2] += d[2] + cm * sz;
+        // q packed: xx0 xy1 xz2 yy3 yz4 zz5
+        Q[0] += q[0] + 2.0 * d[0] * sx + cm * sx * sx;
+        Q[1] += q[1] + d[0] * sy + d[1] * sx + cm * sx * sy;
+        Q[2] += q[2] + d[0] * sz + d[2] * sx + cm * sx * sz;
+        Q[3] += q[3] + 2.0 * d[1] * sy + cm * sy * sy;
+        Q[4] += q[4] + d[1] * sz + d[2] * sy + cm * sy * sz;
+        Q[5] += q[5] + 2.0 * d[2] * sz + cm * sz * sz;
+        O[0] += o[0] + 3.0 * q[0] * sx + 3.0 * d[0] * sx * sx + cm * sx * sx * sx;                          // xxx
+        O[1] += o[1] + q[0] * sy + 2.0 * q[1] * sx + d[1] * sx * sx + 2.0 * d[0] * sx * sy + cm * sx * sx * sy;  // xxy
+        O[2] += o[2] + q[0] * sz + 2.0 * q[2] * sx + d[2] * sx * sx + 2.0 * d[0] * sx * sz + cm * sx * sx * sz;  // xxz
+        O[3] += o[3] + q[3] * sx + 2.0 * q[1] * sy + d[0] * sy * sy + 2.0 * d[1] * sx * sy + cm * sx * sy * sy;  // xyy
+        O[4] += o[4] + q[1] * sz + q[2] * sy + q[4] * sx + d[0] * sy * sz + d[1] * sx * sz + d[2] * sx * sy +
+                cm * sx * sy * sz;                                                                           // xyz
+        O[5] += o[5] + q[5] * sx + 2.0 * q[2] * sz + d[0] * sz * sz + 2.0 * d[2] * sx * sz + cm * sx * sz * sz;  // xzz
+        O[6] += o[6] + 3.0 * q[3] * sy + 3.0 * d[1] * sy * sy + cm * sy * sy * sy;                          // yyy
+        O[7] += o[7] + q[3] * sz + 2.0 * q[4] * sy + d[2] * sy * sy + 2.0 * d[1] * sy * sz + cm * sy * sy * sz;  // yyz
+        O[8] += o[8] + q[5] * sy + 2.0 * q[4] * sz + d[1] * sz * sz + 2.0 * d[2] * sy * sz + cm * sy * sz * sz;  // yzz
+        O[9] += o[9] + 3.0 * q[5] * sz + 3.0 * d[2] * sz * sz + cm * sz * sz * sz;                          // zzz
+    }
+    ld.mass[pi] = m;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ld.dip[k * PS + pi] = D[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ld.mp[(3 + k) * PS + pi] = Q[k];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) ld.mp[(9 + k) * PS + pi] = O[k];
+}
+
 // ------------------------------------------------------------------ M2L
 // Multipole-to-local of one ordered pair A <- B (R = z_A - z_B), truncated
 // at total order 3 (L^(n) takes source moments of order <= 3 - n), with the
@@ -273,9 +358,13 @@ __device__ inline void finish_l2_l3(Acc<T> &a) {
 // T = double: everything in FP64.  T = float (mixed precision): the L0..L3
 // contractions run in FP32 with FP32 partial sums; R, the radial factors and
 // the correction stay FP64.
-template <bool LEAF_TARGET, typename T>
+// DIP: the source also has a dipole d (second source expanded about the
+// density's centres): L0 += d.D1, L1_a += d_b D2_ab, L2_ab += d_c D3_abc,
+// i.e. with w = d.R: L0 += f1 w; L1_a += f2 w R_a + f1 d_a;
+// L2_ab += f3 w R_a R_b + f2 (w d_ab + R_a d_b + R_b d_a).
+template <bool LEAF_TARGET, bool DIP, typename T>
 __device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, const double *Q64, const double *O64,
-                                double mu, const double *OA, bool amc, Acc<T> &a) {
+                                const double *D64, double mu, const double *OA, bool amc, Acc<T> &a) {
     const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
     const double d0 = rsqrt(r2);
     const double ir2 = d0 * d0;
@@ -305,23 +394,48 @@ __device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, co
         const T ORz = O[2] * xx + O[7] * yy + O[9] * zz + two * (O[4] * xy + O[5] * xz + O[8] * yz);
         const T ORRR = rx * ORx + ry * ORy + rz * ORz;
         const T tOR = (O[0] + O[3] + O[5]) * rx + (O[1] + O[6] + O[8]) * ry + (O[2] + O[7] + O[9]) * rz;
-        // L0 = -[m f0 + 1/2 (f2 RQR + f1 trQ) - 1/6 (f3 ORRR + 3 f2 tOR)]
-        a.L0 -= mB * f0 + half * (f2 * RQR + f1 * trQ) - (f3 * ORRR + three * f2 * tOR) * sixth;
-        // L1_a = -[m f1 R_a + 1/2 (f3 R_a RQR + f2 (2 QR_a + R_a trQ))]
-        const T c1 = mB * f1 + half * (f3 * RQR + f2 * trQ);
-        a.L1[0] -= c1 * rx + f2 * QRx;
-        a.L1[1] -= c1 * ry + f2 * QRy;
-        a.L1[2] -= c1 * rz + f2 * QRz;
+        T dx = 0, dy = 0, dz = 0, w = 0;
+        if (DIP) {
+            dx = (T)D64[0];
+            dy = (T)D64[1];
+            dz = (T)D64[2];
+            w = dx * rx + dy * ry + dz * rz;
+        }
+        // L0 = -[m f0 + 1/2 (f2 RQR + f1 trQ) - 1/6 (f3 ORRR + 3 f2 tOR)] (+ f1 w)
+        const T m0 = DIP ? mB * f0 - f1 * w : mB * f0;
+        a.L0 -= m0 + half * (f2 * RQR + f1 * trQ) - (f3 * ORRR + three * f2 * tOR) * sixth;
+        // L1_a = -[m f1 R_a + 1/2 (f3 R_a RQR + f2 (2 QR_a + R_a trQ))] (+ f2 w R_a + f1 d_a)
+        const T c1 = (DIP ? mB * f1 - f2 * w : mB * f1) + half * (f3 * RQR + f2 * trQ);
+        if (DIP) {
+            a.L1[0] -= c1 * rx + f2 * QRx - f1 * dx;
+            a.L1[1] -= c1 * ry + f2 * QRy - f1 * dy;
+            a.L1[2] -= c1 * rz + f2 * QRz - f1 * dz;
+        } else {
+            a.L1[0] -= c1 * rx + f2 * QRx;
+            a.L1[1] -= c1 * ry + f2 * QRy;
+            a.L1[2] -= c1 * rz + f2 * QRz;
+        }
         if (!LEAF_TARGET) {
             // L2_ab = -m (f2 R_a R_b + f1 d_ab): raw sums T2 (in L2) and s1
+            // (dipole: T2 += -w f3 R_a R_b - f2 (R_a d_b + R_b d_a), s1 += -w f2)
             const T m2 = mB * f2;
-            a.s1 += mB * f1;
-            a.L2[0] += m2 * xx;
-            a.L2[1] += m2 * xy;
-            a.L2[2] += m2 * xz;
-            a.L2[3] += m2 * yy;
-            a.L2[4] += m2 * yz;
-            a.L2[5] += m2 * zz;
+            const T e2 = DIP ? m2 - w * f3 : m2;
+            a.s1 += DIP ? mB * f1 - w * f2 : mB * f1;
+            a.L2[0] += e2 * xx;
+            a.L2[1] += e2 * xy;
+            a.L2[2] += e2 * xz;
+            a.L2[3] += e2 * yy;
+            a.L2[4] += e2 * yz;
+            a.L2[5] += e2 * zz;
+            if (DIP) {
+                const T fx = f2 * dx, fy = f2 * dy, fz = f2 * dz;
+                a.L2[0] -= two * fx * rx;
+                a.L2[1] -= fx * ry + fy * rx;
+                a.L2[2] -= fx * rz + fz * rx;
+                a.L2[3] -= two * fy * ry;
+                a.L2[4] -= fy * rz + fz * ry;
+                a.L2[5] -= two * fz * rz;
+            }
             // L3_abc = -m (f3 R_a R_b R_c + f2 (d_ab R_c + d_ac R_b + d_bc R_a)):
             // raw sums T3 (in L3) and U = sum m f2 R
             const T m3 = mB * f3;
@@ -341,7 +455,7 @@ __device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, co
             a.L3[9] += m3z * zz;
         }
     }
-    if (amc) {
+    if (!DIP && amc) {
         // n = M3_B - mu M3_A; n : D4 = f4 R s + 3 f3 (v + R (t.R)) + 3 f2 t   (FP64)
         double n[10];
 #pragma unroll
@@ -360,7 +474,7 @@ __device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, co
     }
 }
 
-template <bool LEAF_TARGET, typename T>
+template <bool LEAF_TARGET, bool DIP, typename T>
 __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilDev &st, const M2LItem item,
                          const int *s_nbr, int64_t *cnt_out) {
     const int lane = threadIdx.x;
@@ -374,13 +488,14 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
     const double mA = ld.mass[ti];
     double OA[10];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) OA[k] = ld.mp[(9 + k) * S + ti];
-    const bool amc = td.amc && mA > 0.0;
+    for (int k = 0; k < 10; ++k) OA[k] = DIP ? 0.0 : ld.mp[(9 + k) * S + ti];
+    const bool amc = !DIP && td.amc && mA > 0.0;
     const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
     Acc<T> a;
     acc_zero(a);
     int cnt = 0;
     const int n_src_max = LEAF_TARGET ? ld.n_int : ld.n_rec;  // leaf <- leaf pairs are direct
+    double Dp[3] = {0.0, 0.0, 0.0};
     if (ld.level == 0) {
         // root: every other root cell is a candidate; multipole iff well separated
         const int parts = LEAF_TARGET ? 1 : ld.n_parts;
@@ -398,8 +513,10 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
             for (int q = 0; q < 6; ++q) Q[q] = ld.mp[(3 + q) * S + si];
 #pragma unroll
             for (int q = 0; q < 10; ++q) O[q] = ld.mp[(9 + q) * S + si];
-            m2l_pair<LEAF_TARGET, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
-                                  mB * imA, OA, amc, a);
+            if (DIP)
+                for (int q = 0; q < 3; ++q) Dp[q] = ld.dip[q * S + si];
+            m2l_pair<LEAF_TARGET, DIP, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
+                                          Dp, mB * imA, OA, amc, a);
             ++cnt;
         }
     } else {
@@ -419,8 +536,10 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
             for (int q = 0; q < 6; ++q) Q[q] = ld.mp[(3 + q) * S + si];
 #pragma unroll
             for (int q = 0; q < 10; ++q) O[q] = ld.mp[(9 + q) * S + si];
-            m2l_pair<LEAF_TARGET, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
-                                  mB * imA, OA, amc, a);
+            if (DIP)
+                for (int q = 0; q < 3; ++q) Dp[q] = ld.dip[q * S + si];
+            m2l_pair<LEAF_TARGET, DIP, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
+                                          Dp, mB * imA, OA, amc, a);
             ++cnt;
         }
     }
@@ -453,7 +572,7 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
     if (lane == 0) *cnt_out = tot;
 }
 
-template <typename T>
+template <typename T, bool DIP>
 __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                             const M2LItem *__restrict__ items, int n_items, StencilDev st,
                                             int64_t *__restrict__ cnt) {
@@ -466,9 +585,9 @@ __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, con
     if (threadIdx.x < 27) s_nbr[threadIdx.x] = ld.nbr[item.node * 27 + threadIdx.x];
     __syncthreads();
     if (item.node < ld.n_int)
-        m2l_item<false, T>(ld, td, st, item, s_nbr, cnt + it);
+        m2l_item<false, DIP, T>(ld, td, st, item, s_nbr, cnt + it);
     else
-        m2l_item<true, T>(ld, td, st, item, s_nbr, cnt + it);
+        m2l_item<true, DIP, T>(ld, td, st, item, s_nbr, cnt + it);
 }
 
 
@@ -477,7 +596,9 @@ __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, con
 // within 5 cells of the node form a 9x9x9 lattice (20 FP64 values each,
 // 117 KB); every wavefront (one target parity class) walks the part of its
 // stencil whose sources fall in the staged class.
-template <typename T>
+// DIP: second-source solve; each source cell also carries its dipole (23
+// values in 12 double2 planes), rows padded to 10 instead of 12 to fit LDS.
+template <typename T, bool DIP>
 __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                                  const M2LItem *__restrict__ items, int n_items, StencilDev st,
                                                  int64_t *__restrict__ cnt_out) {
@@ -489,8 +610,9 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     const int node = item.node;
     // halo of one source class: 9x9x9 lattice, rows padded to 12 so that the
     // 8 lanes of each 16-byte LDS read phase hit distinct banks
-    constexpr int HY = 12, HX = 9 * 12, HN = 9 * 9 * 12;
-    __shared__ double2 s_src[10][HN];
+    constexpr int NV = DIP ? 12 : 10;  // double2 planes per source cell
+    constexpr int HY = DIP ? 10 : 12, HX = 9 * HY, HN = 9 * 9 * HY;
+    __shared__ double2 s_src[NV][HN];
     __shared__ int s_nbr[27];
     __shared__ int s_cnt[8];
     const int tid = threadIdx.x;
@@ -506,8 +628,8 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     const double mA = ld.mass[ti];
     double OA[10];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) OA[k] = ld.mp[(9 + k) * S + ti];
-    const bool amc = td.amc && mA > 0.0;
+    for (int k = 0; k < 10; ++k) OA[k] = DIP ? 0.0 : ld.mp[(9 + k) * S + ti];
+    const bool amc = !DIP && td.amc && mA > 0.0;
     const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
     Acc<T> a;
     acc_zero(a);
@@ -523,7 +645,7 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
         // is stored so that all 40 loads are in flight together.  Cells that
         // are not sources get mass -0.0 (counted as absent, contributes
         // exact zeros) and a far-away centre.
-        double v[2][20];
+        double v[2][2 * NV];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int cc = tid + 512 * u;
@@ -535,12 +657,17 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
                 v[u][0] = ld.mass[si];
 #pragma unroll
                 for (int k = 0; k < kRec; ++k) v[u][1 + k] = ld.mp[k * S + si];
+                if (DIP) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) v[u][20 + k] = ld.dip[k * S + si];
+                }
             } else {
                 v[u][0] = -0.0;
                 v[u][1] = v[u][2] = v[u][3] = 1.0e3;
 #pragma unroll
-                for (int k = 4; k < 20; ++k) v[u][k] = 0.0;
+                for (int k = 4; k < 20 + (DIP ? 3 : 0); ++k) v[u][k] = 0.0;
             }
+            if (DIP) v[u][23] = 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -549,7 +676,7 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
                 const int ix = cc / 81, iy = (cc / 9) % 9, iz = cc % 9;
                 const int c = ix * HX + iy * HY + iz;
 #pragma unroll
-                for (int k = 0; k < 10; ++k) s_src[k][c] = make_double2(v[u][2 * k], v[u][2 * k + 1]);
+                for (int k = 0; k < NV; ++k) s_src[k][c] = make_double2(v[u][2 * k], v[u][2 * k + 1]);
             }
         }
         __syncthreads();
@@ -576,7 +703,14 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
                 O[2 * j] = e.x;
                 O[2 * j + 1] = e.y;
             }
-            m2l_pair<false, T>(zAx - e0.y, zAy - e1.x, zAz - e1.y, e0.x, Q, O, e0.x * imA, OA, amc, a);
+            double Dp[3] = {0.0, 0.0, 0.0};
+            if (DIP) {
+                const double2 e10 = s_src[10 % NV][h], e11 = s_src[11 % NV][h];
+                Dp[0] = e10.x;
+                Dp[1] = e10.y;
+                Dp[2] = e11.x;
+            }
+            m2l_pair<false, DIP, T>(zAx - e0.y, zAy - e1.x, zAz - e1.y, e0.x, Q, O, Dp, e0.x * imA, OA, amc, a);
         }
         __syncthreads();
     }
@@ -911,7 +1045,8 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
 // kernel, the cell's own multipole-to-local sums (record leaves) and the
 // parent's expansion shifted to the cell centre give phi and g = -grad phi,
 // written in the caller's layout, plus per-node partial sums of the
-// diagnostics.
+// diagnostics.  SRC (second-source solve): the potential only.
+template <bool SRC>
 __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                              const LeafItem *__restrict__ items, int n_items,
                                              double *__restrict__ stat) {
@@ -969,6 +1104,7 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
     }
     const int64_t o = ld.out_base[node] + x * td.sx + y * td.sy + z * td.sz;
     td.phi[o] = phi;
+    if (SRC) return;
     td.g[o] = gx;
     td.g[td.n_leaf_cells + o] = gy;
     td.g[2 * td.n_leaf_cells + o] = gz;
@@ -1046,8 +1182,23 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     auto mark = [&](int i) {
         if (o.phase_events) check_hip(hipEventRecord(o.phase_events[i], s), "phase event");
     };
+    const bool src = o.source;
     mark(0);
-    if (p.n_p2m) hipLaunchKernelGGL(k_p2m, dim3(2 * p.n_p2m), dim3(256), 0, s, p.d_levels, p.d_trees, p.d_p2m, p.n_p2m);
+    if (p.n_p2m)
+        hipLaunchKernelGGL(k_p2m<false>, dim3(2 * p.n_p2m), dim3(256), 0, s, p.d_levels, p.d_trees, p.d_p2m, p.n_p2m);
+    if (src) {
+        // the density's centres of mass first, then the second source's
+        // leaf cells (which replace the leaf masses for the near field)
+        for (int l = p.n_levels_max - 1; l >= 0; --l) {
+            const int n = p.n_interior[l];
+            if (n)
+                hipLaunchKernelGGL(k_m2m, dim3(2 * n), dim3(256), 0, s, p.d_levels, p.d_interior + p.interior_off[l],
+                                   n);
+        }
+        if (p.n_p2m)
+            hipLaunchKernelGGL(k_p2m<true>, dim3(2 * p.n_p2m), dim3(256), 0, s, p.d_levels, p.d_trees, p.d_p2m,
+                               p.n_p2m);
+    }
     mark(1);
     // the near field needs only the leaf masses: it runs on its own stream,
     // concurrently with the upward pass, the multipole phase and the downward pass
@@ -1059,8 +1210,9 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     }
     if (p.n_leaf) {
         const int grid = ((p.n_leaf + kXcd - 1) / kXcd) * kXcd;
-        auto near = o.precision == OCTO_MIXED ? (o.count ? k_near<float, true> : k_near<float, false>)
-                                              : (o.count ? k_near<double, true> : k_near<double, false>);
+        const bool count = o.count && !src;
+        auto near = o.precision == OCTO_MIXED ? (count ? k_near<float, true> : k_near<float, false>)
+                                              : (count ? k_near<double, true> : k_near<double, false>);
         hipLaunchKernelGGL(near, dim3(grid), dim3(512), 0, sn, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
                            p.d_leaf_cnt);
     }
@@ -1068,7 +1220,9 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     mark(2);
     for (int l = p.n_levels_max - 1; l >= 0; --l) {
         const int n = p.n_interior[l];
-        if (n) hipLaunchKernelGGL(k_m2m, dim3(2 * n), dim3(256), 0, s, p.d_levels, p.d_interior + p.interior_off[l], n);
+        if (n)
+            hipLaunchKernelGGL(src ? k_m2m_src : k_m2m, dim3(2 * n), dim3(256), 0, s, p.d_levels,
+                               p.d_interior + p.interior_off[l], n);
     }
     mark(3);
     // the per-wavefront multipole items (root, sparse levels, leaf targets)
@@ -1079,24 +1233,20 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
         check_hip(hipEventRecord(o.fork, s), "fork");
         check_hip(hipStreamWaitEvent(o.aux, o.fork, 0), "fork");
     }
+    const bool mixed = o.precision == OCTO_MIXED;
     if (p.n_m2l) {
         const int grid = ((p.n_m2l + kXcd - 1) / kXcd) * kXcd;
-        if (o.precision == OCTO_MIXED)
-            hipLaunchKernelGGL(k_m2l<float>, dim3(grid), dim3(64), 0, sm, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st,
-                               p.d_m2l_cnt);
-        else
-            hipLaunchKernelGGL(k_m2l<double>, dim3(grid), dim3(64), 0, sm, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st,
-                               p.d_m2l_cnt);
+        auto k = mixed ? (src ? k_m2l<float, true> : k_m2l<float, false>)
+                       : (src ? k_m2l<double, true> : k_m2l<double, false>);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, sm, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st, p.d_m2l_cnt);
     }
     if (fork) check_hip(hipEventRecord(o.join, o.aux), "join");
     if (p.n_m2l_nodes) {
         const int grid = ((p.n_m2l_nodes + kXcd - 1) / kXcd) * kXcd;
-        if (o.precision == OCTO_MIXED)
-            hipLaunchKernelGGL(k_m2l_lds<float>, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes,
-                               p.n_m2l_nodes, st, p.d_m2l_cnt + p.n_m2l);
-        else
-            hipLaunchKernelGGL(k_m2l_lds<double>, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes,
-                               p.n_m2l_nodes, st, p.d_m2l_cnt + p.n_m2l);
+        auto k = mixed ? (src ? k_m2l_lds<float, true> : k_m2l_lds<float, false>)
+                       : (src ? k_m2l_lds<double, true> : k_m2l_lds<double, false>);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes, p.n_m2l_nodes, st,
+                           p.d_m2l_cnt + p.n_m2l);
     }
     if (fork) check_hip(hipStreamWaitEvent(s, o.join, 0), "join");
     mark(4);
@@ -1115,11 +1265,13 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     if (near_fork) check_hip(hipStreamWaitEvent(s, o.join_near, 0), "join");
     if (p.n_leaf) {
         const int grid = ((p.n_leaf + kXcd - 1) / kXcd) * kXcd;
-        hipLaunchKernelGGL(k_l2p, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, p.d_stat);
+        hipLaunchKernelGGL(src ? k_l2p<true> : k_l2p<false>, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees,
+                           p.d_leaf, p.n_leaf, p.d_stat);
     }
     mark(6);
-    hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(1024), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg,
-                       p.d_tree_m2ln_beg, p.n_m2l, p.d_stat, p.d_leaf_cnt, p.d_m2l_cnt, p.d_out);
+    if (!src)
+        hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(1024), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg,
+                           p.d_tree_m2ln_beg, p.n_m2l, p.d_stat, p.d_leaf_cnt, p.d_m2l_cnt, p.d_out);
     mark(7);
     check_hip(hipGetLastError(), "kernel launch");
 }

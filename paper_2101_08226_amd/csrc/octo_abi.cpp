@@ -78,7 +78,7 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
     const int nl = L.n_levels;
     size_t bytes = 0;
     std::vector<size_t> off_nbr(nl), off_child(nl), off_parent(nl), off_coord(nl), off_out(nl), off_mass(nl),
-        off_mp(nl), off_loc(nl), off_lacc(nl), off_nf(nl);
+        off_mp(nl), off_loc(nl), off_lacc(nl), off_nf(nl), off_dip(nl);
     t->parts_alloc.assign(nl, 1);
     t->parts.assign(nl, 1);
     t->m2l_lds.assign(nl, 0);
@@ -112,6 +112,8 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
         bytes += al((size_t)kLacc * (h.n_rec - h.n_int) * kCells * 8);
         off_nf[l] = bytes;
         bytes += al((size_t)4 * (h.n_nodes - h.n_int) * kCells * 8);
+        off_dip[l] = bytes;
+        bytes += al((size_t)3 * h.n_rec * kCells * 8);
     }
     const size_t off_rho = bytes;
     bytes += al((size_t)L.n_leaf_cells * 8);
@@ -156,6 +158,7 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
         d.loc = (double *)(base + off_loc[l]);
         d.lacc = (double *)(base + off_lacc[l]);
         d.nf = (double *)(base + off_nf[l]);
+        d.dip = (double *)(base + off_dip[l]);
     }
     t->rho = (double *)(base + off_rho);
     t->stage = (double *)(base + off_stage);
@@ -582,6 +585,24 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
                     stats->phase_ms[i] = pm;
                 }
         }
+    });
+}
+
+octo_status octo_solve_dphidt(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, const double *drho_dt,
+                              double *dphi_dt) {
+    return guard([&] {
+        if (!ctx || !tree) fail(OCTO_E_INVALID, "NULL argument");
+        if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+        validate_opts(opts);
+        if (!drho_dt || !dphi_dt) fail(OCTO_E_INVALID, "NULL source or output");
+        DeviceGuard dg(ctx->device);
+        std::vector<TreeDesc> want = tree->plan.trees_host;
+        want[0].phi = dphi_dt;
+        want[0].g = nullptr;
+        want[0].src = drho_dt;
+        want[0].G = opts->G;
+        want[0].amc = 0;
+        run_plan(ctx, tree->plan, tree->graphs, want, opts, false, true);
     });
 }
 

@@ -57,12 +57,14 @@ struct LevelDesc {
     double *loc;              // n_parts * kLoc * n_int * 512 (slot-major)
     double *lacc;             // kLacc * (n_rec - n_int) * 512
     double *nf;               // 4 * (n_nodes - n_int) * 512: direct-sum phi, g of leaf cells
+    double *dip;              // 3 * n_rec * 512: dipole of a second source about the density's centres
 };
 
 struct TreeDesc {
     const double *rho;  // caller layout
     double *phi;        // caller layout, set per solve
-    double *g;          // 3 x n_leaf_cells, set per solve
+    double *g;          // 3 x n_leaf_cells, set per solve (NULL in second-source solves)
+    const double *src;  // second source (a density rate), caller layout, set per second-source solve
     int64_t n_leaf_cells;
     int64_t sx, sy, sz;  // caller-layout strides of local cell (x, y, z)
     double G;

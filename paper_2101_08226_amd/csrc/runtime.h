@@ -120,6 +120,7 @@ struct StencilDevHolder {
 struct LaunchOpts {
     int precision = OCTO_FP64;
     bool count = true;                   // count evaluated pairs (statistics)
+    bool source = false;                 // second-source solve (potential of the density rate)
     hipEvent_t *phase_events = nullptr;  // 8 events around the 7 phases, or NULL
     hipStream_t aux = nullptr;           // second stream for concurrent multipole work, or NULL
     hipEvent_t fork = nullptr, join = nullptr;
@@ -229,7 +230,7 @@ struct octo_tree {
 namespace octo {
 // launch a plan through a cached graph (captured on first use) or directly
 void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs,
-              const std::vector<TreeDesc> &want, const octo_opts *o, bool count = true);
+              const std::vector<TreeDesc> &want, const octo_opts *o, bool count = true, bool source = false);
 void drop_graphs(std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs);
 void build_tree_plan(octo_tree *t);
 }  // namespace octo

@@ -352,3 +352,95 @@ def test_coupling_kernels(ctx):
     ref = oracle.coupling.energy_update(E_h, rho_h, pb.cpu().numpy(), phi.cpu().numpy())
     assert np.max(np.abs(E.cpu().numpy() - ref)) <= 1e-15 * np.max(np.abs(ref))
     tree.destroy()
+
+
+# --------------------------------------------------------------------------
+# dphi/dt: the density rate as a second source (Sec. 2.1)
+# Bar (FP64): max_i |d_i| / max_i |ref_i| <= 1e-12 (normwise: the rate and its
+# potential change sign).  Mixed: MIXED_DPHI, 4x the largest error measured.
+# --------------------------------------------------------------------------
+
+MIXED_DPHI = 1e-4
+
+
+def _dev(a):
+    import torch
+
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("seed,max_level,rate", [(21, 2, "noisy"), (22, 3, "orbital"), (23, 3, "noisy")])
+def test_dphidt_parity(ctx, seed, max_level, rate):
+    leaves, f = random_amr_leaves(seed, max_level=max_level, n_stars=2)
+    say(f"dphidt seed={seed} max_level={max_level} rate={rate} leaves={len(leaves)}")
+    tree = ctx.adaptive_tree(f, max_level, 1e-4)
+    lv = tree.leaves()
+    rho = w.leaf_density(f, lv)
+    src = w.noisy_rate(rho, seed) if rate == "noisy" else w.leaf_density(w.OrbitalRate(f, 1.0, 1e-3), lv)
+    t = oracle.Tree(lv, rho)
+    x, m = t.leaf_cells()
+    md = src.ravel() * (m / rho.ravel())
+    drho = _dev(src.ravel())
+    for theta in (0.5, 0.34):
+        ref = t.solve_source(src, theta=theta)
+        d64 = ctx.solve_dphidt(tree, drho, theta=theta).cpu().numpy()
+        e = float(np.max(np.abs(d64 - ref)) / np.max(np.abs(ref)))
+        phi, _, _ = gpu_solve(ctx, tree, theta=theta)
+        scale = np.sum(np.abs(phi * md)) + np.sum(np.abs(m * d64))
+        cancel = abs(np.dot(phi, md) - np.dot(m, d64)) / scale
+        d32 = ctx.solve_dphidt(tree, drho, theta=theta, precision=lib.OCTO_MIXED).cpu().numpy()
+        e32 = float(np.max(np.abs(d32 - ref)) / np.max(np.abs(ref)))
+        say(f"  theta={theta} e={e:.2e} cancel={cancel:.2e} mixed e={e32:.2e}")
+        assert e <= TOL
+        assert cancel < 1e-13
+        assert e32 <= MIXED_DPHI
+    # the solve of the density itself is unaffected by an interleaved rate solve
+    phi2, g2, _ = gpu_solve(ctx, tree, theta=0.5)
+    p_ref, g_ref = t.solve(theta=0.5)
+    e2 = errs(phi2, g2, p_ref, g_ref)
+    assert e2[0] <= TOL and e2[1] <= TOL
+    tree.destroy()
+
+
+def test_dphidt_uniform_and_full_size(ctx):
+    """32^3 random density with a noisy rate (every cell), then the 128^3
+    binary with its orbital rate (sampled cells against the oracle, the
+    cancellation over all cells)."""
+    rng = np.random.default_rng(33)
+    rho = rng.uniform(0.1, 1.0, (32, 32, 32))
+    src = w.noisy_rate(rho, 33)
+    say("dphidt uniform 32")
+    tree = ctx.uniform_tree(rho)
+    d = ctx.solve_dphidt(tree, _dev(src.ravel())).cpu().numpy()
+    tree.destroy()
+    t = oracle.Tree(w.uniform_leaves(2), w.grid_to_leaves(rho))
+    ref = t.solve_source(w.grid_to_leaves(src))
+    d_l = w.grid_to_leaves(d.reshape(32, 32, 32)).ravel()
+    e = float(np.max(np.abs(d_l - ref)) / np.max(np.abs(ref)))
+    say(f"  e={e:.2e}")
+    assert e <= TOL
+
+    f = w.binary_polytrope_128()
+    rho = w.uniform_grid(f, 4)
+    src = w.uniform_grid(w.OrbitalRate(f, 1.0, 1e-3), 4)
+    say("dphidt c2 128^3")
+    tree = ctx.uniform_tree(rho)
+    d = ctx.solve_dphidt(tree, _dev(src.ravel())).cpu().numpy()
+    phi, _, _ = gpu_solve(ctx, tree, theta=0.5)
+    tree.destroy()
+    vol = (1.0 / 128) ** 3
+    m, md = rho.ravel() * vol, src.ravel() * vol
+    scale = np.sum(np.abs(phi * md)) + np.sum(np.abs(m * d))
+    cancel = abs(np.dot(phi, md) - np.dot(m, d)) / scale
+    from helpers import grid_ids
+
+    sel = np.random.default_rng(7).choice(128 ** 3, 300, replace=False)
+    # the stars, where the rate lives
+    star = np.nonzero(np.abs(src.ravel()) > 1e-3 * np.abs(src).max())[0]
+    sel = np.concatenate([sel, np.random.default_rng(8).choice(star, 300, replace=False)])
+    t = oracle.Tree(w.uniform_leaves(4), w.grid_to_leaves(rho))
+    ref = t.solve_source(w.grid_to_leaves(src), sample=grid_ids(4, sel))
+    e = float(np.max(np.abs(d[sel] - ref)) / np.max(np.abs(ref)))
+    say(f"  e={e:.2e} cancel={cancel:.2e}")
+    assert e <= TOL
+    assert cancel < 1e-13

@@ -203,6 +203,34 @@ class UniformSphere(Field):
         return np.where(r < a, -m * (3 * a * a - r * r) / (2 * a ** 3), -m / np.maximum(r, 1e-300))
 
 
+@dataclass
+class OrbitalRate(Field):
+    """Density rate (a second, signed source) of a field whose pattern turns
+    rigidly about the z axis at angular speed omega, as a binary does on a grid
+    that does not co-rotate: the central difference of the base density over
+    rotations by -omega*dt and +omega*dt, divided by 2*dt.  (The rotation's
+    cosine and sine are computed once, so points are evaluated with the same
+    operations as densities.)"""
+
+    base: Field = None
+    omega: float = 1.0
+    dt: float = 1.0e-3
+
+    def density(self, x, y, z):
+        c, s = math.cos(self.omega * self.dt), math.sin(self.omega * self.dt)
+        # the pattern at time t is the base density at R(-omega t) x
+        later = self.base.density(c * x + s * y, c * y - s * x, z)  # R(-omega dt) x
+        earlier = self.base.density(c * x - s * y, c * y + s * x, z)  # R(+omega dt) x
+        return (later - earlier) / (2.0 * self.dt)
+
+
+def noisy_rate(rho: np.ndarray, seed: int) -> np.ndarray:
+    """A signed rate with no structure: rho * N(0, 1) per cell (seeded, in
+    array order)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    return rho * np.random.default_rng(seed).standard_normal(rho.shape)
+
+
 def binary_polytrope_128() -> Polytropes:
     """Binary n = 3/2 polytropes: radii 0.12 and 0.10, centres 0.35 apart on x
     with the centre of mass at the origin, mass ratio M2/M1 = 0.7, maximum
