@@ -86,7 +86,7 @@ def roofline_m2l(pairs, m2l_ms, prec):
             "kernel_ms": round(m2l_ms, 4)}
 
 
-def single_tree_bench(a, lib, w, ctx, tree, n_cells, workload, oracle_fn=None):
+def single_tree_bench(a, lib, w, ctx, tree, n_cells, workload, rate=None):
     import torch
 
     dev = ctx.device
@@ -108,6 +108,17 @@ def single_tree_bench(a, lib, w, ctx, tree, n_cells, workload, oracle_fn=None):
         ph = phase_times(lib, ctx, lambda: lib.octo_solve(ctx.handle, tree.handle, opts, phi.data_ptr(),
                                                           g.data_ptr(), True))
         res[prec_name] = dict(sec=sec, stats=st, phases=ph)
+    if rate is not None:
+        # dphi/dt: the density rate as a second source on the same tree
+        drho = torch.tensor(np.ascontiguousarray(rate).ravel(), dtype=torch.float64, device=dev)
+        dphi = torch.empty(n_cells, dtype=torch.float64, device=dev)
+        for prec_name in ["fp64", "mixed"] if not a.no_mixed else ["fp64"]:
+            prec = lib.OCTO_FP64 if prec_name == "fp64" else lib.OCTO_MIXED
+            opts = lib.make_opts(a.theta, 1.0, prec, False)
+            print(f"[bench] {workload} dphi/dt {prec_name}: timing {a.steps}", file=sys.stderr, flush=True)
+            sec = timed(lambda: lib.octo_solve_dphidt(ctx.handle, tree.handle, opts, drho.data_ptr(),
+                                                      dphi.data_ptr()), sync, a.steps, a.warmup)
+            res["dphidt_" + prec_name] = dict(sec=sec)
     return res
 
 
@@ -140,11 +151,13 @@ def main():
     if a.config in ("c1", "c2", "c3"):
         if a.config == "c1":
             rho = w.noisy_sphere_16()
+            rate = w.noisy_rate(rho, 1)
             tree = ctx.uniform_tree(rho)
             desc = "uniform 16^3 (2^3 sub-grids), noisy sphere rho=1(1+0.01N) inside r=0.4, floor 1e-10"
             oracle_tree = lambda: __import__("oracle").Tree(w.uniform_leaves(1), w.grid_to_leaves(rho))  # noqa
         elif a.config == "c2":
             rho = w.uniform_grid(w.binary_polytrope_128(), 4)
+            rate = w.uniform_grid(w.OrbitalRate(w.binary_polytrope_128(), 1.0, 1e-3), 4)
             tree = ctx.uniform_tree(rho)
             desc = ("uniform 128^3 (16^3 sub-grids), binary n=1.5 polytropes R=0.12/0.10, sep 0.35, q=0.7, "
                     "max rho 1, floor 1e-10")
@@ -153,6 +166,7 @@ def main():
             f = w.binary_polytrope_128()
             print("[bench] building the adaptive tree (level 6)", file=sys.stderr, flush=True)
             tree = ctx.adaptive_tree(f, 6, 1e-4)
+            rate = w.leaf_density(w.OrbitalRate(f, 1.0, 1e-3), tree.leaves())
             desc = ("adaptive to level 6 (root sub-grid = level 0; 7736 leaf sub-grids, 3.96M leaf cells), "
                     "refined where box-max rho > 1e-4, 26-neighbour 2:1 balance; c2 field")
 
@@ -161,7 +175,7 @@ def main():
                 lv = tree.leaves()
                 return oracle.Tree(lv, w.leaf_density(f, lv))
         n_cells = tree.n_leaf_cells
-        res = single_tree_bench(a, lib, w, ctx, tree, n_cells, a.config)
+        res = single_tree_bench(a, lib, w, ctx, tree, n_cells, a.config, rate)
         main_p = "fp64" if a.precision == "fp64" else "mixed"
         r = res[main_p]
         out.update(value=round(n_cells / r["sec"], 1), ms_per_step=round(r["sec"] * 1e3, 4),
@@ -179,6 +193,12 @@ def main():
             out["mixed"] = {"value": round(n_cells / m["sec"], 1), "ms_per_step": round(m["sec"] * 1e3, 4),
                             "torque": m["stats"]["torque"],
                             "phase_ms": {k: round(v, 4) for k, v in zip(PHASES, m["phases"])}}
+        for k in ("dphidt_fp64", "dphidt_mixed"):
+            if k in res:
+                out.setdefault("dphidt", {})[k.split("_")[1]] = {
+                    "value": round(n_cells / res[k]["sec"], 1), "ms_per_step": round(res[k]["sec"] * 1e3, 4),
+                    "source": "orbital density rate (pattern turning about z)" if a.config != "c1" else
+                              "rho * N(0,1)"}
         if not a.no_cpu:
             print(f"[bench] CPU oracle, {a.cpu_threads} threads", file=sys.stderr, flush=True)
             t = oracle_tree()
