@@ -37,7 +37,29 @@ METRIC = "FMM cells solved/s (FP64 vs mixed, 1 GPU); p50/p99 served solve latenc
 M2L_FLOPS_PER_PAIR = 297
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector
-PHASES = ["p2m", "near", "m2m", "m2l", "l2l", "l2p", "stats"]
+PHASES = ["p2m", "near", "m2m", "m2l", "l2l", "l2p", "stats", "m2l_lds_kernel"]
+# HBM traffic of the LDS-staged multipole kernel on the c2 workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a copy of known size; the
+# record names the kernel source it was taken with, and is ignored (traffic
+# null) once that source has changed.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_m2l_lds_c2_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2101_08226_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(workload):
+    import hashlib
+
+    if workload != "c2" or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_RECORD):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if rec.get("kernels_hip_sha256") != src or "traffic_bytes_per_launch" not in rec:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -72,18 +94,22 @@ def timed(step, sync, steps, warmup):
 
 def phase_times(lib, ctx, solve_once, n=5):
     ctx.set_profiling(True)
-    acc = np.zeros(7)
+    acc = np.zeros(8)
     for _ in range(n):
         acc += np.array(solve_once().phase_ms[:])
     ctx.set_profiling(False)
     return acc / n
 
 
-def roofline_m2l(pairs, m2l_ms, prec):
-    achieved = pairs * M2L_FLOPS_PER_PAIR / (m2l_ms * 1e-3) / 1e12
+def roofline_m2l(pairs, kernel_ms, prec, traffic=None):
+    """The LDS-staged multipole kernel alone: its pairs x the per-pair count
+    over its own launch duration (HIP events around it, kernels one by one)."""
+    achieved = pairs * M2L_FLOPS_PER_PAIR / (kernel_ms * 1e-3) / 1e12
+    t = "double" if prec == "fp64" else "float"
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None, "kernel": "M2L (k_m2l_lds + k_m2l)",
-            "kernel_ms": round(m2l_ms, 4)}
+            "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+            "kernel": f"k_m2l_lds<{t}, false>", "kernel_ms": round(kernel_ms, 4), "pairs_per_launch": int(pairs),
+            "flops_per_pair": M2L_FLOPS_PER_PAIR}
 
 
 def single_tree_bench(a, lib, w, ctx, tree, n_cells, workload, rate=None):
@@ -185,7 +211,8 @@ def main():
                          "m2l_pairs": int(r["stats"]["m2l_pairs"]), "direct_pairs": int(r["stats"]["direct_pairs"])}
         out["torque"] = r["stats"]["torque"]
         out["force"] = r["stats"]["force"]
-        rl = roofline_m2l(r["stats"]["m2l_pairs"], r["phases"][3], main_p)
+        rl = roofline_m2l(r["stats"]["m2l_lds_pairs"], r["phases"][7], main_p,
+                          measured_traffic(a.config) if main_p == "fp64" else None)
         rl["phase_ms"] = {k: round(v, 4) for k, v in zip(PHASES, r["phases"])}
         out["roofline"] = rl
         if "mixed" in res and main_p == "fp64":

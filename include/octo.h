@@ -104,6 +104,7 @@ typedef struct {
     int64_t n_leaf_cells;
     int64_t m2l_pairs;
     int64_t direct_pairs;
+    int64_t m2l_lds_pairs;  /* the part of m2l_pairs evaluated by the LDS-staged kernel */
     double device_ms;
     /* per-phase device time (ms) when profiling is on (octo_ctx_set_profiling;
      * the phases then run one after the other): [0] leaf masses (P2M),
@@ -111,8 +112,9 @@ typedef struct {
      * pass (M2M, all levels), [3] multipole interactions (M2L with the
      * correction, all levels), [4] downward pass (L2L, interior levels),
      * [5] leaves (final shift, potential and acceleration), [6] statistics
-     * reduction; zeros otherwise */
-    double phase_ms[7];
+     * reduction, [7] the LDS-staged multipole kernel alone (part of [3],
+     * the pairs of m2l_lds_pairs); zeros otherwise */
+    double phase_ms[8];
 } octo_stats;
 
 /* Density at n points: xyz is 3n doubles (x0,y0,z0,x1,...), rho_out n doubles. */

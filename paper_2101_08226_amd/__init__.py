@@ -53,15 +53,16 @@ class octo_stats(ctypes.Structure):
     _fields_ = [("total_mass", ctypes.c_double), ("net_force", ctypes.c_double * 3),
                 ("net_torque", ctypes.c_double * 3), ("force_scale", ctypes.c_double),
                 ("torque_scale", ctypes.c_double), ("n_leaf_cells", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
-                ("direct_pairs", ctypes.c_int64), ("device_ms", ctypes.c_double),
-                ("phase_ms", ctypes.c_double * 7)]
+                ("direct_pairs", ctypes.c_int64), ("m2l_lds_pairs", ctypes.c_int64), ("device_ms", ctypes.c_double),
+                ("phase_ms", ctypes.c_double * 8)]
 
     def as_dict(self):
         F = np.array(self.net_force[:])
         T = np.array(self.net_torque[:])
         return dict(total_mass=self.total_mass, net_force=F, net_torque=T, force_scale=self.force_scale,
                     torque_scale=self.torque_scale, n_leaf_cells=self.n_leaf_cells, m2l_pairs=self.m2l_pairs,
-                    direct_pairs=self.direct_pairs, device_ms=self.device_ms, phase_ms=list(self.phase_ms),
+                    direct_pairs=self.direct_pairs, m2l_lds_pairs=self.m2l_lds_pairs, device_ms=self.device_ms,
+                    phase_ms=list(self.phase_ms),
                     force=float(np.linalg.norm(F) / self.force_scale) if self.force_scale else 0.0,
                     torque=float(np.linalg.norm(T) / self.torque_scale) if self.torque_scale else 0.0)
 

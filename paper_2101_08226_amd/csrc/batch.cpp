@@ -162,6 +162,7 @@ static void fill(const double *v, int64_t n_leaf_cells, double ms, octo_stats *s
     st->n_leaf_cells = n_leaf_cells;
     st->m2l_pairs = (int64_t)v[9];
     st->direct_pairs = (int64_t)v[10];
+    st->m2l_lds_pairs = (int64_t)v[11];
     st->device_ms = ms;
 }
 

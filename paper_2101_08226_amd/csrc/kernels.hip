@@ -1141,38 +1141,41 @@ __global__ __launch_bounds__(1024) void k_stats(const int32_t *__restrict__ leaf
     const int t = blockIdx.x;
     constexpr int NT = 1024;
     __shared__ double sh[kStat][NT / 64];
-    __shared__ long long shc[2][NT / 64];
+    __shared__ long long shc[3][NT / 64];
     double acc[kStat];
 #pragma unroll
     for (int k = 0; k < kStat; ++k) acc[k] = 0.0;
-    long long c_m2l = 0, c_dir = 0;
+    long long c_m2l = 0, c_dir = 0, c_lds = 0;
     for (int i = leaf_beg[t] + threadIdx.x; i < leaf_beg[t + 1]; i += NT) {
 #pragma unroll
         for (int k = 0; k < kStat; ++k) acc[k] += stat[(size_t)i * kStat + k];
         c_dir += leaf_cnt[i];
     }
     for (int i = m2l_beg[t] + threadIdx.x; i < m2l_beg[t + 1]; i += NT) c_m2l += m2l_cnt[i];
-    for (int i = m2ln_beg[t] + threadIdx.x; i < m2ln_beg[t + 1]; i += NT) c_m2l += m2l_cnt[n_m2l + i];
+    for (int i = m2ln_beg[t] + threadIdx.x; i < m2ln_beg[t + 1]; i += NT) c_lds += m2l_cnt[n_m2l + i];
 #pragma unroll
     for (int k = 0; k < kStat; ++k) acc[k] = wave_sum(acc[k]);
     c_m2l = wave_sum(c_m2l);
     c_dir = wave_sum(c_dir);
+    c_lds = wave_sum(c_lds);
     const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int k = 0; k < kStat; ++k) sh[k][wv] = acc[k];
-        shc[0][wv] = c_m2l;
+        shc[0][wv] = c_m2l + c_lds;
         shc[1][wv] = c_dir;
+        shc[2][wv] = c_lds;
     }
     __syncthreads();
+    // out per tree: 9 sums, multipole pairs, direct pairs, LDS-kernel pairs
     if (threadIdx.x < kStat) {
         double v = 0.0;
         for (int w = 0; w < NT / 64; ++w) v += sh[threadIdx.x][w];
         out[t * 12 + threadIdx.x] = v;
-    } else if (threadIdx.x < kStat + 2) {
+    } else if (threadIdx.x < kStat + 3) {
         long long v = 0;
         for (int w = 0; w < NT / 64; ++w) v += shc[threadIdx.x - kStat][w];
-        out[t * 12 + (threadIdx.x == kStat ? kStat : kStat + 1)] = (double)v;
+        out[t * 12 + threadIdx.x] = (double)v;
     }
 }
 
@@ -1241,6 +1244,7 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
         hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, sm, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st, p.d_m2l_cnt);
     }
     if (fork) check_hip(hipEventRecord(o.join, o.aux), "join");
+    mark(8);
     if (p.n_m2l_nodes) {
         const int grid = ((p.n_m2l_nodes + kXcd - 1) / kXcd) * kXcd;
         auto k = mixed ? (src ? k_m2l_lds<float, true> : k_m2l_lds<float, false>)

@@ -268,6 +268,7 @@ void fill_stats(const double *v, int64_t n_leaf_cells, double ms, octo_stats *st
     st->n_leaf_cells = n_leaf_cells;
     st->m2l_pairs = (int64_t)v[9];
     st->direct_pairs = (int64_t)v[10];
+    st->m2l_lds_pairs = (int64_t)v[11];
     st->device_ms = ms;
 }
 
@@ -377,7 +378,7 @@ octo_status octo_ctx_create(int device, void *hip_stream, const octo_allocator *
         check_hip(hipEventCreateWithFlags(&c->join_near_ev, hipEventDisableTiming), "event");
         if (const char *e = getenv("OCTO_GRAPHS")) c->use_graphs = atoi(e) != 0;
         check_hip(hipEventCreate(&c->ev0), "event");
-        for (int i = 0; i < 8; ++i) check_hip(hipEventCreate(&c->phase_ev[i]), "event");
+        for (int i = 0; i < 9; ++i) check_hip(hipEventCreate(&c->phase_ev[i]), "event");
         check_hip(hipEventCreate(&c->ev1), "event");
         c->h_stats_cap = 12 * 1024;
         check_hip(hipHostMalloc((void **)&c->h_stats, c->h_stats_cap * sizeof(double), hipHostMallocDefault),
@@ -406,7 +407,7 @@ octo_status octo_ctx_destroy(octo_ctx *ctx) {
         hipEventDestroy(ctx->fork_near_ev);
         hipEventDestroy(ctx->join_near_ev);
         hipEventDestroy(ctx->ev0);
-        for (int i = 0; i < 8; ++i) hipEventDestroy(ctx->phase_ev[i]);
+        for (int i = 0; i < 9; ++i) hipEventDestroy(ctx->phase_ev[i]);
         hipEventDestroy(ctx->ev1);
         hipHostFree(ctx->h_stats);
         if (ctx->own_stream) hipStreamDestroy(ctx->stream);
@@ -579,11 +580,16 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
             hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
             fill_stats(ctx->h_stats, n, ms, stats);
             if (ctx->profiling)
+            {
                 for (int i = 0; i < 7; ++i) {
                     float pm = 0.f;
                     hipEventElapsedTime(&pm, ctx->phase_ev[i], ctx->phase_ev[i + 1]);
                     stats->phase_ms[i] = pm;
                 }
+                float pm = 0.f;
+                hipEventElapsedTime(&pm, ctx->phase_ev[8], ctx->phase_ev[4]);
+                stats->phase_ms[7] = pm;
+            }
         }
     });
 }

@@ -121,7 +121,7 @@ struct LaunchOpts {
     int precision = OCTO_FP64;
     bool count = true;                   // count evaluated pairs (statistics)
     bool source = false;                 // second-source solve (potential of the density rate)
-    hipEvent_t *phase_events = nullptr;  // 8 events around the 7 phases, or NULL
+    hipEvent_t *phase_events = nullptr;  // 8 events around the 7 phases + 1 before the LDS M2L kernel, or NULL
     hipStream_t aux = nullptr;           // second stream for concurrent multipole work, or NULL
     hipEvent_t fork = nullptr, join = nullptr;
     hipStream_t aux_near = nullptr;      // third stream for the near field, or NULL
@@ -191,7 +191,7 @@ struct octo_ctx {
     hipEvent_t fork_near_ev = nullptr, join_near_ev = nullptr;
     bool use_graphs = true;
     bool profiling = false;
-    hipEvent_t phase_ev[8] = {};
+    hipEvent_t phase_ev[9] = {};
     double *h_stats = nullptr;  // pinned host staging for stats
     size_t h_stats_cap = 0;
     // last batch signature (octo_solve_batch)
