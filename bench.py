@@ -31,10 +31,11 @@ sys.path.insert(0, ROOT)
 METRIC = "FMM cells solved/s (FP64 vs mixed, 1 GPU); p50/p99 served solve latency"
 
 # Algorithmic FP64 operations per ordered multipole-to-local pair with an
-# interior target and the correction on: adds, multiplies and rsqrt count as
-# one, a fused multiply-add as two (188 for R and the L0..L3 terms, 109 for the
-# correction); the accounting is in the design notes.
-M2L_FLOPS_PER_PAIR = 297
+# interior target and the correction on, in the trace-free formulation the
+# kernels use: adds, multiplies and rsqrt count as one, a fused multiply-add as
+# two (150 for R and the L0..L3 terms, 64 for the correction and the mass
+# ratio); the accounting is in the design notes.
+M2L_FLOPS_PER_PAIR = 214
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector
 PHASES = ["p2m", "near", "m2m", "m2l", "l2l", "l2p", "stats", "m2l_lds_kernel"]

@@ -81,6 +81,46 @@ __device__ inline void t3_trace(const double *T, double &tx, double &ty, double 
     tz = T[2] + T[7] + T[9];
 }
 
+// Trace-free parts of the raw moments.  Every contraction the multipole step
+// makes is with a derivative tensor D^(k) of 1/r, k >= 2, which is trace-free
+// in every index pair (1/r is harmonic), so only these parts contribute:
+//   Q' = Q - (tr Q / 3) I,  O'_abc = O_abc - (d_ab t_c + d_ac t_b + d_bc t_a) / 5,
+// t_a = O_abb.  Stored as independent components: q5 = xx xy xz yy yz
+// (zz = -xx - yy); o7 = xxx xxy xxz xyy xyz yyy yyz (xzz = -xxx - xyy,
+// yzz = -xxy - yyy, zzz = -xxz - yyz).
+__device__ inline void detrace_q(const double *Q, double *q5) {
+    const double t = (Q[0] + Q[3] + Q[5]) * (1.0 / 3.0);
+    q5[0] = Q[0] - t;
+    q5[1] = Q[1];
+    q5[2] = Q[2];
+    q5[3] = Q[3] - t;
+    q5[4] = Q[4];
+}
+__device__ inline void detrace_o(const double *O, double *o7) {
+    double tx, ty, tz;
+    t3_trace(O, tx, ty, tz);
+    tx *= 0.2;
+    ty *= 0.2;
+    tz *= 0.2;
+    o7[0] = O[0] - 3.0 * tx;
+    o7[1] = O[1] - ty;
+    o7[2] = O[2] - tz;
+    o7[3] = O[3] - tx;
+    o7[4] = O[4];
+    o7[5] = O[6] - 3.0 * ty;
+    o7[6] = O[7] - tz;
+}
+
+// (O':RR)_a = sum_bc O'_abc R_b R_c for a trace-free O' (o7 packing), given
+// e = xx - zz, f = yy - zz, u = 2xy, v = 2xz, w = 2yz of R.
+template <typename T>
+__device__ inline void o7_rr(const T *o, T e, T f, T u, T v, T w, T &ox, T &oy, T &oz) {
+    const T xzz = -(o[0] + o[3]), yzz = -(o[1] + o[5]);
+    ox = o[0] * e + o[3] * f + o[1] * u + o[2] * v + o[4] * w;
+    oy = o[1] * e + o[5] * f + o[3] * u + o[4] * v + o[6] * w;
+    oz = o[2] * e + o[6] * f + o[4] * u + xzz * v + yzz * w;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ P2M
@@ -357,43 +397,48 @@ __device__ inline void finish_l2_l3(Acc<T> &a) {
 
 // T = double: everything in FP64.  T = float (mixed precision): the L0..L3
 // contractions run in FP32 with FP32 partial sums; R, the radial factors and
-// the correction stay FP64.
+// the correction stay FP64.  The source's second and third moments come
+// trace-free (q5, o7 packing); with D^(k) = f_k-chain tensors of R:
+//   L0 -= m f0 + (1/2) f2 R.Q'.R - (1/6) f3 O'.RRR
+//   L1_a -= (m f1 + (1/2) f3 R.Q'.R) R_a + f2 (Q'R)_a
+// (the trace terms f1 tr Q, f2 tr O vanish).
 // DIP: the source also has a dipole d (second source expanded about the
 // density's centres): L0 += d.D1, L1_a += d_b D2_ab, L2_ab += d_c D3_abc,
 // i.e. with w = d.R: L0 += f1 w; L1_a += f2 w R_a + f1 d_a;
 // L2_ab += f3 w R_a R_b + f2 (w d_ab + R_a d_b + R_b d_a).
+// Correction (FP64): n = O'_B - mu O'_A is trace-free, so n : D4 reduces to
+// f4 (n:RR . R) R + 3 f3 (n:RR), with n:RR = O'_B:RR - mu O'_A:RR.
 template <bool LEAF_TARGET, bool DIP, typename T>
-__device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, const double *Q64, const double *O64,
-                                const double *D64, double mu, const double *OA, bool amc, Acc<T> &a) {
+__device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, const double *q64, const double *o64,
+                                const double *D64, double mu, const double *oA, bool amc, Acc<T> &a) {
     const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
     const double d0 = rsqrt(r2);
     const double ir2 = d0 * d0;
     const double d1 = -d0 * ir2;
     const double d2 = -3.0 * d1 * ir2;
     const double d3 = -5.0 * d2 * ir2;
+    T ORx, ORy, ORz, ORRR;  // O'_B : RR and O'_B : RRR in T
     {
         const T rx = (T)Rx, ry = (T)Ry, rz = (T)Rz;
         const T f0 = (T)d0, f1 = (T)d1, f2 = (T)d2, f3 = (T)d3;
         const T mB = (T)mB64;
-        T Q[6], O[10];
+        T q[5], o[7];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) Q[k] = (T)Q64[k];
+        for (int k = 0; k < 5; ++k) q[k] = (T)q64[k];
 #pragma unroll
-        for (int k = 0; k < 10; ++k) O[k] = (T)O64[k];
-        const T half = (T)0.5, three = (T)3.0, sixth = (T)(1.0 / 6.0), two = (T)2.0;
+        for (int k = 0; k < 7; ++k) o[k] = (T)o64[k];
+        const T half = (T)0.5, sixth = (T)(1.0 / 6.0), two = (T)2.0;
         // quadrupole contractions
-        const T QRx = Q[0] * rx + Q[1] * ry + Q[2] * rz;
-        const T QRy = Q[1] * rx + Q[3] * ry + Q[4] * rz;
-        const T QRz = Q[2] * rx + Q[4] * ry + Q[5] * rz;
+        const T qzz = -(q[0] + q[3]);
+        const T QRx = q[0] * rx + q[1] * ry + q[2] * rz;
+        const T QRy = q[1] * rx + q[3] * ry + q[4] * rz;
+        const T QRz = q[2] * rx + q[4] * ry + qzz * rz;
         const T RQR = rx * QRx + ry * QRy + rz * QRz;
-        const T trQ = Q[0] + Q[3] + Q[5];
         // octupole contractions
         const T xx = rx * rx, yy = ry * ry, zz = rz * rz, xy = rx * ry, xz = rx * rz, yz = ry * rz;
-        const T ORx = O[0] * xx + O[3] * yy + O[5] * zz + two * (O[1] * xy + O[2] * xz + O[4] * yz);
-        const T ORy = O[1] * xx + O[6] * yy + O[8] * zz + two * (O[3] * xy + O[4] * xz + O[7] * yz);
-        const T ORz = O[2] * xx + O[7] * yy + O[9] * zz + two * (O[4] * xy + O[5] * xz + O[8] * yz);
-        const T ORRR = rx * ORx + ry * ORy + rz * ORz;
-        const T tOR = (O[0] + O[3] + O[5]) * rx + (O[1] + O[6] + O[8]) * ry + (O[2] + O[7] + O[9]) * rz;
+        const T e = xx - zz, f = yy - zz, u = two * xy, v = two * xz, w2 = two * yz;
+        o7_rr(o, e, f, u, v, w2, ORx, ORy, ORz);
+        ORRR = rx * ORx + ry * ORy + rz * ORz;
         T dx = 0, dy = 0, dz = 0, w = 0;
         if (DIP) {
             dx = (T)D64[0];
@@ -401,11 +446,9 @@ __device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, co
             dz = (T)D64[2];
             w = dx * rx + dy * ry + dz * rz;
         }
-        // L0 = -[m f0 + 1/2 (f2 RQR + f1 trQ) - 1/6 (f3 ORRR + 3 f2 tOR)] (+ f1 w)
         const T m0 = DIP ? mB * f0 - f1 * w : mB * f0;
-        a.L0 -= m0 + half * (f2 * RQR + f1 * trQ) - (f3 * ORRR + three * f2 * tOR) * sixth;
-        // L1_a = -[m f1 R_a + 1/2 (f3 R_a RQR + f2 (2 QR_a + R_a trQ))] (+ f2 w R_a + f1 d_a)
-        const T c1 = (DIP ? mB * f1 - f2 * w : mB * f1) + half * (f3 * RQR + f2 * trQ);
+        a.L0 -= m0 + half * f2 * RQR - sixth * f3 * ORRR;
+        const T c1 = (DIP ? mB * f1 - f2 * w : mB * f1) + half * f3 * RQR;
         if (DIP) {
             a.L1[0] -= c1 * rx + f2 * QRx - f1 * dx;
             a.L1[1] -= c1 * ry + f2 * QRy - f1 * dy;
@@ -456,21 +499,28 @@ __device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, co
         }
     }
     if (!DIP && amc) {
-        // n = M3_B - mu M3_A; n : D4 = f4 R s + 3 f3 (v + R (t.R)) + 3 f2 t   (FP64)
-        double n[10];
-#pragma unroll
-        for (int k = 0; k < 10; ++k) n[k] = O64[k] - mu * OA[k];
+        const double xx = Rx * Rx, yy = Ry * Ry, zz = Rz * Rz;
+        const double e = xx - zz, f = yy - zz, u = 2.0 * (Rx * Ry), v = 2.0 * (Rx * Rz), w = 2.0 * (Ry * Rz);
+        double bx, by, bz, bR;  // O'_B : RR, O'_B : RRR in FP64
+        if constexpr (sizeof(T) == sizeof(double)) {
+            bx = (double)ORx;
+            by = (double)ORy;
+            bz = (double)ORz;
+            bR = (double)ORRR;
+        } else {
+            o7_rr(o64, e, f, u, v, w, bx, by, bz);
+            bR = bx * Rx + by * Ry + bz * Rz;
+        }
+        double ax, ay, az;
+        o7_rr(oA, e, f, u, v, w, ax, ay, az);
+        const double vx = bx - mu * ax, vy = by - mu * ay, vz = bz - mu * az;
+        const double sv = bR - mu * (ax * Rx + ay * Ry + az * Rz);
         const double d4 = -7.0 * d3 * ir2;
-        double vx, vy, vz, tx, ty, tz;
-        t3_uu(n, Rx, Ry, Rz, vx, vy, vz);
-        t3_trace(n, tx, ty, tz);
-        const double sv = vx * Rx + vy * Ry + vz * Rz;
-        const double tR = tx * Rx + ty * Ry + tz * Rz;
-        const double cR = d4 * sv + 3.0 * d3 * tR;
+        const double cR = d4 * sv, c3 = 3.0 * d3;
         constexpr double k6 = 1.0 / 6.0;
-        a.C[0] -= k6 * (cR * Rx + 3.0 * (d3 * vx + d2 * tx));
-        a.C[1] -= k6 * (cR * Ry + 3.0 * (d3 * vy + d2 * ty));
-        a.C[2] -= k6 * (cR * Rz + 3.0 * (d3 * vz + d2 * tz));
+        a.C[0] -= k6 * (cR * Rx + c3 * vx);
+        a.C[1] -= k6 * (cR * Ry + c3 * vy);
+        a.C[2] -= k6 * (cR * Rz + c3 * vz);
     }
 }
 
@@ -486,9 +536,10 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
     const size_t ti = (size_t)node * kCells + s;
     const double zAx = ld.mp[ti], zAy = ld.mp[S + ti], zAz = ld.mp[2 * S + ti];
     const double mA = ld.mass[ti];
-    double OA[10];
+    double OA[10], oA[7];
 #pragma unroll
     for (int k = 0; k < 10; ++k) OA[k] = DIP ? 0.0 : ld.mp[(9 + k) * S + ti];
+    detrace_o(OA, oA);
     const bool amc = !DIP && td.amc && mA > 0.0;
     const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
     Acc<T> a;
@@ -496,6 +547,7 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
     int cnt = 0;
     const int n_src_max = LEAF_TARGET ? ld.n_int : ld.n_rec;  // leaf <- leaf pairs are direct
     double Dp[3] = {0.0, 0.0, 0.0};
+    double q5[5], o7[7];
     if (ld.level == 0) {
         // root: every other root cell is a candidate; multipole iff well separated
         const int parts = LEAF_TARGET ? 1 : ld.n_parts;
@@ -515,8 +567,10 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
             for (int q = 0; q < 10; ++q) O[q] = ld.mp[(9 + q) * S + si];
             if (DIP)
                 for (int q = 0; q < 3; ++q) Dp[q] = ld.dip[q * S + si];
-            m2l_pair<LEAF_TARGET, DIP, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
-                                          Dp, mB * imA, OA, amc, a);
+            detrace_q(Q, q5);
+            detrace_o(O, o7);
+            m2l_pair<LEAF_TARGET, DIP, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, q5, o7,
+                                          Dp, mB * imA, oA, amc, a);
             ++cnt;
         }
     } else {
@@ -538,8 +592,10 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
             for (int q = 0; q < 10; ++q) O[q] = ld.mp[(9 + q) * S + si];
             if (DIP)
                 for (int q = 0; q < 3; ++q) Dp[q] = ld.dip[q * S + si];
-            m2l_pair<LEAF_TARGET, DIP, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, Q, O,
-                                          Dp, mB * imA, OA, amc, a);
+            detrace_q(Q, q5);
+            detrace_o(O, o7);
+            m2l_pair<LEAF_TARGET, DIP, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, q5, o7,
+                                          Dp, mB * imA, oA, amc, a);
             ++cnt;
         }
     }
@@ -593,11 +649,11 @@ __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, con
 
 // Multipole-to-local for all 512 cells of one interior node, with the source
 // halo staged in LDS one parity class at a time: the cells of one parity class
-// within 5 cells of the node form a 9x9x9 lattice (20 FP64 values each,
-// 117 KB); every wavefront (one target parity class) walks the part of its
-// stencil whose sources fall in the staged class.
-// DIP: second-source solve; each source cell also carries its dipole (23
-// values in 12 double2 planes), rows padded to 10 instead of 12 to fit LDS.
+// within 5 cells of the node form a 9x9x9 lattice; each staged cell holds its
+// mass, centre of mass and trace-free moments (16 FP64 values in 8 double2
+// planes, 124 KB; DIP: + the dipole, 10 planes, 155 KB).  Every wavefront (one
+// target parity class) walks the part of its stencil whose sources fall in
+// the staged class.
 template <typename T, bool DIP>
 __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                                  const M2LItem *__restrict__ items, int n_items, StencilDev st,
@@ -609,9 +665,9 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     const TreeDesc td = TD[ld.tree];
     const int node = item.node;
     // halo of one source class: 9x9x9 lattice, rows padded to 12 so that the
-    // 8 lanes of each 16-byte LDS read phase hit distinct banks
-    constexpr int NV = DIP ? 12 : 10;  // double2 planes per source cell
-    constexpr int HY = DIP ? 10 : 12, HX = 9 * HY, HN = 9 * 9 * HY;
+    // lanes of each 16-byte LDS read phase hit distinct banks
+    constexpr int NV = DIP ? 10 : 8;  // double2 planes per source cell
+    constexpr int HY = 12, HX = 9 * HY, HN = 9 * 9 * HY;
     __shared__ double2 s_src[NV][HN];
     __shared__ int s_nbr[27];
     __shared__ int s_cnt[8];
@@ -626,9 +682,10 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     const size_t ti = (size_t)node * kCells + s;
     const double zAx = ld.mp[ti], zAy = ld.mp[S + ti], zAz = ld.mp[2 * S + ti];
     const double mA = ld.mass[ti];
-    double OA[10];
+    double OA[10], oA[7];
 #pragma unroll
     for (int k = 0; k < 10; ++k) OA[k] = DIP ? 0.0 : ld.mp[(9 + k) * S + ti];
+    detrace_o(OA, oA);
     const bool amc = !DIP && td.amc && mA > 0.0;
     const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
     Acc<T> a;
@@ -642,10 +699,10 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
         const int qx = q >> 2, qy = (q >> 1) & 1, qz = q & 1;
         // stage source class q: lattice index i in [0,9) <-> local coordinate
         // 2i - 4 - parity; both cells of this thread are loaded before either
-        // is stored so that all 40 loads are in flight together.  Cells that
-        // are not sources get mass -0.0 (counted as absent, contributes
-        // exact zeros) and a far-away centre.
-        double v[2][2 * NV];
+        // is stored so that all loads are in flight together.  Cells that are
+        // not sources get mass -0.0 (counted as absent, contributes exact
+        // zeros) and a far-away centre.
+        double v[2][23];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int cc = tid + 512 * u;
@@ -657,17 +714,14 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
                 v[u][0] = ld.mass[si];
 #pragma unroll
                 for (int k = 0; k < kRec; ++k) v[u][1 + k] = ld.mp[k * S + si];
-                if (DIP) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) v[u][20 + k] = ld.dip[k * S + si];
-                }
+                for (int k = 0; k < 3; ++k) v[u][20 + k] = DIP ? ld.dip[k * S + si] : 0.0;
             } else {
                 v[u][0] = -0.0;
                 v[u][1] = v[u][2] = v[u][3] = 1.0e3;
 #pragma unroll
-                for (int k = 4; k < 20 + (DIP ? 3 : 0); ++k) v[u][k] = 0.0;
+                for (int k = 4; k < 23; ++k) v[u][k] = 0.0;
             }
-            if (DIP) v[u][23] = 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -675,8 +729,22 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
             if (cc < 729) {
                 const int ix = cc / 81, iy = (cc / 9) % 9, iz = cc % 9;
                 const int c = ix * HX + iy * HY + iz;
+                // record: m z(3) q5 o7 [d(3) 0]
+                double r[2 * NV];
+                r[0] = v[u][0];
+                r[1] = v[u][1];
+                r[2] = v[u][2];
+                r[3] = v[u][3];
+                detrace_q(&v[u][4], &r[4]);
+                detrace_o(&v[u][10], &r[9]);
+                if (DIP) {
+                    r[16 % (2 * NV)] = v[u][20];
+                    r[17 % (2 * NV)] = v[u][21];
+                    r[18 % (2 * NV)] = v[u][22];
+                    r[19 % (2 * NV)] = 0.0;
+                }
 #pragma unroll
-                for (int k = 0; k < NV; ++k) s_src[k][c] = make_double2(v[u][2 * k], v[u][2 * k + 1]);
+                for (int k = 0; k < NV; ++k) s_src[k][c] = make_double2(r[2 * k], r[2 * k + 1]);
             }
         }
         __syncthreads();
@@ -686,31 +754,16 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
             int dx, dy, dz;
             unpack(st.m2l_src[k], dx, dy, dz);
             const int h = ((x + dx + 5) >> 1) * HX + ((y + dy + 5) >> 1) * HY + ((z + dz + 5) >> 1);
-            const double2 e0 = s_src[0][h];
-            cnt += signbit(e0.x) ? 0 : 1;  // absent sources carry -0.0
-            const double2 e1 = s_src[1][h];
-            double Q[6], O[10];
-            const double2 e2 = s_src[2][h], e3 = s_src[3][h], e4 = s_src[4][h];
-            Q[0] = e2.x;
-            Q[1] = e2.y;
-            Q[2] = e3.x;
-            Q[3] = e3.y;
-            Q[4] = e4.x;
-            Q[5] = e4.y;
+            double r[2 * NV];
 #pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                const double2 e = s_src[5 + j][h];
-                O[2 * j] = e.x;
-                O[2 * j + 1] = e.y;
+            for (int j = 0; j < NV; ++j) {
+                const double2 e = s_src[j][h];
+                r[2 * j] = e.x;
+                r[2 * j + 1] = e.y;
             }
-            double Dp[3] = {0.0, 0.0, 0.0};
-            if (DIP) {
-                const double2 e10 = s_src[10 % NV][h], e11 = s_src[11 % NV][h];
-                Dp[0] = e10.x;
-                Dp[1] = e10.y;
-                Dp[2] = e11.x;
-            }
-            m2l_pair<false, DIP, T>(zAx - e0.y, zAy - e1.x, zAz - e1.y, e0.x, Q, O, Dp, e0.x * imA, OA, amc, a);
+            cnt += signbit(r[0]) ? 0 : 1;  // absent sources carry -0.0
+            m2l_pair<false, DIP, T>(zAx - r[1], zAy - r[2], zAz - r[3], r[0], &r[4], &r[9], &r[16 % (2 * NV)],
+                                    r[0] * imA, oA, amc, a);
         }
         __syncthreads();
     }
