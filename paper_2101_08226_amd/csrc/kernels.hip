@@ -647,6 +647,10 @@ __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, con
 }
 
 
+#ifndef OCTO_M2L_UNROLL
+#define OCTO_M2L_UNROLL 2
+#endif
+
 // Multipole-to-local for all 512 cells of one interior node, with the source
 // halo staged in LDS one parity class at a time: the cells of one parity class
 // within 5 cells of the node form a 9x9x9 lattice; each staged cell holds its
@@ -667,7 +671,7 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     // halo of one source class: 9x9x9 lattice, rows padded to 12 so that the
     // lanes of each 16-byte LDS read phase hit distinct banks
     constexpr int NV = DIP ? 10 : 8;  // double2 planes per source cell
-    constexpr int HY = 12, HX = 9 * HY, HN = 9 * 9 * HY;
+    constexpr int HY = kHaloY, HX = kHaloX, HN = kHaloN;
     __shared__ double2 s_src[NV][HN];
     __shared__ int s_nbr[27];
     __shared__ int s_cnt[8];
@@ -749,11 +753,12 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
         }
         __syncthreads();
         const int beg = st.m2l_src_beg[p * 9 + q], end = st.m2l_src_beg[p * 9 + q + 1];
-#pragma unroll 2
+        const int hb = (x >> 1) * HX + (y >> 1) * HY + (z >> 1);
+        // independent pairs interleaved per iteration (latency hiding at two
+        // waves per SIMD)
+#pragma unroll OCTO_M2L_UNROLL
         for (int k = beg; k < end; ++k) {
-            int dx, dy, dz;
-            unpack(st.m2l_src[k], dx, dy, dz);
-            const int h = ((x + dx + 5) >> 1) * HX + ((y + dy + 5) >> 1) * HY + ((z + dz + 5) >> 1);
+            const int h = hb + st.m2l_src[k];  // the offset is uniform over the wavefront
             double r[2 * NV];
 #pragma unroll
             for (int j = 0; j < NV; ++j) {

@@ -115,6 +115,32 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
         off_dip[l] = bytes;
         bytes += al((size_t)3 * h.n_rec * kCells * 8);
     }
+    // The LDS-staged levels share one launch: split each node's source parity
+    // classes into g groups (one work-group each) so that the launch fills
+    // whole rounds of the device's compute units (one work-group per CU at a
+    // time): time ~ rounds x classes per group.
+    {
+        int n_lds = 0, g_max = 8;
+        for (int l = 0; l < nl; ++l)
+            if (t->m2l_lds[l]) {
+                n_lds += L.lv[l].n_int;
+                g_max = std::min(g_max, t->parts_alloc[l]);
+            }
+        if (n_lds > 0) {
+            const int64_t cus = std::max(1, ctx->n_cu);
+            int best = 1;
+            int64_t best_cost = INT64_MAX;
+            for (int g = 1; g <= g_max; g *= 2) {
+                const int64_t cost = ((int64_t)n_lds * g + cus - 1) / cus * (8 / g);
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best = g;
+                }
+            }
+            for (int l = 0; l < nl; ++l)
+                if (t->m2l_lds[l]) t->parts[l] = best;
+        }
+    }
     const size_t off_rho = bytes;
     bytes += al((size_t)L.n_leaf_cells * 8);
     const size_t off_stage = bytes;
@@ -377,6 +403,9 @@ octo_status octo_ctx_create(int device, void *hip_stream, const octo_allocator *
         check_hip(hipEventCreateWithFlags(&c->fork_near_ev, hipEventDisableTiming), "event");
         check_hip(hipEventCreateWithFlags(&c->join_near_ev, hipEventDisableTiming), "event");
         if (const char *e = getenv("OCTO_GRAPHS")) c->use_graphs = atoi(e) != 0;
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+            c->n_cu = ncu;
         check_hip(hipEventCreate(&c->ev0), "event");
         for (int i = 0; i < 9; ++i) check_hip(hipEventCreate(&c->phase_ev[i]), "event");
         check_hip(hipEventCreate(&c->ev1), "event");

@@ -39,6 +39,9 @@ constexpr int kLoc = 23;
 constexpr int kLacc = 7;
 // per leaf work item partial sums: M, F (3), T (3), S_F, S_T
 constexpr int kStat = 9;
+// halo of one source parity class in the LDS-staged multipole kernel: a 9x9x9
+// lattice, rows padded to 12 (index ix * kHaloX + iy * kHaloY + iz)
+constexpr int kHaloY = 12, kHaloX = 9 * kHaloY, kHaloN = 9 * kHaloX;
 
 struct LevelDesc {
     int32_t level, n_nodes, n_int, n_rec;
@@ -98,7 +101,8 @@ struct StencilDev {
     const int32_t *leaf;   // m2l followed by near, with weights
     const double *leaf_w;  // 4 per leaf entry: 1/|d|, d/|d|^3
     const float *leaf_w32; // the same weights rounded to FP32 (mixed precision)
-    const int32_t *m2l_src;  // m2l entries regrouped by source parity class
+    const int32_t *m2l_src;  // m2l entries regrouped by source parity class, as halo offsets: the entry
+                             // (dx,dy,dz) of target class p reads halo index (x>>1, y>>1, z>>1) + offset
     const int32_t *leaf_hoff;  // leaf entries as offsets in an 18^3 halo: (dx*18 + dy)*18 + dz
     int32_t m2l_beg[9];
     int32_t near_beg[9];

@@ -176,6 +176,7 @@ struct Wave {
 
 struct octo_ctx {
     int device = 0;
+    int n_cu = 256;  // compute units of the device (sizes the multipole work shape)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool has_alloc = false;

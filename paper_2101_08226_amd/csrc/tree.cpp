@@ -320,14 +320,19 @@ Stencil make_stencil(double theta) {
     s.m2l_beg[8] = (int)s.m2l.size();
     s.near_beg[8] = (int)s.nearo.size();
     s.leaf_beg[8] = (int)s.leaf.size();
-    // the same multipole entries grouped by the parity class of the source cell
+    // the same multipole entries grouped by the parity class of the source
+    // cell, stored as offsets in the staged halo of that class: a target at
+    // x = 2i + px reads lattice index (x + dx + 5) >> 1 = i + ((px + dx + 5) >> 1),
+    // so the offset is the same for every cell of the target class
     for (int p = 0; p < 8; ++p) {
         int px = p >> 2, py = (p >> 1) & 1, pz = p & 1;
         for (int q = 0; q < 8; ++q) {
             s.m2l_src_beg[p * 9 + q] = (int)s.m2l_src.size();
             for (auto &d : m2l[p]) {
                 int qq = (((px + d[0]) & 1) << 2) | (((py + d[1]) & 1) << 1) | ((pz + d[2]) & 1);
-                if (qq == q) s.m2l_src.push_back(pack_off(d[0], d[1], d[2]));
+                if (qq == q)
+                    s.m2l_src.push_back(((px + d[0] + 5) >> 1) * kHaloX + ((py + d[1] + 5) >> 1) * kHaloY +
+                                        ((pz + d[2] + 5) >> 1));
             }
         }
         s.m2l_src_beg[p * 9 + 8] = (int)s.m2l_src.size();
