@@ -116,9 +116,11 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
         bytes += al((size_t)3 * h.n_rec * kCells * 8);
     }
     // The LDS-staged levels share one launch: split each node's source parity
-    // classes into g groups (one work-group each) so that the launch fills
-    // whole rounds of the device's compute units (one work-group per CU at a
-    // time): time ~ rounds x classes per group.
+    // classes into g groups (one work-group each, one work-group per CU at a
+    // time).  Time ~ rounds x classes per group (a round stages and walks
+    // one class per work-group) + the downward pass reading g partial slots
+    // per node; on MI355X one slot of one node costs about 0.002 of a
+    // class-round (c2: 23.6 us per class-round, 0.047 us per node-slot).
     {
         int n_lds = 0, g_max = 8;
         for (int l = 0; l < nl; ++l)
@@ -129,9 +131,10 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
         if (n_lds > 0) {
             const int64_t cus = std::max(1, ctx->n_cu);
             int best = 1;
-            int64_t best_cost = INT64_MAX;
+            double best_cost = 1e300;
             for (int g = 1; g <= g_max; g *= 2) {
-                const int64_t cost = ((int64_t)n_lds * g + cus - 1) / cus * (8 / g);
+                const double cost =
+                    (double)(((int64_t)n_lds * g + cus - 1) / cus * (8 / g)) + 0.002 * (double)n_lds * g;
                 if (cost < best_cost) {
                     best_cost = cost;
                     best = g;
