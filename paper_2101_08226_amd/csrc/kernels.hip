@@ -888,11 +888,51 @@ template <typename T>
 __device__ inline const T *weights(const StencilDev &st);
 template <>
 __device__ inline const double *weights<double>(const StencilDev &st) {
-    return st.leaf_w;
+    return st.leaf_tab;
 }
 template <>
 __device__ inline const float *weights<float>(const StencilDev &st) {
-    return st.leaf_w32;
+    return st.leaf_tab32;
+}
+
+// Near-field entries of one sign octant (SX, SY, SZ = +1 or -1: the signs of
+// d, zero counted as +1, applied at compile time to the |d| weights):
+// phi sum += m / |d|, g sums += m d / |d|^3, in blocks of 8 entries whose
+// offsets and weight indices are fetched together (uniform over the
+// wavefront: scalar loads), two accumulator sets.  COUNT: absent partners
+// carry mass -1 and are masked and counted.
+template <typename T, bool COUNT, int SX, int SY, int SZ>
+__device__ inline void near_octant(const T *__restrict__ s_m, int base, const int32_t *__restrict__ off,
+                                   const int32_t *__restrict__ widx, const T *__restrict__ tab, int beg, int end,
+                                   T *acc, int &cnt) {
+    auto add = [&](T m, const T *w, int set) {
+        T mm = m;
+        if (COUNT) {
+            const bool ok = m >= (T)0;
+            mm = ok ? m : (T)0;
+            cnt += ok ? 1 : 0;
+        }
+        T *a = acc + 4 * set;
+        a[0] += mm * w[0];
+        if (SX > 0) a[1] += mm * w[1]; else a[1] -= mm * w[1];
+        if (SY > 0) a[2] += mm * w[2]; else a[2] -= mm * w[2];
+        if (SZ > 0) a[3] += mm * w[3]; else a[3] -= mm * w[3];
+    };
+    int k = beg;
+    for (; k + 8 <= end; k += 8) {
+        int o[8], wi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            o[u] = off[k + u];
+            wi[u] = widx[k + u];
+        }
+        T m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m[u] = s_m[base + o[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) add(m[u], tab + 4 * wi[u], u & 1);
+    }
+    for (; k < end; ++k) add(s_m[base + off[k]], tab + 4 * widx[k], 0);
 }
 __device__ inline double rsqrt_t(double v) { return rsqrt(v); }
 
@@ -924,9 +964,10 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
     // wave-uniform (one wavefront per parity class): keep it in a scalar register
     const int p = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int node = item.node;
-    // masses of the 18^3 cells within 5 cells of this node; -1 where the cell
-    // is not a leaf of this level (absent or interior)
-    __shared__ T s_m[18 * 18 * 18];
+    // masses of the 18^3 cells within 5 cells of this node, split by parity
+    // class; -1 (COUNT) or 0 where the cell is not a leaf of this level
+    // (absent or interior)
+    __shared__ T s_m[kNearN];
     __shared__ int s_nbr[27];
     __shared__ int s_pnbr[27];
     if (tid < 27) {
@@ -947,8 +988,14 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
                                   : (T)(COUNT ? -1 : 0);
         }
 #pragma unroll
-        for (int u = 0; u < NU; ++u)
-            if (tid + 512 * u < NH) s_m[tid + 512 * u] = v[u];
+        for (int u = 0; u < NU; ++u) {
+            const int c = tid + 512 * u;
+            if (c < NH) {
+                const int ux = c / 324, uy = (c / 18) % 18, uz = c % 18;
+                const int q = ((ux & 1) << 2) | ((uy & 1) << 1) | (uz & 1);
+                s_m[q * kNearQ + (ux >> 1) * kNearX + (uy >> 1) * kNearY + (uz >> 1)] = v[u];
+            }
+        }
     }
     __syncthreads();
     const int s = tid;  // parity-major storage: wavefront p holds class p
@@ -961,7 +1008,6 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
 
     // same-level leaf partners: phi = -(1/h) sum m w0, g = (1/h^2) sum m w1
     T sp = 0, sgx = 0, sgy = 0, sgz = 0;
-    const T *lw = weights<T>(st);
     if (ld.level == 0) {
         for (int k = 0; k < kCells; ++k) {
             if (k == s) continue;
@@ -978,56 +1024,22 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
             ++cnt;
         }
     } else {
-        const int base = ((x + 5) * 18 + (y + 5)) * 18 + (z + 5);
-        const int beg = st.leaf_beg[p], end = st.leaf_beg[p + 1];
-        // blocks of 8 stencil entries: 8 LDS reads in flight, weights and
-        // offsets as scalar loads, absent partners (-1) masked arithmetically
-        T sp2 = 0, sgx2 = 0, sgy2 = 0, sgz2 = 0;
-        int k = beg;
-        for (; k + 8 <= end; k += 8) {
-            T m[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) m[u] = s_m[base + st.leaf_hoff[k + u]];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const T *w = lw + 4 * (k + u);
-                T mm = m[u];
-                if (COUNT) {
-                    const bool ok = m[u] >= (T)0;
-                    mm = ok ? m[u] : (T)0;
-                    cnt += ok ? 1 : 0;
-                }
-                if (u & 1) {
-                    sp2 += mm * w[0];
-                    sgx2 += mm * w[1];
-                    sgy2 += mm * w[2];
-                    sgz2 += mm * w[3];
-                } else {
-                    sp += mm * w[0];
-                    sgx += mm * w[1];
-                    sgy += mm * w[2];
-                    sgz += mm * w[3];
-                }
-            }
-        }
-        for (; k < end; ++k) {
-            const T m = s_m[base + st.leaf_hoff[k]];
-            T mm = m;
-            if (COUNT) {
-                const bool ok = m >= (T)0;
-                mm = ok ? m : (T)0;
-                cnt += ok ? 1 : 0;
-            }
-            const T *w = lw + 4 * k;
-            sp += mm * w[0];
-            sgx += mm * w[1];
-            sgy += mm * w[2];
-            sgz += mm * w[3];
-        }
-        sp += sp2;
-        sgx += sgx2;
-        sgy += sgy2;
-        sgz += sgz2;
+        const int base = (x >> 1) * kNearX + (y >> 1) * kNearY + (z >> 1);
+        const int *ob = st.leaf_oct_beg + p * 9;
+        const T *tab = weights<T>(st);
+        T acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        near_octant<T, COUNT, 1, 1, 1>(s_m, base, st.leaf_off, st.leaf_widx, tab, ob[0], ob[1], acc, cnt);
+        near_octant<T, COUNT, 1, 1, -1>(s_m, base, st.leaf_off, st.leaf_widx, tab, ob[1], ob[2], acc, cnt);
+        near_octant<T, COUNT, 1, -1, 1>(s_m, base, st.leaf_off, st.leaf_widx, tab, ob[2], ob[3], acc, cnt);
+        near_octant<T, COUNT, 1, -1, -1>(s_m, base, st.leaf_off, st.leaf_widx, tab, ob[3], ob[4], acc, cnt);
+        near_octant<T, COUNT, -1, 1, 1>(s_m, base, st.leaf_off, st.leaf_widx, tab, ob[4], ob[5], acc, cnt);
+        near_octant<T, COUNT, -1, 1, -1>(s_m, base, st.leaf_off, st.leaf_widx, tab, ob[5], ob[6], acc, cnt);
+        near_octant<T, COUNT, -1, -1, 1>(s_m, base, st.leaf_off, st.leaf_widx, tab, ob[6], ob[7], acc, cnt);
+        near_octant<T, COUNT, -1, -1, -1>(s_m, base, st.leaf_off, st.leaf_widx, tab, ob[7], ob[8], acc, cnt);
+        sp = acc[0] + acc[4];
+        sgx = acc[1] + acc[5];
+        sgy = acc[2] + acc[6];
+        sgz = acc[3] + acc[7];
     }
     const T ih = (T)(1.0 / h);
     T phi_t = -sp * ih;

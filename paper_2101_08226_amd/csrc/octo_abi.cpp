@@ -337,9 +337,10 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     auto h = std::make_unique<StencilDevHolder>();
     h->host = make_stencil(theta);
     const Stencil &S = h->host;
-    std::vector<float> w32(S.leaf_w.begin(), S.leaf_w.end());
-    size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_w.size() * 8) +
-               al(w32.size() * 4) + al(S.m2l_src.size() * 4) + al(S.leaf_hoff.size() * 4);
+    std::vector<float> w32(S.leaf_tab.begin(), S.leaf_tab.end());
+    size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_tab.size() * 8) +
+               al(w32.size() * 4) + al(S.m2l_src.size() * 4) + al(S.leaf_off.size() * 4) +
+               al(S.leaf_widx.size() * 4);
     void *mem = nullptr;
     check_hip(hipMalloc(&mem, b), "stencil alloc");
     h->block.ptr = mem;
@@ -355,10 +356,12 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     h->dev.m2l = (const int32_t *)put(S.m2l.data(), S.m2l.size() * 4);
     h->dev.nearo = (const int32_t *)put(S.nearo.data(), S.nearo.size() * 4);
     h->dev.leaf = (const int32_t *)put(S.leaf.data(), S.leaf.size() * 4);
-    h->dev.leaf_w = (const double *)put(S.leaf_w.data(), S.leaf_w.size() * 8);
-    h->dev.leaf_w32 = (const float *)put(w32.data(), w32.size() * 4);
+    h->dev.leaf_tab = (const double *)put(S.leaf_tab.data(), S.leaf_tab.size() * 8);
+    h->dev.leaf_tab32 = (const float *)put(w32.data(), w32.size() * 4);
     h->dev.m2l_src = (const int32_t *)put(S.m2l_src.data(), S.m2l_src.size() * 4);
-    h->dev.leaf_hoff = (const int32_t *)put(S.leaf_hoff.data(), S.leaf_hoff.size() * 4);
+    h->dev.leaf_off = (const int32_t *)put(S.leaf_off.data(), S.leaf_off.size() * 4);
+    h->dev.leaf_widx = (const int32_t *)put(S.leaf_widx.data(), S.leaf_widx.size() * 4);
+    for (int k = 0; k < 73; ++k) h->dev.leaf_oct_beg[k] = S.leaf_oct_beg[k];
     for (int k = 0; k < 73; ++k) h->dev.m2l_src_beg[k] = S.m2l_src_beg[k];
     for (int p = 0; p < 9; ++p) {
         h->dev.m2l_beg[p] = S.m2l_beg[p];

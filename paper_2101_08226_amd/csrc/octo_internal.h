@@ -42,6 +42,14 @@ constexpr int kStat = 9;
 // halo of one source parity class in the LDS-staged multipole kernel: a 9x9x9
 // lattice, rows padded to 12 (index ix * kHaloX + iy * kHaloY + iz)
 constexpr int kHaloY = 12, kHaloX = 9 * kHaloY, kHaloN = 9 * kHaloX;
+// leaf-mass halo of the near-field kernel: the 18^3 cells within 5 cells of a
+// node, split by parity class into eight 9x9x9 lattices (lattice index
+// (ux>>1, uy>>1, uz>>1) of halo cell u = local + 5 at ix * kNearX + iy * kNearY
+// + iz; rows and planes padded so that the lanes of a wavefront, one parity
+// class of targets, read distinct LDS banks), class q at q * kNearQ
+constexpr int kNearY = 12, kNearX = 112, kNearQ = 9 * kNearX, kNearN = 8 * kNearQ;
+// near-field weights by |d| pattern: index (|dx| * 6 + |dy|) * 6 + |dz|
+constexpr int kNearTab = 216;
 
 struct LevelDesc {
     int32_t level, n_nodes, n_int, n_rec;
@@ -98,15 +106,20 @@ struct NodeItem {
 struct StencilDev {
     const int32_t *m2l;    // well separated, parents not
     const int32_t *nearo;  // not well separated, parents not, d != 0
-    const int32_t *leaf;   // m2l followed by near, with weights
-    const double *leaf_w;  // 4 per leaf entry: 1/|d|, d/|d|^3
-    const float *leaf_w32; // the same weights rounded to FP32 (mixed precision)
+    const int32_t *leaf;   // m2l followed by near (packed offsets)
+    // near-field entries per target class, grouped by the sign octant o of d
+    // (o = (dx<0)<<2 | (dy<0)<<1 | (dz<0)): offset into the parity-split halo
+    // relative to the target's lattice position, and weight-table index
+    const int32_t *leaf_off;
+    const int32_t *leaf_widx;
+    const double *leaf_tab;   // kNearTab x 4: 1/|d|, |dx|/|d|^3, |dy|/|d|^3, |dz|/|d|^3
+    const float *leaf_tab32;  // the same weights rounded to FP32 (mixed precision)
     const int32_t *m2l_src;  // m2l entries regrouped by source parity class, as halo offsets: the entry
                              // (dx,dy,dz) of target class p reads halo index (x>>1, y>>1, z>>1) + offset
-    const int32_t *leaf_hoff;  // leaf entries as offsets in an 18^3 halo: (dx*18 + dy)*18 + dz
     int32_t m2l_beg[9];
     int32_t near_beg[9];
     int32_t leaf_beg[9];
+    int32_t leaf_oct_beg[73];  // target class p, octant o: [p*9+o, p*9+o+1)
     int32_t m2l_src_beg[73];  // target class p, source class q: [p*9+q, p*9+q+1)
     double theta2;
 };

@@ -2,6 +2,7 @@
 // refinement from a density field, interaction stencils and work plans.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <unordered_map>
 #include <unordered_set>
@@ -305,18 +306,46 @@ Stencil make_stencil(double theta) {
         for (auto &d : nr[p]) s.nearo.push_back(pack_off(d[0], d[1], d[2]));
         s.leaf_beg[p] = (int)s.leaf.size();
         for (int pass = 0; pass < 2; ++pass)
-            for (auto &d : (pass == 0 ? m2l[p] : nr[p])) {
-                s.leaf.push_back(pack_off(d[0], d[1], d[2]));
-                s.leaf_hoff.push_back((d[0] * 18 + d[1]) * 18 + d[2]);
-                double r = std::sqrt((double)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+            for (auto &d : (pass == 0 ? m2l[p] : nr[p])) s.leaf.push_back(pack_off(d[0], d[1], d[2]));
+    }
+    // near-field weights by |d| pattern (shared by all target classes, small
+    // enough to stay in the scalar cache)
+    s.leaf_tab.assign(kNearTab * 4, 0.0);
+    for (int a = 0; a <= 5; ++a)
+        for (int b = 0; b <= 5; ++b)
+            for (int c = 0; c <= 5; ++c) {
+                if (!(a | b | c)) continue;
+                double r = std::sqrt((double)(a * a + b * b + c * c));
                 double w0 = 1.0 / r;
                 double w3 = w0 * w0 * w0;
-                s.leaf_w.push_back(w0);
-                s.leaf_w.push_back(d[0] * w3);
-                s.leaf_w.push_back(d[1] * w3);
-                s.leaf_w.push_back(d[2] * w3);
+                double *t = &s.leaf_tab[4 * ((a * 6 + b) * 6 + c)];
+                t[0] = w0;
+                t[1] = a * w3;
+                t[2] = b * w3;
+                t[3] = c * w3;
             }
+    // near-field entries per target class grouped by sign octant, as offsets
+    // into the parity-split halo: a target at x = 2i + px reads halo cell
+    // ux = x + dx + 5, of class (px + dx + 5) & 1 at lattice index
+    // i + ((px + dx + 5) >> 1), so the offset is the same for every cell of
+    // the class
+    for (int p = 0; p < 8; ++p) {
+        int px = p >> 2, py = (p >> 1) & 1, pz = p & 1;
+        for (int o = 0; o < 8; ++o) {
+            s.leaf_oct_beg[p * 9 + o] = (int)s.leaf_off.size();
+            for (int pass = 0; pass < 2; ++pass)
+                for (auto &d : (pass == 0 ? m2l[p] : nr[p])) {
+                    int od = ((d[0] < 0) << 2) | ((d[1] < 0) << 1) | (d[2] < 0);
+                    if (od != o) continue;
+                    int ux = px + d[0] + 5, uy = py + d[1] + 5, uz = pz + d[2] + 5;
+                    int q = ((ux & 1) << 2) | ((uy & 1) << 1) | (uz & 1);
+                    s.leaf_off.push_back(q * kNearQ + (ux >> 1) * kNearX + (uy >> 1) * kNearY + (uz >> 1));
+                    s.leaf_widx.push_back((std::abs(d[0]) * 6 + std::abs(d[1])) * 6 + std::abs(d[2]));
+                }
+        }
+        s.leaf_oct_beg[p * 9 + 8] = (int)s.leaf_off.size();
     }
+    s.leaf_oct_beg[72] = (int)s.leaf_off.size();
     s.m2l_beg[8] = (int)s.m2l.size();
     s.near_beg[8] = (int)s.nearo.size();
     s.leaf_beg[8] = (int)s.leaf.size();
