@@ -899,8 +899,10 @@ __device__ inline const float *weights<float>(const StencilDev &st) {
 // d, zero counted as +1, applied at compile time to the |d| weights):
 // phi sum += m / |d|, g sums += m d / |d|^3, in blocks of 8 entries whose
 // offsets and weight indices are fetched together (uniform over the
-// wavefront: scalar loads), two accumulator sets.  COUNT: absent partners
-// carry mass -1 and are masked and counted.
+// wavefront: scalar loads), two accumulator sets.  Each octant's list is
+// padded to whole blocks with zero-weight entries (weight row 0).  COUNT:
+// absent partners carry mass -1 and are masked; real entries (w0 > 0) with
+// a present partner are counted.
 template <typename T, bool COUNT, int SX, int SY, int SZ>
 __device__ inline void near_octant(const T *__restrict__ s_m, int base, const int32_t *__restrict__ off,
                                    const int32_t *__restrict__ widx, const T *__restrict__ tab, int beg, int end,
@@ -910,7 +912,7 @@ __device__ inline void near_octant(const T *__restrict__ s_m, int base, const in
         if (COUNT) {
             const bool ok = m >= (T)0;
             mm = ok ? m : (T)0;
-            cnt += ok ? 1 : 0;
+            cnt += (ok && w[0] > (T)0) ? 1 : 0;
         }
         T *a = acc + 4 * set;
         a[0] += mm * w[0];
@@ -918,8 +920,12 @@ __device__ inline void near_octant(const T *__restrict__ s_m, int base, const in
         if (SY > 0) a[2] += mm * w[2]; else a[2] -= mm * w[2];
         if (SZ > 0) a[3] += mm * w[3]; else a[3] -= mm * w[3];
     };
-    int k = beg;
-    for (; k + 8 <= end; k += 8) {
+    // weight rows addressed by an unsigned 32-bit byte offset from the table
+    // base, so the scalar load takes it as its offset operand
+    auto row = [&](int wi) {
+        return (const T *)((const char *)tab + (unsigned)wi * (unsigned)(4 * sizeof(T)));
+    };
+    for (int k = beg; k < end; k += 8) {
         int o[8], wi[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -930,9 +936,8 @@ __device__ inline void near_octant(const T *__restrict__ s_m, int base, const in
 #pragma unroll
         for (int u = 0; u < 8; ++u) m[u] = s_m[base + o[u]];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) add(m[u], tab + 4 * wi[u], u & 1);
+        for (int u = 0; u < 8; ++u) add(m[u], row(wi[u]), u & 1);
     }
-    for (; k < end; ++k) add(s_m[base + off[k]], tab + 4 * widx[k], 0);
 }
 __device__ inline double rsqrt_t(double v) { return rsqrt(v); }
 

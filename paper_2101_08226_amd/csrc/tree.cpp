@@ -342,6 +342,12 @@ Stencil make_stencil(double theta) {
                     s.leaf_off.push_back(q * kNearQ + (ux >> 1) * kNearX + (uy >> 1) * kNearY + (uz >> 1));
                     s.leaf_widx.push_back((std::abs(d[0]) * 6 + std::abs(d[1])) * 6 + std::abs(d[2]));
                 }
+            // pad to whole blocks of 8 with entries of zero weight (row 0,
+            // d = 0) that read the target's own halo cell
+            while ((s.leaf_off.size() - s.leaf_oct_beg[p * 9 + o]) % 8) {
+                s.leaf_off.push_back(0);
+                s.leaf_widx.push_back(0);
+            }
         }
         s.leaf_oct_beg[p * 9 + 8] = (int)s.leaf_off.size();
     }
