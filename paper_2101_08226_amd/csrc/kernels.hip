@@ -577,7 +577,12 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
         const int beg = st.m2l_beg[p], len = st.m2l_beg[p + 1] - beg;
         const int parts = LEAF_TARGET ? 1 : ld.n_parts;
         const int k0 = beg + len * item.chunk / parts, k1 = beg + len * (item.chunk + 1) / parts;
+        // neighbour sub-grids holding sources for this target (uniform)
+        int src_mask = 0;
+        for (int b = 0; b < 27; ++b) src_mask |= (s_nbr[b] >= 0 && s_nbr[b] < n_src_max) ? (1 << b) : 0;
+        src_mask = __builtin_amdgcn_readfirstlane(src_mask);
         for (int k = k0; k < k1; ++k) {
+            if (!(st.m2l_touch[k] & src_mask)) continue;  // no lane reaches a source
             int dx, dy, dz;
             unpack(st.m2l[k], dx, dy, dz);
             const int sx = x + dx, sy = y + dy, sz = z + dz;
@@ -1055,7 +1060,11 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
         // interior cells B of this level, near (not well separated, parents not): sum over B's children
         const LevelDesc cl = L[ld.child_ld >= 0 ? ld.child_ld : item.ld];
         const int beg = st.near_beg[p], end = st.near_beg[p + 1];
+        int int_mask = 0;  // neighbour sub-grids that are interior (uniform)
+        for (int b = 0; b < 27; ++b) int_mask |= (s_nbr[b] >= 0 && s_nbr[b] < ld.n_int) ? (1 << b) : 0;
+        int_mask = __builtin_amdgcn_readfirstlane(int_mask);
         for (int k = beg; k < end; ++k) {
+            if (!(st.near_touch[k] & int_mask)) continue;  // no lane reaches an interior cell
             int dx, dy, dz;
             unpack(st.nearo[k], dx, dy, dz);
             const int sx = x + dx, sy = y + dy, sz = z + dz;

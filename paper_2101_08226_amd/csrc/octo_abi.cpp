@@ -340,7 +340,7 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     std::vector<float> w32(S.leaf_tab.begin(), S.leaf_tab.end());
     size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_tab.size() * 8) +
                al(w32.size() * 4) + al(S.m2l_src.size() * 4) + al(S.leaf_off.size() * 4) +
-               al(S.leaf_widx.size() * 4);
+               al(S.leaf_widx.size() * 4) + al(S.m2l_touch.size() * 4) + al(S.near_touch.size() * 4);
     void *mem = nullptr;
     check_hip(hipMalloc(&mem, b), "stencil alloc");
     h->block.ptr = mem;
@@ -355,6 +355,8 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     };
     h->dev.m2l = (const int32_t *)put(S.m2l.data(), S.m2l.size() * 4);
     h->dev.nearo = (const int32_t *)put(S.nearo.data(), S.nearo.size() * 4);
+    h->dev.m2l_touch = (const int32_t *)put(S.m2l_touch.data(), S.m2l_touch.size() * 4);
+    h->dev.near_touch = (const int32_t *)put(S.near_touch.data(), S.near_touch.size() * 4);
     h->dev.leaf = (const int32_t *)put(S.leaf.data(), S.leaf.size() * 4);
     h->dev.leaf_tab = (const double *)put(S.leaf_tab.data(), S.leaf_tab.size() * 8);
     h->dev.leaf_tab32 = (const float *)put(w32.data(), w32.size() * 4);

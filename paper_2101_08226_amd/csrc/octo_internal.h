@@ -106,6 +106,8 @@ struct NodeItem {
 struct StencilDev {
     const int32_t *m2l;    // well separated, parents not
     const int32_t *nearo;  // not well separated, parents not, d != 0
+    const int32_t *m2l_touch;   // per m2l entry: mask of the 27 neighbour sub-grids it reaches from the class
+    const int32_t *near_touch;  // the same for the near entries
     const int32_t *leaf;   // m2l followed by near (packed offsets)
     // near-field entries per target class, grouped by the sign octant o of d
     // (o = (dx<0)<<2 | (dy<0)<<1 | (dz<0)): offset into the parity-split halo

@@ -299,11 +299,32 @@ Stencil make_stencil(double theta) {
                         nr[p].push_back({dx, dy, dz});
                 }
     }
+    // neighbour sub-grids (slot (ox+1)*9 + (oy+1)*3 + oz+1) that an entry
+    // reaches from any cell of target class p: a wavefront skips the entry
+    // when none of them holds a source
+    auto touch = [](int p, const std::array<int, 3> &d) {
+        int px = p >> 2, py = (p >> 1) & 1, pz = p & 1;
+        int32_t m = 0;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j)
+                for (int k = 0; k < 4; ++k) {
+                    int sx = 2 * i + px + d[0], sy = 2 * j + py + d[1], sz = 2 * k + pz + d[2];
+                    auto o = [](int v) { return v < 0 ? 0 : (v < 8 ? 1 : 2); };
+                    m |= 1 << (o(sx) * 9 + o(sy) * 3 + o(sz));
+                }
+        return m;
+    };
     for (int p = 0; p < 8; ++p) {
         s.m2l_beg[p] = (int)s.m2l.size();
-        for (auto &d : m2l[p]) s.m2l.push_back(pack_off(d[0], d[1], d[2]));
+        for (auto &d : m2l[p]) {
+            s.m2l.push_back(pack_off(d[0], d[1], d[2]));
+            s.m2l_touch.push_back(touch(p, d));
+        }
         s.near_beg[p] = (int)s.nearo.size();
-        for (auto &d : nr[p]) s.nearo.push_back(pack_off(d[0], d[1], d[2]));
+        for (auto &d : nr[p]) {
+            s.nearo.push_back(pack_off(d[0], d[1], d[2]));
+            s.near_touch.push_back(touch(p, d));
+        }
         s.leaf_beg[p] = (int)s.leaf.size();
         for (int pass = 0; pass < 2; ++pass)
             for (auto &d : (pass == 0 ? m2l[p] : nr[p])) s.leaf.push_back(pack_off(d[0], d[1], d[2]));
