@@ -25,6 +25,12 @@
  * context's allocator (or hipMalloc when none is given) at tree-build time; a
  * solve allocates nothing.
  *
+ * Threads: calls on one context are serialised by a lock inside the
+ * context.  octo_tree_build and octo_tree_build_adaptive validate the leaf
+ * list, check the density and lay the tree out before taking that lock, so
+ * several host threads may build trees for one context at the same time
+ * (the part that allocates and uploads is serialised).
+ *
  * Errors: every call returns an octo_status; nothing throws or aborts across
  * this interface.  octo_last_error() returns a thread-local description of the
  * last failure on the calling thread.

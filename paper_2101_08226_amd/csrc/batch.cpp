@@ -172,10 +172,30 @@ void octo_ctx::release_batch(BatchPlan *bp) {
     if (!bp) return;
     drop_graphs(bp->graphs);
     if (bp->mem) dev_free(bp->mem, bp->bytes);
-    if (bp->staging) hipHostFree(bp->staging);
+    if (bp->staging) pinned_put(bp->staging, bp->staging_bytes);
     bp->mem = nullptr;
     bp->staging = nullptr;
 }
+
+void *octo_ctx::pinned_get(size_t bytes, size_t *got) {
+    size_t best = pinned_free.size();
+    for (size_t i = 0; i < pinned_free.size(); ++i)
+        if (pinned_free[i].second >= bytes && (best == pinned_free.size() || pinned_free[i].second < pinned_free[best].second))
+            best = i;
+    if (best < pinned_free.size()) {
+        auto b = pinned_free[best];
+        pinned_free.erase(pinned_free.begin() + best);
+        *got = b.second;
+        return b.first;
+    }
+    const size_t n = std::max(bytes, (size_t)1 << 20);
+    void *p = nullptr;
+    check_hip(hipHostMalloc(&p, n, hipHostMallocDefault), "pinned staging");
+    *got = n;
+    return p;
+}
+
+void octo_ctx::pinned_put(void *p, size_t bytes) { pinned_free.emplace_back(p, bytes); }
 
 void octo_ctx::invalidate_batches() {
     if (batch) {
@@ -276,7 +296,7 @@ static void pump(octo_ctx *ctx) {
         bp->mem = mem;
         bp->bytes = bytes;
         plan_layout(bp->ph, mem, bp->plan, img);
-        check_hip(hipHostMalloc(&bp->staging, img.size(), hipHostMallocDefault), "pinned staging");
+        bp->staging = ctx->pinned_get(img.size(), &bp->staging_bytes);
         memcpy(bp->staging, img.data(), img.size());
         check_hip(hipMemcpyAsync(mem, bp->staging, img.size(), hipMemcpyHostToDevice, ctx->stream), "wave upload");
         const StencilDevHolder &st = ctx->stencil(theta);
@@ -292,6 +312,7 @@ static void pump(octo_ctx *ctx) {
         Wave w;
         check_hip(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "event");
         check_hip(hipEventRecord(w.done, ctx->stream), "event");
+        for (octo_tree *t : trees) check_hip(hipEventRecord(t->last_use, ctx->stream), "event");
         w.tickets = take;
         w.bp = std::move(bp);
         const int id = ctx->next_wave++;
@@ -312,6 +333,8 @@ octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, 
     return guard_b([&] {
         if (!ctx || !trees || n <= 0 || !phi || !g) fail(OCTO_E_INVALID, "bad batch arguments");
         validate(opts);
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+
         std::set<octo_tree *> seen;
         for (int i = 0; i < n; ++i) {
             if (!trees[i] || !phi[i] || !g[i]) fail(OCTO_E_INVALID, "NULL tree or output in batch");
@@ -340,6 +363,7 @@ octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, 
         }
         if (stats) check_hip(hipEventRecord(ctx->ev0, ctx->stream), "event");
         run_plan(ctx, bp.plan, bp.graphs, want, opts, stats != nullptr);
+        for (int i = 0; i < n; ++i) check_hip(hipEventRecord(trees[i]->last_use, ctx->stream), "event");
         if (stats) {
             check_hip(hipEventRecord(ctx->ev1, ctx->stream), "event");
             if ((size_t)n * 12 > ctx->h_stats_cap) fail(OCTO_E_INVALID, "batch too large for statistics");
@@ -370,6 +394,8 @@ octo_status octo_submit(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, d
         if (!ctx || !tree || !phi_dev || !g_dev || !ticket) fail(OCTO_E_INVALID, "NULL argument");
         if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
         validate(opts);
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+
         hipSetDevice(ctx->device);
         Request r{};
         r.ticket = ctx->next_ticket++;
@@ -393,6 +419,7 @@ octo_status octo_submit(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, d
 octo_status octo_poll(octo_ctx *ctx, octo_ticket ticket, int *done) {
     return guard_b([&] {
         if (!ctx || !done) fail(OCTO_E_INVALID, "NULL argument");
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         auto it = ctx->requests.find(ticket);
         if (it == ctx->requests.end()) fail(OCTO_E_INVALID, "unknown ticket");
         hipSetDevice(ctx->device);
@@ -405,6 +432,7 @@ octo_status octo_poll(octo_ctx *ctx, octo_ticket ticket, int *done) {
 octo_status octo_wait(octo_ctx *ctx, octo_ticket ticket, octo_stats *stats) {
     return guard_b([&] {
         if (!ctx) fail(OCTO_E_INVALID, "NULL argument");
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         auto it = ctx->requests.find(ticket);
         if (it == ctx->requests.end()) fail(OCTO_E_INVALID, "unknown ticket");
         hipSetDevice(ctx->device);

@@ -447,6 +447,7 @@ octo_status octo_ctx_destroy(octo_ctx *ctx) {
         for (int i = 0; i < 9; ++i) hipEventDestroy(ctx->phase_ev[i]);
         hipEventDestroy(ctx->ev1);
         hipHostFree(ctx->h_stats);
+        for (auto &b : ctx->pinned_free) hipHostFree(b.first);
         if (ctx->own_stream) hipStreamDestroy(ctx->stream);
         delete ctx;
     });
@@ -455,6 +456,7 @@ octo_status octo_ctx_destroy(octo_ctx *ctx) {
 octo_status octo_ctx_set_profiling(octo_ctx *ctx, int on) {
     return guard([&] {
         if (!ctx) fail(OCTO_E_INVALID, "ctx is NULL");
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         ctx->profiling = on != 0;
     });
 }
@@ -462,6 +464,7 @@ octo_status octo_ctx_set_profiling(octo_ctx *ctx, int on) {
 octo_status octo_ctx_memory(const octo_ctx *ctx, size_t *bytes_in_use, size_t *budget) {
     return guard([&] {
         if (!ctx) fail(OCTO_E_INVALID, "ctx is NULL");
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         if (bytes_in_use) *bytes_in_use = ctx->in_use;
         if (budget) *budget = ctx->budget;
     });
@@ -473,12 +476,16 @@ static octo_status make_tree(octo_ctx *ctx, const octo_leaf *leaves, int64_t n, 
                              int rho_on_device, octo_tree **out) {
     return guard([&] {
         if (!ctx || !out || !rho) fail(OCTO_E_INVALID, "NULL argument");
-        DeviceGuard dg(ctx->device);
         auto t = std::make_unique<octo_tree>();
         t->ctx = ctx;
+        // validation and layout need no device and no context state
         t->layout = build_layout(leaves, n, grid_level);
         if (!rho_on_device) check_density_host(rho, t->layout.n_leaf_cells);
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        DeviceGuard dg(ctx->device);
         finish_tree(t.get(), rho, rho_on_device);
+        check_hip(hipEventCreateWithFlags(&t->last_use, hipEventDisableTiming), "event");
+        check_hip(hipEventRecord(t->last_use, ctx->stream), "event");
         ctx->n_trees++;
         *out = t.release();
     });
@@ -539,11 +546,13 @@ octo_status octo_tree_build_adaptive(octo_ctx *ctx, octo_density_fn density, oct
 octo_status octo_tree_set_density(octo_tree *t, const double *rho, int rho_on_device) {
     return guard([&] {
         if (!t || !rho) fail(OCTO_E_INVALID, "NULL argument");
-        DeviceGuard dg(t->ctx->device);
         if (!rho_on_device) check_density_host(rho, t->layout.n_leaf_cells);
+        std::lock_guard<std::recursive_mutex> lk(t->ctx->mu);
+        DeviceGuard dg(t->ctx->device);
         check_hip(hipMemcpyAsync(t->rho, rho, (size_t)t->layout.n_leaf_cells * 8,
                                  rho_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, t->ctx->stream),
                   "density upload");
+        check_hip(hipEventRecord(t->last_use, t->ctx->stream), "event");
         if (!rho_on_device) check_hip(hipStreamSynchronize(t->ctx->stream), "density upload");
     });
 }
@@ -567,11 +576,14 @@ octo_status octo_tree_leaves(const octo_tree *t, octo_leaf *out) {
 octo_status octo_tree_destroy(octo_tree *t) {
     return guard([&] {
         if (!t) return;
+        std::lock_guard<std::recursive_mutex> lk(t->ctx->mu);
         DeviceGuard dg(t->ctx->device);
         for (auto &kv : t->ctx->requests)
             if (kv.second.tree == t && !kv.second.done)
                 fail(OCTO_E_STATE, "tree has an unfinished request");
-        hipStreamSynchronize(t->ctx->stream);
+        // the tree's own last work, not everything queued on the stream since
+        hipEventSynchronize(t->last_use);
+        hipEventDestroy(t->last_use);
         if (t->ctx->batch &&
             std::find(t->ctx->batch->sig.begin(), t->ctx->batch->sig.end(), t) != t->ctx->batch->sig.end())
             t->ctx->invalidate_batches();
@@ -592,6 +604,8 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
         if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
         validate_opts(opts);
         if (!phi || !g) fail(OCTO_E_INVALID, "NULL output");
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+
         DeviceGuard dg(ctx->device);
         const int64_t n = tree->layout.n_leaf_cells;
         std::vector<TreeDesc> want = tree->plan.trees_host;
@@ -601,6 +615,7 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
         want[0].amc = opts->amc ? 1 : 0;
         if (stats) check_hip(hipEventRecord(ctx->ev0, ctx->stream), "event");
         run_plan(ctx, tree->plan, tree->graphs, want, opts, stats != nullptr);
+        check_hip(hipEventRecord(tree->last_use, ctx->stream), "event");
         if (stats) {
             check_hip(hipEventRecord(ctx->ev1, ctx->stream), "event");
             check_hip(hipMemcpyAsync(ctx->h_stats, tree->plan.d_out, 12 * sizeof(double), hipMemcpyDeviceToHost,
@@ -638,6 +653,8 @@ octo_status octo_solve_dphidt(octo_ctx *ctx, octo_tree *tree, const octo_opts *o
         if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
         validate_opts(opts);
         if (!drho_dt || !dphi_dt) fail(OCTO_E_INVALID, "NULL source or output");
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+
         DeviceGuard dg(ctx->device);
         std::vector<TreeDesc> want = tree->plan.trees_host;
         want[0].phi = dphi_dt;
@@ -646,6 +663,7 @@ octo_status octo_solve_dphidt(octo_ctx *ctx, octo_tree *tree, const octo_opts *o
         want[0].G = opts->G;
         want[0].amc = 0;
         run_plan(ctx, tree->plan, tree->graphs, want, opts, false, true);
+        check_hip(hipEventRecord(tree->last_use, ctx->stream), "event");
     });
 }
 
@@ -656,10 +674,12 @@ octo_status octo_gravity_sources(octo_ctx *ctx, octo_tree *tree, const double *o
         if (!ctx || !tree || !omega || !rho || !s || !phi || !g || !src_s || !src_e)
             fail(OCTO_E_INVALID, "NULL argument");
         if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         for (int k = 0; k < 3; ++k)
             if (!std::isfinite(omega[k])) fail(OCTO_E_INVALID, "omega not finite");
         DeviceGuard dg(ctx->device);
         launch_sources(tree->plan, omega, rho, s, phi, g, drho_dt, dphi_dt, src_s, src_e, ctx->stream);
+        check_hip(hipEventRecord(tree->last_use, ctx->stream), "event");
     });
 }
 
@@ -668,6 +688,8 @@ octo_status octo_energy_update(octo_ctx *ctx, octo_tree *tree, const double *rho
     return guard([&] {
         if (!ctx || !tree || !rho || !phi_before || !phi_after || !E) fail(OCTO_E_INVALID, "NULL argument");
         if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+
         DeviceGuard dg(ctx->device);
         launch_energy_update(tree->layout.n_leaf_cells, rho, phi_before, phi_after, E, ctx->stream);
     });
@@ -681,6 +703,7 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
         if (!ctx || !tree) fail(OCTO_E_INVALID, "NULL argument");
         if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
         validate_opts(opts);
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         DeviceGuard dg(ctx->device);
         if (ctx->batch &&
             std::find(ctx->batch->sig.begin(), ctx->batch->sig.end(), tree) != ctx->batch->sig.end())
@@ -697,6 +720,7 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
             double best = 1e30;
             for (int rep = 0; rep < 4; ++rep) {
                 run_plan(ctx, tree->plan, tree->graphs, want, opts, false);
+                check_hip(hipEventRecord(tree->last_use, ctx->stream), "event");
                 check_hip(hipStreamSynchronize(ctx->stream), "autotune");
                 float ms = 0.f;
                 hipEventElapsedTime(&ms, ctx->phase_ev[3], ctx->phase_ev[4]);

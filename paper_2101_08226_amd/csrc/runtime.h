@@ -8,6 +8,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -151,7 +152,8 @@ struct BatchPlan {
     void *mem = nullptr;
     size_t bytes = 0;
     std::map<std::pair<uint64_t, int>, hipGraphExec_t> graphs;  // (theta bits, precision)
-    void *staging = nullptr;  // pinned upload image (asynchronous waves)
+    void *staging = nullptr;  // pinned upload image (asynchronous waves), from the context's pool
+    size_t staging_bytes = 0;
     std::vector<double> stats;  // per tree, 12 values, after completion
 };
 
@@ -176,6 +178,9 @@ struct Wave {
 }  // namespace octo
 
 struct octo_ctx {
+    // serialises every call that touches the context (several threads may
+    // build trees at once: validation and layout happen before the lock)
+    mutable std::recursive_mutex mu;
     int device = 0;
     int n_cu = 256;  // compute units of the device (sizes the multipole work shape)
     hipStream_t stream = nullptr;
@@ -195,6 +200,11 @@ struct octo_ctx {
     bool profiling = false;
     hipEvent_t phase_ev[9] = {};
     double *h_stats = nullptr;  // pinned host staging for stats
+    // pinned upload buffers of finished waves, reused (freeing pinned memory
+    // can wait for the device)
+    std::vector<std::pair<void *, size_t>> pinned_free;
+    void *pinned_get(size_t bytes, size_t *got);
+    void pinned_put(void *p, size_t bytes);
     size_t h_stats_cap = 0;
     // last batch signature (octo_solve_batch)
     std::unique_ptr<octo::BatchPlan> batch;
@@ -225,6 +235,7 @@ struct octo_tree {
     std::vector<int> parts_alloc, parts, m2l_lds;  // per level: multipole work choices
     double *rho = nullptr;
     double *stage = nullptr;  // device staging of phi, g for host outputs
+    hipEvent_t last_use = nullptr;  // recorded after the last work enqueued on the tree's memory
     size_t bytes = 0;
     std::map<std::pair<uint64_t, int>, hipGraphExec_t> graphs;  // (theta bits, precision)
 };

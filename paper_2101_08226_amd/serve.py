@@ -1,23 +1,27 @@
 """Request server: solves of differently sized octrees arriving over time.
 
 Each request carries its tree (leaf list and leaf-cell densities, prepared by
-the client).  The server admits requests in arrival order while the context's
-HBM budget holds their trees (octo_tree_build fails with OCTO_E_BUDGET when it
-does not), submits them with octo_submit -- the library merges requests that
-are pending while earlier ones run into its next launch wave (continuous
-batching) -- polls for completions, releases finished trees, and records the
-latency from arrival to result.
+the client).  The server builds the trees of arrived requests on a pool of
+host threads (the library validates and lays out a tree before taking the
+context's lock, so builds run in parallel), admits them in arrival order
+while the context's HBM budget holds their trees (a build fails with
+OCTO_E_BUDGET when it does not), submits them with octo_submit -- the library
+merges requests that are pending while earlier ones run into its next launch
+wave (continuous batching) -- polls for completions, releases finished trees,
+and records the latency from arrival to result.
 """
 from __future__ import annotations
 
 import time
+from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import List, Optional
 
 import numpy as np
 
 from . import (OCTO_E_BUDGET, Context, OctoError, Tree, make_opts, octo_poll, octo_submit, octo_tree_build,
-               octo_wait)
+               octo_tree_destroy, octo_wait)
 
 
 @dataclass
@@ -45,58 +49,106 @@ class Record:
         return self.done - self.arrival
 
 
+class _Slot:
+    """A queued request and its tree build (a future of a tree handle)."""
+
+    def __init__(self, p: Payload):
+        self.p = p
+        self.build = None
+
+
 def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, poll_sleep: float = 2e-4,
-          time_limit: Optional[float] = None):
+          time_limit: Optional[float] = None, builders: int = 8, lookahead: int = 16):
     """Run the stream in real time; returns (records, outputs by index if
-    keep_outputs, wall seconds)."""
+    keep_outputs, wall seconds).  `builders` host threads build the trees of
+    up to `lookahead` queued requests ahead of admission."""
     import torch
+
+    def build(p: Payload) -> int:
+        return octo_tree_build(ctx.handle, p.leaves, p.rho.ctypes.data, False)
 
     pending = sorted(payloads, key=lambda p: p.arrival)
     nxt = 0
-    queue: List[Payload] = []
+    queue: deque = deque()
     inflight = {}  # ticket -> (payload, tree, phi, g, admitted)
     records: List[Record] = []
     outputs = {}
+    pool = ThreadPoolExecutor(max_workers=max(1, builders))
     t0 = time.perf_counter()
-    while nxt < len(pending) or queue or inflight:
-        now = time.perf_counter() - t0
-        if time_limit is not None and now > time_limit:
-            raise TimeoutError(f"serving exceeded {time_limit} s")
-        while nxt < len(pending) and pending[nxt].arrival <= now:
-            queue.append(pending[nxt])
-            nxt += 1
-        # admission in arrival order while the budget holds
-        while queue:
-            p = queue[0]
-            try:
-                h = octo_tree_build(ctx.handle, p.leaves, p.rho.ctypes.data, False)
-            except OctoError as e:
-                if e.status == OCTO_E_BUDGET and inflight:
-                    break  # wait for completions to free memory
-                raise
-            tree = Tree(ctx, h)
-            phi = torch.empty(tree.n_leaf_cells, dtype=torch.float64, device=ctx.device)
-            g = torch.empty((3, tree.n_leaf_cells), dtype=torch.float64, device=ctx.device)
-            tk = octo_submit(ctx.handle, h, make_opts(p.theta, 1.0, p.precision, True), phi.data_ptr(), g.data_ptr())
-            inflight[tk] = (p, tree, phi, g, time.perf_counter() - t0)
-            queue.pop(0)
-        # completions
-        progressed = False
-        for tk in list(inflight):
-            if octo_poll(ctx.handle, tk):
-                st = octo_wait(ctx.handle, tk).as_dict()
-                p, tree, phi, g, adm = inflight.pop(tk)
-                done = time.perf_counter() - t0
-                records.append(Record(p.index, p.arrival, adm, done, tree.n_leaf_cells, p.precision, st))
-                if keep_outputs:
-                    outputs[p.index] = (phi.cpu().numpy(), g.cpu().numpy())
-                tree.destroy()
+    try:
+        while nxt < len(pending) or queue or inflight:
+            now = time.perf_counter() - t0
+            if time_limit is not None and now > time_limit:
+                raise TimeoutError(f"serving exceeded {time_limit} s")
+            while nxt < len(pending) and pending[nxt].arrival <= now:
+                queue.append(_Slot(pending[nxt]))
+                nxt += 1
+            for k, slot in enumerate(queue):
+                if k >= lookahead:
+                    break
+                if slot.build is None:
+                    slot.build = pool.submit(build, slot.p)
+            progressed = False
+            # admission in arrival order
+            while queue and queue[0].build is not None and queue[0].build.done():
+                slot = queue[0]
+                try:
+                    h = slot.build.result()
+                except OctoError as e:
+                    if e.status != OCTO_E_BUDGET:
+                        raise
+                    if inflight:
+                        slot.build = None  # retry once completions free memory
+                        break
+                    # nothing on the device: release trees built ahead so the
+                    # head of the queue fits, then retry it
+                    freed = False
+                    for later in list(queue)[1:]:
+                        if later.build is not None:
+                            try:
+                                octo_tree_destroy(later.build.result())
+                                freed = True
+                            except OctoError:
+                                pass
+                            later.build = None
+                    if not freed:
+                        raise
+                    slot.build = None
+                    break
+                p = slot.p
+                tree = Tree(ctx, h)
+                phi = torch.empty(tree.n_leaf_cells, dtype=torch.float64, device=ctx.device)
+                g = torch.empty((3, tree.n_leaf_cells), dtype=torch.float64, device=ctx.device)
+                tk = octo_submit(ctx.handle, h, make_opts(p.theta, 1.0, p.precision, True), phi.data_ptr(),
+                                 g.data_ptr())
+                inflight[tk] = (p, tree, phi, g, time.perf_counter() - t0)
+                queue.popleft()
                 progressed = True
-        if not progressed and (not queue or inflight):
-            wait = poll_sleep
-            if not inflight and not queue and nxt < len(pending):
-                wait = max(0.0, pending[nxt].arrival - (time.perf_counter() - t0))
-            time.sleep(min(wait, 0.01))
+            # completions
+            for tk in list(inflight):
+                if octo_poll(ctx.handle, tk):
+                    st = octo_wait(ctx.handle, tk).as_dict()
+                    p, tree, phi, g, adm = inflight.pop(tk)
+                    done = time.perf_counter() - t0
+                    records.append(Record(p.index, p.arrival, adm, done, tree.n_leaf_cells, p.precision, st))
+                    if keep_outputs:
+                        outputs[p.index] = (phi.cpu().numpy(), g.cpu().numpy())
+                    tree.destroy()
+                    progressed = True
+            if not progressed:
+                wait = poll_sleep
+                if not inflight and not queue and nxt < len(pending):
+                    wait = max(0.0, pending[nxt].arrival - (time.perf_counter() - t0))
+                time.sleep(min(wait, 0.01))
+    finally:
+        # trees built for requests that were never admitted
+        for slot in queue:
+            if slot.build is not None:
+                try:
+                    octo_tree_destroy(slot.build.result())
+                except OctoError:
+                    pass
+        pool.shutdown(wait=True)
     wall = time.perf_counter() - t0
     return records, outputs, wall
 

@@ -198,6 +198,34 @@ def test_batch_and_async_equal_single(ctx):
         t.destroy()
 
 
+def test_served_stream_equals_single():
+    """The request server (parallel tree builds, budget admission, requests
+    merged into launch waves) returns for every request exactly what a solve
+    of that tree alone returns, in both precisions."""
+    from paper_2101_08226_amd import serve
+
+    c = lib.Context(0, hbm_budget=160 << 20)  # a few trees at a time: admission waits
+    try:
+        stream = w.mixes.served_stream(14, 200.0, seed=77, min_cells=4096, max_cells=1 << 17,
+                                       count_leaves=lambda f, lv: 512 * len(lib.octo_host_adaptive_leaves(f, lv, 1e-4)))
+        payloads = []
+        for r in stream:
+            lv = lib.octo_host_adaptive_leaves(r.field, r.max_level, 1e-4)
+            payloads.append(serve.Payload(r.index, r.arrival, lv, w.leaf_density(r.field, lv), r.precision))
+        say(f"served stream: {len(payloads)} requests, {sum(p.leaves.shape[0] for p in payloads) * 512} cells")
+        rec, outs, wall = serve.serve(c, payloads, keep_outputs=True, builders=4, lookahead=6, time_limit=60.0)
+        assert sorted(r.index for r in rec) == list(range(len(payloads)))
+        for p in payloads:
+            t = c.tree(p.leaves, p.rho)
+            phi, g, _ = c.solve(t, precision=p.precision)
+            assert np.array_equal(outs[p.index][0], phi.cpu().numpy()), p.index
+            assert np.array_equal(outs[p.index][1], g.cpu().numpy()), p.index
+            t.destroy()
+        say(f"  wall {wall * 1e3:.1f} ms, p50 {serve.summary(rec, wall)['p50_ms']:.2f} ms")
+    finally:
+        c.close()
+
+
 def test_errors(ctx):
     rho = np.ones((16, 16, 16))
     tree = ctx.uniform_tree(rho)
