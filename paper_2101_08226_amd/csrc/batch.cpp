@@ -179,14 +179,21 @@ void octo_ctx::release_batch(BatchPlan *bp) {
 
 void *octo_ctx::pinned_get(size_t bytes, size_t *got) {
     size_t best = pinned_free.size();
-    for (size_t i = 0; i < pinned_free.size(); ++i)
-        if (pinned_free[i].second >= bytes && (best == pinned_free.size() || pinned_free[i].second < pinned_free[best].second))
-            best = i;
+    for (size_t i = 0; i < pinned_free.size(); ++i) {
+        Pinned &b = pinned_free[i];
+        if (b.bytes < bytes || (best < pinned_free.size() && b.bytes >= pinned_free[best].bytes)) continue;
+        if (b.ready) {
+            if (hipEventQuery(b.ready) != hipSuccess) continue;  // its upload is still queued
+            hipEventDestroy(b.ready);
+            b.ready = nullptr;
+        }
+        best = i;
+    }
     if (best < pinned_free.size()) {
-        auto b = pinned_free[best];
+        Pinned b = pinned_free[best];
         pinned_free.erase(pinned_free.begin() + best);
-        *got = b.second;
-        return b.first;
+        *got = b.bytes;
+        return b.p;
     }
     const size_t n = std::max(bytes, (size_t)1 << 20);
     void *p = nullptr;
@@ -195,7 +202,7 @@ void *octo_ctx::pinned_get(size_t bytes, size_t *got) {
     return p;
 }
 
-void octo_ctx::pinned_put(void *p, size_t bytes) { pinned_free.emplace_back(p, bytes); }
+void octo_ctx::pinned_put(void *p, size_t bytes, hipEvent_t ready) { pinned_free.push_back(Pinned{p, bytes, ready}); }
 
 void octo_ctx::invalidate_batches() {
     if (batch) {

@@ -70,15 +70,19 @@ int n_parts_for(int n_int, int target) {
     return std::max(1, std::min(32, p));
 }
 
-// Allocate the tree's data block (tables and fields), upload tables and
-// density, and fill the level and tree descriptors of its plan.
-void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
-    octo_ctx *ctx = t->ctx;
-    Layout &L = t->layout;
+// Offsets in a tree's device data block: every index table first, then the
+// density (together one contiguous upload), then the per-level fields.
+struct TreeBlock {
+    std::vector<size_t> nbr, child, parent, coord, out, mass, mp, loc, lacc, nf, dip;
+    size_t rho = 0, stage = 0, upload = 0, bytes = 0;
+};
+
+// Per-level work shapes (partial slots, LDS-staged multipole kernel) and the
+// data block's offsets: host work only, no context state but its CU count.
+void shape_tree(octo_tree *t, TreeBlock &B) {
+    const octo_ctx *ctx = t->ctx;
+    const Layout &L = t->layout;
     const int nl = L.n_levels;
-    size_t bytes = 0;
-    std::vector<size_t> off_nbr(nl), off_child(nl), off_parent(nl), off_coord(nl), off_out(nl), off_mass(nl),
-        off_mp(nl), off_loc(nl), off_lacc(nl), off_nf(nl), off_dip(nl);
     t->parts_alloc.assign(nl, 1);
     t->parts.assign(nl, 1);
     t->m2l_lds.assign(nl, 0);
@@ -88,32 +92,8 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
         const HostLevel &h = L.lv[l];
         t->parts_alloc[l] = std::max(n_parts_for(h.n_int, 1024), l >= 1 ? 4 : 1);
         t->parts[l] = n_parts_for(h.n_int, 256);
-        // dense levels take the LDS-staged kernel: one work-group per (node,
-        // half of the source parity classes)
+        // dense levels take the LDS-staged kernel
         t->m2l_lds[l] = (lds && l >= 1 && t->parts[l] == 1) ? 1 : 0;
-        if (t->m2l_lds[l]) t->parts[l] = 2;
-        off_nbr[l] = bytes;
-        bytes += al(h.nbr.size() * 4);
-        off_child[l] = bytes;
-        bytes += al(h.child.size() * 4);
-        off_parent[l] = bytes;
-        bytes += al(h.parent.size() * 4);
-        off_coord[l] = bytes;
-        bytes += al(h.coord.size() * 4);
-        off_out[l] = bytes;
-        bytes += al(h.out_base.size() * 8);
-        off_mass[l] = bytes;
-        bytes += al((size_t)h.n_nodes * kCells * 8);
-        off_mp[l] = bytes;
-        bytes += al((size_t)kRec * h.n_rec * kCells * 8);
-        off_loc[l] = bytes;
-        bytes += al((size_t)t->parts_alloc[l] * kLoc * h.n_int * kCells * 8);
-        off_lacc[l] = bytes;
-        bytes += al((size_t)kLacc * (h.n_rec - h.n_int) * kCells * 8);
-        off_nf[l] = bytes;
-        bytes += al((size_t)4 * (h.n_nodes - h.n_int) * kCells * 8);
-        off_dip[l] = bytes;
-        bytes += al((size_t)3 * h.n_rec * kCells * 8);
     }
     // The LDS-staged levels share one launch: split each node's source parity
     // classes into g groups (one work-group each, one work-group per CU at a
@@ -144,29 +124,87 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
                 if (t->m2l_lds[l]) t->parts[l] = best;
         }
     }
-    const size_t off_rho = bytes;
+    for (auto *v : {&B.nbr, &B.child, &B.parent, &B.coord, &B.out, &B.mass, &B.mp, &B.loc, &B.lacc, &B.nf, &B.dip})
+        v->assign(nl, 0);
+    size_t bytes = 0;
+    for (int l = 0; l < nl; ++l) {
+        const HostLevel &h = L.lv[l];
+        B.nbr[l] = bytes;
+        bytes += al(h.nbr.size() * 4);
+        B.child[l] = bytes;
+        bytes += al(h.child.size() * 4);
+        B.parent[l] = bytes;
+        bytes += al(h.parent.size() * 4);
+        B.coord[l] = bytes;
+        bytes += al(h.coord.size() * 4);
+        B.out[l] = bytes;
+        bytes += al(h.out_base.size() * 8);
+    }
+    B.rho = bytes;
     bytes += al((size_t)L.n_leaf_cells * 8);
-    const size_t off_stage = bytes;
+    B.upload = bytes;
+    for (int l = 0; l < nl; ++l) {
+        const HostLevel &h = L.lv[l];
+        B.mass[l] = bytes;
+        bytes += al((size_t)h.n_nodes * kCells * 8);
+        B.mp[l] = bytes;
+        bytes += al((size_t)kRec * h.n_rec * kCells * 8);
+        B.loc[l] = bytes;
+        bytes += al((size_t)t->parts_alloc[l] * kLoc * h.n_int * kCells * 8);
+        B.lacc[l] = bytes;
+        bytes += al((size_t)kLacc * (h.n_rec - h.n_int) * kCells * 8);
+        B.nf[l] = bytes;
+        bytes += al((size_t)4 * (h.n_nodes - h.n_int) * kCells * 8);
+        B.dip[l] = bytes;
+        bytes += al((size_t)3 * h.n_rec * kCells * 8);
+    }
+    B.stage = bytes;
     bytes += al((size_t)L.n_leaf_cells * 8 * 4);
-    void *mem = ctx->dev_alloc(bytes);
+    B.bytes = bytes;
+}
+
+// The upload image: tables (and a host density) at their offsets.
+void stage_tree(const octo_tree *t, const TreeBlock &B, const double *rho_host, char *img) {
+    const Layout &L = t->layout;
+    for (int l = 0; l < L.n_levels; ++l) {
+        const HostLevel &h = L.lv[l];
+        if (!h.nbr.empty()) memcpy(img + B.nbr[l], h.nbr.data(), h.nbr.size() * 4);
+        if (!h.child.empty()) memcpy(img + B.child[l], h.child.data(), h.child.size() * 4);
+        if (!h.parent.empty()) memcpy(img + B.parent[l], h.parent.data(), h.parent.size() * 4);
+        if (!h.coord.empty()) memcpy(img + B.coord[l], h.coord.data(), h.coord.size() * 4);
+        if (!h.out_base.empty()) memcpy(img + B.out[l], h.out_base.data(), h.out_base.size() * 8);
+    }
+    if (rho_host) memcpy(img + B.rho, rho_host, (size_t)L.n_leaf_cells * 8);
+}
+
+// Under the context lock: allocate the data block, enqueue the upload of the
+// image (pinned; handed back to the context's pool, reusable once the copy is
+// done) and fill the level and tree descriptors.
+void commit_tree(octo_tree *t, const TreeBlock &B, void *img, size_t img_bytes, const double *rho_dev) {
+    octo_ctx *ctx = t->ctx;
+    const Layout &L = t->layout;
+    const int nl = L.n_levels;
+    void *mem = ctx->dev_alloc(B.bytes);
     t->data.ptr = mem;
-    t->data.bytes = bytes;
+    t->data.bytes = B.bytes;
     char *base = (char *)mem;
     hipStream_t s = ctx->stream;
-    auto up = [&](size_t off, const void *src, size_t n) {
-        if (n) check_hip(hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s), "tree upload");
-    };
+    check_hip(hipMemcpyAsync(base, img, rho_dev ? B.rho : B.upload, hipMemcpyHostToDevice, s), "tree upload");
+    if (rho_dev)
+        check_hip(hipMemcpyAsync(base + B.rho, rho_dev, (size_t)L.n_leaf_cells * 8, hipMemcpyDeviceToDevice, s),
+                  "density copy");
+    hipEvent_t done = nullptr;
+    check_hip(hipEventCreateWithFlags(&done, hipEventDisableTiming), "event");
+    check_hip(hipEventRecord(done, s), "event");
+    // a caller's device density is read by the copy: done before returning
+    if (rho_dev) check_hip(hipEventSynchronize(done), "density copy");
+    ctx->pinned_put(img, img_bytes, done);
     PlanHost &ph = t->ph;
     ph = PlanHost{};
     ph.levels.resize(nl);
     ph.trees.resize(1);
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
-        up(off_nbr[l], h.nbr.data(), h.nbr.size() * 4);
-        up(off_child[l], h.child.data(), h.child.size() * 4);
-        up(off_parent[l], h.parent.data(), h.parent.size() * 4);
-        up(off_coord[l], h.coord.data(), h.coord.size() * 4);
-        up(off_out[l], h.out_base.data(), h.out_base.size() * 8);
         LevelDesc &d = ph.levels[l];
         d.level = l;
         d.n_nodes = h.n_nodes;
@@ -177,20 +215,20 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
         d.n_parts = t->parts[l];
         d.tree = 0;
         d.h = 1.0 / (double)(8 << l);
-        d.nbr = (const int32_t *)(base + off_nbr[l]);
-        d.child = (const int32_t *)(base + off_child[l]);
-        d.parent = (const int32_t *)(base + off_parent[l]);
-        d.coord = (const int32_t *)(base + off_coord[l]);
-        d.out_base = (const int64_t *)(base + off_out[l]);
-        d.mass = (double *)(base + off_mass[l]);
-        d.mp = (double *)(base + off_mp[l]);
-        d.loc = (double *)(base + off_loc[l]);
-        d.lacc = (double *)(base + off_lacc[l]);
-        d.nf = (double *)(base + off_nf[l]);
-        d.dip = (double *)(base + off_dip[l]);
+        d.nbr = (const int32_t *)(base + B.nbr[l]);
+        d.child = (const int32_t *)(base + B.child[l]);
+        d.parent = (const int32_t *)(base + B.parent[l]);
+        d.coord = (const int32_t *)(base + B.coord[l]);
+        d.out_base = (const int64_t *)(base + B.out[l]);
+        d.mass = (double *)(base + B.mass[l]);
+        d.mp = (double *)(base + B.mp[l]);
+        d.loc = (double *)(base + B.loc[l]);
+        d.lacc = (double *)(base + B.lacc[l]);
+        d.nf = (double *)(base + B.nf[l]);
+        d.dip = (double *)(base + B.dip[l]);
     }
-    t->rho = (double *)(base + off_rho);
-    t->stage = (double *)(base + off_stage);
+    t->rho = (double *)(base + B.rho);
+    t->stage = (double *)(base + B.stage);
     TreeDesc &td = ph.trees[0];
     td = TreeDesc{};
     td.rho = t->rho;
@@ -202,10 +240,6 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
     td.sz = L.sz;
     td.G = 1.0;
     td.amc = 1;
-    check_hip(hipMemcpyAsync(t->rho, rho, (size_t)L.n_leaf_cells * 8,
-                             rho_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
-              "density upload");
-    check_hip(hipStreamSynchronize(s), "tree upload");
 }
 
 }  // namespace
@@ -213,6 +247,7 @@ void alloc_tree(octo_tree *t, const double *rho, int rho_on_device) {
 namespace octo {
 // (Re)build the tree's single-tree plan from its per-level choices: multipole
 // kernel (LDS-staged per node, or chunked per wavefront with `parts` slots).
+// The plan image goes up from pinned staging, ordered on the context stream.
 void build_tree_plan(octo_tree *t) {
     octo_ctx *ctx = t->ctx;
     const Layout &L = t->layout;
@@ -247,30 +282,29 @@ void build_tree_plan(octo_tree *t) {
     void *mem = ctx->dev_alloc(bytes);
     const TreeDesc keep = t->plan.trees_host.empty() ? ph.trees[0] : t->plan.trees_host[0];
     if (t->plan_block.ptr) {
+        // a rebuilt plan: the old one may still be in use by queued work
         check_hip(hipStreamSynchronize(ctx->stream), "plan rebuild");
         ctx->dev_free(t->plan_block.ptr, t->plan_block.bytes);
     }
     t->plan_block.ptr = mem;
     t->plan_block.bytes = bytes;
     ph.trees[0] = keep;
-    plan_upload(ph, mem, t->plan, ctx->stream);
+    std::vector<char> img;
+    plan_layout(ph, mem, t->plan, img);
+    size_t got = 0;
+    void *pin = ctx->pinned_get(img.size(), &got);
+    memcpy(pin, img.data(), img.size());
+    check_hip(hipMemcpyAsync(mem, pin, img.size(), hipMemcpyHostToDevice, ctx->stream), "plan upload");
+    hipEvent_t done = nullptr;
+    check_hip(hipEventCreateWithFlags(&done, hipEventDisableTiming), "event");
+    check_hip(hipEventRecord(done, ctx->stream), "event");
+    ctx->pinned_put(pin, got, done);
     drop_graphs(t->graphs);
     t->bytes = t->data.bytes + bytes;
 }
 }  // namespace octo
 
 namespace {
-
-void finish_tree(octo_tree *t, const double *rho, int rho_on_device) {
-    alloc_tree(t, rho, rho_on_device);
-    try {
-        build_tree_plan(t);
-    } catch (...) {
-        t->ctx->dev_free(t->data.ptr, t->data.bytes);
-        t->data.ptr = nullptr;
-        throw;
-    }
-}
 
 void check_density_host(const double *rho, int64_t n) {
     for (int64_t i = 0; i < n; ++i)
@@ -447,7 +481,10 @@ octo_status octo_ctx_destroy(octo_ctx *ctx) {
         for (int i = 0; i < 9; ++i) hipEventDestroy(ctx->phase_ev[i]);
         hipEventDestroy(ctx->ev1);
         hipHostFree(ctx->h_stats);
-        for (auto &b : ctx->pinned_free) hipHostFree(b.first);
+        for (auto &b : ctx->pinned_free) {
+            if (b.ready) hipEventDestroy(b.ready);
+            hipHostFree(b.p);
+        }
         if (ctx->own_stream) hipStreamDestroy(ctx->stream);
         delete ctx;
     });
@@ -478,12 +515,35 @@ static octo_status make_tree(octo_ctx *ctx, const octo_leaf *leaves, int64_t n, 
         if (!ctx || !out || !rho) fail(OCTO_E_INVALID, "NULL argument");
         auto t = std::make_unique<octo_tree>();
         t->ctx = ctx;
-        // validation and layout need no device and no context state
+        // validation, layout, work shape and the upload image need no device
+        // and no context state: they run before the lock
         t->layout = build_layout(leaves, n, grid_level);
         if (!rho_on_device) check_density_host(rho, t->layout.n_leaf_cells);
-        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        TreeBlock B;
+        shape_tree(t.get(), B);
         DeviceGuard dg(ctx->device);
-        finish_tree(t.get(), rho, rho_on_device);
+        size_t img_bytes = 0;
+        void *img = nullptr;
+        {
+            std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+            img = ctx->pinned_get(B.upload, &img_bytes);
+        }
+        stage_tree(t.get(), B, rho_on_device ? nullptr : rho, (char *)img);
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        try {
+            commit_tree(t.get(), B, img, img_bytes, rho_on_device ? rho : nullptr);
+        } catch (...) {
+            if (!t->data.ptr) ctx->pinned_put(img, img_bytes, nullptr);  // the upload was never enqueued
+            throw;
+        }
+        try {
+            build_tree_plan(t.get());
+        } catch (...) {
+            hipStreamSynchronize(ctx->stream);
+            ctx->dev_free(t->data.ptr, t->data.bytes);
+            t->data.ptr = nullptr;
+            throw;
+        }
         check_hip(hipEventCreateWithFlags(&t->last_use, hipEventDisableTiming), "event");
         check_hip(hipEventRecord(t->last_use, ctx->stream), "event");
         ctx->n_trees++;

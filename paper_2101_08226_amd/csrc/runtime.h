@@ -200,11 +200,16 @@ struct octo_ctx {
     bool profiling = false;
     hipEvent_t phase_ev[9] = {};
     double *h_stats = nullptr;  // pinned host staging for stats
-    // pinned upload buffers of finished waves, reused (freeing pinned memory
-    // can wait for the device)
-    std::vector<std::pair<void *, size_t>> pinned_free;
+    // pinned upload buffers, reused (freeing pinned memory can wait for the
+    // device); each is free once its event (the upload that read it) is done
+    struct Pinned {
+        void *p;
+        size_t bytes;
+        hipEvent_t ready;  // NULL: free now
+    };
+    std::vector<Pinned> pinned_free;
     void *pinned_get(size_t bytes, size_t *got);
-    void pinned_put(void *p, size_t bytes);
+    void pinned_put(void *p, size_t bytes, hipEvent_t ready = nullptr);
     size_t h_stats_cap = 0;
     // last batch signature (octo_solve_batch)
     std::unique_ptr<octo::BatchPlan> batch;
