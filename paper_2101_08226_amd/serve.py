@@ -124,17 +124,19 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                 inflight[tk] = (p, tree, phi, g, time.perf_counter() - t0)
                 queue.popleft()
                 progressed = True
-            # completions
+            # completions: requests finish with their launch wave and waves
+            # retire in submission order, so stop at the first unfinished one
             for tk in list(inflight):
-                if octo_poll(ctx.handle, tk):
-                    st = octo_wait(ctx.handle, tk).as_dict()
-                    p, tree, phi, g, adm = inflight.pop(tk)
-                    done = time.perf_counter() - t0
-                    records.append(Record(p.index, p.arrival, adm, done, tree.n_leaf_cells, p.precision, st))
-                    if keep_outputs:
-                        outputs[p.index] = (phi.cpu().numpy(), g.cpu().numpy())
-                    tree.destroy()
-                    progressed = True
+                if not octo_poll(ctx.handle, tk):
+                    break
+                st = octo_wait(ctx.handle, tk).as_dict()
+                p, tree, phi, g, adm = inflight.pop(tk)
+                done = time.perf_counter() - t0
+                records.append(Record(p.index, p.arrival, adm, done, tree.n_leaf_cells, p.precision, st))
+                if keep_outputs:
+                    outputs[p.index] = (phi.cpu().numpy(), g.cpu().numpy())
+                tree.destroy()
+                progressed = True
             if not progressed:
                 wait = poll_sleep
                 if not inflight and not queue and nxt < len(pending):
