@@ -58,7 +58,7 @@ class _Slot:
 
 
 def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, poll_sleep: float = 2e-4,
-          time_limit: Optional[float] = None, builders: int = 8, lookahead: int = 16):
+          time_limit: Optional[float] = None, builders: int = 12, lookahead: int = 24):
     """Run the stream in real time; returns (records, outputs by index if
     keep_outputs, wall seconds).  `builders` host threads build the trees of
     up to `lookahead` queued requests ahead of admission."""
