@@ -311,7 +311,10 @@ def main():
                                      f"{a.budget_gib} GiB", "requests": a.requests, "rate": rate}
         out["served"] = {"p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
                          "throughput_req_s": round(s["throughput_req_s"], 2),
-                         "saturation_req_s": round(sat["throughput_req_s"], 2)}
+                         "saturation_req_s": round(sat["throughput_req_s"], 2),
+                         "host": {k: round(v, 4) if isinstance(v, float) else v
+                                  for k, v in getattr(serve.serve, "last_profile", {}).items()},
+                         "wall_s": round(wall, 3)}
         out["roofline"] = None
 
     out["cpu_baseline"] = cpu

@@ -61,11 +61,20 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
           time_limit: Optional[float] = None, builders: int = 12, lookahead: int = 24):
     """Run the stream in real time; returns (records, outputs by index if
     keep_outputs, wall seconds).  `builders` host threads build the trees of
-    up to `lookahead` queued requests ahead of admission."""
+    up to `lookahead` queued requests ahead of admission.  Host time spent in
+    builds, admission, completions and idle waits is left in
+    serve.last_profile."""
     import torch
 
+    prof = dict(build_s=0.0, builds=0, admit_s=0.0, complete_s=0.0, idle_s=0.0, loops=0)
+
     def build(p: Payload) -> int:
-        return octo_tree_build(ctx.handle, p.leaves, p.rho.ctypes.data, False)
+        b0 = time.perf_counter()
+        try:
+            return octo_tree_build(ctx.handle, p.leaves, p.rho.ctypes.data, False)
+        finally:
+            prof["build_s"] += time.perf_counter() - b0  # float += under the GIL
+            prof["builds"] += 1
 
     pending = sorted(payloads, key=lambda p: p.arrival)
     nxt = 0
@@ -89,6 +98,8 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                 if slot.build is None:
                     slot.build = pool.submit(build, slot.p)
             progressed = False
+            prof["loops"] += 1
+            a0 = time.perf_counter()
             # admission in arrival order
             while queue and queue[0].build is not None and queue[0].build.done():
                 slot = queue[0]
@@ -124,6 +135,8 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                 inflight[tk] = (p, tree, phi, g, time.perf_counter() - t0)
                 queue.popleft()
                 progressed = True
+            a1 = time.perf_counter()
+            prof["admit_s"] += a1 - a0
             # completions: requests finish with their launch wave and waves
             # retire in submission order, so stop at the first unfinished one
             for tk in list(inflight):
@@ -137,11 +150,14 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                     outputs[p.index] = (phi.cpu().numpy(), g.cpu().numpy())
                 tree.destroy()
                 progressed = True
+            prof["complete_s"] += time.perf_counter() - a1
             if not progressed:
                 wait = poll_sleep
                 if not inflight and not queue and nxt < len(pending):
                     wait = max(0.0, pending[nxt].arrival - (time.perf_counter() - t0))
+                i0 = time.perf_counter()
                 time.sleep(min(wait, 0.01))
+                prof["idle_s"] += time.perf_counter() - i0
     finally:
         # trees built for requests that were never admitted
         for slot in queue:
@@ -152,6 +168,7 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                     pass
         pool.shutdown(wait=True)
     wall = time.perf_counter() - t0
+    serve.last_profile = prof
     return records, outputs, wall
 
 
