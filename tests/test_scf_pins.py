@@ -1,0 +1,196 @@
+"""Pins of the self-consistent-field oracle (the initial binary model of
+Sec. 4.1) against what physics and brute force fix, independent of its code.
+
+The potential solve inside these runs is an FFT convolution of the cell masses
+with the point-mass Green's function on a zero-padded grid (Hockney's method):
+exact for the cell-centre point-mass model, independent of the multipole code,
+and fast enough for converged runs on 64^3 grids.  It is itself pinned against
+a brute-force sum, and the oracle's multipole solve is compared with it.
+
+What the pins fix:
+* the grid's total mass is M1 + M2 plus the floor (step 1 normalises each star);
+* an equal-mass binary converges to a mirror-symmetric density about the
+  plane through its centre of mass, also when the grid is shifted off the
+  origin (rotation about the centre of mass, same treatment of both stars);
+* at the fixed point each star is hydrostatic in the rotating frame,
+  K (n + 1) rho^(1/n) + phi_eff = C_i, with phi_eff rebuilt here from the
+  returned potential and Omega;
+* each star of a wide equal-mass binary obeys the Lane-Emden relation between
+  K, its mass and its central density, to the grid's resolution;
+* the separation relaxes towards a0 (the orbit J0 fixes is Keplerian at a0)
+  from either side without overshooting;
+* the lobes: a cell holds more than the floor only on its star's side of L1
+  and within |x_L1 - x_centre| of its centre; where the equipotential opens
+  beyond that ball, the ball is the star (brute force on an 8^3 grid).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import scf as S
+
+
+def fft_poisson(level: int, G: float = 1.0):
+    """phi_i = -G sum_{j != i} m_j / |x_i - x_j| over the cell centres of the
+    uniform grid of `level`, by zero-padded FFT convolution."""
+    n = 8 << level
+    h = 1.0 / n
+    m = 2 * n
+    k = np.arange(m)
+    k = np.where(k < n, k, k - m) * h
+    X, Y, Z = np.meshgrid(k, k, k, indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    g = np.zeros_like(r)
+    g[r > 0] = 1.0 / r[r > 0]
+    gh = np.fft.rfftn(g)
+
+    def solve(rho):
+        pad = np.zeros((m, m, m))
+        pad[:n, :n, :n] = rho * h ** 3
+        return -G * np.fft.irfftn(np.fft.rfftn(pad) * gh, s=(m, m, m), axes=(0, 1, 2))[:n, :n, :n]
+
+    return solve
+
+
+def _run(level, iters, M1, M2, a0, a_init, R1, R2, f=0.9, shift=(0, 0)):
+    p = S.SCFParams(M1=M1, M2=M2, a0=a0, f=f)
+    rho0, p.K0 = w.scf_initial_binary(level, M1, M2, a_init, R1, R2)
+    rho0 = np.roll(rho0, shift, axis=(0, 1))
+    rho, phi, hist = S.run(rho0, level, p, iters, fft_poisson(level))
+    return p, rho, phi, hist
+
+
+def test_fft_poisson_equals_direct_sum():
+    rng = np.random.default_rng(11)
+    rho = rng.uniform(0.0, 1.0, (8, 8, 8))
+    phi = fft_poisson(0)(rho)
+    c = (np.arange(8) + 0.5) / 8 - 0.5
+    X = np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3)
+    d = np.linalg.norm(X[:, None, :] - X[None, :, :], axis=-1)
+    np.fill_diagonal(d, np.inf)
+    ref = -(rho.ravel() / 512.0 / d).sum(axis=1)
+    assert np.abs(phi.ravel() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_oracle_multipole_solve_agrees_with_fft():
+    rho, _ = w.scf_initial_binary(1, 1.0, 0.7, 0.4, 0.15, 0.12)
+    a = S.oracle_solver(1)(rho)
+    b = fft_poisson(1)(rho)
+    assert np.abs(a - b).max() <= 2e-3 * np.abs(b).max()
+
+
+def test_scf_with_oracle_solve_tracks_fft_solve():
+    # the same two iterations with either solve: the scalars agree to the
+    # multipole error
+    p = S.SCFParams(M1=1.0, M2=0.7, a0=0.4)
+    rho0, p.K0 = w.scf_initial_binary(1, 1.0, 0.7, 0.4, 0.15, 0.12)
+    _, _, ha = S.run(rho0, 1, p, 2, S.oracle_solver(1))
+    _, _, hb = S.run(rho0, 1, p, 2, fft_poisson(1))
+    for sa, sb in zip(ha, hb):
+        assert (sa.c1, sa.c2, sa.l1) == (sb.c1, sb.c2, sb.l1)
+        for k in ("omega", "K", "C1", "C2", "a"):
+            assert abs(getattr(sa, k) - getattr(sb, k)) <= 5e-3 * abs(getattr(sb, k)), k
+
+
+def test_total_mass_is_the_two_stars_plus_floor():
+    p, rho, _, _ = _run(2, 10, 1.0, 0.7, 0.4, 0.4, 0.1, 0.09)
+    total = rho.sum() / rho.size
+    assert abs(total - (p.M1 + p.M2)) <= p.floor + 1e-12
+
+
+@pytest.mark.parametrize("shift", [(0, 0), (4, 3)])
+def test_equal_masses_converge_mirror_symmetric(shift):
+    _, rho, _, _ = _run(2, 20, 1.0, 1.0, 0.4, 0.4, 0.1, 0.1, shift=shift)
+    sx, sy = shift
+    mx = np.roll(rho[::-1], 2 * sx, axis=0)
+    my = np.roll(rho[:, ::-1], 2 * sy, axis=1)
+    # one layer of cells at the L1 plane and the L1 row are decided by ties
+    assert np.abs(rho - mx).max() <= 2e-2 * rho.max()
+    assert np.abs(rho - my).max() <= 2e-2 * rho.max()
+
+
+def _phi_eff(level, rho, phi, omega):
+    n = 8 << level
+    c = (np.arange(n) + 0.5) / n - 0.5
+    X, Y, _ = np.meshgrid(c, c, c, indexing="ij")
+    m = rho / rho.size
+    xc, yc = (m * X).sum() / m.sum(), (m * Y).sum() / m.sum()
+    return phi - 0.5 * omega ** 2 * ((X - xc) ** 2 + (Y - yc) ** 2), X
+
+
+def test_fixed_point_is_hydrostatic():
+    p, rho, phi, hist = _run(3, 30, 1.0, 1.0, 0.4, 0.4, 0.1, 0.1)
+    s = hist[-1]
+    pe, X = _phi_eff(3, rho, phi, s.omega)
+    lhs = s.K * (p.n + 1.0) * rho ** (1.0 / p.n) + pe
+    dense = rho > 1e-2 * rho.max()
+    for C, side, c in ((s.C1, X < s.x_L1, s.c1), (s.C2, X >= s.x_L1, s.c2)):
+        sel = dense & side
+        assert sel.sum() > 100
+        # relative to the depth of the star's well
+        assert np.abs(lhs[sel] - C).max() <= 3e-3 * abs(C - pe.ravel()[c])
+
+
+def test_stars_follow_lane_emden():
+    p, rho, _, hist = _run(3, 30, 1.0, 1.0, 0.4, 0.4, 0.1, 0.1)
+    s = hist[-1]
+    _, _, _, xi1, dth1 = w.lane_emden_table(p.n)
+    for M, c in ((p.M1, s.c1), (p.M2, s.c2)):
+        rc = rho.ravel()[c]
+        # radius of the n = 3/2 polytrope of mass M and central density rc,
+        # and the K that radius and density need
+        R = (M * xi1 / (4.0 * math.pi * rc * (-dth1))) ** (1.0 / 3.0)
+        K_le = 4.0 * math.pi * R * R * rc ** (1.0 - 1.0 / p.n) / ((p.n + 1.0) * xi1 * xi1)
+        # stars about 8 cells in radius: the point-mass cell model is good to ~10%
+        assert abs(s.K / K_le - 1.0) <= 0.1
+
+
+@pytest.mark.parametrize("a0,a_init", [(0.38, 0.46), (0.46, 0.38)])
+def test_separation_relaxes_towards_a0(a0, a_init):
+    _, _, _, hist = _run(2, 20, 1.0, 0.7, a0, a_init, 0.1, 0.09, f=0.6)
+    a = np.array([s.a for s in hist])
+    step = np.sign(a0 - a_init)
+    assert np.all(step * np.diff(a[2:]) > 0.0)
+    assert step * (a[-1] - a[0]) >= 0.01
+    assert step * (a0 - a[-1]) > 0.0
+
+
+def test_lobes_bound_the_stars_brute_force():
+    # constant potential and a huge K: the accretor's equipotential covers the
+    # whole grid, so its lobe (the ball about its centre reaching L1, on its
+    # side) is exactly where it ends up; the donor fills its ball wherever the
+    # rotation lowers phi_eff below its centre's
+    n = 8
+    rho = np.full((n, n, n), 1e-3)
+    rho[1, 3, 4] = 1.0
+    rho[6, 4, 4] = 0.5
+    phi = np.full((n, n, n), -50.0)
+    p = S.SCFParams(M1=1.0, M2=0.5, a0=0.4, f=0.95, K0=1e4)
+    out, st = S.scf_step(rho, phi, 0, p, p.K0, 0.0, S.initial_angular_momentum(p))
+    c = (np.arange(n) + 0.5) / n - 0.5
+    xL = c[np.unravel_index(st.l1, rho.shape)[0]]
+    i1, i2 = np.unravel_index(st.c1, rho.shape), np.unravel_index(st.c2, rho.shape)
+    assert i1 == (1, 3, 4) and i2 == (6, 4, 4)
+    mass = rho / rho.size
+    X, Y, _ = np.meshgrid(c, c, c, indexing="ij")
+    xc, yc = (mass * X).sum() / mass.sum(), (mass * Y).sum() / mass.sum()
+    d2c = (c[i2[0]] - xc) ** 2 + (c[i2[1]] - yc) ** 2
+    for ix in range(n):
+        for iy in range(n):
+            for iz in range(n):
+                x = (c[ix], c[iy], c[iz])
+                r1 = math.dist(x, (c[i1[0]], c[i1[1]], c[i1[2]]))
+                r2 = math.dist(x, (c[i2[0]], c[i2[1]], c[i2[2]]))
+                in1 = x[0] < xL and r1 < abs(xL - c[i1[0]])
+                in2 = x[0] >= xL and r2 < abs(xL - c[i2[0]])
+                v = out[ix, iy, iz]
+                if not (in1 or in2):
+                    assert v == p.floor, (ix, iy, iz)
+                if in1:
+                    assert v > p.floor, (ix, iy, iz)
+                if in2 and (x[0] - xc) ** 2 + (x[1] - yc) ** 2 > d2c:
+                    assert v > p.floor, (ix, iy, iz)
