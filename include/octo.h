@@ -260,6 +260,94 @@ octo_status octo_gravity_sources(octo_ctx *ctx, octo_tree *tree, const double *o
 octo_status octo_energy_update(octo_ctx *ctx, octo_tree *tree, const double *rho, const double *phi_before,
                                const double *phi_after, double *E);
 
+/* ---- initial binary model: self-consistent field (Sec. 4.1) ------------- */
+
+/* Parameters of the self-consistent-field (SCF) iteration that builds a
+ * synchronously rotating binary of two polytropes (Sec. 4.1, "The Initial
+ * Stellar Model").  The accretor (mass M1) lies on the low-x side of the L1
+ * point, the donor (M2) on the high-x side. */
+typedef struct {
+    double M1, M2;     /* masses the two stars are normalised to (step 1) */
+    double n;          /* polytropic index */
+    double a0;         /* separation fixing the orbital angular momentum
+                          J0 = mu a0^2 Omega_K(a0), Omega_K^2 = G (M1 + M2) / a0^3,
+                          mu = M1 M2 / (M1 + M2) (step 3) */
+    double f;          /* Roche filling factor of the donor (step 4) */
+    double K0;         /* polytropic constant before the first update */
+    double rho_floor;  /* density of every cell outside the two stars */
+    double G;          /* gravitational constant (J0 and the potential solve) */
+    double x_L1;       /* split between the two sides before the first
+                          iteration; must be a cell centre or a cell face */
+} octo_scf_params;
+
+/* Scalars of one SCF iteration. */
+typedef struct {
+    double omega;      /* angular frequency from J0 and the separation (step 3) */
+    double K;          /* updated polytropic constant (step 5) */
+    double C1, C2;     /* integration constants of accretor and donor (step 4) */
+    double x_L1;       /* x of the new L1 cell (step 4) */
+    double a;          /* separation of the stars' centres of mass (step 3) */
+    double mass1, mass2; /* the stars' masses in the iteration's input density */
+    int64_t c1, c2;    /* centre cells (densest cell of each side) */
+    int64_t l1;        /* L1 cell */
+} octo_scf_state;
+
+/* The readings of Sec. 4.1 this library takes (where the text is silent):
+ * cells are indexed g = (ix*n + iy)*n + iz on the n^3 grid of a uniform tree
+ * (n = 8 * 2^level), cell centres at -1/2 + (i + 1/2)/n;
+ * - the sides: a cell is on the accretor's side when its x is below the
+ *   split; the centre cell of a side is its densest cell; a star is the cells
+ *   of its side closer to its centre cell than |split - x_centre|; ties of
+ *   every maximum go to the smallest g;
+ * - step 1 multiplies each star's cells by M_i / (its mass), others unchanged;
+ * - step 2: the rotation axis is parallel to z through the grid's centre of
+ *   mass (xc, yc); phi_eff = phi - Omega^2 ((x - xc)^2 + (y - yc)^2) / 2;
+ * - step 3: a = distance of the stars' centres of mass,
+ *   Omega = J0 (M1 + M2) / (M1 M2 a^2);
+ * - step 4: L1 is the cell of largest phi_eff on the grid row (iy, iz of the
+ *   accretor's centre) strictly between the two centre cells;
+ *   C1 = K (n + 1) rho_c1^(1/n) + phi_eff(c1) with the K in force;
+ *   C2 = (1 - f) phi_eff(c2) + f phi_eff(L1);
+ * - step 5: K = (C2 - phi_eff(c2)) / ((n + 1) rho_c2^(1/n));
+ * - step 6: with the sides and radii taken about the new L1 and the same
+ *   centre cells, rho = ((C_i - phi_eff) / (K (n + 1)))^n inside star i where
+ *   C_i - phi_eff > 0, else 0; then rho = max(rho, rho_floor);
+ * - step 7 solves for the density after step 1 of the next iteration (each
+ *   iteration normalises, then solves, then takes steps 2-6), so the
+ *   potential of steps 2-6 is the one of the density they act on. */
+
+/* Steps 2-6 of one SCF iteration from a density `rho` (already normalised)
+ * and its potential `phi` on the grid of `level` (0..6): writes the new
+ * density to rho_out and the iteration's scalars to *state.  K: the
+ * polytropic constant in force; x_L1: the split of the previous iteration
+ * (p->x_L1 is ignored).  rho, phi, rho_out: device, n^3 doubles each in the
+ * grid layout above; rho_out may equal rho; state: host.  Device scratch of a
+ * few tens of KiB is taken from the context's allocator for the call.
+ * Returns when the results are ready.
+ * Errors: OCTO_E_INVALID (NULL pointer, level out of range, x_L1 neither a
+ * cell centre nor a cell face, non-finite or non-positive masses, n, a0 or G),
+ * OCTO_E_BUDGET, OCTO_E_DEVICE. */
+octo_status octo_scf_step(octo_ctx *ctx, int level, const octo_scf_params *p, double K, double x_L1,
+                          const double *rho, const double *phi, double *rho_out, octo_scf_state *state);
+
+/* `iterations` SCF iterations (Sec. 4.1) on a uniform tree (built by
+ * octo_tree_build_uniform), starting from the tree's density and from
+ * K = p->K0 and the split p->x_L1; each iteration normalises the stars (step
+ * 1), solves for the potential with `opts` (theta, precision, amc; the
+ * constant G is p->G) and takes steps 2-6.  After the last iteration the
+ * stars are normalised once more and their potential solved.  On return the
+ * tree holds that final density; rho_out (device, n^3 doubles, or NULL)
+ * receives a copy of it and phi_out (device, n^3 doubles) its potential;
+ * history (host, `iterations` entries, or NULL) the scalars of every
+ * iteration.  Every step runs on the device; the host only enqueues.  Device
+ * scratch (3 n^3 doubles for the acceleration of the solve, plus a few tens
+ * of KiB) is taken from the context's allocator for the call.  Returns when
+ * the results are ready.
+ * Errors: as octo_scf_step, plus OCTO_E_INVALID (tree not uniform,
+ * iterations < 0), OCTO_E_UNSUPPORTED (bad opts), OCTO_E_STATE. */
+octo_status octo_scf_run(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, const octo_scf_params *p,
+                         int32_t iterations, double *rho_out, double *phi_out, octo_scf_state *history);
+
 /* ---- asynchronous requests (continuous batching) ------------------------ */
 
 typedef int64_t octo_ticket;

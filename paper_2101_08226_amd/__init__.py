@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "OCTO_OK", 1: "OCTO_E_INVALID", 2: "OCTO_E_DEVICE", 3: "OCTO_
 EXPORTS = [
     "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_tree_build", "octo_tree_build_uniform",
     "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
-    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
+    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_run", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
     "octo_host_stencil_sizes", "octo_host_layout", "octo_host_adaptive_leaves",
 ]
 
@@ -47,6 +47,26 @@ class octo_leaf(ctypes.Structure):
 class octo_opts(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("G", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("amc", ctypes.c_int32)]
+
+
+class octo_scf_params(ctypes.Structure):
+    _fields_ = [("M1", ctypes.c_double), ("M2", ctypes.c_double), ("n", ctypes.c_double), ("a0", ctypes.c_double),
+                ("f", ctypes.c_double), ("K0", ctypes.c_double), ("rho_floor", ctypes.c_double),
+                ("G", ctypes.c_double), ("x_L1", ctypes.c_double)]
+
+
+class octo_scf_state(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("K", ctypes.c_double), ("C1", ctypes.c_double), ("C2", ctypes.c_double),
+                ("x_L1", ctypes.c_double), ("a", ctypes.c_double), ("mass1", ctypes.c_double),
+                ("mass2", ctypes.c_double), ("c1", ctypes.c_int64), ("c2", ctypes.c_int64), ("l1", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def make_scf_params(M1, M2, n=1.5, a0=0.35, f=0.9, K0=0.1, rho_floor=1e-10, G=1.0, x_L1=0.0) -> octo_scf_params:
+    return octo_scf_params(float(M1), float(M2), float(n), float(a0), float(f), float(K0), float(rho_floor), float(G),
+                           float(x_L1))
 
 
 class octo_stats(ctypes.Structure):
@@ -116,6 +136,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_solve_dphidt": [_P, _P, ctypes.POINTER(octo_opts), _D, _D],
         "octo_gravity_sources": [_P, _P, _D, _D, _D, _D, _D, _D, _D, _D, _D],
         "octo_energy_update": [_P, _P, _D, _D, _D, _D],
+        "octo_scf_step": [_P, _I, ctypes.POINTER(octo_scf_params), ctypes.c_double, ctypes.c_double, _D, _D, _D,
+                          ctypes.POINTER(octo_scf_state)],
+        "octo_scf_run": [_P, _P, ctypes.POINTER(octo_opts), ctypes.POINTER(octo_scf_params), ctypes.c_int32, _D, _D,
+                         ctypes.POINTER(octo_scf_state)],
         "octo_poll": [_P, _I64, ctypes.POINTER(_I)],
         "octo_wait": [_P, _I64, ctypes.POINTER(octo_stats)],
         "octo_host_stencil_sizes": [ctypes.c_double, ctypes.POINTER(ctypes.c_int32)],
@@ -270,6 +294,22 @@ def octo_energy_update(ctx: int, tree: int, rho: int, phi_before: int, phi_after
     _check(load_library().octo_energy_update(ctx, tree, _dptr(rho), _dptr(phi_before), _dptr(phi_after), _dptr(E)))
 
 
+def octo_scf_step(ctx: int, level: int, params: octo_scf_params, K: float, x_L1: float, rho: int, phi: int,
+                  rho_out: int) -> octo_scf_state:
+    st = octo_scf_state()
+    _check(load_library().octo_scf_step(ctx, int(level), ctypes.byref(params), float(K), float(x_L1), _dptr(rho),
+                                        _dptr(phi), _dptr(rho_out), ctypes.byref(st)))
+    return st
+
+
+def octo_scf_run(ctx: int, tree: int, opts: octo_opts, params: octo_scf_params, iterations: int, rho_out: int,
+                 phi_out: int) -> list:
+    hist = (octo_scf_state * max(1, iterations))()
+    _check(load_library().octo_scf_run(ctx, tree, ctypes.byref(opts), ctypes.byref(params), int(iterations),
+                                       _dptr(rho_out), _dptr(phi_out), hist))
+    return list(hist)[:iterations]
+
+
 def octo_submit(ctx: int, tree: int, opts: octo_opts, phi_ptr: int, g_ptr: int) -> int:
     t = _I64()
     _check(load_library().octo_submit(ctx, tree, ctypes.byref(opts), _dptr(phi_ptr), _dptr(g_ptr), ctypes.byref(t)))
@@ -414,6 +454,35 @@ class Context:
                           dphi.data_ptr())
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return dphi
+
+    def scf_step(self, level: int, rho, phi, K: float, x_L1: float, params: octo_scf_params, out=None):
+        """Steps 2-6 of one SCF iteration (Sec. 4.1) from a normalised density
+        and its potential (float64 device tensors, n^3 in grid order): the new
+        density and the iteration's scalars."""
+        torch = self.torch
+        n3 = (8 << level) ** 3
+        for t in (rho, phi):
+            assert t.dtype == torch.float64 and t.is_contiguous() and t.numel() == n3 and t.device == self.device
+        rho_out = torch.empty(n3, dtype=torch.float64, device=self.device) if out is None else out
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        st = octo_scf_step(self.handle, level, params, K, x_L1, rho.data_ptr(), phi.data_ptr(), rho_out.data_ptr())
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return rho_out, st.as_dict()
+
+    def scf_run(self, tree: "Tree", params: octo_scf_params, iterations: int, theta=0.5, precision=OCTO_FP64,
+                amc=True):
+        """SCF iterations (Sec. 4.1) on a uniform tree from its density: the
+        final normalised density, its potential (n^3 device tensors, grid
+        order) and the scalars of every iteration."""
+        torch = self.torch
+        n = tree.n_leaf_cells
+        rho = torch.empty(n, dtype=torch.float64, device=self.device)
+        phi = torch.empty(n, dtype=torch.float64, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        hist = octo_scf_run(self.handle, tree.handle, make_opts(theta, params.G, precision, amc), params, iterations,
+                            rho.data_ptr(), phi.data_ptr())
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return rho, phi, [h.as_dict() for h in hist]
 
     def gravity_sources(self, tree: "Tree", omega, rho, s, phi, g, drho_dt=None, dphi_dt=None):
         """Source terms (src_s (3, n), src_e (n)) from device tensors in the

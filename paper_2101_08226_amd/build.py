@@ -9,7 +9,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liboctofmm.so")
-SOURCES = ["kernels.hip", "tree.cpp", "octo_abi.cpp", "batch.cpp", "host_api.cpp"]
+SOURCES = ["kernels.hip", "scf.hip", "tree.cpp", "octo_abi.cpp", "batch.cpp", "host_api.cpp"]
+# per-source flags: the SCF steps round as written (no contraction into FMA)
+EXTRA = {"scf.hip": ["-ffp-contract=off"]}
 ARCH = os.environ.get("OCTO_ARCH", "gfx950")
 
 FLAGS = [
@@ -23,7 +25,7 @@ FLAGS = [
 
 def _compile(src):
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", "-x", "hip", *FLAGS, "-c", os.path.join(CSRC, src), "-o", out]
+    cmd = ["hipcc", "-x", "hip", *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

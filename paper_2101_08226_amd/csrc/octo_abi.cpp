@@ -755,6 +755,71 @@ octo_status octo_energy_update(octo_ctx *ctx, octo_tree *tree, const double *rho
     });
 }
 
+namespace {
+
+void validate_scf(const octo_scf_params *p) {
+    if (!p) fail(OCTO_E_INVALID, "SCF parameters are NULL");
+    const double pos[] = {p->M1, p->M2, p->n, p->a0, p->G};
+    for (double v : pos)
+        if (!std::isfinite(v) || v <= 0.0) fail(OCTO_E_INVALID, "SCF masses, n, a0 and G must be finite and positive");
+    if (!std::isfinite(p->f) || !std::isfinite(p->K0)) fail(OCTO_E_INVALID, "SCF f and K0 must be finite");
+    if (!std::isfinite(p->rho_floor) || p->rho_floor < 0.0) fail(OCTO_E_INVALID, "SCF floor density must be >= 0");
+}
+
+// the split x in half-cell units of the grid of `level` (a cell centre or face)
+int64_t scf_split(double x, int level) {
+    const double n2 = 2.0 * (double)(8 << level);
+    const double u = (x + 0.5) * n2;
+    if (!std::isfinite(u) || u != std::floor(u) || u < 0.0 || u > n2)
+        fail(OCTO_E_INVALID, "x_L1 must be a cell centre or a cell face of the grid");
+    return (int64_t)u;
+}
+
+// the level of a tree built on the uniform grid layout, else -1
+int uniform_level(const octo_tree *t) {
+    const Layout &L = t->layout;
+    const int level = L.n_levels - 1;
+    if (level < 0 || level > 6) return -1;
+    const int64_t n = (int64_t)8 << level;
+    if (L.n_leaf_cells != n * n * n || L.sx != n * n || L.sy != n || L.sz != 1) return -1;
+    return level;
+}
+
+}  // namespace
+
+octo_status octo_scf_step(octo_ctx *ctx, int level, const octo_scf_params *p, double K, double x_L1,
+                          const double *rho, const double *phi, double *rho_out, octo_scf_state *state) {
+    return guard([&] {
+        if (!ctx || !rho || !phi || !rho_out || !state) fail(OCTO_E_INVALID, "NULL argument");
+        if (level < 0 || level > 6) fail(OCTO_E_INVALID, "level must lie in [0, 6]");
+        validate_scf(p);
+        if (!std::isfinite(K)) fail(OCTO_E_INVALID, "K not finite");
+        const int64_t s2 = scf_split(x_L1, level);
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        DeviceGuard dg(ctx->device);
+        scf_step(ctx, level, *p, K, s2, rho, phi, rho_out, state);
+    });
+}
+
+octo_status octo_scf_run(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, const octo_scf_params *p,
+                         int32_t iterations, double *rho_out, double *phi_out, octo_scf_state *history) {
+    return guard([&] {
+        if (!ctx || !tree || !phi_out) fail(OCTO_E_INVALID, "NULL argument");
+        if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+        validate_opts(opts);
+        validate_scf(p);
+        if (iterations < 0) fail(OCTO_E_INVALID, "iterations < 0");
+        const int level = uniform_level(tree);
+        if (level < 0) fail(OCTO_E_INVALID, "the SCF iteration needs a tree from octo_tree_build_uniform");
+        const int64_t s2 = scf_split(p->x_L1, level);
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        DeviceGuard dg(ctx->device);
+        octo_opts o = *opts;
+        o.G = p->G;
+        scf_run(ctx, tree, level, o, *p, s2, iterations, rho_out, phi_out, history);
+    });
+}
+
 // Autotuner: for each level with interior nodes, time the multipole phase
 // with each candidate work shape (LDS-staged per node, or per wavefront with
 // 1..parts_alloc stencil chunks) and keep the fastest, level by level.

@@ -250,5 +250,11 @@ namespace octo {
 void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs,
               const std::vector<TreeDesc> &want, const octo_opts *o, bool count = true, bool source = false);
 void drop_graphs(std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs);
+// self-consistent-field iteration (Sec. 4.1) on the n^3 grid of `level`; s2:
+// split between the two sides in half-cell units, x = s2 h/2 - 1/2
+void scf_step(octo_ctx *ctx, int level, const octo_scf_params &p, double K, int64_t s2, const double *rho,
+              const double *phi, double *rho_out, octo_scf_state *state);
+void scf_run(octo_ctx *ctx, octo_tree *t, int level, const octo_opts &o, const octo_scf_params &p, int64_t s2,
+             int iterations, double *rho_out, double *phi_out, octo_scf_state *history);
 void build_tree_plan(octo_tree *t);
 }  // namespace octo

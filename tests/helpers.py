@@ -83,3 +83,25 @@ def grid_ids(level: int, sel: np.ndarray) -> np.ndarray:
     inv = np.empty_like(L)
     inv[L] = np.arange(L.size)
     return inv[np.asarray(sel)]
+
+
+def fft_poisson(level: int, G: float = 1.0):
+    """phi_i = -G sum_{j != i} m_j / |x_i - x_j| over the cell centres of the
+    uniform grid of `level`, by zero-padded FFT convolution."""
+    n = 8 << level
+    h = 1.0 / n
+    m = 2 * n
+    k = np.arange(m)
+    k = np.where(k < n, k, k - m) * h
+    X, Y, Z = np.meshgrid(k, k, k, indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    g = np.zeros_like(r)
+    g[r > 0] = 1.0 / r[r > 0]
+    gh = np.fft.rfftn(g)
+
+    def solve(rho):
+        pad = np.zeros((m, m, m))
+        pad[:n, :n, :n] = rho * h ** 3
+        return -G * np.fft.irfftn(np.fft.rfftn(pad) * gh, s=(m, m, m), axes=(0, 1, 2))[:n, :n, :n]
+
+    return solve

@@ -232,17 +232,19 @@ def noisy_rate(rho: np.ndarray, seed: int) -> np.ndarray:
 
 
 def scf_initial_binary(level: int, M1: float, M2: float, a0: float, R1: float, R2: float, n: float = 1.5,
-                       G: float = 1.0):
+                       G: float = 1.0, yz=(0.0, 0.0)):
     """Starting model of a binary self-consistent-field iteration: two
     n-polytropes of masses M1 (at x < 0) and M2 with radii R1, R2, centres a0
-    apart on x about the origin, on the uniform grid of `level`; also returns
-    the polytropic constant of the first star, K = 4 pi G R1^2 rho_c1^(1-1/n) /
-    ((n+1) xi1^2), as the iteration's starting K."""
+    apart on the line y, z = `yz` parallel to x, with their centre of mass at
+    x = 0, on the uniform grid of `level`; also returns the polytropic
+    constant of the first star, K = 4 pi G R1^2 rho_c1^(1-1/n) / ((n+1) xi1^2),
+    as the iteration's starting K.  A `yz` off the cell faces makes each
+    star's densest cell unique (on the axis the cells around it tie)."""
     _, _, _, xi1, dth1 = lane_emden_table(n)
     x1, x2 = -a0 * M2 / (M1 + M2), a0 * M1 / (M1 + M2)
     rc1 = M1 / (4.0 * math.pi * R1 ** 3 * (-dth1 / xi1))
     rc2 = M2 / (4.0 * math.pi * R2 ** 3 * (-dth1 / xi1))
-    f = Polytropes(stars=[Star((x1, 0.0, 0.0), R1, rc1, n), Star((x2, 0.0, 0.0), R2, rc2, n)])
+    f = Polytropes(stars=[Star((x1, yz[0], yz[1]), R1, rc1, n), Star((x2, yz[0], yz[1]), R2, rc2, n)])
     K0 = 4.0 * math.pi * G * R1 * R1 * rc1 ** (1.0 - 1.0 / n) / ((n + 1.0) * xi1 * xi1)
     return uniform_grid(f, level), K0
 
