@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000, help="c5: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="c5: arrivals per second (0: 0.8 x measured saturation)")
     ap.add_argument("--budget-gib", type=float, default=16.0, help="c5: HBM budget of the server context")
+    ap.add_argument("--no-scf", action="store_true", help="c2: skip the self-consistent-field timing")
+    ap.add_argument("--scf-level", type=int, default=4, help="c2: uniform level of the SCF grid (4: 128^3)")
+    ap.add_argument("--scf-iters", type=int, default=20, help="c2: SCF iterations per timed run")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration) and exit")
     return ap.parse_args()
@@ -147,6 +150,51 @@ def single_tree_bench(a, lib, w, ctx, tree, n_cells, workload, rate=None):
                                                       dphi.data_ptr()), sync, a.steps, a.warmup)
             res["dphidt_" + prec_name] = dict(sec=sec)
     return res
+
+
+def scf_bench(a, lib, w, ctx, level, iters):
+    """Self-consistent-field iterations (initial binary model, Sec. 4.1) on
+    the uniform grid of `level`: each timed run restores the starting
+    density, then runs `iters` iterations (normalise, solve, steps 2-6) plus
+    the closing normalise and solve; a run of 0 iterations times that
+    frame, and the difference over `iters` is the time of one iteration."""
+    import torch
+
+    rho0, K0 = w.scf_initial_binary(level, 1.0, 0.7, 0.4, 0.12, 0.10, yz=(0.0123, 0.0071))
+    n = rho0.shape[0]
+    par = lib.make_scf_params(1.0, 0.7, 1.5, 0.4, 0.9, K0, 1e-10, 1.0, 0.0)
+    tree = ctx.uniform_tree(rho0)
+    start = torch.tensor(rho0.ravel(), dtype=torch.float64, device=ctx.device)
+    rho = torch.empty(n ** 3, dtype=torch.float64, device=ctx.device)
+    phi = torch.empty(n ** 3, dtype=torch.float64, device=ctx.device)
+    opts = lib.make_opts(a.theta, 1.0, lib.OCTO_FP64, True)
+    torch.cuda.synchronize()
+
+    def run(k):
+        lib.octo_tree_set_density(tree.handle, start.data_ptr(), True)
+        return lib.octo_scf_run(ctx.handle, tree.handle, opts, par, k, rho.data_ptr(), phi.data_ptr())
+
+    print(f"[bench] SCF {n}^3: {iters} iterations per run", file=sys.stderr, flush=True)
+    for _ in range(2):
+        run(iters)
+        run(0)
+    reps = 5
+    t_it, t_0 = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        hist = run(iters)
+        t_it.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        run(0)
+        t_0.append(time.perf_counter() - t0)
+    tree.destroy()
+    per = (float(np.median(t_it)) - float(np.median(t_0))) / iters
+    last = hist[-1]
+    return {"grid": f"{n}^3", "cells": n ** 3, "iterations": iters, "ms_per_iteration": round(per * 1e3, 4),
+            "iterations_per_s": round(1.0 / per, 1), "cell_updates_per_s": round(n ** 3 / per, 1),
+            "frame_ms": round(float(np.median(t_0)) * 1e3, 4),
+            "model": "n=1.5 binary, M1=1, M2=0.7, a0=0.4, f=0.9, R=0.12/0.10 start, stars' axis at y,z=0.0123,0.0071",
+            "last": {"omega": last.omega, "K": last.K, "C1": last.C1, "C2": last.C2, "x_L1": last.x_L1, "a": last.a}}
 
 
 def main():
@@ -227,6 +275,8 @@ def main():
                     "value": round(n_cells / res[k]["sec"], 1), "ms_per_step": round(res[k]["sec"] * 1e3, 4),
                     "source": "orbital density rate (pattern turning about z)" if a.config != "c1" else
                               "rho * N(0,1)"}
+        if a.config == "c2" and not a.no_scf:
+            out["scf"] = scf_bench(a, lib, w, ctx, a.scf_level, a.scf_iters)
         if not a.no_cpu:
             print(f"[bench] CPU oracle, {a.cpu_threads} threads", file=sys.stderr, flush=True)
             t = oracle_tree()

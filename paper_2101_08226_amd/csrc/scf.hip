@@ -26,8 +26,9 @@
 namespace octo {
 namespace {
 
-constexpr int kT = 256;         // threads per block
-constexpr int kMaxParts = 1024;  // partial results per streaming pass
+constexpr int kT = 256;          // threads per block
+constexpr int kMaxParts = 2048;  // partial results per streaming pass (blocks)
+constexpr int kUnr = 4;          // cells per thread with their loads in flight together
 constexpr int kSums = 11;        // moments gathered by the moments pass
 constexpr int64_t kNone = INT64_MAX;
 
@@ -93,7 +94,8 @@ __device__ inline double wsum(double v) {
     return v;
 }
 
-__device__ inline void cell_ijk(int64_t g, const ScfConst &k, int &i, int &j, int &l) {
+// grids up to 512^3 cells: flat indices fit 32 bits
+__device__ inline void cell_ijk(uint32_t g, const ScfConst &k, int &i, int &j, int &l) {
     i = (int)(g >> (2 * k.lg));
     j = (int)(g >> k.lg) & (k.n - 1);
     l = (int)g & (k.n - 1);
@@ -102,22 +104,24 @@ __device__ inline void cell_ijk(int64_t g, const ScfConst &k, int &i, int &j, in
 __device__ inline double centre_of(int i, double h) { return (i + 0.5) * h - 0.5; }
 
 // Side 0 (accretor) holds the cells whose centre lies below the split.
-__device__ inline int side_of(int i, int64_t s2) { return (int64_t)(2 * i + 1) < s2 ? 0 : 1; }
+// Offsets and radii in half-cell units stay below 2^11 (n <= 512), their
+// squares and sums below 2^31.
+__device__ inline int side_of(int i, int64_t s2) { return 2 * i + 1 < (int)s2 ? 0 : 1; }
 
 struct Star {
     int ci, cj, cl;
-    int64_t r2sq;  // squared radius in half-cell units
+    int r2sq;  // squared radius in half-cell units
 };
 
 __device__ inline Star star_of(int64_t c, int64_t r2, const ScfConst &k) {
     Star s;
-    cell_ijk(c, k, s.ci, s.cj, s.cl);
-    s.r2sq = r2 * r2;
+    cell_ijk((uint32_t)c, k, s.ci, s.cj, s.cl);
+    s.r2sq = (int)(r2 * r2);
     return s;
 }
 
 __device__ inline bool inside(const Star &s, int i, int j, int l) {
-    const int64_t di = i - s.ci, dj = j - s.cj, dl = l - s.cl;
+    const int di = i - s.ci, dj = j - s.cj, dl = l - s.cl;
     return 4 * (di * di + dj * dj + dl * dl) < s.r2sq;
 }
 
@@ -170,29 +174,38 @@ __global__ __launch_bounds__(kT) void k_scf_pass(ScfConst k, const ScfDev *__res
         kn = st->K_new * (k.npoly + 1.0);
     }
     Arg best[2] = {{-INFINITY, kNone}, {-INFINITY, kNone}};
-    const int64_t stride = (int64_t)gridDim.x * kT;
-    for (int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x; g < k.cells; g += stride) {
-        int i, j, l;
-        cell_ijk(g, k, i, j, l);
-        const int s = side_of(i, s2);
-        double v;
-        if (MODE == 0) {
-            v = rho[g];
-        } else if (MODE == 1) {
-            v = rho[g];
-            if (inside(S[s], i, j, l)) {
-                v = v * q[s];
+    const uint32_t cells = (uint32_t)k.cells, stride = gridDim.x * kT;
+    const double *src = MODE == 2 ? phi : rho;
+    for (uint32_t g0 = blockIdx.x * kT + threadIdx.x; g0 < cells; g0 += kUnr * stride) {
+        double in[kUnr];
+#pragma unroll
+        for (int u = 0; u < kUnr; ++u) {
+            const uint32_t g = g0 + u * stride;
+            in[u] = g < cells ? src[g] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnr; ++u) {
+            const uint32_t g = g0 + u * stride;
+            if (g >= cells) break;
+            int i, j, l;
+            cell_ijk(g, k, i, j, l);
+            const int s = side_of(i, s2);
+            double v = in[u];
+            if (MODE == 1) {
+                if (inside(S[s], i, j, l)) {
+                    v = v * q[s];
+                    rho[g] = v;
+                }
+            } else if (MODE == 2) {
+                const double dx = centre_of(i, k.h) - xc, dy = centre_of(j, k.h) - yc;
+                const double pe = in[u] - w2 * (dx * dx + dy * dy);
+                const double H = inside(S[s], i, j, l) ? C[s] - pe : -1.0;
+                v = H > 0.0 ? pow(H / kn, k.npoly) : 0.0;
+                v = v < k.rho_floor ? k.rho_floor : v;
                 rho[g] = v;
             }
-        } else {
-            const double dx = centre_of(i, k.h) - xc, dy = centre_of(j, k.h) - yc;
-            const double pe = phi[g] - w2 * (dx * dx + dy * dy);
-            const double H = inside(S[s], i, j, l) ? C[s] - pe : -1.0;
-            v = H > 0.0 ? pow(H / kn, k.npoly) : 0.0;
-            v = v < k.rho_floor ? k.rho_floor : v;
-            rho[g] = v;
+            take(best[s], v, g);
         }
-        take(best[s], v, g);
     }
     store_arg(best, bv, bi);
 }
@@ -229,21 +242,32 @@ __global__ __launch_bounds__(kT) void k_scf_moments(ScfConst k, const ScfDev *__
     const int64_t s2 = st->s2;
     double acc[kSums];
     for (int q = 0; q < kSums; ++q) acc[q] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * kT;
-    for (int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x; g < k.cells; g += stride) {
-        int i, j, l;
-        cell_ijk(g, k, i, j, l);
-        const double r = rho[g];
-        const double x = centre_of(i, k.h), y = centre_of(j, k.h), z = centre_of(l, k.h);
-        acc[0] += r;
-        acc[1] += r * x;
-        acc[2] += r * y;
-        const int s = side_of(i, s2);
-        if (inside(S[s], i, j, l)) {
-            acc[3 + 4 * s] += r;
-            acc[4 + 4 * s] += r * x;
-            acc[5 + 4 * s] += r * y;
-            acc[6 + 4 * s] += r * z;
+    const uint32_t cells = (uint32_t)k.cells, stride = gridDim.x * kT;
+    for (uint32_t g0 = blockIdx.x * kT + threadIdx.x; g0 < cells; g0 += kUnr * stride) {
+        double in[kUnr];
+#pragma unroll
+        for (int u = 0; u < kUnr; ++u) {
+            const uint32_t g = g0 + u * stride;
+            in[u] = g < cells ? rho[g] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnr; ++u) {
+            const uint32_t g = g0 + u * stride;
+            if (g >= cells) break;
+            int i, j, l;
+            cell_ijk(g, k, i, j, l);
+            const double r = in[u];
+            const double x = centre_of(i, k.h), y = centre_of(j, k.h), z = centre_of(l, k.h);
+            acc[0] += r;
+            acc[1] += r * x;
+            acc[2] += r * y;
+            const int s = side_of(i, s2);
+            if (inside(S[s], i, j, l)) {
+                acc[3 + 4 * s] += r;
+                acc[4 + 4 * s] += r * x;
+                acc[5 + 4 * s] += r * y;
+                acc[6 + 4 * s] += r * z;
+            }
         }
     }
     __shared__ double lds[kT / 64][kSums];
@@ -405,7 +429,7 @@ ScfConst make_const(int level, const octo_scf_params &p) {
 }
 
 int parts_for(int64_t cells) {
-    const int64_t per = (int64_t)kT * 8;
+    const int64_t per = (int64_t)kT * 2 * kUnr;
     const int64_t p = (cells + per - 1) / per;
     return (int)(p < 1 ? 1 : (p > kMaxParts ? kMaxParts : p));
 }
