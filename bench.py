@@ -197,6 +197,28 @@ def scf_bench(a, lib, w, ctx, level, iters):
             "last": {"omega": last.omega, "K": last.K, "C1": last.C1, "C2": last.C2, "x_L1": last.x_L1, "a": last.a}}
 
 
+def regrid_bench(tree, host_build_ms, l_max=7, rho_r=0.1, n_target=4000, reps=5):
+    """One regrid of the adaptive tree by the density criterion on the device
+    (flags, balance, new leaves and densities) plus the host layout of the
+    new tree; the tree's own host build from the analytic field beside it."""
+    print(f"[bench] regrid: {reps} runs", file=sys.stderr, flush=True)
+    t2, st = tree.regrid(l_max, rho_r, n_target)  # warm-up
+    t2.destroy()
+    wall, flag, lay = [], [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        t2, st = tree.regrid(l_max, rho_r, n_target)
+        wall.append((time.perf_counter() - t0) * 1e3)
+        flag.append(st["flag_ms"])
+        lay.append(st["layout_ms"])
+        t2.destroy()
+    return {"l_max": l_max, "rho_r": rho_r, "n_target": n_target, "ms": round(float(np.median(wall)), 3),
+            "device_part_ms": round(float(np.median(flag)), 3), "layout_ms": round(float(np.median(lay)), 3),
+            "refined": st["refined"], "balance_refined": st["balance_refined"], "derefined": st["derefined"],
+            "n_leaves_out": st["n_leaves"], "n_grids_out": st["n_grids"], "rho_r_next": st["rho_r_next"],
+            "host_build_from_field_ms": round(host_build_ms, 3)}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -240,7 +262,9 @@ def main():
         else:
             f = w.binary_polytrope_128()
             print("[bench] building the adaptive tree (level 6)", file=sys.stderr, flush=True)
+            tb = time.perf_counter()
             tree = ctx.adaptive_tree(f, 6, 1e-4)
+            host_build_ms = (time.perf_counter() - tb) * 1e3
             rate = w.leaf_density(w.OrbitalRate(f, 1.0, 1e-3), tree.leaves())
             desc = ("adaptive to level 6 (root sub-grid = level 0; 7736 leaf sub-grids, 3.96M leaf cells), "
                     "refined where box-max rho > 1e-4, 26-neighbour 2:1 balance; c2 field")
@@ -277,6 +301,8 @@ def main():
                               "rho * N(0,1)"}
         if a.config == "c2" and not a.no_scf:
             out["scf"] = scf_bench(a, lib, w, ctx, a.scf_level, a.scf_iters)
+        if a.config == "c3":
+            out["regrid"] = regrid_bench(tree, host_build_ms)
         if not a.no_cpu:
             print(f"[bench] CPU oracle, {a.cpu_threads} threads", file=sys.stderr, flush=True)
             t = oracle_tree()

@@ -176,6 +176,10 @@ octo_status octo_tree_build_adaptive(octo_ctx *ctx, octo_density_fn density, oct
                                      int max_level, double threshold, octo_tree **out);
 /* Replace the tree's density (same layout as at build time). */
 octo_status octo_tree_set_density(octo_tree *tree, const double *rho, int rho_on_device);
+/* Copy the tree's density (its layout, n_leaf_cells doubles) into rho: host
+ * memory (the call returns when the copy is done) or, when rho_on_device != 0,
+ * device memory (stream-ordered on the context stream). */
+octo_status octo_tree_get_density(const octo_tree *tree, double *rho, int rho_on_device);
 /* Sizes: leaf cells, levels (deepest level + 1), device bytes held. */
 octo_status octo_tree_info(const octo_tree *tree, int64_t *n_leaf_cells, int32_t *n_levels, size_t *bytes);
 /* Copy the leaf list (n_leaves entries) into caller memory. */
@@ -347,6 +351,56 @@ octo_status octo_scf_step(octo_ctx *ctx, int level, const octo_scf_params *p, do
  * iterations < 0), OCTO_E_UNSUPPORTED (bad opts), OCTO_E_STATE. */
 octo_status octo_scf_run(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, const octo_scf_params *p,
                          int32_t iterations, double *rho_out, double *phi_out, octo_scf_state *history);
+
+/* ---- regrid by the density criterion (Sec. 2.7) ------------------------- */
+
+typedef struct {
+    int32_t l_max;     /* deepest refinement level allowed (0..9) */
+    double rho_r;      /* refinement density cut-off (> 0) */
+    int64_t n_target;  /* desired number of sub-grids; <= 0 keeps rho_r */
+} octo_regrid_params;
+
+typedef struct {
+    int64_t refined;          /* leaves refined by the criterion */
+    int64_t balance_refined;  /* further leaves refined for the 2:1 balance */
+    int64_t derefined;        /* interior nodes whose children were removed */
+    int64_t n_leaves;         /* leaf sub-grids of the new tree */
+    int64_t n_grids;          /* sub-grids of the new tree, leaves and interior nodes */
+    double rho_r_next;        /* (n_grids / n_target)^2 rho_r, or rho_r when n_target <= 0 */
+    double flag_ms;           /* host wall time of the device part (flags, balance, new leaves and densities) */
+    double layout_ms;         /* host wall time of laying out and uploading the new tree */
+} octo_regrid_stats;
+
+/* One regrid of `tree` by the density criterion of Sec. 2.7, computed on the
+ * device from the tree's current density, into a new tree (*out); `tree` is
+ * left unchanged.  The readings this library takes where the text is silent:
+ * - a cell of level l is flagged when rho > 8^(l + 1 - l_max) rho_r (the largest
+ *   level L with rho > 8^(L - l_max) rho_r exceeds l; with the exponent as
+ *   printed the inequality would hold at l_max whenever it holds anywhere);
+ * - refinement and de-refinement move one level per call: a leaf below l_max
+ *   with a flagged cell gets 8 children; an interior node whose 8 children
+ *   are leaves loses them when none of its cells (the means of the child
+ *   cells under them) and none of its children's cells is flagged;
+ * - 2:1 balance over faces, edges and corners: a refined leaf refines the
+ *   coarser leaves next to it, to a fixed point; a de-refinement is dropped
+ *   when a child is refined, or when a child of a same-level neighbour that
+ *   touches the node is interior or refined; the input must be balanced;
+ * - densities move with the cells: a new child's cell takes the density of
+ *   the parent cell containing it, a de-refined node's cell the mean of its 8
+ *   child cells (summed in child-cell order x, y, z, then divided by 8), so
+ *   sum(rho h^3) is kept;
+ * - the two-cell refinement window and the regrid cadence (time stepping)
+ *   are not applied.
+ * The new tree uses the leaf-list density layout of octo_tree_build, with the
+ * leaves in the order octo_tree_leaves returns; its density is written on the
+ * device (only the leaf list, 16 bytes per leaf, goes to the host, which lays
+ * the tree out).  stats may be NULL.  Device scratch of 8 bytes per node of
+ * `tree` plus the new tree's leaves and densities is taken from the context's
+ * allocator for the call.  Returns when the new tree is ready.
+ * Errors: OCTO_E_INVALID (NULL pointer, l_max outside [0, 9], rho_r not
+ * finite and positive), OCTO_E_STATE, OCTO_E_BUDGET, OCTO_E_DEVICE. */
+octo_status octo_regrid(octo_ctx *ctx, octo_tree *tree, const octo_regrid_params *p, octo_tree **out,
+                        octo_regrid_stats *stats);
 
 /* ---- asynchronous requests (continuous batching) ------------------------ */
 

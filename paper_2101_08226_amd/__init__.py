@@ -28,8 +28,8 @@ STATUS_NAMES = {0: "OCTO_OK", 1: "OCTO_E_INVALID", 2: "OCTO_E_DEVICE", 3: "OCTO_
 # every symbol include/octo.h declares
 EXPORTS = [
     "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_tree_build", "octo_tree_build_uniform",
-    "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
-    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_run", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
+    "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_get_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
+    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_run", "octo_regrid", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
     "octo_host_stencil_sizes", "octo_host_layout", "octo_host_adaptive_leaves",
 ]
 
@@ -67,6 +67,19 @@ class octo_scf_state(ctypes.Structure):
 def make_scf_params(M1, M2, n=1.5, a0=0.35, f=0.9, K0=0.1, rho_floor=1e-10, G=1.0, x_L1=0.0) -> octo_scf_params:
     return octo_scf_params(float(M1), float(M2), float(n), float(a0), float(f), float(K0), float(rho_floor), float(G),
                            float(x_L1))
+
+
+class octo_regrid_params(ctypes.Structure):
+    _fields_ = [("l_max", ctypes.c_int32), ("rho_r", ctypes.c_double), ("n_target", ctypes.c_int64)]
+
+
+class octo_regrid_stats(ctypes.Structure):
+    _fields_ = [("refined", ctypes.c_int64), ("balance_refined", ctypes.c_int64), ("derefined", ctypes.c_int64),
+                ("n_leaves", ctypes.c_int64), ("n_grids", ctypes.c_int64), ("rho_r_next", ctypes.c_double),
+                ("flag_ms", ctypes.c_double), ("layout_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class octo_stats(ctypes.Structure):
@@ -125,6 +138,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_tree_build_uniform": [_P, _I, _D, _I, _PP],
         "octo_tree_build_adaptive": [_P, DENSITY_FN, BOXMAX_FN, _P, _I, ctypes.c_double, _PP],
         "octo_tree_set_density": [_P, _D, _I],
+        "octo_tree_get_density": [_P, _D, _I],
+        "octo_regrid": [_P, _P, ctypes.POINTER(octo_regrid_params), _PP, ctypes.POINTER(octo_regrid_stats)],
         "octo_tree_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t)],
         "octo_tree_leaves": [_P, ctypes.POINTER(octo_leaf)],
         "octo_tree_destroy": [_P],
@@ -229,6 +244,19 @@ def octo_tree_build_adaptive(ctx: int, field, max_level: int, threshold: float) 
 
 def octo_tree_set_density(tree: int, rho_ptr: int, rho_on_device: bool) -> None:
     _check(load_library().octo_tree_set_density(tree, _dptr(rho_ptr), int(rho_on_device)))
+
+
+def octo_tree_get_density(tree: int, rho_ptr: int, rho_on_device: bool) -> None:
+    _check(load_library().octo_tree_get_density(tree, _dptr(rho_ptr), int(rho_on_device)))
+
+
+def octo_regrid(ctx: int, tree: int, l_max: int, rho_r: float, n_target: int = 0):
+    """One regrid (Sec. 2.7): (new tree handle, octo_regrid_stats)."""
+    p = octo_regrid_params(int(l_max), float(rho_r), int(n_target))
+    out = ctypes.c_void_p()
+    st = octo_regrid_stats()
+    _check(load_library().octo_regrid(ctx, tree, ctypes.byref(p), ctypes.byref(out), ctypes.byref(st)))
+    return out.value, st
 
 
 def octo_tree_info(tree: int):
@@ -530,6 +558,18 @@ class Tree:
     def set_density(self, rho) -> None:
         rho = np.ascontiguousarray(rho, dtype=np.float64)
         octo_tree_set_density(self.handle, rho.ctypes.data, False)
+
+    def density(self) -> np.ndarray:
+        """The tree's density (its layout) copied to the host."""
+        out = np.empty(self.n_leaf_cells, dtype=np.float64)
+        octo_tree_get_density(self.handle, out.ctypes.data, False)
+        return out
+
+    def regrid(self, l_max: int, rho_r: float, n_target: int = 0):
+        """One regrid by the density criterion (Sec. 2.7): the new Tree and the
+        regrid statistics; this tree is unchanged."""
+        h, st = octo_regrid(self.ctx.handle, self.handle, l_max, rho_r, n_target)
+        return Tree(self.ctx, h), st.as_dict()
 
     def destroy(self):
         if self.handle:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -617,6 +618,18 @@ octo_status octo_tree_set_density(octo_tree *t, const double *rho, int rho_on_de
     });
 }
 
+octo_status octo_tree_get_density(const octo_tree *t, double *rho, int rho_on_device) {
+    return guard([&] {
+        if (!t || !rho) fail(OCTO_E_INVALID, "NULL argument");
+        std::lock_guard<std::recursive_mutex> lk(t->ctx->mu);
+        DeviceGuard dg(t->ctx->device);
+        check_hip(hipMemcpyAsync(rho, t->rho, (size_t)t->layout.n_leaf_cells * 8,
+                                 rho_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, t->ctx->stream),
+                  "density copy");
+        if (!rho_on_device) check_hip(hipStreamSynchronize(t->ctx->stream), "density copy");
+    });
+}
+
 octo_status octo_tree_info(const octo_tree *t, int64_t *n_leaf_cells, int32_t *n_levels, size_t *bytes) {
     return guard([&] {
         if (!t) fail(OCTO_E_INVALID, "tree is NULL");
@@ -817,6 +830,42 @@ octo_status octo_scf_run(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, 
         octo_opts o = *opts;
         o.G = p->G;
         scf_run(ctx, tree, level, o, *p, s2, iterations, rho_out, phi_out, history);
+    });
+}
+
+octo_status octo_regrid(octo_ctx *ctx, octo_tree *tree, const octo_regrid_params *p, octo_tree **out,
+                        octo_regrid_stats *stats) {
+    return guard([&] {
+        if (!ctx || !tree || !p || !out) fail(OCTO_E_INVALID, "NULL argument");
+        if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+        if (p->l_max < 0 || p->l_max > kMaxLevel) fail(OCTO_E_INVALID, "l_max must lie in [0, 9]");
+        if (!std::isfinite(p->rho_r) || p->rho_r <= 0.0) fail(OCTO_E_INVALID, "rho_r must be finite and positive");
+        RegridOut r;
+        const auto t0 = std::chrono::steady_clock::now();
+        {
+            std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+            DeviceGuard dg(ctx->device);
+            regrid_device(ctx, tree, p->l_max, p->rho_r, r);
+        }
+        const auto t1 = std::chrono::steady_clock::now();
+        octo_tree *t = nullptr;
+        const octo_status st = make_tree(ctx, r.leaves.data(), (int64_t)r.leaves.size(), -1, r.rho, 1, &t);
+        if (st != OCTO_OK) throw Error{st, g_err};
+        const auto t2 = std::chrono::steady_clock::now();
+        int64_t grids = 0;
+        for (const HostLevel &h : t->layout.lv) grids += h.n_nodes;
+        *out = t;
+        if (stats) {
+            stats->refined = r.refined;
+            stats->balance_refined = r.balance_refined;
+            stats->derefined = r.derefined;
+            stats->n_leaves = (int64_t)r.leaves.size();
+            stats->n_grids = grids;
+            const double ratio = (double)grids / (double)p->n_target;
+            stats->rho_r_next = p->n_target > 0 ? p->rho_r * (ratio * ratio) : p->rho_r;
+            stats->flag_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            stats->layout_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
+        }
     });
 }
 

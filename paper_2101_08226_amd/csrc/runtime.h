@@ -256,5 +256,20 @@ void scf_step(octo_ctx *ctx, int level, const octo_scf_params &p, double K, int6
               const double *phi, double *rho_out, octo_scf_state *state);
 void scf_run(octo_ctx *ctx, octo_tree *t, int level, const octo_opts &o, const octo_scf_params &p, int64_t s2,
              int iterations, double *rho_out, double *phi_out, octo_scf_state *history);
+// one regrid by the density criterion (Sec. 2.7) on the device: the new leaf
+// list (host) and its densities (device, leaf layout), owned until destruction
+struct RegridOut {
+    octo_ctx *ctx = nullptr;
+    void *scratch = nullptr, *out = nullptr;
+    size_t scratch_bytes = 0, out_bytes = 0;
+    double *rho = nullptr;
+    std::vector<octo_leaf> leaves;
+    int64_t refined = 0, balance_refined = 0, derefined = 0;
+    RegridOut() = default;
+    RegridOut(const RegridOut &) = delete;
+    RegridOut &operator=(const RegridOut &) = delete;
+    ~RegridOut();
+};
+void regrid_device(octo_ctx *ctx, octo_tree *t, int l_max, double rho_r, RegridOut &r);
 void build_tree_plan(octo_tree *t);
 }  // namespace octo
