@@ -37,7 +37,6 @@ struct Node {
     int l, x, y, z;
     bool leaf;
     int64_t leaf_index;  // caller order, -1 for interior
-    int idx = -1;        // index within its level after sorting
 };
 
 }  // namespace
@@ -46,6 +45,8 @@ Layout build_layout(const octo_leaf *leaves, int64_t n, int grid_level) {
     if (n <= 0 || !leaves) fail(OCTO_E_INVALID, "empty leaf list");
     std::vector<Node> nodes;
     nodes.reserve((size_t)n * 8 / 7 + 8);
+    std::vector<int> parent;  // global index of each node's parent, -1 at the root
+    parent.reserve(nodes.capacity());
     std::unordered_map<uint64_t, int> at;
     at.reserve((size_t)n * 2);
     int deepest = 0;
@@ -55,64 +56,109 @@ Layout build_layout(const octo_leaf *leaves, int64_t n, int grid_level) {
         int m = 1 << f.level;
         if (f.ix < 0 || f.iy < 0 || f.iz < 0 || f.ix >= m || f.iy >= m || f.iz >= m)
             fail(OCTO_E_INVALID, "leaf " + std::to_string(k) + ": index out of range");
-        uint64_t kk = key(f.level, f.ix, f.iy, f.iz);
-        if (at.count(kk)) fail(OCTO_E_INVALID, "leaf " + std::to_string(k) + ": duplicate");
-        at[kk] = (int)nodes.size();
+        if (!at.emplace(key(f.level, f.ix, f.iy, f.iz), (int)nodes.size()).second)
+            fail(OCTO_E_INVALID, "leaf " + std::to_string(k) + ": duplicate");
         nodes.push_back(Node{f.level, f.ix, f.iy, f.iz, true, k});
+        parent.push_back(-1);
         deepest = std::max(deepest, f.level);
     }
-    // ancestors
+    // ancestors, and every node's parent
     for (int64_t k = 0; k < n; ++k) {
-        Node f = nodes[k];
-        int x = f.x, y = f.y, z = f.z;
-        for (int l = f.l - 1; l >= 0; --l) {
+        int child = (int)k;
+        int x = nodes[k].x, y = nodes[k].y, z = nodes[k].z;
+        for (int l = nodes[k].l - 1; l >= 0; --l) {
             x >>= 1;
             y >>= 1;
             z >>= 1;
-            auto it = at.find(key(l, x, y, z));
-            if (it != at.end()) {
-                if (nodes[it->second].leaf)
-                    fail(OCTO_E_INVALID, "leaf " + std::to_string(k) + " lies inside another leaf");
+            auto ins = at.emplace(key(l, x, y, z), (int)nodes.size());
+            const int p = ins.first->second;
+            parent[child] = p;
+            if (!ins.second) {
+                if (nodes[p].leaf) fail(OCTO_E_INVALID, "leaf " + std::to_string(k) + " lies inside another leaf");
                 break;
             }
-            at[key(l, x, y, z)] = (int)nodes.size();
             nodes.push_back(Node{l, x, y, z, false, -1});
+            parent.push_back(-1);
+            child = p;
         }
     }
     if (!at.count(key(0, 0, 0, 0))) fail(OCTO_E_INVALID, "no root");
-    auto find = [&](int l, int x, int y, int z) -> int {
-        if (l < 0) return -1;
-        int m = 1 << l;
-        if (x < 0 || y < 0 || z < 0 || x >= m || y >= m || z >= m) return -1;
-        auto it = at.find(key(l, x, y, z));
-        return it == at.end() ? -1 : it->second;
-    };
-    // every interior node has its 8 children
-    for (const Node &p : nodes) {
+    const int nn = (int)nodes.size();
+    // children from the parent links; every interior node needs all 8
+    std::vector<int> childg((size_t)nn * 8, -1);
+    for (int i = 0; i < nn; ++i) {
+        if (parent[i] < 0) continue;
+        const Node &a = nodes[i];
+        childg[(size_t)parent[i] * 8 + (((a.x & 1) << 2) | ((a.y & 1) << 1) | (a.z & 1))] = i;
+    }
+    std::vector<std::vector<int>> per(deepest + 1);
+    for (int i = 0; i < nn; ++i) per[nodes[i].l].push_back(i);
+    for (int i = 0; i < nn; ++i) {
+        const Node &p = nodes[i];
         if (p.leaf) continue;
         for (int c = 0; c < 8; ++c)
-            if (find(p.l + 1, 2 * p.x + (c >> 2), 2 * p.y + ((c >> 1) & 1), 2 * p.z + (c & 1)) < 0)
+            if (childg[(size_t)i * 8 + c] < 0)
                 fail(OCTO_E_INVALID, "the leaves leave a gap below node (" + std::to_string(p.l) + "," +
                                          std::to_string(p.x) + "," + std::to_string(p.y) + "," + std::to_string(p.z) +
                                          ")");
     }
+    // compact copies of the per-node data the passes below walk
+    std::vector<uint8_t> isleaf(nn);
+    std::vector<int32_t> pos((size_t)nn * 3);
+    for (int i = 0; i < nn; ++i) {
+        isleaf[i] = nodes[i].leaf;
+        pos[3 * (size_t)i] = nodes[i].x;
+        pos[3 * (size_t)i + 1] = nodes[i].y;
+        pos[3 * (size_t)i + 2] = nodes[i].z;
+    }
+    // same-level neighbours, level by level from the parents' neighbours: the
+    // node at q exists when the node at q/2 exists and is interior.  Per axis,
+    // a coordinate of parity b moved by d in {-1, 0, 1} lands in the parent
+    // cell offset (b + d) >> 1 (floor) at child parity (b + d) & 1.
+    std::vector<int> nbrg((size_t)nn * 27, -1);
+    for (int l = 1; l <= deepest; ++l) {
+        const int m = 1 << l;
+        for (int i : per[l]) {
+            const int ax = pos[3 * (size_t)i], ay = pos[3 * (size_t)i + 1], az = pos[3 * (size_t)i + 2];
+            const int *pn = &nbrg[(size_t)parent[i] * 27];
+            const int p = parent[i];
+            int *out = &nbrg[(size_t)i * 27];
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int qx = ax + dx;
+                if (qx < 0 || qx >= m) continue;
+                const int px = ((ax & 1) + dx) >> 1, cx = (qx & 1) << 2;
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int qy = ay + dy;
+                    if (qy < 0 || qy >= m) continue;
+                    const int py = ((ay & 1) + dy) >> 1, cy = (qy & 1) << 1;
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const int qz = az + dz;
+                        if (qz < 0 || qz >= m) continue;
+                        const int pz = ((az & 1) + dz) >> 1;
+                        const int d = (px + 1) * 9 + (py + 1) * 3 + pz + 1;
+                        const int pq = d == 13 ? p : pn[d];
+                        if (pq < 0 || isleaf[pq]) continue;
+                        out[(dx + 1) * 9 + (dy + 1) * 3 + dz + 1] = childg[(size_t)pq * 8 + (cx | cy | (qz & 1))];
+                    }
+                }
+            }
+        }
+    }
     // proper nesting: no leaf touches an interior node one level finer
-    for (const Node &a : nodes) {
-        if (!a.leaf) continue;
+    for (int i = 0; i < nn; ++i) {
+        if (!isleaf[i]) continue;
         for (int o = 0; o < 27; ++o) {
+            const int b = nbrg[(size_t)i * 27 + o];
+            if (b < 0 || isleaf[b]) continue;
             int dx = o / 9 - 1, dy = (o / 3) % 3 - 1, dz = o % 3 - 1;
-            if (!dx && !dy && !dz) continue;
-            int b = find(a.l, a.x + dx, a.y + dy, a.z + dz);
-            if (b < 0 || nodes[b].leaf) continue;
-            const Node &p = nodes[b];
-            // children of p on the faces/edges/corner towards a
+            // children of b on the faces/edges/corner towards a
             for (int c = 0; c < 8; ++c) {
                 int cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
                 if ((dx > 0 && cx) || (dx < 0 && !cx) || (dy > 0 && cy) || (dy < 0 && !cy) || (dz > 0 && cz) ||
                     (dz < 0 && !cz))
                     continue;
-                int q = find(p.l + 1, 2 * p.x + cx, 2 * p.y + cy, 2 * p.z + cz);
-                if (!nodes[q].leaf) fail(OCTO_E_INVALID, "leaves are not properly nested (2:1 balance)");
+                if (!isleaf[childg[(size_t)b * 8 + c]])
+                    fail(OCTO_E_INVALID, "leaves are not properly nested (2:1 balance)");
             }
         }
     }
@@ -122,34 +168,38 @@ Layout build_layout(const octo_leaf *leaves, int64_t n, int grid_level) {
     L.leaves.assign(leaves, leaves + n);
     L.n_leaf_cells = n * 512;
     L.lv.resize(L.n_levels);
-    std::vector<std::vector<int>> per(L.n_levels);
-    for (int i = 0; i < (int)nodes.size(); ++i) per[nodes[i].l].push_back(i);
     // classification: interior, record leaf (touches an interior node of its level), other leaf
-    std::vector<int> cls(nodes.size());
-    for (int i = 0; i < (int)nodes.size(); ++i) {
-        const Node &a = nodes[i];
-        if (!a.leaf) {
+    std::vector<int> cls(nn);
+    for (int i = 0; i < nn; ++i) {
+        if (!isleaf[i]) {
             cls[i] = 0;
             continue;
         }
         bool rec = false;
         for (int o = 0; o < 27 && !rec; ++o) {
-            int b = find(a.l, a.x + o / 9 - 1, a.y + (o / 3) % 3 - 1, a.z + o % 3 - 1);
-            if (b >= 0 && !nodes[b].leaf) rec = true;
+            const int b = nbrg[(size_t)i * 27 + o];
+            if (b >= 0 && !isleaf[b]) rec = true;
         }
         cls[i] = rec ? 1 : 2;
     }
+    // per level: sort (class, Morton key) pairs, then number the nodes
+    std::vector<int> idx(nn);
+    std::vector<std::pair<uint64_t, int>> ord;
     for (int l = 0; l < L.n_levels; ++l) {
         auto &v = per[l];
-        std::sort(v.begin(), v.end(), [&](int a, int b) {
-            if (cls[a] != cls[b]) return cls[a] < cls[b];
-            return morton(nodes[a].x, nodes[a].y, nodes[a].z) < morton(nodes[b].x, nodes[b].y, nodes[b].z);
-        });
+        ord.clear();
+        for (int i : v) ord.emplace_back(((uint64_t)cls[i] << 62) | morton(nodes[i].x, nodes[i].y, nodes[i].z), i);
+        std::sort(ord.begin(), ord.end());
         HostLevel &h = L.lv[l];
         h.n_nodes = (int)v.size();
-        h.n_int = (int)std::count_if(v.begin(), v.end(), [&](int a) { return cls[a] == 0; });
-        h.n_rec = h.n_int + (int)std::count_if(v.begin(), v.end(), [&](int a) { return cls[a] == 1; });
-        for (int k = 0; k < h.n_nodes; ++k) nodes[v[k]].idx = k;
+        h.n_int = 0;
+        h.n_rec = 0;
+        for (int k = 0; k < h.n_nodes; ++k) {
+            v[k] = ord[k].second;
+            idx[v[k]] = k;
+            h.n_int += cls[v[k]] == 0;
+            h.n_rec += cls[v[k]] <= 1;
+        }
     }
     const int64_t gn = grid_level >= 0 ? (int64_t)8 << grid_level : 0;
     if (grid_level >= 0) {
@@ -167,19 +217,18 @@ Layout build_layout(const octo_leaf *leaves, int64_t n, int grid_level) {
         h.out_base.assign(h.n_nodes, -1);
         h.flags.assign(h.n_nodes, 0);
         for (int k = 0; k < h.n_nodes; ++k) {
-            const Node &a = nodes[v[k]];
+            const int i = v[k];
+            const Node &a = nodes[i];
             h.coord[3 * k] = a.x;
             h.coord[3 * k + 1] = a.y;
             h.coord[3 * k + 2] = a.z;
             for (int o = 0; o < 27; ++o) {
-                int b = find(l, a.x + o / 9 - 1, a.y + (o / 3) % 3 - 1, a.z + o % 3 - 1);
-                h.nbr[27 * k + o] = b < 0 ? -1 : nodes[b].idx;
+                const int b = nbrg[(size_t)i * 27 + o];
+                h.nbr[27 * k + o] = b < 0 ? -1 : idx[b];
             }
-            if (l > 0) h.parent[k] = nodes[find(l - 1, a.x >> 1, a.y >> 1, a.z >> 1)].idx;
+            if (l > 0) h.parent[k] = idx[parent[i]];
             if (!a.leaf) {
-                for (int c = 0; c < 8; ++c)
-                    h.child[8 * k + c] =
-                        nodes[find(l + 1, 2 * a.x + (c >> 2), 2 * a.y + ((c >> 1) & 1), 2 * a.z + (c & 1))].idx;
+                for (int c = 0; c < 8; ++c) h.child[8 * k + c] = idx[childg[(size_t)i * 8 + c]];
             } else {
                 if (grid_level >= 0)
                     h.out_base[k] = ((int64_t)8 * a.x * gn + 8 * a.y) * gn + 8 * a.z;
@@ -188,11 +237,9 @@ Layout build_layout(const octo_leaf *leaves, int64_t n, int grid_level) {
                 int32_t f = 0;
                 if (k < h.n_rec) f |= kLeafX1 | kLeafLacc;
                 if (l > 0) {
-                    const Node &p = nodes[find(l - 1, a.x >> 1, a.y >> 1, a.z >> 1)];
-                    for (int o = 0; o < 27; ++o) {
-                        int b = find(l - 1, p.x + o / 9 - 1, p.y + (o / 3) % 3 - 1, p.z + o % 3 - 1);
-                        if (b >= 0 && nodes[b].leaf) f |= kLeafX2;
-                    }
+                    const int *pn = &nbrg[(size_t)parent[i] * 27];
+                    for (int o = 0; o < 27; ++o)
+                        if (pn[o] >= 0 && isleaf[pn[o]]) f |= kLeafX2;
                 }
                 h.flags[k] = f;
             }
