@@ -136,30 +136,29 @@ __global__ __launch_bounds__(kRgT) void k_rg_balance(RgConst k, const LevelDesc 
             }
 }
 
-// de-refinements that would break the balance
-__global__ __launch_bounds__(kRgT) void k_rg_cancel(RgConst k, const LevelDesc *__restrict__ lv, int32_t *marks) {
-    const int g = blockIdx.x * kRgT + threadIdx.x;
-    if (g >= k.n_total) return;
+// de-refinements that would break the balance: one wavefront per node, a
+// lane per (neighbour, child) pair
+__global__ __launch_bounds__(64) void k_rg_cancel(RgConst k, const LevelDesc *__restrict__ lv, int32_t *marks) {
+    const int g = blockIdx.x;
     if (!(marks[g] & 4)) return;
     const int l = level_of(k, g);
     const LevelDesc L = lv[l], C = lv[l + 1];
     const int node = g - k.nodeoff[l];
-    bool bad = false;
-    for (int i = 0; i < 8; ++i) bad = bad || (marks[k.nodeoff[l + 1] + L.child[node * 8 + i]] & 3);
     const int px = L.coord[node * 3], py = L.coord[node * 3 + 1], pz = L.coord[node * 3 + 2];
-    for (int d = 0; d < 27 && !bad; ++d) {
+    bool bad = false;
+    if (threadIdx.x < 8) bad = marks[k.nodeoff[l + 1] + L.child[node * 8 + threadIdx.x]] & 3;
+    for (int t = threadIdx.x; t < 27 * 8; t += 64) {
+        const int d = t >> 3, i = t & 7;
         if (d == 13) continue;
         const int q = L.nbr[node * 27 + d];
         if (q < 0 || q >= L.n_int) continue;
-        for (int i = 0; i < 8; ++i) {
-            const int c = L.child[q * 8 + i];
-            const int cx = C.coord[c * 3], cy = C.coord[c * 3 + 1], cz = C.coord[c * 3 + 2];
-            const bool touch = cx >= 2 * px - 1 && cx <= 2 * px + 2 && cy >= 2 * py - 1 && cy <= 2 * py + 2 &&
-                               cz >= 2 * pz - 1 && cz <= 2 * pz + 2;
-            if (touch && (c < C.n_int || (marks[k.nodeoff[l + 1] + c] & 3))) bad = true;
-        }
+        const int c = L.child[q * 8 + i];
+        const int cx = C.coord[c * 3], cy = C.coord[c * 3 + 1], cz = C.coord[c * 3 + 2];
+        const bool touch = cx >= 2 * px - 1 && cx <= 2 * px + 2 && cy >= 2 * py - 1 && cy <= 2 * py + 2 &&
+                           cz >= 2 * pz - 1 && cz <= 2 * pz + 2;
+        if (touch && (c < C.n_int || (marks[k.nodeoff[l + 1] + c] & 3))) bad = true;
     }
-    if (bad) marks[g] |= 8;
+    if (__any(bad) && threadIdx.x == 0) marks[g] |= 8;
 }
 
 __device__ inline bool derefined(int32_t m) { return (m & 4) && !(m & 8); }
@@ -289,7 +288,7 @@ void regrid_device(octo_ctx *ctx, octo_tree *t, int l_max, double rho_r, RegridO
     const int nb = (total + kRgT - 1) / kRgT;
     // each pass carries the cascade at least one level up; nl passes reach the root
     for (int i = 0; i < nl; ++i) hipLaunchKernelGGL(k_rg_balance, dim3(nb), dim3(kRgT), 0, q, k, dl, marks);
-    hipLaunchKernelGGL(k_rg_cancel, dim3(nb), dim3(kRgT), 0, q, k, dl, marks);
+    hipLaunchKernelGGL(k_rg_cancel, dim3(total), dim3(64), 0, q, k, dl, marks);
     hipLaunchKernelGGL(k_rg_count, dim3(nb), dim3(kRgT), 0, q, k, dl, marks, cnt);
     hipLaunchKernelGGL(k_rg_scan, dim3(1), dim3(1024), 0, q, cnt, off, total);
     std::vector<int32_t> hm(total);
