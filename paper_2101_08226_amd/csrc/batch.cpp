@@ -44,6 +44,7 @@ void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipG
     lo.precision = o->precision;
     lo.count = count;
     lo.source = source;
+    lo.amc = o->amc != 0;
     lo.fork = ctx->fork_ev;
     lo.join = ctx->join_ev;
     lo.fork_near = ctx->fork_near_ev;
@@ -63,7 +64,8 @@ void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipG
     lo.aux = ctx->capture_aux;
     lo.aux_near = ctx->capture_near;
     const auto key =
-        std::make_pair(theta_bits(o->theta), (int)o->precision * 4 + (source ? 2 : 0) + (count ? 1 : 0));
+        std::make_pair(theta_bits(o->theta),
+                       (int)o->precision * 8 + (o->amc ? 4 : 0) + (source ? 2 : 0) + (count ? 1 : 0));
     auto it = graphs.find(key);
     if (it == graphs.end()) {
         hipGraph_t g = nullptr;
@@ -264,19 +266,21 @@ static void retire_waves(octo_ctx *ctx) {
 
 // Launch waves while fewer than max_inflight_waves are on the device: each
 // wave takes the pending requests with the first request's (theta,
-// precision), at most one request per tree.
+// precision, correction switch), at most one request per tree.
 static void pump(octo_ctx *ctx) {
     retire_waves(ctx);
     while (!ctx->pending.empty() && (int)ctx->waves.size() < ctx->max_inflight_waves) {
         const Request &first = ctx->requests.at(ctx->pending.front());
         const double theta = first.opts.theta;
         const int prec = first.opts.precision;
+        const bool amc = first.opts.amc != 0;
         std::vector<octo_ticket> take;
         std::set<octo_tree *> used;
         std::deque<octo_ticket> rest;
         for (octo_ticket t : ctx->pending) {
             Request &r = ctx->requests.at(t);
-            if (r.opts.theta == theta && r.opts.precision == prec && !used.count(r.tree)) {
+            if (r.opts.theta == theta && r.opts.precision == prec && (r.opts.amc != 0) == amc &&
+                !used.count(r.tree)) {
                 used.insert(r.tree);
                 take.push_back(t);
             } else {
@@ -309,6 +313,7 @@ static void pump(octo_ctx *ctx) {
         const StencilDevHolder &st = ctx->stencil(theta);
         LaunchOpts lo;
         lo.precision = prec;
+        lo.amc = amc;
         lo.aux = ctx->aux;
         lo.fork = ctx->fork_ev;
         lo.join = ctx->join_ev;

@@ -412,7 +412,12 @@ template <bool LEAF_TARGET, bool DIP, typename T>
 __device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, const double *q64, const double *o64,
                                 const double *D64, double mu, const double *oA, bool amc, Acc<T> &a) {
     const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
-    const double d0 = rsqrt(r2);
+    // 1/|R|: the hardware estimate, then the second-order correction
+    // (1 - e)^(-1/2) ~ 1 + e/2 + 3e^2/8 with e = 1 - r2 y0^2 (r2 is positive
+    // and normal: distinct cells)
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double e0 = __builtin_fma(-r2, y0 * y0, 1.0);
+    const double d0 = __builtin_fma(y0 * e0, __builtin_fma(e0, 0.375, 0.5), y0);
     const double ir2 = d0 * d0;
     const double d1 = -d0 * ir2;
     const double d2 = -3.0 * d1 * ir2;
@@ -526,7 +531,7 @@ __device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, co
 
 template <bool LEAF_TARGET, bool DIP, typename T>
 __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilDev &st, const M2LItem item,
-                         const int *s_nbr, int64_t *cnt_out) {
+                         const int *s_nbr, int64_t *cnt_out, bool count) {
     const int lane = threadIdx.x;
     const int node = item.node, p = item.parity;
     const int s = (p << 6) | lane;
@@ -540,7 +545,9 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
 #pragma unroll
     for (int k = 0; k < 10; ++k) OA[k] = DIP ? 0.0 : ld.mp[(9 + k) * S + ti];
     detrace_o(OA, oA);
-    const bool amc = !DIP && td.amc && mA > 0.0;
+    // the correction is applied to every lane (a uniform branch); targets
+    // without mass drop it at the end
+    const bool amc = !DIP && td.amc;
     const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
     Acc<T> a;
     acc_zero(a);
@@ -571,7 +578,7 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
             detrace_o(O, o7);
             m2l_pair<LEAF_TARGET, DIP, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, q5, o7,
                                           Dp, mB * imA, oA, amc, a);
-            ++cnt;
+            if (count) ++cnt;
         }
     } else {
         const int beg = st.m2l_beg[p], len = st.m2l_beg[p + 1] - beg;
@@ -601,9 +608,10 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
             detrace_o(O, o7);
             m2l_pair<LEAF_TARGET, DIP, T>(zAx - ld.mp[si], zAy - ld.mp[S + si], zAz - ld.mp[2 * S + si], mB, q5, o7,
                                           Dp, mB * imA, oA, amc, a);
-            ++cnt;
+            if (count) ++cnt;
         }
     }
+    if (!(mA > 0.0)) a.C[0] = a.C[1] = a.C[2] = 0.0;
     const double G = td.G;
     if (LEAF_TARGET) {
         const size_t LS = (size_t)(ld.n_rec - ld.n_int) * kCells;
@@ -636,7 +644,7 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
 template <typename T, bool DIP>
 __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                             const M2LItem *__restrict__ items, int n_items, StencilDev st,
-                                            int64_t *__restrict__ cnt) {
+                                            int64_t *__restrict__ cnt, int count) {
     const int it = xcd_item(n_items);
     if (it >= n_items) return;
     const M2LItem item = items[it];
@@ -646,9 +654,9 @@ __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, con
     if (threadIdx.x < 27) s_nbr[threadIdx.x] = ld.nbr[item.node * 27 + threadIdx.x];
     __syncthreads();
     if (item.node < ld.n_int)
-        m2l_item<false, DIP, T>(ld, td, st, item, s_nbr, cnt + it);
+        m2l_item<false, DIP, T>(ld, td, st, item, s_nbr, cnt + it, count != 0);
     else
-        m2l_item<true, DIP, T>(ld, td, st, item, s_nbr, cnt + it);
+        m2l_item<true, DIP, T>(ld, td, st, item, s_nbr, cnt + it, count != 0);
 }
 
 
@@ -663,10 +671,10 @@ __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, con
 // planes, 124 KB; DIP: + the dipole, 10 planes, 155 KB).  Every wavefront (one
 // target parity class) walks the part of its stencil whose sources fall in
 // the staged class.
-template <typename T, bool DIP>
+template <typename T, bool DIP, bool AMC>
 __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                                  const M2LItem *__restrict__ items, int n_items, StencilDev st,
-                                                 int64_t *__restrict__ cnt_out) {
+                                                 int64_t *__restrict__ cnt_out, int count) {
     const int it = xcd_item(n_items);
     if (it >= n_items) return;
     const M2LItem item = items[it];
@@ -695,7 +703,10 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
 #pragma unroll
     for (int k = 0; k < 10; ++k) OA[k] = DIP ? 0.0 : ld.mp[(9 + k) * S + ti];
     detrace_o(OA, oA);
-    const bool amc = !DIP && td.amc && mA > 0.0;
+    // the correction (a compile-time choice) is applied to every lane;
+    // targets without mass drop it at the end
+    constexpr bool amc = AMC && !DIP;
+    const bool counting = count != 0;
     const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
     Acc<T> a;
     acc_zero(a);
@@ -771,12 +782,13 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
                 r[2 * j] = e.x;
                 r[2 * j + 1] = e.y;
             }
-            cnt += signbit(r[0]) ? 0 : 1;  // absent sources carry -0.0
+            if (counting) cnt += signbit(r[0]) ? 0 : 1;  // absent sources carry -0.0
             m2l_pair<false, DIP, T>(zAx - r[1], zAy - r[2], zAz - r[3], r[0], &r[4], &r[9], &r[16 % (2 * NV)],
                                     r[0] * imA, oA, amc, a);
         }
         __syncthreads();
     }
+    if (!(mA > 0.0)) a.C[0] = a.C[1] = a.C[2] = 0.0;
     const double G = td.G;
     finish_l2_l3(a);
     const size_t IS = (size_t)ld.n_int * kCells;
@@ -1325,16 +1337,19 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
         const int grid = ((p.n_m2l + kXcd - 1) / kXcd) * kXcd;
         auto k = mixed ? (src ? k_m2l<float, true> : k_m2l<float, false>)
                        : (src ? k_m2l<double, true> : k_m2l<double, false>);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, sm, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st, p.d_m2l_cnt);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, sm, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st, p.d_m2l_cnt,
+                           o.count ? 1 : 0);
     }
     if (fork) check_hip(hipEventRecord(o.join, o.aux), "join");
     mark(8);
     if (p.n_m2l_nodes) {
         const int grid = ((p.n_m2l_nodes + kXcd - 1) / kXcd) * kXcd;
-        auto k = mixed ? (src ? k_m2l_lds<float, true> : k_m2l_lds<float, false>)
-                       : (src ? k_m2l_lds<double, true> : k_m2l_lds<double, false>);
+        auto k = mixed ? (src ? k_m2l_lds<float, true, false>
+                              : (o.amc ? k_m2l_lds<float, false, true> : k_m2l_lds<float, false, false>))
+                       : (src ? k_m2l_lds<double, true, false>
+                              : (o.amc ? k_m2l_lds<double, false, true> : k_m2l_lds<double, false, false>));
         hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes, p.n_m2l_nodes, st,
-                           p.d_m2l_cnt + p.n_m2l);
+                           p.d_m2l_cnt + p.n_m2l, o.count ? 1 : 0);
     }
     if (fork) check_hip(hipStreamWaitEvent(s, o.join, 0), "join");
     mark(4);

@@ -123,6 +123,7 @@ struct LaunchOpts {
     int precision = OCTO_FP64;
     bool count = true;                   // count evaluated pairs (statistics)
     bool source = false;                 // second-source solve (potential of the density rate)
+    bool amc = true;                     // angular-momentum correction (a kernel variant of the LDS-staged M2L)
     hipEvent_t *phase_events = nullptr;  // 8 events around the 7 phases + 1 before the LDS M2L kernel, or NULL
     hipStream_t aux = nullptr;           // second stream for concurrent multipole work, or NULL
     hipEvent_t fork = nullptr, join = nullptr;
