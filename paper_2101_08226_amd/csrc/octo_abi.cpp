@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -97,32 +98,75 @@ void shape_tree(octo_tree *t, TreeBlock &B) {
         t->m2l_lds[l] = (lds && l >= 1 && t->parts[l] == 1) ? 1 : 0;
     }
     // The LDS-staged levels share one launch: split each node's source parity
-    // classes into g groups (one work-group each, one work-group per CU at a
-    // time).  Time ~ rounds x classes per group (a round stages and walks
-    // one class per work-group) + the downward pass reading g partial slots
-    // per node; on MI355X one slot of one node costs about 0.002 of a
-    // class-round (c2: 23.6 us per class-round, 0.047 us per node-slot).
+    // classes into g_l groups per level (one work-group each, one work-group
+    // per CU at a time).  The items are dealt to the 8 XCDs in equal shares of
+    // every level, larger items first (the order build_tree_plan gives them),
+    // and each XCD's CUs take the next item as they free up; the time is the
+    // simulated makespan in class-rounds (a round stages and walks one class
+    // per work-group) plus the downward pass reading g_l partial slots per
+    // node: on MI355X one slot of one node costs about 0.002 of a class-round
+    // (c2: 23.6 us per class-round, 0.047 us per node-slot).  Levels are
+    // tuned one at a time from a common best g, fewest nodes first.
     {
-        int n_lds = 0, g_max = 8;
+        std::vector<int> lds_levels;
+        int g_max = 8;
         for (int l = 0; l < nl; ++l)
-            if (t->m2l_lds[l]) {
-                n_lds += L.lv[l].n_int;
+            if (t->m2l_lds[l] && L.lv[l].n_int > 0) {
+                lds_levels.push_back(l);
                 g_max = std::min(g_max, t->parts_alloc[l]);
             }
-        if (n_lds > 0) {
-            const int64_t cus = std::max(1, ctx->n_cu);
-            int best = 1;
+        if (!lds_levels.empty()) {
+            const int cus = std::max(8, ctx->n_cu), per_xcd = std::max(1, cus / 8);
+            auto cost = [&](const std::vector<int> &g) {
+                // items of each level: (8 / g) classes, n_int * g of them, 1/8 to each XCD
+                std::vector<std::pair<int, int64_t>> groups;  // (classes per item, items per XCD)
+                double slots = 0.0;
+                for (size_t i = 0; i < lds_levels.size(); ++i) {
+                    const int64_t n = L.lv[lds_levels[i]].n_int;
+                    groups.push_back({8 / g[i], (n * g[i] + 7) / 8});
+                    slots += (double)n * g[i];
+                }
+                std::sort(groups.begin(), groups.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+                std::map<int64_t, int64_t> load{{0, per_xcd}};  // CU load -> number of CUs
+                for (const auto &gr : groups) {
+                    int64_t left = gr.second;
+                    while (left > 0) {
+                        auto it = load.begin();
+                        const int64_t at = it->first, k = std::min(left, it->second);
+                        if ((it->second -= k) == 0) load.erase(it);
+                        load[at + gr.first] += k;
+                        left -= k;
+                    }
+                }
+                return (double)load.rbegin()->first + 0.002 * slots;
+            };
+            std::vector<int> g(lds_levels.size(), 1);
             double best_cost = 1e300;
-            for (int g = 1; g <= g_max; g *= 2) {
-                const double cost =
-                    (double)(((int64_t)n_lds * g + cus - 1) / cus * (8 / g)) + 0.002 * (double)n_lds * g;
-                if (cost < best_cost) {
-                    best_cost = cost;
-                    best = g;
+            for (int gu = 1; gu <= g_max; gu *= 2) {
+                std::vector<int> u(lds_levels.size(), gu);
+                const double c = cost(u);
+                if (c < best_cost) {
+                    best_cost = c;
+                    g = u;
                 }
             }
-            for (int l = 0; l < nl; ++l)
-                if (t->m2l_lds[l]) t->parts[l] = best;
+            std::vector<size_t> order(lds_levels.size());
+            for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+            std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+                return L.lv[lds_levels[a]].n_int < L.lv[lds_levels[b]].n_int;
+            });
+            for (size_t i : order) {
+                for (int gi = 1; gi <= g_max; gi *= 2) {
+                    std::vector<int> trial = g;
+                    trial[i] = gi;
+                    const double c = cost(trial);
+                    if (c < best_cost - 1e-9) {
+                        best_cost = c;
+                        g = trial;
+                    }
+                }
+            }
+            for (size_t i = 0; i < lds_levels.size(); ++i) t->parts[lds_levels[i]] = g[i];
         }
     }
     for (auto *v : {&B.nbr, &B.child, &B.parent, &B.coord, &B.out, &B.mass, &B.mp, &B.loc, &B.lacc, &B.nf, &B.dip})
@@ -265,16 +309,50 @@ void build_tree_plan(octo_tree *t) {
         for (int n = h.n_int; n < h.n_nodes; ++n) ph.p2m.push_back(NodeItem{l, n});
         for (int n = 0; n < h.n_int; ++n) ph.interior[l].push_back(NodeItem{l, n});
         for (int n = 0; n < h.n_int; ++n) {
-            if (t->m2l_lds[l]) {
-                for (int c = 0; c < t->parts[l]; ++c) ph.m2l_nodes.push_back(M2LItem{l, n, 0, c});
-                continue;
-            }
+            if (t->m2l_lds[l]) continue;  // ordered below
             for (int c = 0; c < t->parts[l]; ++c)
                 for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, c});
         }
         for (int n = h.n_int; n < h.n_rec; ++n)
             for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, 0});
         for (int n = h.n_int; n < h.n_nodes; ++n) ph.leaf.push_back(LeafItem{l, n, 0, h.flags[n]});
+    }
+    // LDS-staged items: the kernel gives XCD k the k-th of 8 equal slices of
+    // the list; fill each slice with its share of every level's items (a
+    // contiguous run in node order), levels with larger items first
+    {
+        std::vector<std::vector<M2LItem>> lv_items;
+        for (int l = 0; l < nl; ++l) {
+            if (!t->m2l_lds[l] || L.lv[l].n_int == 0) continue;
+            std::vector<M2LItem> v;
+            for (int n = 0; n < L.lv[l].n_int; ++n)
+                for (int c = 0; c < t->parts[l]; ++c) v.push_back(M2LItem{l, n, 0, c});
+            lv_items.push_back(std::move(v));
+        }
+        std::stable_sort(lv_items.begin(), lv_items.end(), [&](const auto &a, const auto &b) {
+            return t->parts[a[0].ld] < t->parts[b[0].ld];  // fewer groups = more classes per item
+        });
+        size_t total = 0;
+        for (const auto &v : lv_items) total += v.size();
+        const size_t per = (total + 7) / 8;
+        std::vector<std::vector<M2LItem>> slice(8);
+        for (const auto &v : lv_items) {
+            const size_t n = v.size();
+            size_t pos = 0;
+            for (int k = 0; k < 8 && pos < n; ++k) {
+                const size_t want = n / 8 + ((size_t)k < n % 8 ? 1 : 0);
+                const size_t room = per - slice[k].size();
+                const size_t take = std::min({want, room, n - pos});
+                slice[k].insert(slice[k].end(), v.begin() + pos, v.begin() + pos + take);
+                pos += take;
+            }
+            for (int k = 0; k < 8 && pos < n; ++k) {  // what did not fit its share
+                const size_t take = std::min(per - slice[k].size(), n - pos);
+                slice[k].insert(slice[k].end(), v.begin() + pos, v.begin() + pos + take);
+                pos += take;
+            }
+        }
+        for (const auto &sl : slice) ph.m2l_nodes.insert(ph.m2l_nodes.end(), sl.begin(), sl.end());
     }
     ph.tree_leaf_beg = {0, (int32_t)ph.leaf.size()};
     ph.tree_m2l_beg = {0, (int32_t)ph.m2l.size()};
