@@ -1145,7 +1145,7 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
 template <bool SRC>
 __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                              const LeafItem *__restrict__ items, int n_items,
-                                             double *__restrict__ stat) {
+                                             double *__restrict__ stat, int stats) {
     const int it = xcd_item(n_items);
     if (it >= n_items) return;
     const LeafItem item = items[it];
@@ -1174,18 +1174,31 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
         gy += -ld.lacc[2 * LS + li] + ld.lacc[5 * LS + li];
         gz += -ld.lacc[3 * LS + li] + ld.lacc[6 * LS + li];
     }
-    // parent expansion shifted to the cell centre, evaluated there
-    if (ld.parent_ld >= 0) {
+    // parent expansion shifted to the cell centre, evaluated there.  The 64
+    // parent cells over this node (a 4x4x4 block of the parent) are staged in
+    // LDS by the whole work-group, component by component, then each is read
+    // by the 8 cells under it (lane q of every wavefront reads block cell q)
+    __shared__ double s_par[3 + kLoc][64];
+    const bool has_parent = ld.parent_ld >= 0;  // uniform
+    if (has_parent) {
         const LevelDesc pl = L[ld.parent_ld];
         const int pn = ld.parent[node];
-        const int ps = store_idx(4 * (ld.coord[3 * node] & 1) + (x >> 1), 4 * (ld.coord[3 * node + 1] & 1) + (y >> 1),
-                                 4 * (ld.coord[3 * node + 2] & 1) + (z >> 1));
-        const size_t pi = (size_t)pn * kCells + ps;
+        const int ox = 4 * (ld.coord[3 * node] & 1), oy = 4 * (ld.coord[3 * node + 1] & 1),
+                  oz = 4 * (ld.coord[3 * node + 2] & 1);
         const size_t PIS = (size_t)pl.n_int * kCells, PRS = (size_t)pl.n_rec * kCells;
-        const double dx = cx - pl.mp[pi], dy = cy - pl.mp[PRS + pi], dz = cz - pl.mp[2 * PRS + pi];
+        for (int t = tid; t < (3 + kLoc) * 64; t += 512) {
+            const int c = t >> 6, j = t & 63;
+            const size_t pi = (size_t)pn * kCells + store_idx(ox + (j >> 4), oy + ((j >> 2) & 3), oz + (j & 3));
+            s_par[c][j] = c < 3 ? pl.mp[c * PRS + pi] : pl.loc[(c - 3) * PIS + pi];
+        }
+    }
+    __syncthreads();
+    if (has_parent) {
+        const int j = ((x >> 1) << 4) | ((y >> 1) << 2) | (z >> 1);
+        const double dx = cx - s_par[0][j], dy = cy - s_par[1][j], dz = cz - s_par[2][j];
         double P[kLoc];
 #pragma unroll
-        for (int c = 0; c < kLoc; ++c) P[c] = pl.loc[c * PIS + pi];
+        for (int c = 0; c < kLoc; ++c) P[c] = s_par[3 + c][j];
         const double *P2 = P + 4, *P3 = P + 10;
         double Tx, Ty, Tz;
         t3_uu(P3, dx, dy, dz, Tx, Ty, Tz);
@@ -1204,6 +1217,7 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
     td.g[o] = gx;
     td.g[td.n_leaf_cells + o] = gy;
     td.g[2 * td.n_leaf_cells + o] = gz;
+    if (!stats) return;  // uniform
 
     // per-wavefront partial sums for the diagnostics
     const double m = ld.mass[(size_t)node * kCells + s];
@@ -1369,10 +1383,11 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     if (p.n_leaf) {
         const int grid = ((p.n_leaf + kXcd - 1) / kXcd) * kXcd;
         hipLaunchKernelGGL(src ? k_l2p<true> : k_l2p<false>, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees,
-                           p.d_leaf, p.n_leaf, p.d_stat);
+                           p.d_leaf, p.n_leaf, p.d_stat, o.count ? 1 : 0);
     }
     mark(6);
-    if (!src)
+    // the diagnostics only when they are asked for (a solve with statistics)
+    if (!src && o.count)
         hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(1024), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg,
                            p.d_tree_m2ln_beg, p.n_m2l, p.d_stat, p.d_leaf_cnt, p.d_m2l_cnt, p.d_out);
     mark(7);
