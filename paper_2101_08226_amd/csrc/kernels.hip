@@ -852,21 +852,34 @@ __global__ __launch_bounds__(256) void k_l2l(const LevelDesc *__restrict__ L, co
 #pragma unroll
         for (int c = 0; c < kLoc; ++c) v[c] += src[c * IS];
     }
-    if (ld.parent_ld >= 0) {
+    // the 64 parent cells over this node (a 4x4x4 block of the parent) staged
+    // in LDS, component by component; lane q of every wavefront reads block
+    // cell q
+    __shared__ double s_par[3 + kLoc][64];
+    const bool has_parent = ld.parent_ld >= 0;  // uniform
+    if (has_parent) {
         const LevelDesc pl = L[ld.parent_ld];
+        const int pn = ld.parent[node];
+        const int ox = 4 * (ld.coord[3 * node] & 1), oy = 4 * (ld.coord[3 * node + 1] & 1),
+                  oz = 4 * (ld.coord[3 * node + 2] & 1);
+        const size_t PIS = (size_t)pl.n_int * kCells, PRS = (size_t)pl.n_rec * kCells;
+        for (int t = threadIdx.x; t < (3 + kLoc) * 64; t += 256) {
+            const int c = t >> 6, j = t & 63;
+            const size_t pi = (size_t)pn * kCells + store_idx(ox + (j >> 4), oy + ((j >> 2) & 3), oz + (j & 3));
+            s_par[c][j] = c < 3 ? pl.mp[c * PRS + pi] : pl.loc[(c - 3) * PIS + pi];
+        }
+    }
+    __syncthreads();
+    if (has_parent) {
         int x, y, z;
         local_xyz(s, x, y, z);
-        const int pn = ld.parent[node];
-        const int ps = store_idx(4 * (ld.coord[3 * node] & 1) + (x >> 1), 4 * (ld.coord[3 * node + 1] & 1) + (y >> 1),
-                                 4 * (ld.coord[3 * node + 2] & 1) + (z >> 1));
-        const size_t pi = (size_t)pn * kCells + ps;
-        const size_t PIS = (size_t)pl.n_int * kCells, PRS = (size_t)pl.n_rec * kCells;
+        const int j = ((x >> 1) << 4) | ((y >> 1) << 2) | (z >> 1);
         const size_t RS = (size_t)ld.n_rec * kCells;
-        const double dx = ld.mp[ci] - pl.mp[pi], dy = ld.mp[RS + ci] - pl.mp[PRS + pi],
-                     dz = ld.mp[2 * RS + ci] - pl.mp[2 * PRS + pi];
+        const double dx = ld.mp[ci] - s_par[0][j], dy = ld.mp[RS + ci] - s_par[1][j],
+                     dz = ld.mp[2 * RS + ci] - s_par[2][j];
         double P[kLoc];
 #pragma unroll
-        for (int c = 0; c < kLoc; ++c) P[c] = pl.loc[c * PIS + pi];
+        for (int c = 0; c < kLoc; ++c) P[c] = s_par[3 + c][j];
         const double *P2 = P + 4, *P3 = P + 10;
         double Tx, Ty, Tz;  // sum_bc L3_abc d_b d_c
         t3_uu(P3, dx, dy, dz, Tx, Ty, Tz);
