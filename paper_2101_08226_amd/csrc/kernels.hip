@@ -1344,21 +1344,39 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     }
     if (near_fork) check_hip(hipEventRecord(o.join_near, o.aux_near), "join");
     mark(2);
-    for (int l = p.n_levels_max - 1; l >= 0; --l) {
+    // With a second stream, the levels below the shallowest LDS-staged level
+    // (the root and other sparse levels) go there: their upward pass, their
+    // per-wavefront multipole work (with the leaf targets of every level) and
+    // their downward pass depend only on each other and on the deeper
+    // levels' upward pass, so they overlap the LDS-staged kernel.  M2L at a
+    // level reads only that level's multipoles.
+    const bool fork = o.aux && p.n_m2l && p.n_m2l_nodes;
+    const int lsplit = fork ? std::min(p.lds_min_level, p.n_levels_max) : 0;
+    auto upward = [&](int l, hipStream_t q) {
         const int n = p.n_interior[l];
         if (n)
-            hipLaunchKernelGGL(src ? k_m2m_src : k_m2m, dim3(2 * n), dim3(256), 0, s, p.d_levels,
+            hipLaunchKernelGGL(src ? k_m2m_src : k_m2m, dim3(2 * n), dim3(256), 0, q, p.d_levels,
                                p.d_interior + p.interior_off[l], n);
-    }
-    mark(3);
-    // the per-wavefront multipole items (root, sparse levels, leaf targets)
-    // run on the auxiliary stream, concurrently with the LDS-staged kernel
-    const bool fork = o.aux && p.n_m2l && p.n_m2l_nodes;
+    };
+    auto downward = [&](int l, hipStream_t q) {
+        const int n = p.n_interior[l];
+        if (!n) return;
+        // levels with few nodes sum their many partial slots in a separate wide pass
+        const bool wide = p.sum_parts_level.size() > (size_t)l && p.sum_parts_level[l];
+        if (wide)
+            hipLaunchKernelGGL(k_sum_parts, dim3((n * kCells * kLoc + 255) / 256), dim3(256), 0, q, p.d_levels,
+                               p.d_interior + p.interior_off[l], n);
+        hipLaunchKernelGGL(k_l2l, dim3(2 * n), dim3(256), 0, q, p.d_levels, p.d_interior + p.interior_off[l], n,
+                           wide ? 1 : 0);
+    };
+    for (int l = p.n_levels_max - 1; l >= lsplit; --l) upward(l, s);
     hipStream_t sm = fork ? o.aux : s;
     if (fork) {
         check_hip(hipEventRecord(o.fork, s), "fork");
         check_hip(hipStreamWaitEvent(o.aux, o.fork, 0), "fork");
     }
+    for (int l = lsplit - 1; l >= 0; --l) upward(l, sm);
+    mark(3);
     const bool mixed = o.precision == OCTO_MIXED;
     if (p.n_m2l) {
         const int grid = ((p.n_m2l + kXcd - 1) / kXcd) * kXcd;
@@ -1367,6 +1385,7 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
         hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, sm, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st, p.d_m2l_cnt,
                            o.count ? 1 : 0);
     }
+    for (int l = 0; l < lsplit; ++l) downward(l, sm);
     if (fork) check_hip(hipEventRecord(o.join, o.aux), "join");
     mark(8);
     if (p.n_m2l_nodes) {
@@ -1380,17 +1399,7 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     }
     if (fork) check_hip(hipStreamWaitEvent(s, o.join, 0), "join");
     mark(4);
-    for (int l = 0; l < p.n_levels_max; ++l) {
-        const int n = p.n_interior[l];
-        if (!n) continue;
-        // levels with few nodes sum their many partial slots in a separate wide pass
-        const bool wide = p.sum_parts_level.size() > (size_t)l && p.sum_parts_level[l];
-        if (wide)
-            hipLaunchKernelGGL(k_sum_parts, dim3((n * kCells * kLoc + 255) / 256), dim3(256), 0, s, p.d_levels,
-                               p.d_interior + p.interior_off[l], n);
-        hipLaunchKernelGGL(k_l2l, dim3(2 * n), dim3(256), 0, s, p.d_levels, p.d_interior + p.interior_off[l], n,
-                           wide ? 1 : 0);
-    }
+    for (int l = lsplit; l < p.n_levels_max; ++l) downward(l, s);
     mark(5);
     if (near_fork) check_hip(hipStreamWaitEvent(s, o.join_near, 0), "join");
     if (p.n_leaf) {

@@ -97,6 +97,7 @@ struct Plan {
     NodeItem *d_p2m = nullptr;
     M2LItem *d_m2l_nodes = nullptr;
     std::vector<char> sum_parts_level;  // per level index: partial slots summed in a separate wide pass
+    int lds_min_level = 0;  // shallowest level with LDS-staged multipole items (n_levels_max if none)
     NodeItem *d_interior = nullptr;
     int32_t *d_tree_leaf_beg = nullptr, *d_tree_m2l_beg = nullptr, *d_tree_m2ln_beg = nullptr;
     double *d_stat = nullptr;      // n_leaf * kStat (per leaf node)

@@ -489,6 +489,8 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
     p.d_leaf = (LeafItem *)put(ph.leaf.data(), ph.leaf.size() * sizeof(LeafItem));
     p.d_p2m = (NodeItem *)put(ph.p2m.data(), ph.p2m.size() * sizeof(NodeItem));
     p.d_m2l_nodes = (M2LItem *)put(ph.m2l_nodes.data(), ph.m2l_nodes.size() * sizeof(M2LItem));
+    p.lds_min_level = (int)ph.interior.size();
+    for (const M2LItem &q : ph.m2l_nodes) p.lds_min_level = std::min(p.lds_min_level, ph.levels[q.ld].level);
     std::vector<NodeItem> all;
     p.n_interior.clear();
     p.interior_off.clear();
