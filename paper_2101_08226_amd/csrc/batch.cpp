@@ -108,9 +108,14 @@ static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, con
         ph.tree_leaf_beg.push_back((int32_t)ph.leaf.size());
         ph.tree_m2l_beg.push_back((int32_t)ph.m2l.size());
         ph.tree_m2ln_beg.push_back((int32_t)ph.m2l_nodes.size());
+        ph.tree_m2lf_beg.push_back((int32_t)ph.m2l_leaf.size());
         for (M2LItem q : t.m2l_nodes) {
             q.ld += base;
             ph.m2l_nodes.push_back(q);
+        }
+        for (M2LItem q : t.m2l_leaf) {
+            q.ld += base;
+            ph.m2l_leaf.push_back(q);
         }
         for (M2LItem m : t.m2l) {
             m.ld += base;
@@ -133,6 +138,7 @@ static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, con
     ph.tree_leaf_beg.push_back((int32_t)ph.leaf.size());
     ph.tree_m2l_beg.push_back((int32_t)ph.m2l.size());
     ph.tree_m2ln_beg.push_back((int32_t)ph.m2l_nodes.size());
+    ph.tree_m2lf_beg.push_back((int32_t)ph.m2l_leaf.size());
     return bp;
 }
 

@@ -664,14 +664,16 @@ __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, con
 #define OCTO_M2L_UNROLL 2
 #endif
 
-// Multipole-to-local for all 512 cells of one interior node, with the source
-// halo staged in LDS one parity class at a time: the cells of one parity class
+// Multipole-to-local for all 512 cells of one interior node (LEAF: of one
+// leaf node next to interior nodes of its level, whose cells take only L0, L1
+// and the correction from the interior cells), with the source halo staged in
+// LDS one parity class at a time: the cells of one parity class
 // within 5 cells of the node form a 9x9x9 lattice; each staged cell holds its
 // mass, centre of mass and trace-free moments (16 FP64 values in 8 double2
 // planes, 124 KB; DIP: + the dipole, 10 planes, 155 KB).  Every wavefront (one
 // target parity class) walks the part of its stencil whose sources fall in
 // the staged class.
-template <typename T, bool DIP, bool AMC>
+template <typename T, bool DIP, bool AMC, bool LEAF>
 __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                                  const M2LItem *__restrict__ items, int n_items, StencilDev st,
                                                  int64_t *__restrict__ cnt_out, int count) {
@@ -714,8 +716,23 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     __syncthreads();
     // this item's share of the source parity classes; its partial locals go
     // to slot `chunk` and are summed by the downward pass
-    const int q0 = 8 * item.chunk / ld.n_parts, q1 = 8 * (item.chunk + 1) / ld.n_parts;
+    const int q0 = LEAF ? 0 : 8 * item.chunk / ld.n_parts, q1 = LEAF ? 8 : 8 * (item.chunk + 1) / ld.n_parts;
+    // sources: interior nodes and record leaves of this level; a leaf target's only the interior ones
+    const int n_src = LEAF ? ld.n_int : ld.n_rec;
+    // leaf targets: the neighbour sub-grids that hold sources (uniform); source
+    // classes no entry of any target class reaches are skipped, and so are
+    // the entries that reach none of them
+    int src_mask = 0, q_need = 0xff;
+    if (LEAF) {
+        for (int b = 0; b < 27; ++b) src_mask |= (s_nbr[b] >= 0 && s_nbr[b] < n_src) ? (1 << b) : 0;
+        src_mask = __builtin_amdgcn_readfirstlane(src_mask);
+        q_need = 0;
+        for (int q = 0; q < 8; ++q)
+            for (int pp = 0; pp < 8; ++pp)
+                if (st.m2l_src_any[pp * 8 + q] & src_mask) q_need |= 1 << q;
+    }
     for (int q = q0; q < q1; ++q) {
+        if (!((q_need >> q) & 1)) continue;  // uniform over the work-group
         const int qx = q >> 2, qy = (q >> 1) & 1, qz = q & 1;
         // stage source class q: lattice index i in [0,9) <-> local coordinate
         // 2i - 4 - parity; both cells of this thread are loaded before either
@@ -729,7 +746,7 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
             const int ix = cc / 81, iy = (cc / 9) % 9, iz = cc % 9;
             const int sx = 2 * ix - 4 - qx, sy = 2 * iy - 4 - qy, sz = 2 * iz - 4 - qz;
             const int nb = cc < 729 ? s_nbr[nbr_slot(sx, sy, sz)] : -1;
-            if (nb >= 0 && nb < ld.n_rec) {
+            if (nb >= 0 && nb < n_src) {
                 const size_t si = (size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7);
                 v[u][0] = ld.mass[si];
 #pragma unroll
@@ -774,6 +791,7 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
         // waves per SIMD)
 #pragma unroll OCTO_M2L_UNROLL
         for (int k = beg; k < end; ++k) {
+            if (LEAF && !(st.m2l_src_touch[k] & src_mask)) continue;  // uniform
             const int h = hb + st.m2l_src[k];  // the offset is uniform over the wavefront
             double r[2 * NV];
 #pragma unroll
@@ -783,25 +801,35 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
                 r[2 * j + 1] = e.y;
             }
             if (counting) cnt += signbit(r[0]) ? 0 : 1;  // absent sources carry -0.0
-            m2l_pair<false, DIP, T>(zAx - r[1], zAy - r[2], zAz - r[3], r[0], &r[4], &r[9], &r[16 % (2 * NV)],
-                                    r[0] * imA, oA, amc, a);
+            m2l_pair<LEAF, DIP, T>(zAx - r[1], zAy - r[2], zAz - r[3], r[0], &r[4], &r[9], &r[16 % (2 * NV)],
+                                   r[0] * imA, oA, amc, a);
         }
         __syncthreads();
     }
     if (!(mA > 0.0)) a.C[0] = a.C[1] = a.C[2] = 0.0;
     const double G = td.G;
-    finish_l2_l3(a);
-    const size_t IS = (size_t)ld.n_int * kCells;
-    double *out = ld.loc + (size_t)item.chunk * kLoc * IS + (size_t)node * kCells + s;
-    out[0] = G * (double)a.L0;
+    if (LEAF) {
+        const size_t LS = (size_t)(ld.n_rec - ld.n_int) * kCells;
+        const size_t li = (size_t)(node - ld.n_int) * kCells + s;
+        ld.lacc[li] = G * (double)a.L0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) out[(1 + k) * IS] = G * (double)a.L1[k];
+        for (int k = 0; k < 3; ++k) ld.lacc[(1 + k) * LS + li] = G * (double)a.L1[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) out[(4 + k) * IS] = G * (double)a.L2[k];
+        for (int k = 0; k < 3; ++k) ld.lacc[(4 + k) * LS + li] = G * a.C[k];
+    } else {
+        finish_l2_l3(a);
+        const size_t IS = (size_t)ld.n_int * kCells;
+        double *out = ld.loc + (size_t)item.chunk * kLoc * IS + (size_t)node * kCells + s;
+        out[0] = G * (double)a.L0;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) out[(10 + k) * IS] = G * (double)a.L3[k];
+        for (int k = 0; k < 3; ++k) out[(1 + k) * IS] = G * (double)a.L1[k];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) out[(20 + k) * IS] = G * a.C[k];
+        for (int k = 0; k < 6; ++k) out[(4 + k) * IS] = G * (double)a.L2[k];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) out[(10 + k) * IS] = G * (double)a.L3[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[(20 + k) * IS] = G * a.C[k];
+    }
     const int tot = wave_sum(cnt);
     if (lane == 0) s_cnt[p] = tot;
     __syncthreads();
@@ -1258,7 +1286,8 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
 // thread a fixed strided subset, then a fixed-shape tree in LDS).
 __global__ __launch_bounds__(1024) void k_stats(const int32_t *__restrict__ leaf_beg,
                                                 const int32_t *__restrict__ m2l_beg,
-                                                const int32_t *__restrict__ m2ln_beg, int n_m2l,
+                                                const int32_t *__restrict__ m2ln_beg,
+                                                const int32_t *__restrict__ m2lf_beg, int n_m2l, int n_m2ln,
                                                 const double *__restrict__ stat, const int64_t *__restrict__ leaf_cnt,
                                                 const int64_t *__restrict__ m2l_cnt, double *__restrict__ out) {
     const int t = blockIdx.x;
@@ -1276,6 +1305,7 @@ __global__ __launch_bounds__(1024) void k_stats(const int32_t *__restrict__ leaf
     }
     for (int i = m2l_beg[t] + threadIdx.x; i < m2l_beg[t + 1]; i += NT) c_m2l += m2l_cnt[i];
     for (int i = m2ln_beg[t] + threadIdx.x; i < m2ln_beg[t + 1]; i += NT) c_lds += m2l_cnt[n_m2l + i];
+    for (int i = m2lf_beg[t] + threadIdx.x; i < m2lf_beg[t + 1]; i += NT) c_m2l += m2l_cnt[n_m2l + n_m2ln + i];
 #pragma unroll
     for (int k = 0; k < kStat; ++k) acc[k] = wave_sum(acc[k]);
     c_m2l = wave_sum(c_m2l);
@@ -1350,7 +1380,7 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     // their downward pass depend only on each other and on the deeper
     // levels' upward pass, so they overlap the LDS-staged kernel.  M2L at a
     // level reads only that level's multipoles.
-    const bool fork = o.aux && p.n_m2l && p.n_m2l_nodes;
+    const bool fork = o.aux && (p.n_m2l || p.n_m2l_leaf) && p.n_m2l_nodes;
     const int lsplit = fork ? std::min(p.lds_min_level, p.n_levels_max) : 0;
     auto upward = [&](int l, hipStream_t q) {
         const int n = p.n_interior[l];
@@ -1385,15 +1415,24 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
         hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, sm, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st, p.d_m2l_cnt,
                            o.count ? 1 : 0);
     }
+    if (p.n_m2l_leaf) {
+        const int grid = ((p.n_m2l_leaf + kXcd - 1) / kXcd) * kXcd;
+        auto k = mixed ? (src ? k_m2l_lds<float, true, false, true>
+                              : (o.amc ? k_m2l_lds<float, false, true, true> : k_m2l_lds<float, false, false, true>))
+                       : (src ? k_m2l_lds<double, true, false, true>
+                              : (o.amc ? k_m2l_lds<double, false, true, true> : k_m2l_lds<double, false, false, true>));
+        hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, sm, p.d_levels, p.d_trees, p.d_m2l_leaf, p.n_m2l_leaf, st,
+                           p.d_m2l_cnt + p.n_m2l + p.n_m2l_nodes, o.count ? 1 : 0);
+    }
     for (int l = 0; l < lsplit; ++l) downward(l, sm);
     if (fork) check_hip(hipEventRecord(o.join, o.aux), "join");
     mark(8);
     if (p.n_m2l_nodes) {
         const int grid = ((p.n_m2l_nodes + kXcd - 1) / kXcd) * kXcd;
-        auto k = mixed ? (src ? k_m2l_lds<float, true, false>
-                              : (o.amc ? k_m2l_lds<float, false, true> : k_m2l_lds<float, false, false>))
-                       : (src ? k_m2l_lds<double, true, false>
-                              : (o.amc ? k_m2l_lds<double, false, true> : k_m2l_lds<double, false, false>));
+        auto k = mixed ? (src ? k_m2l_lds<float, true, false, false>
+                              : (o.amc ? k_m2l_lds<float, false, true, false> : k_m2l_lds<float, false, false, false>))
+                       : (src ? k_m2l_lds<double, true, false, false>
+                              : (o.amc ? k_m2l_lds<double, false, true, false> : k_m2l_lds<double, false, false, false>));
         hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes, p.n_m2l_nodes, st,
                            p.d_m2l_cnt + p.n_m2l, o.count ? 1 : 0);
     }
@@ -1411,7 +1450,8 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     // the diagnostics only when they are asked for (a solve with statistics)
     if (!src && o.count)
         hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(1024), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg,
-                           p.d_tree_m2ln_beg, p.n_m2l, p.d_stat, p.d_leaf_cnt, p.d_m2l_cnt, p.d_out);
+                           p.d_tree_m2ln_beg, p.d_tree_m2lf_beg, p.n_m2l, p.n_m2l_nodes, p.d_stat, p.d_leaf_cnt,
+                           p.d_m2l_cnt, p.d_out);
     mark(7);
     check_hip(hipGetLastError(), "kernel launch");
 }

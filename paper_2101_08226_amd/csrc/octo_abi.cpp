@@ -90,6 +90,7 @@ void shape_tree(octo_tree *t, TreeBlock &B) {
     t->m2l_lds.assign(nl, 0);
     const char *mode = getenv("OCTO_M2L");
     const bool lds = !(mode && std::string(mode) == "global");
+    t->leaf_lds = lds;
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
         t->parts_alloc[l] = std::max(n_parts_for(h.n_int, 1024), l >= 1 ? 4 : 1);
@@ -300,6 +301,7 @@ void build_tree_plan(octo_tree *t) {
     PlanHost &ph = t->ph;
     ph.m2l.clear();
     ph.m2l_nodes.clear();
+    ph.m2l_leaf.clear();
     ph.leaf.clear();
     ph.p2m.clear();
     ph.interior.assign(nl, {});
@@ -313,8 +315,14 @@ void build_tree_plan(octo_tree *t) {
             for (int c = 0; c < t->parts[l]; ++c)
                 for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, c});
         }
-        for (int n = h.n_int; n < h.n_rec; ++n)
+        // leaf targets next to interior nodes: staged in LDS (below the root)
+        for (int n = h.n_int; n < h.n_rec; ++n) {
+            if (l >= 1 && t->leaf_lds) {
+                ph.m2l_leaf.push_back(M2LItem{l, n, 0, 0});
+                continue;
+            }
             for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, 0});
+        }
         for (int n = h.n_int; n < h.n_nodes; ++n) ph.leaf.push_back(LeafItem{l, n, 0, h.flags[n]});
     }
     // LDS-staged items: the kernel gives XCD k the k-th of 8 equal slices of
@@ -357,6 +365,7 @@ void build_tree_plan(octo_tree *t) {
     ph.tree_leaf_beg = {0, (int32_t)ph.leaf.size()};
     ph.tree_m2l_beg = {0, (int32_t)ph.m2l.size()};
     ph.tree_m2ln_beg = {0, (int32_t)ph.m2l_nodes.size()};
+    ph.tree_m2lf_beg = {0, (int32_t)ph.m2l_leaf.size()};
     const size_t bytes = plan_bytes(ph);
     void *mem = ctx->dev_alloc(bytes);
     const TreeDesc keep = t->plan.trees_host.empty() ? ph.trees[0] : t->plan.trees_host[0];
@@ -453,7 +462,8 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     std::vector<float> w32(S.leaf_tab.begin(), S.leaf_tab.end());
     size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_tab.size() * 8) +
                al(w32.size() * 4) + al(S.m2l_src.size() * 4) + al(S.leaf_off.size() * 4) +
-               al(S.leaf_widx.size() * 4) + al(S.m2l_touch.size() * 4) + al(S.near_touch.size() * 4);
+               al(S.leaf_widx.size() * 4) + al(S.m2l_touch.size() * 4) + al(S.near_touch.size() * 4) +
+               al(S.m2l_src_touch.size() * 4);
     void *mem = nullptr;
     check_hip(hipMalloc(&mem, b), "stencil alloc");
     h->block.ptr = mem;
@@ -476,6 +486,8 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     h->dev.m2l_src = (const int32_t *)put(S.m2l_src.data(), S.m2l_src.size() * 4);
     h->dev.leaf_off = (const int32_t *)put(S.leaf_off.data(), S.leaf_off.size() * 4);
     h->dev.leaf_widx = (const int32_t *)put(S.leaf_widx.data(), S.leaf_widx.size() * 4);
+    h->dev.m2l_src_touch = (const int32_t *)put(S.m2l_src_touch.data(), S.m2l_src_touch.size() * 4);
+    for (int k = 0; k < 64; ++k) h->dev.m2l_src_any[k] = S.m2l_src_any[k];
     for (int k = 0; k < 73; ++k) h->dev.leaf_oct_beg[k] = S.leaf_oct_beg[k];
     for (int k = 0; k < 73; ++k) h->dev.m2l_src_beg[k] = S.m2l_src_beg[k];
     for (int p = 0; p < 9; ++p) {

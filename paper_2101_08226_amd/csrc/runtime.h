@@ -55,11 +55,12 @@ std::vector<octo_leaf> adaptive_leaves(octo_boxmax_fn boxmax, void *user, int ma
 
 struct Stencil {
     double theta = 0;
-    std::vector<int32_t> m2l, nearo, leaf, m2l_src, leaf_off, leaf_widx, m2l_touch, near_touch;
+    std::vector<int32_t> m2l, nearo, leaf, m2l_src, leaf_off, leaf_widx, m2l_touch, near_touch, m2l_src_touch;
     std::vector<double> leaf_tab;
     int m2l_beg[9], near_beg[9], leaf_beg[9];
     int leaf_oct_beg[73];
     int m2l_src_beg[73];
+    int m2l_src_any[64];  // per (target class, source class): the union of its entries' touch masks
 };
 
 Stencil make_stencil(double theta);
@@ -75,9 +76,10 @@ struct PlanHost {
     std::vector<LeafItem> leaf;
     std::vector<NodeItem> p2m;
     std::vector<M2LItem> m2l_nodes;  // (node, source-class group) items of the LDS-staged kernel
+    std::vector<M2LItem> m2l_leaf;   // record leaves (leaf targets next to interior nodes), LDS-staged
     // interior nodes by level index (level l of every tree)
     std::vector<std::vector<NodeItem>> interior;
-    std::vector<int32_t> tree_leaf_beg, tree_m2l_beg, tree_m2ln_beg;  // per tree, +1 sentinel
+    std::vector<int32_t> tree_leaf_beg, tree_m2l_beg, tree_m2ln_beg, tree_m2lf_beg;  // per tree, +1 sentinel
 };
 
 struct DeviceBlock {
@@ -87,7 +89,7 @@ struct DeviceBlock {
 
 struct Plan {
     int n_trees = 0, n_levels_max = 0;
-    int n_m2l = 0, n_leaf = 0, n_p2m = 0, n_m2l_nodes = 0;
+    int n_m2l = 0, n_leaf = 0, n_p2m = 0, n_m2l_nodes = 0, n_m2l_leaf = 0;
     std::vector<int> n_interior;        // per level index
     std::vector<size_t> interior_off;   // element offset into d_interior per level index
     LevelDesc *d_levels = nullptr;
@@ -96,10 +98,12 @@ struct Plan {
     LeafItem *d_leaf = nullptr;
     NodeItem *d_p2m = nullptr;
     M2LItem *d_m2l_nodes = nullptr;
+    M2LItem *d_m2l_leaf = nullptr;
     std::vector<char> sum_parts_level;  // per level index: partial slots summed in a separate wide pass
     int lds_min_level = 0;  // shallowest level with LDS-staged multipole items (n_levels_max if none)
     NodeItem *d_interior = nullptr;
-    int32_t *d_tree_leaf_beg = nullptr, *d_tree_m2l_beg = nullptr, *d_tree_m2ln_beg = nullptr;
+    int32_t *d_tree_leaf_beg = nullptr, *d_tree_m2l_beg = nullptr, *d_tree_m2ln_beg = nullptr,
+            *d_tree_m2lf_beg = nullptr;
     double *d_stat = nullptr;      // n_leaf * kStat (per leaf node)
     int64_t *d_leaf_cnt = nullptr;  // n_leaf
     int64_t *d_m2l_cnt = nullptr;   // n_m2l + n_m2l_nodes
@@ -240,6 +244,7 @@ struct octo_tree {
     octo::DeviceBlock data;        // tables + fields
     octo::DeviceBlock plan_block;  // work plan
     std::vector<int> parts_alloc, parts, m2l_lds;  // per level: multipole work choices
+    bool leaf_lds = true;  // leaf targets of multipole work in the LDS-staged kernel
     double *rho = nullptr;
     double *stage = nullptr;  // device staging of phi, g for host outputs
     hipEvent_t last_use = nullptr;  // recorded after the last work enqueued on the tree's memory

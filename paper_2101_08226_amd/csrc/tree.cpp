@@ -431,11 +431,15 @@ Stencil make_stencil(double theta) {
         int px = p >> 2, py = (p >> 1) & 1, pz = p & 1;
         for (int q = 0; q < 8; ++q) {
             s.m2l_src_beg[p * 9 + q] = (int)s.m2l_src.size();
+            s.m2l_src_any[p * 8 + q] = 0;
             for (auto &d : m2l[p]) {
                 int qq = (((px + d[0]) & 1) << 2) | (((py + d[1]) & 1) << 1) | ((pz + d[2]) & 1);
-                if (qq == q)
+                if (qq == q) {
                     s.m2l_src.push_back(((px + d[0] + 5) >> 1) * kHaloX + ((py + d[1] + 5) >> 1) * kHaloY +
                                         ((pz + d[2] + 5) >> 1));
+                    s.m2l_src_touch.push_back(touch(p, d));
+                    s.m2l_src_any[p * 8 + q] |= s.m2l_src_touch.back();
+                }
             }
         }
         s.m2l_src_beg[p * 9 + 8] = (int)s.m2l_src.size();
@@ -482,6 +486,7 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
     p.n_leaf = (int)ph.leaf.size();
     p.n_p2m = (int)ph.p2m.size();
     p.n_m2l_nodes = (int)ph.m2l_nodes.size();
+    p.n_m2l_leaf = (int)ph.m2l_leaf.size();
     p.n_levels_max = (int)ph.interior.size();
     p.d_levels = (LevelDesc *)put(ph.levels.data(), ph.levels.size() * sizeof(LevelDesc));
     p.d_trees = (TreeDesc *)put(ph.trees.data(), ph.trees.size() * sizeof(TreeDesc));
@@ -489,6 +494,7 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
     p.d_leaf = (LeafItem *)put(ph.leaf.data(), ph.leaf.size() * sizeof(LeafItem));
     p.d_p2m = (NodeItem *)put(ph.p2m.data(), ph.p2m.size() * sizeof(NodeItem));
     p.d_m2l_nodes = (M2LItem *)put(ph.m2l_nodes.data(), ph.m2l_nodes.size() * sizeof(M2LItem));
+    p.d_m2l_leaf = (M2LItem *)put(ph.m2l_leaf.data(), ph.m2l_leaf.size() * sizeof(M2LItem));
     p.lds_min_level = (int)ph.interior.size();
     for (const M2LItem &q : ph.m2l_nodes) p.lds_min_level = std::min(p.lds_min_level, ph.levels[q.ld].level);
     std::vector<NodeItem> all;
@@ -510,9 +516,11 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
     p.d_tree_leaf_beg = (int32_t *)put(ph.tree_leaf_beg.data(), ph.tree_leaf_beg.size() * sizeof(int32_t));
     p.d_tree_m2l_beg = (int32_t *)put(ph.tree_m2l_beg.data(), ph.tree_m2l_beg.size() * sizeof(int32_t));
     p.d_tree_m2ln_beg = (int32_t *)put(ph.tree_m2ln_beg.data(), ph.tree_m2ln_beg.size() * sizeof(int32_t));
+    p.d_tree_m2lf_beg = (int32_t *)put(ph.tree_m2lf_beg.data(), ph.tree_m2lf_beg.size() * sizeof(int32_t));
     p.d_stat = (double *)reserve(ph.leaf.size() * kStat * sizeof(double));
     p.d_leaf_cnt = (int64_t *)reserve(ph.leaf.size() * sizeof(int64_t));
-    p.d_m2l_cnt = (int64_t *)reserve((ph.m2l.size() + ph.m2l_nodes.size()) * sizeof(int64_t));
+    // per-item pair counts: per-wavefront items, LDS-staged nodes, LDS-staged leaf targets
+    p.d_m2l_cnt = (int64_t *)reserve((ph.m2l.size() + ph.m2l_nodes.size() + ph.m2l_leaf.size()) * sizeof(int64_t));
     p.d_out = (double *)reserve(ph.trees.size() * 12 * sizeof(double));
     p.trees_host = ph.trees;
     return off;
