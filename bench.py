@@ -112,7 +112,7 @@ def roofline_m2l(pairs, kernel_ms, prec, traffic=None):
     t = "double" if prec == "fp64" else "float"
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
-            "kernel": f"k_m2l_lds<{t}, false, true>", "kernel_ms": round(kernel_ms, 4), "pairs_per_launch": int(pairs),
+            "kernel": f"k_m2l_lds<{t}, false, true, false>", "kernel_ms": round(kernel_ms, 4), "pairs_per_launch": int(pairs),
             "flops_per_pair": M2L_FLOPS_PER_PAIR}
 
 
