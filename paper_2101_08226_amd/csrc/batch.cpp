@@ -95,6 +95,7 @@ static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, con
     size_t max_lv = 0;
     for (int i = 0; i < n; ++i) max_lv = std::max(max_lv, trees[i]->ph.interior.size());
     ph.interior.resize(max_lv);
+    ph.l2l.resize(max_lv);
     for (int i = 0; i < n; ++i) {
         const PlanHost &t = trees[i]->ph;
         const int base = (int)ph.levels.size();
@@ -129,11 +130,16 @@ static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, con
             q.ld += base;
             ph.p2m.push_back(q);
         }
-        for (size_t l = 0; l < t.interior.size(); ++l)
+        for (size_t l = 0; l < t.interior.size(); ++l) {
             for (NodeItem q : t.interior[l]) {
                 q.ld += base;
                 ph.interior[l].push_back(q);
             }
+            for (NodeItem q : t.l2l[l]) {
+                q.ld += base;
+                ph.l2l[l].push_back(q);
+            }
+        }
     }
     ph.tree_leaf_beg.push_back((int32_t)ph.leaf.size());
     ph.tree_m2l_beg.push_back((int32_t)ph.m2l.size());

@@ -859,9 +859,34 @@ __global__ __launch_bounds__(256) void k_sum_parts(const LevelDesc *__restrict__
 }
 
 // ------------------------------------------------------------------ L2L
-// Interior cells: sum the partial locals, then add the parent's expansion
-// shifted to this cell's centre of mass (Taylor shift of the order-3 local
-// polynomial; the correction C is a uniform acceleration and is inherited).
+// v += the parent expansion P (kLoc values) shifted by d = (dx, dy, dz):
+// Taylor shift of the order-3 local polynomial; the correction C is a
+// uniform acceleration and is inherited.
+__device__ inline void l2l_shift(const double *P, double dx, double dy, double dz, double *v) {
+    const double *P2 = P + 4, *P3 = P + 10;
+    double Tx, Ty, Tz;  // sum_bc L3_abc d_b d_c
+    t3_uu(P3, dx, dy, dz, Tx, Ty, Tz);
+    const double L2dx = P2[0] * dx + P2[1] * dy + P2[2] * dz;
+    const double L2dy = P2[1] * dx + P2[3] * dy + P2[4] * dz;
+    const double L2dz = P2[2] * dx + P2[4] * dy + P2[5] * dz;
+    v[0] += P[0] + P[1] * dx + P[2] * dy + P[3] * dz + 0.5 * (L2dx * dx + L2dy * dy + L2dz * dz) +
+            (Tx * dx + Ty * dy + Tz * dz) * (1.0 / 6.0);
+    v[1] += P[1] + L2dx + 0.5 * Tx;
+    v[2] += P[2] + L2dy + 0.5 * Ty;
+    v[3] += P[3] + L2dz + 0.5 * Tz;
+    // L2_ab += sum_c L3_abc d_c
+    v[4] += P2[0] + P3[0] * dx + P3[1] * dy + P3[2] * dz;  // xx
+    v[5] += P2[1] + P3[1] * dx + P3[3] * dy + P3[4] * dz;  // xy
+    v[6] += P2[2] + P3[2] * dx + P3[4] * dy + P3[5] * dz;  // xz
+    v[7] += P2[3] + P3[3] * dx + P3[6] * dy + P3[7] * dz;  // yy
+    v[8] += P2[4] + P3[4] * dx + P3[7] * dy + P3[8] * dz;  // yz
+    v[9] += P2[5] + P3[5] * dx + P3[8] * dy + P3[9] * dz;  // zz
+#pragma unroll
+    for (int c = 10; c < kLoc; ++c) v[c] += P[c];
+}
+
+// Interior cells with an interior child: sum the partial locals, then add the
+// parent's expansion shifted to this cell's centre of mass.
 __global__ __launch_bounds__(256) void k_l2l(const LevelDesc *__restrict__ L, const NodeItem *__restrict__ items,
                                              int n_items, int parts_done) {
     const int it = blockIdx.x >> 1;
@@ -908,26 +933,7 @@ __global__ __launch_bounds__(256) void k_l2l(const LevelDesc *__restrict__ L, co
         double P[kLoc];
 #pragma unroll
         for (int c = 0; c < kLoc; ++c) P[c] = s_par[3 + c][j];
-        const double *P2 = P + 4, *P3 = P + 10;
-        double Tx, Ty, Tz;  // sum_bc L3_abc d_b d_c
-        t3_uu(P3, dx, dy, dz, Tx, Ty, Tz);
-        const double L2dx = P2[0] * dx + P2[1] * dy + P2[2] * dz;
-        const double L2dy = P2[1] * dx + P2[3] * dy + P2[4] * dz;
-        const double L2dz = P2[2] * dx + P2[4] * dy + P2[5] * dz;
-        v[0] += P[0] + P[1] * dx + P[2] * dy + P[3] * dz + 0.5 * (L2dx * dx + L2dy * dy + L2dz * dz) +
-                (Tx * dx + Ty * dy + Tz * dz) * (1.0 / 6.0);
-        v[1] += P[1] + L2dx + 0.5 * Tx;
-        v[2] += P[2] + L2dy + 0.5 * Ty;
-        v[3] += P[3] + L2dz + 0.5 * Tz;
-        // L2_ab += sum_c L3_abc d_c
-        v[4] += P2[0] + P3[0] * dx + P3[1] * dy + P3[2] * dz;  // xx
-        v[5] += P2[1] + P3[1] * dx + P3[3] * dy + P3[4] * dz;  // xy
-        v[6] += P2[2] + P3[2] * dx + P3[4] * dy + P3[5] * dz;  // xz
-        v[7] += P2[3] + P3[3] * dx + P3[6] * dy + P3[7] * dz;  // yy
-        v[8] += P2[4] + P3[4] * dx + P3[7] * dy + P3[8] * dz;  // yz
-        v[9] += P2[5] + P3[5] * dx + P3[8] * dy + P3[9] * dz;  // zz
-#pragma unroll
-        for (int c = 10; c < kLoc; ++c) v[c] += P[c];
+        l2l_shift(P, dx, dy, dz, v);
     }
 #pragma unroll
     for (int c = 0; c < kLoc; ++c) ld.loc[c * IS + ci] = v[c];
@@ -1227,10 +1233,52 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
         const int ox = 4 * (ld.coord[3 * node] & 1), oy = 4 * (ld.coord[3 * node + 1] & 1),
                   oz = 4 * (ld.coord[3 * node + 2] & 1);
         const size_t PIS = (size_t)pl.n_int * kCells, PRS = (size_t)pl.n_rec * kCells;
+        // a deferred parent: the sum of its partial slots (in slot order), then
+        // the grandparent's finished expansions over the block (2x2x2 cells)
+        // shifted in.  The grandparent values are loaded first, by threads
+        // that stage only three parent values, so that both loads overlap
+        const int parts = (item.flags & kLeafDefer) ? pl.n_parts : 1;
+        const bool gp_stage = (item.flags & kLeafDefer) && pl.parent_ld >= 0;  // uniform
+        constexpr int kGpFirst = 512 - (3 + kLoc) * 8;
+        __shared__ double s_gp[3 + kLoc][8];
+        double gpv = 0.0;
+        if (gp_stage && tid >= kGpFirst) {
+            const LevelDesc gl = L[pl.parent_ld];
+            const int gn = pl.parent[pn];
+            const int gx = 4 * (pl.coord[3 * pn] & 1) + (ox >> 1), gy = 4 * (pl.coord[3 * pn + 1] & 1) + (oy >> 1),
+                      gz = 4 * (pl.coord[3 * pn + 2] & 1) + (oz >> 1);
+            const int c = (tid - kGpFirst) >> 3, k = (tid - kGpFirst) & 7;
+            const size_t gi = (size_t)gn * kCells + store_idx(gx + (k >> 2), gy + ((k >> 1) & 1), gz + (k & 1));
+            gpv = c < 3 ? gl.mp[c * (size_t)gl.n_rec * kCells + gi] : gl.loc[(c - 3) * (size_t)gl.n_int * kCells + gi];
+        }
         for (int t = tid; t < (3 + kLoc) * 64; t += 512) {
             const int c = t >> 6, j = t & 63;
             const size_t pi = (size_t)pn * kCells + store_idx(ox + (j >> 4), oy + ((j >> 2) & 3), oz + (j & 3));
-            s_par[c][j] = c < 3 ? pl.mp[c * PRS + pi] : pl.loc[(c - 3) * PIS + pi];
+            double v;
+            if (c < 3) {
+                v = pl.mp[c * PRS + pi];
+            } else {
+                v = pl.loc[(c - 3) * PIS + pi];
+                for (int part = 1; part < parts; ++part) v += pl.loc[((size_t)part * kLoc + c - 3) * PIS + pi];
+            }
+            s_par[c][j] = v;
+        }
+        if (gp_stage) {
+            // the L2L shift of the 64 block cells, by one wavefront
+            if (tid >= kGpFirst) s_gp[(tid - kGpFirst) >> 3][(tid - kGpFirst) & 7] = gpv;
+            __syncthreads();
+            if (tid < 64) {
+                const int j = tid, k = ((j >> 5) << 2) | (((j >> 3) & 1) << 1) | ((j >> 1) & 1);
+                double P[kLoc], v[kLoc];
+#pragma unroll
+                for (int c = 0; c < kLoc; ++c) {
+                    P[c] = s_gp[3 + c][k];
+                    v[c] = s_par[3 + c][j];
+                }
+                l2l_shift(P, s_par[0][j] - s_gp[0][k], s_par[1][j] - s_gp[1][k], s_par[2][j] - s_gp[2][k], v);
+#pragma unroll
+                for (int c = 0; c < kLoc; ++c) s_par[3 + c][j] = v[c];
+            }
         }
     }
     __syncthreads();
@@ -1388,16 +1436,17 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
             hipLaunchKernelGGL(src ? k_m2m_src : k_m2m, dim3(2 * n), dim3(256), 0, q, p.d_levels,
                                p.d_interior + p.interior_off[l], n);
     };
+    // the L2L pass covers the interior nodes with an interior child; the
+    // others are finished by their leaves in k_l2p
     auto downward = [&](int l, hipStream_t q) {
-        const int n = p.n_interior[l];
+        const int n = p.n_l2l[l];
         if (!n) return;
         // levels with few nodes sum their many partial slots in a separate wide pass
         const bool wide = p.sum_parts_level.size() > (size_t)l && p.sum_parts_level[l];
         if (wide)
             hipLaunchKernelGGL(k_sum_parts, dim3((n * kCells * kLoc + 255) / 256), dim3(256), 0, q, p.d_levels,
-                               p.d_interior + p.interior_off[l], n);
-        hipLaunchKernelGGL(k_l2l, dim3(2 * n), dim3(256), 0, q, p.d_levels, p.d_interior + p.interior_off[l], n,
-                           wide ? 1 : 0);
+                               p.d_l2l + p.l2l_off[l], n);
+        hipLaunchKernelGGL(k_l2l, dim3(2 * n), dim3(256), 0, q, p.d_levels, p.d_l2l + p.l2l_off[l], n, wide ? 1 : 0);
     };
     for (int l = p.n_levels_max - 1; l >= lsplit; --l) upward(l, s);
     hipStream_t sm = fork ? o.aux : s;

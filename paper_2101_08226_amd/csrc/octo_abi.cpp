@@ -305,11 +305,24 @@ void build_tree_plan(octo_tree *t) {
     ph.leaf.clear();
     ph.p2m.clear();
     ph.interior.assign(nl, {});
+    ph.l2l.assign(nl, {});
+    // interior nodes without an interior child: their leaves finish their expansions
+    std::vector<std::vector<char>> defer(nl);
+    for (int l = 0; l < nl; ++l) {
+        const HostLevel &h = L.lv[l];
+        defer[l].assign(h.n_int, 1);
+        for (int n = 0; n < h.n_int; ++n)
+            for (int k = 0; k < 8; ++k)
+                if (h.child[8 * n + k] < L.lv[l + 1].n_int) defer[l][n] = 0;
+    }
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
         ph.levels[l].n_parts = t->parts[l];
         for (int n = h.n_int; n < h.n_nodes; ++n) ph.p2m.push_back(NodeItem{l, n});
-        for (int n = 0; n < h.n_int; ++n) ph.interior[l].push_back(NodeItem{l, n});
+        for (int n = 0; n < h.n_int; ++n) {
+            ph.interior[l].push_back(NodeItem{l, n});
+            if (!defer[l][n]) ph.l2l[l].push_back(NodeItem{l, n});
+        }
         for (int n = 0; n < h.n_int; ++n) {
             if (t->m2l_lds[l]) continue;  // ordered below
             for (int c = 0; c < t->parts[l]; ++c)
@@ -323,7 +336,11 @@ void build_tree_plan(octo_tree *t) {
             }
             for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, 0});
         }
-        for (int n = h.n_int; n < h.n_nodes; ++n) ph.leaf.push_back(LeafItem{l, n, 0, h.flags[n]});
+        for (int n = h.n_int; n < h.n_nodes; ++n) {
+            const int pn = l > 0 ? h.parent[n] : -1;
+            const int32_t f = h.flags[n] | (pn >= 0 && defer[l - 1][pn] ? kLeafDefer : 0);
+            ph.leaf.push_back(LeafItem{l, n, 0, f});
+        }
     }
     // LDS-staged items: the kernel gives XCD k the k-th of 8 equal slices of
     // the list; fill each slice with its share of every level's items (a

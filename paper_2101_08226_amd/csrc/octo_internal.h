@@ -89,7 +89,11 @@ struct M2LItem {
     int32_t ld, node, parity, chunk;
 };
 
-enum : int32_t { kLeafX1 = 1, kLeafX2 = 2, kLeafLacc = 4 };
+// kLeafDefer: the leaf's parent has no interior child, so no L2L pass
+// finishes the parent's expansion: the leaf kernel sums the parent's partial
+// slots and shifts the grandparent's expansion in itself (each parent cell is
+// under exactly one leaf's 4x4x4 block, so no cell is done twice)
+enum : int32_t { kLeafX1 = 1, kLeafX2 = 2, kLeafLacc = 4, kLeafDefer = 8 };
 
 // one work-group of leaf work: the 512 cells of one leaf node (8 wavefronts,
 // one per parity class)

@@ -79,6 +79,9 @@ struct PlanHost {
     std::vector<M2LItem> m2l_leaf;   // record leaves (leaf targets next to interior nodes), LDS-staged
     // interior nodes by level index (level l of every tree)
     std::vector<std::vector<NodeItem>> interior;
+    // the interior nodes with an interior child, by level index: the L2L pass
+    // (the other interior nodes are finished by their leaves, kLeafDefer)
+    std::vector<std::vector<NodeItem>> l2l;
     std::vector<int32_t> tree_leaf_beg, tree_m2l_beg, tree_m2ln_beg, tree_m2lf_beg;  // per tree, +1 sentinel
 };
 
@@ -92,6 +95,8 @@ struct Plan {
     int n_m2l = 0, n_leaf = 0, n_p2m = 0, n_m2l_nodes = 0, n_m2l_leaf = 0;
     std::vector<int> n_interior;        // per level index
     std::vector<size_t> interior_off;   // element offset into d_interior per level index
+    std::vector<int> n_l2l;             // per level index: nodes of the L2L pass
+    std::vector<size_t> l2l_off;        // element offset into d_l2l per level index
     LevelDesc *d_levels = nullptr;
     TreeDesc *d_trees = nullptr;
     M2LItem *d_m2l = nullptr;
@@ -102,6 +107,7 @@ struct Plan {
     std::vector<char> sum_parts_level;  // per level index: partial slots summed in a separate wide pass
     int lds_min_level = 0;  // shallowest level with LDS-staged multipole items (n_levels_max if none)
     NodeItem *d_interior = nullptr;
+    NodeItem *d_l2l = nullptr;
     int32_t *d_tree_leaf_beg = nullptr, *d_tree_m2l_beg = nullptr, *d_tree_m2ln_beg = nullptr,
             *d_tree_m2lf_beg = nullptr;
     double *d_stat = nullptr;      // n_leaf * kStat (per leaf node)

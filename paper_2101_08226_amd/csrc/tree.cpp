@@ -506,12 +506,23 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
         all.insert(all.end(), v.begin(), v.end());
     }
     p.d_interior = (NodeItem *)put(all.data(), all.size() * sizeof(NodeItem));
-    // coarse levels (few interior nodes, many partial slots): separate wide sum
+    all.clear();
+    p.n_l2l.clear();
+    p.l2l_off.clear();
+    for (size_t l = 0; l < ph.interior.size(); ++l) {
+        p.l2l_off.push_back(all.size());
+        const size_t n = l < ph.l2l.size() ? ph.l2l[l].size() : 0;
+        p.n_l2l.push_back((int)n);
+        if (n) all.insert(all.end(), ph.l2l[l].begin(), ph.l2l[l].end());
+    }
+    p.d_l2l = (NodeItem *)put(all.data(), all.size() * sizeof(NodeItem));
+    // coarse levels (few L2L nodes, many partial slots): separate wide sum
     p.sum_parts_level.assign(ph.interior.size(), 0);
     for (size_t l = 0; l < ph.interior.size(); ++l) {
+        if (!p.n_l2l[l]) continue;
         int max_parts = 1;
-        for (const NodeItem &q : ph.interior[l]) max_parts = std::max(max_parts, ph.levels[q.ld].n_parts);
-        p.sum_parts_level[l] = (max_parts > 1 && ph.interior[l].size() <= 128) ? 1 : 0;
+        for (const NodeItem &q : ph.l2l[l]) max_parts = std::max(max_parts, ph.levels[q.ld].n_parts);
+        p.sum_parts_level[l] = (max_parts > 1 && ph.l2l[l].size() <= 128) ? 1 : 0;
     }
     p.d_tree_leaf_beg = (int32_t *)put(ph.tree_leaf_beg.data(), ph.tree_leaf_beg.size() * sizeof(int32_t));
     p.d_tree_m2l_beg = (int32_t *)put(ph.tree_m2l_beg.data(), ph.tree_m2l_beg.size() * sizeof(int32_t));
