@@ -355,12 +355,20 @@ template <typename T>
 struct Acc {
     T L0, L1[3], L2[6], L3[10], s1, U[3];
     double C[3];
+    T A2, A3;  // FP64 density solves: parts of L0 (m2l_pair_f64)
 };
+
+// the FP64 path without a dipole source (density solves) keeps some sums
+// unscaled until the end (acc_close)
+template <bool DIP, typename T>
+constexpr bool kF64Fast = !DIP && sizeof(T) == sizeof(double);
 
 template <typename T>
 __device__ inline void acc_zero(Acc<T> &a) {
     a.L0 = (T)0;
     a.s1 = (T)0;
+    a.A2 = (T)0;
+    a.A3 = (T)0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         a.L1[k] = (T)0;
@@ -371,6 +379,16 @@ __device__ inline void acc_zero(Acc<T> &a) {
     for (int k = 0; k < 6; ++k) a.L2[k] = (T)0;
 #pragma unroll
     for (int k = 0; k < 10; ++k) a.L3[k] = (T)0;
+}
+
+// After the last pair: the unscaled sums of m2l_pair_f64 to the common form.
+template <bool DIP, typename T>
+__device__ inline void acc_close(Acc<T> &a) {
+    if constexpr (kF64Fast<DIP, T>) {
+        a.L0 = -(a.L0 + 1.5 * a.A2 + 2.5 * a.A3);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) a.L3[k] *= -15.0;
+    }
 }
 
 // L2 = -(T2 + s1 I); L3_abc = -(T3_abc + d_ab U_c + d_ac U_b + d_bc U_a)
@@ -395,6 +413,84 @@ __device__ inline void finish_l2_l3(Acc<T> &a) {
     a.L3[9] = -(a.L3[9] + three * a.U[2]);
 }
 
+// FP64 density solves (no dipole): the sums below with the radial chain's
+// constant factors folded into the coefficients.  With g = 1/|R| and
+// p_n = g^(2n+1): f0 = g, f1 = -p1, f2 = 3 p2, f3 = -15 p3, f4 = 105 p4, so
+//   L0 = -(A0 + 3/2 A2 + 5/2 A3), A0 = sum m g, A2 = sum p2 R.Q'.R,
+//        A3 = sum p3 O':RRR (A0 kept in L0 until acc_close);
+//   L1_a += (m p1 + 15/2 p3 R.Q'.R) R_a - 3 p2 (Q'R)_a;
+//   s1 -= m p1;  T2 += 3 m p2 RR;  U += 3 m p2 R;
+//   T3 += m p3 RRR (scaled by -15 in acc_close);
+//   C_a += 15/2 p3 (n:RR)_a - 35/2 p4 (n:RR.R) R_a.
+// Every update is one fused multiply-add.
+template <bool LEAF_TARGET>
+__device__ inline void m2l_pair_f64(double Rx, double Ry, double Rz, double mB, const double *q, const double *o,
+                                    double mu, const double *oA, bool amc, Acc<double> &a) {
+    const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
+    // 1/|R| as in m2l_pair
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double e0 = __builtin_fma(-r2, y0 * y0, 1.0);
+    const double g = __builtin_fma(y0 * e0, __builtin_fma(e0, 0.375, 0.5), y0);
+    const double s = g * g, p1 = g * s, p2 = p1 * s, p3 = p2 * s;
+    // quadrupole contractions
+    const double qzz = -(q[0] + q[3]);
+    const double QRx = q[0] * Rx + q[1] * Ry + q[2] * Rz;
+    const double QRy = q[1] * Rx + q[3] * Ry + q[4] * Rz;
+    const double QRz = q[2] * Rx + q[4] * Ry + qzz * Rz;
+    const double RQR = Rx * QRx + Ry * QRy + Rz * QRz;
+    // octupole contractions
+    const double xx = Rx * Rx, yy = Ry * Ry, zz = Rz * Rz, xy = Rx * Ry, xz = Rx * Rz, yz = Ry * Rz;
+    const double e = xx - zz, f = yy - zz, u = 2.0 * xy, v = 2.0 * xz, w = 2.0 * yz;
+    double ORx, ORy, ORz;
+    o7_rr(o, e, f, u, v, w, ORx, ORy, ORz);
+    const double ORRR = Rx * ORx + Ry * ORy + Rz * ORz;
+    a.L0 = __builtin_fma(mB, g, a.L0);
+    a.A2 = __builtin_fma(p2, RQR, a.A2);
+    a.A3 = __builtin_fma(p3, ORRR, a.A3);
+    const double mp1 = mB * p1, k2 = 3.0 * p2, k3 = 7.5 * p3;
+    const double c = __builtin_fma(k3, RQR, mp1);
+    a.L1[0] = __builtin_fma(-k2, QRx, __builtin_fma(c, Rx, a.L1[0]));
+    a.L1[1] = __builtin_fma(-k2, QRy, __builtin_fma(c, Ry, a.L1[1]));
+    a.L1[2] = __builtin_fma(-k2, QRz, __builtin_fma(c, Rz, a.L1[2]));
+    if (!LEAF_TARGET) {
+        a.s1 -= mp1;
+        const double m2 = mB * k2;
+        a.L2[0] = __builtin_fma(m2, xx, a.L2[0]);
+        a.L2[1] = __builtin_fma(m2, xy, a.L2[1]);
+        a.L2[2] = __builtin_fma(m2, xz, a.L2[2]);
+        a.L2[3] = __builtin_fma(m2, yy, a.L2[3]);
+        a.L2[4] = __builtin_fma(m2, yz, a.L2[4]);
+        a.L2[5] = __builtin_fma(m2, zz, a.L2[5]);
+        a.U[0] = __builtin_fma(m2, Rx, a.U[0]);
+        a.U[1] = __builtin_fma(m2, Ry, a.U[1]);
+        a.U[2] = __builtin_fma(m2, Rz, a.U[2]);
+        const double m3 = mB * p3;
+        const double m3x = m3 * Rx, m3y = m3 * Ry, m3z = m3 * Rz;
+        a.L3[0] = __builtin_fma(m3x, xx, a.L3[0]);
+        a.L3[1] = __builtin_fma(m3x, xy, a.L3[1]);
+        a.L3[2] = __builtin_fma(m3x, xz, a.L3[2]);
+        a.L3[3] = __builtin_fma(m3x, yy, a.L3[3]);
+        a.L3[4] = __builtin_fma(m3x, yz, a.L3[4]);
+        a.L3[5] = __builtin_fma(m3x, zz, a.L3[5]);
+        a.L3[6] = __builtin_fma(m3y, yy, a.L3[6]);
+        a.L3[7] = __builtin_fma(m3y, yz, a.L3[7]);
+        a.L3[8] = __builtin_fma(m3z, yz, a.L3[8]);
+        a.L3[9] = __builtin_fma(m3z, zz, a.L3[9]);
+    }
+    if (amc) {
+        // n:RR = O'_B:RR - mu O'_A:RR
+        double ax, ay, az;
+        o7_rr(oA, e, f, u, v, w, ax, ay, az);
+        const double nx = __builtin_fma(-mu, ax, ORx), ny = __builtin_fma(-mu, ay, ORy),
+                     nz = __builtin_fma(-mu, az, ORz);
+        const double nR = __builtin_fma(-mu, ax * Rx + ay * Ry + az * Rz, ORRR);
+        const double kR = (-17.5 * (p3 * s)) * nR;
+        a.C[0] = __builtin_fma(kR, Rx, __builtin_fma(k3, nx, a.C[0]));
+        a.C[1] = __builtin_fma(kR, Ry, __builtin_fma(k3, ny, a.C[1]));
+        a.C[2] = __builtin_fma(kR, Rz, __builtin_fma(k3, nz, a.C[2]));
+    }
+}
+
 // T = double: everything in FP64.  T = float (mixed precision): the L0..L3
 // contractions run in FP32 with FP32 partial sums; R, the radial factors and
 // the correction stay FP64.  The source's second and third moments come
@@ -411,6 +507,10 @@ __device__ inline void finish_l2_l3(Acc<T> &a) {
 template <bool LEAF_TARGET, bool DIP, typename T>
 __device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, const double *q64, const double *o64,
                                 const double *D64, double mu, const double *oA, bool amc, Acc<T> &a) {
+    if constexpr (kF64Fast<DIP, T>) {
+        m2l_pair_f64<LEAF_TARGET>(Rx, Ry, Rz, mB64, q64, o64, mu, oA, amc, a);
+        return;
+    }
     const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
     // 1/|R|: the hardware estimate, then the second-order correction
     // (1 - e)^(-1/2) ~ 1 + e/2 + 3e^2/8 with e = 1 - r2 y0^2 (r2 is positive
@@ -611,6 +711,7 @@ __device__ void m2l_item(const LevelDesc &ld, const TreeDesc &td, const StencilD
             if (count) ++cnt;
         }
     }
+    acc_close<DIP>(a);
     if (!(mA > 0.0)) a.C[0] = a.C[1] = a.C[2] = 0.0;
     const double G = td.G;
     if (LEAF_TARGET) {
@@ -719,18 +820,16 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     const int q0 = LEAF ? 0 : 8 * item.chunk / ld.n_parts, q1 = LEAF ? 8 : 8 * (item.chunk + 1) / ld.n_parts;
     // sources: interior nodes and record leaves of this level; a leaf target's only the interior ones
     const int n_src = LEAF ? ld.n_int : ld.n_rec;
-    // leaf targets: the neighbour sub-grids that hold sources (uniform); source
-    // classes no entry of any target class reaches are skipped, and so are
-    // the entries that reach none of them
-    int src_mask = 0, q_need = 0xff;
-    if (LEAF) {
-        for (int b = 0; b < 27; ++b) src_mask |= (s_nbr[b] >= 0 && s_nbr[b] < n_src) ? (1 << b) : 0;
-        src_mask = __builtin_amdgcn_readfirstlane(src_mask);
-        q_need = 0;
-        for (int q = 0; q < 8; ++q)
-            for (int pp = 0; pp < 8; ++pp)
-                if (st.m2l_src_any[pp * 8 + q] & src_mask) q_need |= 1 << q;
-    }
+    // the neighbour sub-grids that hold sources (uniform; all 27 inside the
+    // domain's interior): source classes no entry of any target class reaches
+    // are skipped, and so are the entries that reach none of them (at the
+    // domain's boundary and next to coarser regions)
+    int src_mask = 0, q_need = 0;
+    for (int b = 0; b < 27; ++b) src_mask |= (s_nbr[b] >= 0 && s_nbr[b] < n_src) ? (1 << b) : 0;
+    src_mask = __builtin_amdgcn_readfirstlane(src_mask);
+    for (int q = 0; q < 8; ++q)
+        for (int pp = 0; pp < 8; ++pp)
+            if (st.m2l_src_any[pp * 8 + q] & src_mask) q_need |= 1 << q;
     for (int q = q0; q < q1; ++q) {
         if (!((q_need >> q) & 1)) continue;  // uniform over the work-group
         const int qx = q >> 2, qy = (q >> 1) & 1, qz = q & 1;
@@ -787,11 +886,20 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
         __syncthreads();
         const int beg = st.m2l_src_beg[p * 9 + q], end = st.m2l_src_beg[p * 9 + q + 1];
         const int hb = (x >> 1) * HX + (y >> 1) * HY + (z >> 1);
-        // independent pairs interleaved per iteration (latency hiding at two
-        // waves per SIMD)
-#pragma unroll OCTO_M2L_UNROLL
-        for (int k = beg; k < end; ++k) {
-            if (LEAF && !(st.m2l_src_touch[k] & src_mask)) continue;  // uniform
+        if (counting) {
+            // pairs with a present source (absent sources carry -0.0), in a
+            // pass of their own so that the multipole loop carries no count;
+            // four independent counts keep several LDS reads in flight
+            int c4[4] = {0, 0, 0, 0};
+            int k = beg;
+            for (; k + 3 < end; k += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) c4[u] += signbit(s_src[0][hb + st.m2l_src[k + u]].x) ? 0 : 1;
+            }
+            for (; k < end; ++k) c4[0] += signbit(s_src[0][hb + st.m2l_src[k]].x) ? 0 : 1;
+            cnt += c4[0] + c4[1] + c4[2] + c4[3];
+        }
+        auto pair = [&](int k) {
             const int h = hb + st.m2l_src[k];  // the offset is uniform over the wavefront
             double r[2 * NV];
 #pragma unroll
@@ -800,12 +908,24 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
                 r[2 * j] = e.x;
                 r[2 * j + 1] = e.y;
             }
-            if (counting) cnt += signbit(r[0]) ? 0 : 1;  // absent sources carry -0.0
             m2l_pair<LEAF, DIP, T>(zAx - r[1], zAy - r[2], zAz - r[3], r[0], &r[4], &r[9], &r[16 % (2 * NV)],
                                    r[0] * imA, oA, amc, a);
+        };
+        if (LEAF) {
+#pragma unroll OCTO_M2L_UNROLL
+            for (int k = beg; k < end; ++k)
+                if (st.m2l_src_touch[k] & src_mask) pair(k);  // uniform
+        } else {
+            // independent pairs interleaved per iteration (latency hiding at
+            // two waves per SIMD).  Entries that reach only absent sub-grids
+            // (domain boundary) cost their full work: a per-entry skip breaks
+            // the interleaving and is slower overall.
+#pragma unroll OCTO_M2L_UNROLL
+            for (int k = beg; k < end; ++k) pair(k);
         }
         __syncthreads();
     }
+    acc_close<DIP>(a);
     if (!(mA > 0.0)) a.C[0] = a.C[1] = a.C[2] = 0.0;
     const double G = td.G;
     if (LEAF) {
