@@ -830,15 +830,16 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     for (int q = 0; q < 8; ++q)
         for (int pp = 0; pp < 8; ++pp)
             if (st.m2l_src_any[pp * 8 + q] & src_mask) q_need |= 1 << q;
-    for (int q = q0; q < q1; ++q) {
-        if (!((q_need >> q) & 1)) continue;  // uniform over the work-group
+    // Source class q staged in LDS: lattice index i in [0,9) <-> local
+    // coordinate 2i - 4 - parity.  Cells that are not sources get mass -0.0
+    // (counted as absent, contributes exact zeros) and a far-away centre.  A
+    // class's global loads (both cells of this thread, all in flight
+    // together) are issued as soon as this wavefront has finished the
+    // previous class, so that they overlap the other wavefronts' remaining
+    // pairs and the barrier; the LDS stores follow the barrier.
+    double v[2][23];
+    auto load_class = [&](int q) {
         const int qx = q >> 2, qy = (q >> 1) & 1, qz = q & 1;
-        // stage source class q: lattice index i in [0,9) <-> local coordinate
-        // 2i - 4 - parity; both cells of this thread are loaded before either
-        // is stored so that all loads are in flight together.  Cells that are
-        // not sources get mass -0.0 (counted as absent, contributes exact
-        // zeros) and a far-away centre.
-        double v[2][23];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int cc = tid + 512 * u;
@@ -859,6 +860,8 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
                 for (int k = 4; k < 23; ++k) v[u][k] = 0.0;
             }
         }
+    };
+    auto store_class = [&]() {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int cc = tid + 512 * u;
@@ -883,6 +886,17 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
                 for (int k = 0; k < NV; ++k) s_src[k][c] = make_double2(r[2 * k], r[2 * k + 1]);
             }
         }
+    };
+    // the needed classes of this item's share, in order (uniform)
+    auto next_class = [&](int q) {
+        for (++q; q < q1; ++q)
+            if ((q_need >> q) & 1) break;
+        return q;
+    };
+    int q = next_class(q0 - 1);
+    if (q < q1) load_class(q);
+    while (q < q1) {
+        store_class();
         __syncthreads();
         const int beg = st.m2l_src_beg[p * 9 + q], end = st.m2l_src_beg[p * 9 + q + 1];
         const int hb = (x >> 1) * HX + (y >> 1) * HY + (z >> 1);
@@ -923,7 +937,10 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
 #pragma unroll OCTO_M2L_UNROLL
             for (int k = beg; k < end; ++k) pair(k);
         }
+        const int qn = next_class(q);
+        if (qn < q1) load_class(qn);
         __syncthreads();
+        q = qn;
     }
     acc_close<DIP>(a);
     if (!(mA > 0.0)) a.C[0] = a.C[1] = a.C[2] = 0.0;
