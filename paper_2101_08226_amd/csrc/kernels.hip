@@ -478,12 +478,17 @@ __device__ inline void m2l_pair_f64(double Rx, double Ry, double Rz, double mB, 
         a.L3[9] = __builtin_fma(m3z, zz, a.L3[9]);
     }
     if (amc) {
-        // n:RR = O'_B:RR - mu O'_A:RR
-        double ax, ay, az;
-        o7_rr(oA, e, f, u, v, w, ax, ay, az);
-        const double nx = __builtin_fma(-mu, ax, ORx), ny = __builtin_fma(-mu, ay, ORy),
-                     nz = __builtin_fma(-mu, az, ORz);
-        const double nR = __builtin_fma(-mu, ax * Rx + ay * Ry + az * Rz, ORRR);
+        // n:RR = O'_B:RR - mu O'_A:RR; a leaf target is a point mass at its
+        // cell centre (no third moment), so there n:RR = O'_B:RR
+        double nx = ORx, ny = ORy, nz = ORz, nR = ORRR;
+        if (!LEAF_TARGET) {
+            double ax, ay, az;
+            o7_rr(oA, e, f, u, v, w, ax, ay, az);
+            nx = __builtin_fma(-mu, ax, ORx);
+            ny = __builtin_fma(-mu, ay, ORy);
+            nz = __builtin_fma(-mu, az, ORz);
+            nR = __builtin_fma(-mu, ax * Rx + ay * Ry + az * Rz, ORRR);
+        }
         const double kR = (-17.5 * (p3 * s)) * nR;
         a.C[0] = __builtin_fma(kR, Rx, __builtin_fma(k3, nx, a.C[0]));
         a.C[1] = __builtin_fma(kR, Ry, __builtin_fma(k3, ny, a.C[1]));
