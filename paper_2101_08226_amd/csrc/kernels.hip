@@ -1127,9 +1127,10 @@ __device__ inline void near_octant(const T *__restrict__ s_m, int base, const in
         if (SZ > 0) a[3] += mm * w[3]; else a[3] -= mm * w[3];
     };
     // weight rows addressed by an unsigned 32-bit byte offset from the table
-    // base, so the scalar load takes it as its offset operand
-    auto row = [&](int wi) {
-        return (const T *)((const char *)tab + (unsigned)wi * (unsigned)(4 * sizeof(T)));
+    // base (stored for the FP64 table), so the scalar load takes it as its
+    // offset operand
+    auto row = [&](int wb) {
+        return (const T *)((const char *)tab + (sizeof(T) == 8 ? (unsigned)wb : (unsigned)wb >> 1));
     };
     for (int k = beg; k < end; k += 8) {
         int o[8], wi[8];

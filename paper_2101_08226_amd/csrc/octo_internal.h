@@ -115,7 +115,8 @@ struct StencilDev {
     const int32_t *leaf;   // m2l followed by near (packed offsets)
     // near-field entries per target class, grouped by the sign octant o of d
     // (o = (dx<0)<<2 | (dy<0)<<1 | (dz<0)): offset into the parity-split halo
-    // relative to the target's lattice position, and weight-table index
+    // relative to the target's lattice position, and weight-table row as a
+    // byte offset into the FP64 table (half of it into the FP32 table)
     const int32_t *leaf_off;
     const int32_t *leaf_widx;
     const double *leaf_tab;   // kNearTab x 4: 1/|d|, |dx|/|d|^3, |dy|/|d|^3, |dz|/|d|^3

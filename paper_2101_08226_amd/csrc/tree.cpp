@@ -454,7 +454,8 @@ Stencil make_stencil(double theta) {
                 int ux = px + d[0] + 5, uy = py + d[1] + 5, uz = pz + d[2] + 5;
                 int q = ((ux & 1) << 2) | ((uy & 1) << 1) | (uz & 1);
                 s.leaf_off.push_back(q * kNearQ + (ux >> 1) * kNearX + (uy >> 1) * kNearY + (uz >> 1));
-                s.leaf_widx.push_back((std::abs(d[0]) * 6 + std::abs(d[1])) * 6 + std::abs(d[2]));
+                // weight row as a byte offset into the FP64 table (4 values a row)
+                s.leaf_widx.push_back(32 * ((std::abs(d[0]) * 6 + std::abs(d[1])) * 6 + std::abs(d[2])));
             }
             // pad to whole blocks of 8 with entries of zero weight (row 0,
             // d = 0) that read the target's own halo cell
