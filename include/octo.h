@@ -142,7 +142,12 @@ octo_status octo_ctx_create(int device, void *hip_stream, const octo_allocator *
  * destroyed first (OCTO_E_STATE otherwise). */
 octo_status octo_ctx_destroy(octo_ctx *ctx);
 /* Profiling: when on != 0, solves launch their kernels one by one (no graph
- * replay) with HIP events between phases, and octo_stats.phase_ms is filled. */
+ * replay) with HIP events between phases, and octo_stats.phase_ms is filled.
+ * on = 1: the statistics are computed as usual (pairs counted, which adds a
+ * counting pass to the multipole kernels); on = 2: timing only, the kernels
+ * run as in solves without statistics, and the octo_stats fields other than
+ * n_leaf_cells, device_ms and phase_ms are zero.  Other values:
+ * OCTO_E_INVALID. */
 octo_status octo_ctx_set_profiling(octo_ctx *ctx, int on);
 /* Bytes of device memory currently held by the context's trees. */
 octo_status octo_ctx_memory(const octo_ctx *ctx, size_t *bytes_in_use, size_t *budget);

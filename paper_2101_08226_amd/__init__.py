@@ -197,8 +197,8 @@ def octo_ctx_destroy(ctx: int) -> None:
     _check(load_library().octo_ctx_destroy(ctx))
 
 
-def octo_ctx_set_profiling(ctx: int, on: bool) -> None:
-    _check(load_library().octo_ctx_set_profiling(ctx, int(bool(on))))
+def octo_ctx_set_profiling(ctx: int, on) -> None:
+    _check(load_library().octo_ctx_set_profiling(ctx, int(on)))
 
 
 def octo_ctx_memory(ctx: int):
@@ -425,8 +425,9 @@ class Context:
     def memory(self):
         return octo_ctx_memory(self.handle)
 
-    def set_profiling(self, on: bool) -> None:
-        octo_ctx_set_profiling(self.handle, on)
+    def set_profiling(self, on) -> None:
+        """0/False off; 1/True phase timings with statistics; 2 timings only."""
+        octo_ctx_set_profiling(self.handle, int(on))
 
     def uniform_tree(self, rho) -> "Tree":
         rho = np.ascontiguousarray(rho, dtype=np.float64)

@@ -386,7 +386,8 @@ octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, 
             want.push_back(desc_for(t, out_on_device ? phi[i] : t->stage, out_on_device ? g[i] : t->stage + m, opts));
         }
         if (stats) check_hip(hipEventRecord(ctx->ev0, ctx->stream), "event");
-        run_plan(ctx, bp.plan, bp.graphs, want, opts, stats != nullptr);
+        const bool count = stats != nullptr && ctx->profiling != 2;  // timing-only profiling: no counts
+        run_plan(ctx, bp.plan, bp.graphs, want, opts, count);
         for (int i = 0; i < n; ++i) check_hip(hipEventRecord(trees[i]->last_use, ctx->stream), "event");
         if (stats) {
             check_hip(hipEventRecord(ctx->ev1, ctx->stream), "event");
@@ -407,7 +408,14 @@ octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, 
         if (stats) {
             float ms = 0.f;
             hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-            for (int i = 0; i < n; ++i) fill(ctx->h_stats + 12 * i, trees[i]->layout.n_leaf_cells, ms, &stats[i]);
+            for (int i = 0; i < n; ++i) {
+                fill(ctx->h_stats + 12 * i, trees[i]->layout.n_leaf_cells, ms, &stats[i]);
+                if (!count) {
+                    memset(&stats[i], 0, sizeof stats[i]);
+                    stats[i].n_leaf_cells = trees[i]->layout.n_leaf_cells;
+                    stats[i].device_ms = ms;
+                }
+            }
         }
     });
 }

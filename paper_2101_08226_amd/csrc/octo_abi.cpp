@@ -601,8 +601,9 @@ octo_status octo_ctx_destroy(octo_ctx *ctx) {
 octo_status octo_ctx_set_profiling(octo_ctx *ctx, int on) {
     return guard([&] {
         if (!ctx) fail(OCTO_E_INVALID, "ctx is NULL");
+        if (on < 0 || on > 2) fail(OCTO_E_INVALID, "profiling mode must be 0, 1 or 2");
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-        ctx->profiling = on != 0;
+        ctx->profiling = on;
     });
 }
 
@@ -794,7 +795,9 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
         want[0].G = opts->G;
         want[0].amc = opts->amc ? 1 : 0;
         if (stats) check_hip(hipEventRecord(ctx->ev0, ctx->stream), "event");
-        run_plan(ctx, tree->plan, tree->graphs, want, opts, stats != nullptr);
+        // timing-only profiling runs the kernels as a solve without statistics
+        const bool count = stats != nullptr && ctx->profiling != 2;
+        run_plan(ctx, tree->plan, tree->graphs, want, opts, count);
         check_hip(hipEventRecord(tree->last_use, ctx->stream), "event");
         if (stats) {
             check_hip(hipEventRecord(ctx->ev1, ctx->stream), "event");
@@ -811,6 +814,12 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
             float ms = 0.f;
             hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
             fill_stats(ctx->h_stats, n, ms, stats);
+            if (!count) {
+                const double dms = stats->device_ms;
+                memset(stats, 0, sizeof *stats);
+                stats->n_leaf_cells = n;
+                stats->device_ms = dms;
+            }
             if (ctx->profiling)
             {
                 for (int i = 0; i < 7; ++i) {
@@ -989,8 +998,8 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
         if (ctx->batch &&
             std::find(ctx->batch->sig.begin(), ctx->batch->sig.end(), tree) != ctx->batch->sig.end())
             ctx->invalidate_batches();
-        const bool prof = ctx->profiling;
-        ctx->profiling = true;
+        const int prof = ctx->profiling;
+        ctx->profiling = 1;
         const int64_t n = tree->layout.n_leaf_cells;
         auto measure = [&]() {
             std::vector<TreeDesc> want = tree->plan.trees_host;

@@ -209,7 +209,7 @@ struct octo_ctx {
     hipStream_t aux_near = nullptr, capture_near = nullptr;  // near-field streams
     hipEvent_t fork_near_ev = nullptr, join_near_ev = nullptr;
     bool use_graphs = true;
-    bool profiling = false;
+    int profiling = 0;  // 0 off, 1 phase timings with statistics, 2 phase timings only
     hipEvent_t phase_ev[9] = {};
     double *h_stats = nullptr;  // pinned host staging for stats
     // pinned upload buffers, reused (freeing pinned memory can wait for the

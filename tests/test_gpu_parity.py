@@ -475,3 +475,29 @@ def test_dphidt_uniform_and_full_size(ctx):
     say(f"  e={e:.2e} cancel={cancel:.2e}")
     assert e <= TOL
     assert cancel < 1e-13
+
+
+def test_profiling_modes(ctx):
+    """Profiling (kernels one by one) gives the graph solve's results bit for
+    bit; mode 1 keeps the statistics, mode 2 (timing only) zeroes them and
+    still times every phase (64^3: the LDS-staged multipole kernel runs)."""
+    rho = w.uniform_grid(w.binary_polytrope_128(), 3)
+    tree = ctx.uniform_tree(rho)
+    p0, g0, st0 = gpu_solve(ctx, tree)
+    for mode in (1, 2):
+        ctx.set_profiling(mode)
+        try:
+            p, g, st = gpu_solve(ctx, tree)
+        finally:
+            ctx.set_profiling(0)
+        say(f"profiling {mode}: phases {[round(x, 4) for x in st['phase_ms']]}")
+        assert np.array_equal(p, p0) and np.array_equal(g, g0)
+        assert all(x > 0 for i, x in enumerate(st["phase_ms"]) if i != 6)  # [6]: statistics
+        if mode == 1:
+            assert st["m2l_pairs"] == st0["m2l_pairs"] and st["total_mass"] == st0["total_mass"]
+        else:
+            assert st["m2l_pairs"] == 0 and st["total_mass"] == 0.0 and st["n_leaf_cells"] == st0["n_leaf_cells"]
+    for bad in (-1, 3):
+        with pytest.raises(lib.OctoError, match="INVALID"):
+            ctx.set_profiling(bad)
+    tree.destroy()
