@@ -827,8 +827,7 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     const int n_src = LEAF ? ld.n_int : ld.n_rec;
     // the neighbour sub-grids that hold sources (uniform; all 27 inside the
     // domain's interior): source classes no entry of any target class reaches
-    // are skipped, and so are the entries that reach none of them (at the
-    // domain's boundary and next to coarser regions)
+    // are skipped; leaf targets also skip the entries that reach none of them
     int src_mask = 0, q_need = 0;
     for (int b = 0; b < 27; ++b) src_mask |= (s_nbr[b] >= 0 && s_nbr[b] < n_src) ? (1 << b) : 0;
     src_mask = __builtin_amdgcn_readfirstlane(src_mask);
