@@ -24,6 +24,16 @@ extern "C" {
  * Errors: OCTO_E_UNSUPPORTED for theta outside [0.34, 1). */
 octo_status octo_host_stencil_sizes(double theta, int32_t *out);
 
+/* The near-field walk of the leaf kernel for opening angle theta (levels >= 1):
+ * the entries of target class p and sign octant o (o = (dx<0)<<2 | (dy<0)<<1 |
+ * (dz<0) for the nonzero components of d; a zero component may sit in either
+ * octant of its axis) are d[beg[9*p+o] .. beg[9*p+o+1]), each packed as
+ * (dx & 255) | (dy & 255) << 8 | (dz & 255) << 16, with 0 for the padding
+ * that fills every octant list to whole blocks of 8.  beg holds 73 entries
+ * (beg[72] = total).  If d is NULL or cap is too small only beg and *n are set.
+ * Errors: OCTO_E_UNSUPPORTED for theta outside [0.34, 1). */
+octo_status octo_host_near_lists(double theta, int32_t *beg, int32_t *d, int64_t cap, int64_t *n);
+
 /* Validate a leaf list exactly as octo_tree_build does and report its layout:
  * out[3*l+0] = nodes at level l, out[3*l+1] = interior nodes, out[3*l+2] =
  * leaf nodes that touch an interior node of their level; *n_levels = deepest

@@ -46,6 +46,33 @@ octo_status octo_host_stencil_sizes(double theta, int32_t *out) {
     });
 }
 
+octo_status octo_host_near_lists(double theta, int32_t *beg, int32_t *d, int64_t cap, int64_t *n) {
+    return guard_h([&] {
+        if (!beg || !n) fail(OCTO_E_INVALID, "NULL output");
+        if (!(theta >= 0.34 && theta < 1.0)) fail(OCTO_E_UNSUPPORTED, "theta must lie in [0.34, 1)");
+        Stencil s = make_stencil(theta);
+        for (int k = 0; k < 73; ++k) beg[k] = s.leaf_oct_beg[k];
+        *n = (int64_t)s.leaf_off.size();
+        if (!d || cap < *n) return;
+        // back from halo offsets to d: a target of class p reads halo cell
+        // u = x + d + 5 of parity class q at lattice index (u >> 1)
+        for (int p = 0; p < 8; ++p) {
+            const int pc[3] = {p >> 2, (p >> 1) & 1, p & 1};
+            for (int k = s.leaf_oct_beg[9 * p]; k < s.leaf_oct_beg[9 * p + 8]; ++k) {
+                if (s.leaf_widx[k] == 0) {  // padding (row of d = 0)
+                    d[k] = 0;
+                    continue;
+                }
+                const int off = s.leaf_off[k], q = off / kNearQ, r = off % kNearQ;
+                const int lat[3] = {r / kNearX, (r % kNearX) / kNearY, (r % kNearX) % kNearY};
+                int dd[3];
+                for (int a = 0; a < 3; ++a) dd[a] = 2 * lat[a] + ((q >> (2 - a)) & 1) - pc[a] - 5;
+                d[k] = pack_off(dd[0], dd[1], dd[2]);
+            }
+        }
+    });
+}
+
 octo_status octo_host_layout(const octo_leaf *leaves, int64_t n_leaves, int32_t *n_levels, int64_t *out) {
     return guard_h([&] {
         if (!n_levels || !out) fail(OCTO_E_INVALID, "NULL output");

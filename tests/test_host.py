@@ -117,3 +117,45 @@ def test_random_adaptive_trees_match_oracle():
         a = lib.octo_host_adaptive_leaves(f, 4, thr)
         b = oracle.build_adaptive_leaves(f.boxmax, 4, thr)
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("theta", [0.34, 0.5, 0.7])
+def test_near_lists_cover_the_stencil_with_minimal_padding(theta):
+    """The leaf kernel's near-field walk, per target class: exactly the
+    partners whose parents are not well separated (the opening criterion of
+    Sec. 2.2 on the parents' offset, d != 0), each once, each in a sign octant
+    that agrees with its nonzero components, every octant list a whole number
+    of blocks of 8, and the padding no more than the total count forces."""
+    beg, d = lib.octo_host_near_lists(theta)
+    sizes = lib.octo_host_stencil_sizes(theta)
+
+    def fdiv2(v):
+        return v // 2  # floor division, as for the parent index of a cell
+
+    for p in range(8):
+        pc = ((p >> 2) & 1, (p >> 1) & 1, p & 1)
+        want = set()
+        for dx in range(-7, 8):
+            for dy in range(-7, 8):
+                for dz in range(-7, 8):
+                    if (dx, dy, dz) == (0, 0, 0):
+                        continue
+                    D = [fdiv2(c + v) for c, v in zip(pc, (dx, dy, dz))]
+                    if theta * theta * sum(x * x for x in D) <= 1.0:
+                        want.add((dx, dy, dz))
+        got, pad = [], 0
+        for o in range(8):
+            a, b = beg[9 * p + o], beg[9 * p + o + 1]
+            assert (b - a) % 8 == 0
+            for row in d[a:b]:
+                t = tuple(int(v) for v in row)
+                if t == (0, 0, 0):
+                    pad += 1
+                    continue
+                for ax in range(3):
+                    if t[ax] != 0:
+                        assert ((o >> (2 - ax)) & 1) == (t[ax] < 0), (p, o, t)
+                got.append(t)
+        assert len(got) == len(set(got)) and set(got) == want
+        assert len(got) == sizes[p] + sizes[8 + p]
+        assert pad == (8 - len(got) % 8) % 8, (theta, p, pad)
