@@ -112,10 +112,10 @@ def roofline_m2l(pairs, kernel_ms, prec, traffic=None):
     with statistics) x the per-pair count over its own launch duration (HIP
     events around it, kernels one by one, timing-only profiling)."""
     achieved = pairs * M2L_FLOPS_PER_PAIR / (kernel_ms * 1e-3) / 1e12
-    t = "double" if prec == "fp64" else "float"
+    # the multipole kernel is FP64 in both precisions (the mixed mode's FP32 is the near field's)
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
-            "kernel": f"k_m2l_lds<{t}, false, true, false>", "kernel_ms": round(kernel_ms, 4), "pairs_per_launch": int(pairs),
+            "kernel": "k_m2l_lds<double, false, true, false>", "kernel_ms": round(kernel_ms, 4), "pairs_per_launch": int(pairs),
             "flops_per_pair": M2L_FLOPS_PER_PAIR}
 
 

@@ -82,10 +82,11 @@ enum { OCTO_FP64 = 0, OCTO_MIXED = 1 };
  *   Must lie in [0.34, 1): 0.34 is the paper's minimum for 8^3 sub-grids.
  * G: gravitational constant (1 in code units, Sec. 2.8).
  * precision: OCTO_FP64 computes everything in double precision;
- *   OCTO_MIXED evaluates the bulk of the multipole-to-local and near-field
- *   terms in single precision with single-precision partial sums, keeping the
- *   moments, the angular-momentum correction and the final accumulation in
- *   double precision.
+ *   OCTO_MIXED evaluates the leaf near-field sums in single precision with
+ *   single-precision partial sums (weights and masses rounded to float) and
+ *   everything else -- moments, multipole-to-local terms, the
+ *   angular-momentum correction, the downward pass and the final
+ *   accumulation -- in double precision.
  * amc: 1 applies the angular-momentum correction (Sec. 2.2), 0 omits it. */
 typedef struct {
     double theta;

@@ -1213,8 +1213,6 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
     int x, y, z;
     local_xyz(s, x, y, z);
     const double h = ld.h;
-    const int gx0 = 8 * ld.coord[3 * node], gy0 = 8 * ld.coord[3 * node + 1], gz0 = 8 * ld.coord[3 * node + 2];
-    const double cx = centre(gx0 + x, h), cy = centre(gy0 + y, h), cz = centre(gz0 + z, h);
     int cnt = 0;
 
     // same-level leaf partners: phi = -(1/h) sum m w0, g = (1/h^2) sum m w1
@@ -1598,20 +1596,19 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     }
     for (int l = lsplit - 1; l >= 0; --l) upward(l, sm);
     mark(3);
-    const bool mixed = o.precision == OCTO_MIXED;
+    // The multipole work runs in FP64 in both precisions: non-packed FP32
+    // issues at the FP64 rate on this chip, so only the near field (half the
+    // LDS bytes) gains from single precision.
     if (p.n_m2l) {
         const int grid = ((p.n_m2l + kXcd - 1) / kXcd) * kXcd;
-        auto k = mixed ? (src ? k_m2l<float, true> : k_m2l<float, false>)
-                       : (src ? k_m2l<double, true> : k_m2l<double, false>);
+        auto k = src ? k_m2l<double, true> : k_m2l<double, false>;
         hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, sm, p.d_levels, p.d_trees, p.d_m2l, p.n_m2l, st, p.d_m2l_cnt,
                            o.count ? 1 : 0);
     }
     if (p.n_m2l_leaf) {
         const int grid = ((p.n_m2l_leaf + kXcd - 1) / kXcd) * kXcd;
-        auto k = mixed ? (src ? k_m2l_lds<float, true, false, true>
-                              : (o.amc ? k_m2l_lds<float, false, true, true> : k_m2l_lds<float, false, false, true>))
-                       : (src ? k_m2l_lds<double, true, false, true>
-                              : (o.amc ? k_m2l_lds<double, false, true, true> : k_m2l_lds<double, false, false, true>));
+        auto k = src ? k_m2l_lds<double, true, false, true>
+                     : (o.amc ? k_m2l_lds<double, false, true, true> : k_m2l_lds<double, false, false, true>);
         hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, sm, p.d_levels, p.d_trees, p.d_m2l_leaf, p.n_m2l_leaf, st,
                            p.d_m2l_cnt + p.n_m2l + p.n_m2l_nodes, o.count ? 1 : 0);
     }
@@ -1620,10 +1617,8 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     mark(8);
     if (p.n_m2l_nodes) {
         const int grid = ((p.n_m2l_nodes + kXcd - 1) / kXcd) * kXcd;
-        auto k = mixed ? (src ? k_m2l_lds<float, true, false, false>
-                              : (o.amc ? k_m2l_lds<float, false, true, false> : k_m2l_lds<float, false, false, false>))
-                       : (src ? k_m2l_lds<double, true, false, false>
-                              : (o.amc ? k_m2l_lds<double, false, true, false> : k_m2l_lds<double, false, false, false>));
+        auto k = src ? k_m2l_lds<double, true, false, false>
+                     : (o.amc ? k_m2l_lds<double, false, true, false> : k_m2l_lds<double, false, false, false>);
         hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes, p.n_m2l_nodes, st,
                            p.d_m2l_cnt + p.n_m2l, o.count ? 1 : 0);
     }

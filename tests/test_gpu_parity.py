@@ -114,10 +114,11 @@ def test_adaptive_random(ctx, seed, max_level):
     tree.destroy()
 
 
-# Mixed precision (FP32 L-term contractions and near field, FP64 moments,
-# correction and final accumulation): bounds are 4x the largest error measured
-# on these cases and on the full-size adaptive case (largest: e_phi 2.65e-7,
-# e_g 2.62e-7, both on the adaptive level-3 case).
+# Mixed precision (FP32 near field; FP64 moments, multipole-to-local terms,
+# correction and final accumulation): the bounds are 4x the largest error
+# measured when the mixed mode also ran the L-term contractions in FP32 (e_phi
+# 2.65e-7, e_g 2.62e-7, adaptive level-3 case), which bounds the FP32 near
+# field alone as well.
 MIXED_PHI = 1.1e-6
 MIXED_G = 1.1e-6
 
