@@ -358,11 +358,6 @@ struct Acc {
     T A2, A3;  // FP64 density solves: parts of L0 (m2l_pair_f64)
 };
 
-// the FP64 path without a dipole source (density solves) keeps some sums
-// unscaled until the end (acc_close)
-template <bool DIP, typename T>
-constexpr bool kF64Fast = !DIP && sizeof(T) == sizeof(double);
-
 template <typename T>
 __device__ inline void acc_zero(Acc<T> &a) {
     a.L0 = (T)0;
@@ -384,11 +379,9 @@ __device__ inline void acc_zero(Acc<T> &a) {
 // After the last pair: the unscaled sums of m2l_pair_f64 to the common form.
 template <bool DIP, typename T>
 __device__ inline void acc_close(Acc<T> &a) {
-    if constexpr (kF64Fast<DIP, T>) {
-        a.L0 = -(a.L0 + 1.5 * a.A2 + 2.5 * a.A3);
+    a.L0 = -(a.L0 + 1.5 * a.A2 + 2.5 * a.A3);
 #pragma unroll
-        for (int k = 0; k < 10; ++k) a.L3[k] *= -15.0;
-    }
+    for (int k = 0; k < 10; ++k) a.L3[k] *= -15.0;
 }
 
 // L2 = -(T2 + s1 I); L3_abc = -(T3_abc + d_ab U_c + d_ac U_b + d_bc U_a)
@@ -413,7 +406,18 @@ __device__ inline void finish_l2_l3(Acc<T> &a) {
     a.L3[9] = -(a.L3[9] + three * a.U[2]);
 }
 
-// FP64 density solves (no dipole): the sums below with the radial chain's
+// Multipole-to-local of one ordered pair, on trace-free source moments (q5,
+// o7 packing); with D^(k) the derivative tensors of 1/r at R:
+//   L0 -= m f0 + (1/2) f2 R.Q'.R - (1/6) f3 O'.RRR
+//   L1_a -= (m f1 + (1/2) f3 R.Q'.R) R_a + f2 (Q'R)_a
+// (the trace terms f1 tr Q, f2 tr O vanish).  DIP: the source also has a
+// dipole d (second source expanded about the density's centres): L0 += d.D1,
+// L1_a += d_b D2_ab, L2_ab += d_c D3_abc, i.e. with w = d.R: L0 += f1 w;
+// L1_a += f2 w R_a + f1 d_a; L2_ab += f3 w R_a R_b + f2 (w d_ab + R_a d_b +
+// R_b d_a).  Correction: n = O'_B - mu O'_A is trace-free, so n : D4 reduces
+// to f4 (n:RR . R) R + 3 f3 (n:RR), with n:RR = O'_B:RR - mu O'_A:RR.
+//
+// In FP64, with the radial chain's
 // constant factors folded into the coefficients.  With g = 1/|R| and
 // p_n = g^(2n+1): f0 = g, f1 = -p1, f2 = 3 p2, f3 = -15 p3, f4 = 105 p4, so
 //   L0 = -(A0 + 3/2 A2 + 5/2 A3), A0 = sum m g, A2 = sum p2 R.Q'.R,
@@ -422,12 +426,18 @@ __device__ inline void finish_l2_l3(Acc<T> &a) {
 //   s1 -= m p1;  T2 += 3 m p2 RR;  U += 3 m p2 R;
 //   T3 += m p3 RRR (scaled by -15 in acc_close);
 //   C_a += 15/2 p3 (n:RR)_a - 35/2 p4 (n:RR.R) R_a.
+// DIP (a second source with a dipole d about the density's centre, w = d.R,
+// no correction): A0 also sums p1 w; the L1 coefficient gains 3 p2 w and
+// L1_a gains -p1 d_a; s1 -= 3 p2 w; T2 += 15 p3 w RR; and
+// L2_ab -= 3 p2 (d_a R_b + d_b R_a).
 // Every update is one fused multiply-add.
-template <bool LEAF_TARGET>
+template <bool LEAF_TARGET, bool DIP>
 __device__ inline void m2l_pair_f64(double Rx, double Ry, double Rz, double mB, const double *q, const double *o,
-                                    double mu, const double *oA, bool amc, Acc<double> &a) {
+                                    const double *dp, double mu, const double *oA, bool amc, Acc<double> &a) {
     const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
-    // 1/|R| as in m2l_pair
+    // 1/|R|: the hardware estimate, then the second-order correction
+    // (1 - e)^(-1/2) ~ 1 + e/2 + 3e^2/8 with e = 1 - r2 y0^2 (r2 is positive
+    // and normal: distinct cells)
     const double y0 = __builtin_amdgcn_rsq(r2);
     const double e0 = __builtin_fma(-r2, y0 * y0, 1.0);
     const double g = __builtin_fma(y0 * e0, __builtin_fma(e0, 0.375, 0.5), y0);
@@ -444,23 +454,47 @@ __device__ inline void m2l_pair_f64(double Rx, double Ry, double Rz, double mB, 
     double ORx, ORy, ORz;
     o7_rr(o, e, f, u, v, w, ORx, ORy, ORz);
     const double ORRR = Rx * ORx + Ry * ORy + Rz * ORz;
+    double dx = 0.0, dy = 0.0, dz = 0.0, dw = 0.0;
+    if (DIP) {
+        dx = dp[0];
+        dy = dp[1];
+        dz = dp[2];
+        dw = dx * Rx + dy * Ry + dz * Rz;
+    }
     a.L0 = __builtin_fma(mB, g, a.L0);
+    if (DIP) a.L0 = __builtin_fma(p1, dw, a.L0);
     a.A2 = __builtin_fma(p2, RQR, a.A2);
     a.A3 = __builtin_fma(p3, ORRR, a.A3);
     const double mp1 = mB * p1, k2 = 3.0 * p2, k3 = 7.5 * p3;
-    const double c = __builtin_fma(k3, RQR, mp1);
+    const double mp1w = DIP ? __builtin_fma(k2, dw, mp1) : mp1;
+    const double c = __builtin_fma(k3, RQR, mp1w);
     a.L1[0] = __builtin_fma(-k2, QRx, __builtin_fma(c, Rx, a.L1[0]));
     a.L1[1] = __builtin_fma(-k2, QRy, __builtin_fma(c, Ry, a.L1[1]));
     a.L1[2] = __builtin_fma(-k2, QRz, __builtin_fma(c, Rz, a.L1[2]));
+    if (DIP) {
+        a.L1[0] = __builtin_fma(-p1, dx, a.L1[0]);
+        a.L1[1] = __builtin_fma(-p1, dy, a.L1[1]);
+        a.L1[2] = __builtin_fma(-p1, dz, a.L1[2]);
+    }
     if (!LEAF_TARGET) {
-        a.s1 -= mp1;
+        a.s1 -= mp1w;
         const double m2 = mB * k2;
-        a.L2[0] = __builtin_fma(m2, xx, a.L2[0]);
-        a.L2[1] = __builtin_fma(m2, xy, a.L2[1]);
-        a.L2[2] = __builtin_fma(m2, xz, a.L2[2]);
-        a.L2[3] = __builtin_fma(m2, yy, a.L2[3]);
-        a.L2[4] = __builtin_fma(m2, yz, a.L2[4]);
-        a.L2[5] = __builtin_fma(m2, zz, a.L2[5]);
+        const double e2 = DIP ? __builtin_fma(2.0 * k3, dw, m2) : m2;
+        a.L2[0] = __builtin_fma(e2, xx, a.L2[0]);
+        a.L2[1] = __builtin_fma(e2, xy, a.L2[1]);
+        a.L2[2] = __builtin_fma(e2, xz, a.L2[2]);
+        a.L2[3] = __builtin_fma(e2, yy, a.L2[3]);
+        a.L2[4] = __builtin_fma(e2, yz, a.L2[4]);
+        a.L2[5] = __builtin_fma(e2, zz, a.L2[5]);
+        if (DIP) {
+            const double fx = k2 * dx, fy = k2 * dy, fz = k2 * dz;
+            a.L2[0] = __builtin_fma(-2.0 * fx, Rx, a.L2[0]);
+            a.L2[1] = __builtin_fma(-fx, Ry, __builtin_fma(-fy, Rx, a.L2[1]));
+            a.L2[2] = __builtin_fma(-fx, Rz, __builtin_fma(-fz, Rx, a.L2[2]));
+            a.L2[3] = __builtin_fma(-2.0 * fy, Ry, a.L2[3]);
+            a.L2[4] = __builtin_fma(-fy, Rz, __builtin_fma(-fz, Ry, a.L2[4]));
+            a.L2[5] = __builtin_fma(-2.0 * fz, Rz, a.L2[5]);
+        }
         a.U[0] = __builtin_fma(m2, Rx, a.U[0]);
         a.U[1] = __builtin_fma(m2, Ry, a.U[1]);
         a.U[2] = __builtin_fma(m2, Rz, a.U[2]);
@@ -477,7 +511,7 @@ __device__ inline void m2l_pair_f64(double Rx, double Ry, double Rz, double mB, 
         a.L3[8] = __builtin_fma(m3z, yz, a.L3[8]);
         a.L3[9] = __builtin_fma(m3z, zz, a.L3[9]);
     }
-    if (amc) {
+    if (!DIP && amc) {
         // n:RR = O'_B:RR - mu O'_A:RR; a leaf target is a point mass at its
         // cell centre (no third moment), so there n:RR = O'_B:RR
         double nx = ORx, ny = ORy, nz = ORz, nR = ORRR;
@@ -496,142 +530,13 @@ __device__ inline void m2l_pair_f64(double Rx, double Ry, double Rz, double mB, 
     }
 }
 
-// T = double: everything in FP64.  T = float (mixed precision): the L0..L3
-// contractions run in FP32 with FP32 partial sums; R, the radial factors and
-// the correction stay FP64.  The source's second and third moments come
-// trace-free (q5, o7 packing); with D^(k) = f_k-chain tensors of R:
-//   L0 -= m f0 + (1/2) f2 R.Q'.R - (1/6) f3 O'.RRR
-//   L1_a -= (m f1 + (1/2) f3 R.Q'.R) R_a + f2 (Q'R)_a
-// (the trace terms f1 tr Q, f2 tr O vanish).
-// DIP: the source also has a dipole d (second source expanded about the
-// density's centres): L0 += d.D1, L1_a += d_b D2_ab, L2_ab += d_c D3_abc,
-// i.e. with w = d.R: L0 += f1 w; L1_a += f2 w R_a + f1 d_a;
-// L2_ab += f3 w R_a R_b + f2 (w d_ab + R_a d_b + R_b d_a).
-// Correction (FP64): n = O'_B - mu O'_A is trace-free, so n : D4 reduces to
-// f4 (n:RR . R) R + 3 f3 (n:RR), with n:RR = O'_B:RR - mu O'_A:RR.
+// The pair routine of the multipole kernels: FP64 in both precisions (the
+// mixed mode's single precision is the near field's).
 template <bool LEAF_TARGET, bool DIP, typename T>
-__device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB64, const double *q64, const double *o64,
-                                const double *D64, double mu, const double *oA, bool amc, Acc<T> &a) {
-    if constexpr (kF64Fast<DIP, T>) {
-        m2l_pair_f64<LEAF_TARGET>(Rx, Ry, Rz, mB64, q64, o64, mu, oA, amc, a);
-        return;
-    }
-    const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
-    // 1/|R|: the hardware estimate, then the second-order correction
-    // (1 - e)^(-1/2) ~ 1 + e/2 + 3e^2/8 with e = 1 - r2 y0^2 (r2 is positive
-    // and normal: distinct cells)
-    const double y0 = __builtin_amdgcn_rsq(r2);
-    const double e0 = __builtin_fma(-r2, y0 * y0, 1.0);
-    const double d0 = __builtin_fma(y0 * e0, __builtin_fma(e0, 0.375, 0.5), y0);
-    const double ir2 = d0 * d0;
-    const double d1 = -d0 * ir2;
-    const double d2 = -3.0 * d1 * ir2;
-    const double d3 = -5.0 * d2 * ir2;
-    T ORx, ORy, ORz, ORRR;  // O'_B : RR and O'_B : RRR in T
-    {
-        const T rx = (T)Rx, ry = (T)Ry, rz = (T)Rz;
-        const T f0 = (T)d0, f1 = (T)d1, f2 = (T)d2, f3 = (T)d3;
-        const T mB = (T)mB64;
-        T q[5], o[7];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) q[k] = (T)q64[k];
-#pragma unroll
-        for (int k = 0; k < 7; ++k) o[k] = (T)o64[k];
-        const T half = (T)0.5, sixth = (T)(1.0 / 6.0), two = (T)2.0;
-        // quadrupole contractions
-        const T qzz = -(q[0] + q[3]);
-        const T QRx = q[0] * rx + q[1] * ry + q[2] * rz;
-        const T QRy = q[1] * rx + q[3] * ry + q[4] * rz;
-        const T QRz = q[2] * rx + q[4] * ry + qzz * rz;
-        const T RQR = rx * QRx + ry * QRy + rz * QRz;
-        // octupole contractions
-        const T xx = rx * rx, yy = ry * ry, zz = rz * rz, xy = rx * ry, xz = rx * rz, yz = ry * rz;
-        const T e = xx - zz, f = yy - zz, u = two * xy, v = two * xz, w2 = two * yz;
-        o7_rr(o, e, f, u, v, w2, ORx, ORy, ORz);
-        ORRR = rx * ORx + ry * ORy + rz * ORz;
-        T dx = 0, dy = 0, dz = 0, w = 0;
-        if (DIP) {
-            dx = (T)D64[0];
-            dy = (T)D64[1];
-            dz = (T)D64[2];
-            w = dx * rx + dy * ry + dz * rz;
-        }
-        const T m0 = DIP ? mB * f0 - f1 * w : mB * f0;
-        a.L0 -= m0 + half * f2 * RQR - sixth * f3 * ORRR;
-        const T c1 = (DIP ? mB * f1 - f2 * w : mB * f1) + half * f3 * RQR;
-        if (DIP) {
-            a.L1[0] -= c1 * rx + f2 * QRx - f1 * dx;
-            a.L1[1] -= c1 * ry + f2 * QRy - f1 * dy;
-            a.L1[2] -= c1 * rz + f2 * QRz - f1 * dz;
-        } else {
-            a.L1[0] -= c1 * rx + f2 * QRx;
-            a.L1[1] -= c1 * ry + f2 * QRy;
-            a.L1[2] -= c1 * rz + f2 * QRz;
-        }
-        if (!LEAF_TARGET) {
-            // L2_ab = -m (f2 R_a R_b + f1 d_ab): raw sums T2 (in L2) and s1
-            // (dipole: T2 += -w f3 R_a R_b - f2 (R_a d_b + R_b d_a), s1 += -w f2)
-            const T m2 = mB * f2;
-            const T e2 = DIP ? m2 - w * f3 : m2;
-            a.s1 += DIP ? mB * f1 - w * f2 : mB * f1;
-            a.L2[0] += e2 * xx;
-            a.L2[1] += e2 * xy;
-            a.L2[2] += e2 * xz;
-            a.L2[3] += e2 * yy;
-            a.L2[4] += e2 * yz;
-            a.L2[5] += e2 * zz;
-            if (DIP) {
-                const T fx = f2 * dx, fy = f2 * dy, fz = f2 * dz;
-                a.L2[0] -= two * fx * rx;
-                a.L2[1] -= fx * ry + fy * rx;
-                a.L2[2] -= fx * rz + fz * rx;
-                a.L2[3] -= two * fy * ry;
-                a.L2[4] -= fy * rz + fz * ry;
-                a.L2[5] -= two * fz * rz;
-            }
-            // L3_abc = -m (f3 R_a R_b R_c + f2 (d_ab R_c + d_ac R_b + d_bc R_a)):
-            // raw sums T3 (in L3) and U = sum m f2 R
-            const T m3 = mB * f3;
-            const T m3x = m3 * rx, m3y = m3 * ry, m3z = m3 * rz;
-            a.U[0] += m2 * rx;
-            a.U[1] += m2 * ry;
-            a.U[2] += m2 * rz;
-            a.L3[0] += m3x * xx;
-            a.L3[1] += m3x * xy;
-            a.L3[2] += m3x * xz;
-            a.L3[3] += m3x * yy;
-            a.L3[4] += m3x * yz;
-            a.L3[5] += m3x * zz;
-            a.L3[6] += m3y * yy;
-            a.L3[7] += m3y * yz;
-            a.L3[8] += m3z * yz;
-            a.L3[9] += m3z * zz;
-        }
-    }
-    if (!DIP && amc) {
-        const double xx = Rx * Rx, yy = Ry * Ry, zz = Rz * Rz;
-        const double e = xx - zz, f = yy - zz, u = 2.0 * (Rx * Ry), v = 2.0 * (Rx * Rz), w = 2.0 * (Ry * Rz);
-        double bx, by, bz, bR;  // O'_B : RR, O'_B : RRR in FP64
-        if constexpr (sizeof(T) == sizeof(double)) {
-            bx = (double)ORx;
-            by = (double)ORy;
-            bz = (double)ORz;
-            bR = (double)ORRR;
-        } else {
-            o7_rr(o64, e, f, u, v, w, bx, by, bz);
-            bR = bx * Rx + by * Ry + bz * Rz;
-        }
-        double ax, ay, az;
-        o7_rr(oA, e, f, u, v, w, ax, ay, az);
-        const double vx = bx - mu * ax, vy = by - mu * ay, vz = bz - mu * az;
-        const double sv = bR - mu * (ax * Rx + ay * Ry + az * Rz);
-        const double d4 = -7.0 * d3 * ir2;
-        const double cR = d4 * sv, c3 = 3.0 * d3;
-        constexpr double k6 = 1.0 / 6.0;
-        a.C[0] -= k6 * (cR * Rx + c3 * vx);
-        a.C[1] -= k6 * (cR * Ry + c3 * vy);
-        a.C[2] -= k6 * (cR * Rz + c3 * vz);
-    }
+__device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB, const double *q, const double *o,
+                                const double *D, double mu, const double *oA, bool amc, Acc<T> &a) {
+    static_assert(sizeof(T) == sizeof(double), "the multipole work runs in FP64");
+    m2l_pair_f64<LEAF_TARGET, DIP>(Rx, Ry, Rz, mB, q, o, D, mu, oA, amc, a);
 }
 
 template <bool LEAF_TARGET, bool DIP, typename T>
