@@ -306,11 +306,14 @@ void build_tree_plan(octo_tree *t) {
     ph.p2m.clear();
     ph.interior.assign(nl, {});
     ph.l2l.assign(nl, {});
-    // interior nodes without an interior child: their leaves finish their expansions
+    // interior nodes without an interior child: their leaves finish their
+    // expansions, where the level has at most 4 partial slots (each leaf sums
+    // them one after the other; levels with more keep the wide slot sum and
+    // the L2L pass)
     std::vector<std::vector<char>> defer(nl);
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
-        defer[l].assign(h.n_int, 1);
+        defer[l].assign(h.n_int, t->parts[l] <= 4 ? 1 : 0);
         for (int n = 0; n < h.n_int; ++n)
             for (int k = 0; k < 8; ++k)
                 if (h.child[8 * n + k] < L.lv[l + 1].n_int) defer[l][n] = 0;
