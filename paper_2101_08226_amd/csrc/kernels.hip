@@ -52,6 +52,15 @@ __device__ inline void unpack(int32_t off, int &dx, int &dy, int &dz) {
     dz = (int)(int8_t)((off >> 16) & 255);
 }
 
+// a pointer into device memory as a global-address-space pointer: its loads
+// are global loads, which count only against the vector-memory counter
+template <typename T>
+using GPtr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ inline GPtr<T> gptr(T *p) {
+    return (GPtr<T>)p;
+}
+
 __device__ inline int nbr_slot(int sx, int sy, int sz) {
     return ((sx >> 3) + 1) * 9 + ((sy >> 3) + 1) * 3 + ((sz >> 3) + 1);
 }
@@ -746,22 +755,32 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     // together) are issued as soon as this wavefront has finished the
     // previous class, so that they overlap the other wavefronts' remaining
     // pairs and the barrier; the LDS stores follow the barrier.
+    // (The neighbour lookups of both cells come before their loads, and the
+    // loads go through the global address space: a generic (flat) load also
+    // counts as an LDS access, so the second lookup's wait would otherwise
+    // wait for the first cell's loads.)
     double v[2][23];
+    const GPtr<const double> gmass = gptr(ld.mass), gmp = gptr(ld.mp), gdip = gptr(ld.dip);
     auto load_class = [&](int q) {
         const int qx = q >> 2, qy = (q >> 1) & 1, qz = q & 1;
+        int nb[2], si[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int cc = tid + 512 * u;
             const int ix = cc / 81, iy = (cc / 9) % 9, iz = cc % 9;
             const int sx = 2 * ix - 4 - qx, sy = 2 * iy - 4 - qy, sz = 2 * iz - 4 - qz;
-            const int nb = cc < 729 ? s_nbr[nbr_slot(sx, sy, sz)] : -1;
-            if (nb >= 0 && nb < n_src) {
-                const size_t si = (size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7);
-                v[u][0] = ld.mass[si];
+            nb[u] = cc < 729 ? s_nbr[nbr_slot(sx, sy, sz)] : -1;
+            si[u] = store_idx(sx & 7, sy & 7, sz & 7);
+        }
 #pragma unroll
-                for (int k = 0; k < kRec; ++k) v[u][1 + k] = ld.mp[k * S + si];
+        for (int u = 0; u < 2; ++u) {
+            if (nb[u] >= 0 && nb[u] < n_src) {
+                const size_t si_ = (size_t)nb[u] * kCells + si[u];
+                v[u][0] = gmass[si_];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) v[u][20 + k] = DIP ? ld.dip[k * S + si] : 0.0;
+                for (int k = 0; k < kRec; ++k) v[u][1 + k] = gmp[k * S + si_];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) v[u][20 + k] = DIP ? gdip[k * S + si_] : 0.0;
             } else {
                 v[u][0] = -0.0;
                 v[u][1] = v[u][2] = v[u][3] = 1.0e3;
@@ -1092,26 +1111,28 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
     }
     __syncthreads();
     if (ld.level > 0) {
-        // all 12 loads of this thread in flight before any store
-        constexpr int NH = 18 * 18 * 18, NU = (NH + 511) / 512;
+        // all 12 loads of this thread in flight before any store; the cell
+        // indices come from the staging table (the same for every
+        // work-group), not from per-thread integer arithmetic.  The neighbour
+        // lookups (LDS) all come first and the mass loads go through the
+        // global address space: a generic (flat) load also counts as an LDS
+        // access, so each LDS wait would otherwise wait for the loads issued
+        // before it and the 12 loads would run one after the other.
+        constexpr int NU = kNearStage / 512;
+        const GPtr<const int32_t> stage = gptr(st.near_stage);
+        const GPtr<const double> mass = gptr(ld.mass);
+        int e[NU], nb[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) e[u] = stage[u * 512 + tid];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) nb[u] = e[u] >= 0 ? s_nbr[e[u] & 31] : -1;
         T v[NU];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            const int c = tid + 512 * u;
-            const int sx = c / 324 - 5, sy = (c / 18) % 18 - 5, sz = c % 18 - 5;
-            const int nb = c < NH ? s_nbr[nbr_slot(sx, sy, sz)] : -1;
-            v[u] = nb >= ld.n_int ? (T)ld.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)]
-                                  : (T)(COUNT ? -1 : 0);
-        }
+        for (int u = 0; u < NU; ++u)
+            v[u] = nb[u] >= ld.n_int ? (T)mass[(size_t)nb[u] * kCells + ((e[u] >> 5) & 511)] : (T)(COUNT ? -1 : 0);
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            const int c = tid + 512 * u;
-            if (c < NH) {
-                const int ux = c / 324, uy = (c / 18) % 18, uz = c % 18;
-                const int q = ((ux & 1) << 2) | ((uy & 1) << 1) | (uz & 1);
-                s_m[q * kNearQ + (ux >> 1) * kNearX + (uy >> 1) * kNearY + (uz >> 1)] = v[u];
-            }
-        }
+        for (int u = 0; u < NU; ++u)
+            if (e[u] >= 0) s_m[e[u] >> 14] = v[u];
     }
     __syncthreads();
     const int s = tid;  // parity-major storage: wavefront p holds class p

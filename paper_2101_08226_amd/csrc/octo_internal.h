@@ -48,6 +48,13 @@ constexpr int kHaloY = 12, kHaloX = 9 * kHaloY, kHaloN = 9 * kHaloX;
 // + iz; rows and planes padded so that the lanes of a wavefront, one parity
 // class of targets, read distinct LDS banks), class q at q * kNearQ
 constexpr int kNearY = 12, kNearX = 112, kNearQ = 9 * kNearX, kNearN = 8 * kNearQ;
+// staging of that halo by the 512 threads of a near-field work-group: entry
+// u * 512 + t (u < 12) names the halo cell c = u * 512 + t (ux = c / 324,
+// uy = (c / 18) % 18, uz = c % 18, local coordinate u - 5) as
+// slot | store << 5 | dest << 14: the neighbour slot of the sub-grid holding
+// it, its storage index there and its index in the parity-split halo; -1
+// past the 18^3 cells
+constexpr int kNearStage = 12 * 512;
 // near-field weights by |d| pattern: index (|dx| * 6 + |dy|) * 6 + |dz|
 constexpr int kNearTab = 216;
 
@@ -121,6 +128,7 @@ struct StencilDev {
     const int32_t *leaf_widx;
     const double *leaf_tab;   // kNearTab x 4: 1/|d|, |dx|/|d|^3, |dy|/|d|^3, |dz|/|d|^3
     const float *leaf_tab32;  // the same weights rounded to FP32 (mixed precision)
+    const int32_t *near_stage;  // kNearStage staging entries of the near-field halo
     const int32_t *m2l_src;  // m2l entries regrouped by source parity class, as halo offsets: the entry
                              // (dx,dy,dz) of target class p reads halo index (x>>1, y>>1, z>>1) + offset
     int32_t m2l_beg[9];

@@ -492,6 +492,21 @@ Stencil make_stencil(double theta) {
         s.m2l_src_beg[p * 9 + 8] = (int)s.m2l_src.size();
     }
     s.m2l_src_beg[72] = (int)s.m2l_src.size();
+    // staging table of the near-field halo (independent of theta): which
+    // neighbour sub-grid and storage index (parity-major: class << 6 | the
+    // 4x4x4 lattice index) each thread loads, and where it goes in the halo
+    s.near_stage.assign(kNearStage, -1);
+    for (int c = 0; c < 18 * 18 * 18; ++c) {
+        const int ux = c / 324, uy = (c / 18) % 18, uz = c % 18;
+        const int sx = ux - 5, sy = uy - 5, sz = uz - 5;
+        const int slot = ((sx >> 3) + 1) * 9 + ((sy >> 3) + 1) * 3 + ((sz >> 3) + 1);
+        const int ax = sx & 7, ay = sy & 7, az = sz & 7;
+        const int store = ((((ax & 1) << 2) | ((ay & 1) << 1) | (az & 1)) << 6) | ((ax >> 1) << 4) | ((ay >> 1) << 2) |
+                          (az >> 1);
+        const int q = ((ux & 1) << 2) | ((uy & 1) << 1) | (uz & 1);
+        const int dest = q * kNearQ + (ux >> 1) * kNearX + (uy >> 1) * kNearY + (uz >> 1);
+        s.near_stage[c] = slot | store << 5 | dest << 14;
+    }
     return s;
 }
 
