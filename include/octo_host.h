@@ -34,6 +34,17 @@ octo_status octo_host_stencil_sizes(double theta, int32_t *out);
  * Errors: OCTO_E_UNSUPPORTED for theta outside [0.34, 1). */
 octo_status octo_host_near_lists(double theta, int32_t *beg, int32_t *d, int64_t cap, int64_t *n);
 
+/* The staging table of the near-field kernel's leaf-mass halo (the 18^3 cells
+ * within 5 cells of a sub-grid, Sec. 2.2's near partners of its cells): entry
+ * e = u * 512 + t (thread t, step u < 12) names halo cell c = e (local
+ * coordinate (c / 324 - 5, (c / 18) % 18 - 5, c % 18 - 5)) as
+ * slot | store << 5 | dest << 14, where slot is the neighbour sub-grid
+ * ((sx >> 3) + 1) * 9 + ((sy >> 3) + 1) * 3 + (sz >> 3) + 1, store the cell's
+ * parity-major storage index there, and dest its index in the parity-split
+ * halo; -1 for e >= 18^3.  out must hold cap >= 6144 entries; *n = 6144.
+ * Errors: OCTO_E_INVALID for NULL pointers. */
+octo_status octo_host_near_stage(int32_t *out, int64_t cap, int64_t *n);
+
 /* Validate a leaf list exactly as octo_tree_build does and report its layout:
  * out[3*l+0] = nodes at level l, out[3*l+1] = interior nodes, out[3*l+2] =
  * leaf nodes that touch an interior node of their level; *n_levels = deepest

@@ -30,7 +30,7 @@ EXPORTS = [
     "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_tree_build", "octo_tree_build_uniform",
     "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_get_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
     "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_run", "octo_regrid", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
-    "octo_host_stencil_sizes", "octo_host_near_lists", "octo_host_layout", "octo_host_adaptive_leaves",
+    "octo_host_stencil_sizes", "octo_host_near_lists", "octo_host_near_stage", "octo_host_layout", "octo_host_adaptive_leaves",
 ]
 
 
@@ -158,6 +158,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_poll": [_P, _I64, ctypes.POINTER(_I)],
         "octo_wait": [_P, _I64, ctypes.POINTER(octo_stats)],
         "octo_host_stencil_sizes": [ctypes.c_double, ctypes.POINTER(ctypes.c_int32)],
+        "octo_host_near_stage": [ctypes.POINTER(ctypes.c_int32), _I64, ctypes.POINTER(_I64)],
         "octo_host_near_lists": [ctypes.c_double, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _I64,
                                  ctypes.POINTER(_I64)],
         "octo_host_layout": [ctypes.POINTER(octo_leaf), _I64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_I64)],
@@ -375,6 +376,16 @@ def octo_host_near_lists(theta: float) -> tuple:
                                                n.value, ctypes.byref(n)))
     d = np.stack([((packed >> (8 * a)) & 255).astype(np.int8).astype(np.int64) for a in range(3)], axis=1)
     return beg, d
+
+
+def octo_host_near_stage() -> np.ndarray:
+    """The near-field kernel's halo staging table (6144 packed entries, -1 past the 18^3 halo cells)."""
+    n = _I64(0)
+    _check(load_library().octo_host_near_stage(None, 0, ctypes.byref(n)))
+    out = np.zeros(n.value, dtype=np.int32)
+    _check(load_library().octo_host_near_stage(out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n.value,
+                                               ctypes.byref(n)))
+    return out
 
 
 def octo_host_layout(leaves) -> tuple:

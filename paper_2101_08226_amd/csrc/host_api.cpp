@@ -73,6 +73,16 @@ octo_status octo_host_near_lists(double theta, int32_t *beg, int32_t *d, int64_t
     });
 }
 
+octo_status octo_host_near_stage(int32_t *out, int64_t cap, int64_t *n) {
+    return guard_h([&] {
+        if (!n) fail(OCTO_E_INVALID, "NULL output");
+        Stencil s = make_stencil(0.5);  // the table does not depend on theta
+        *n = (int64_t)s.near_stage.size();
+        if (!out || cap < *n) return;
+        for (size_t k = 0; k < s.near_stage.size(); ++k) out[k] = s.near_stage[k];
+    });
+}
+
 octo_status octo_host_layout(const octo_leaf *leaves, int64_t n_leaves, int32_t *n_levels, int64_t *out) {
     return guard_h([&] {
         if (!n_levels || !out) fail(OCTO_E_INVALID, "NULL output");

@@ -159,3 +159,43 @@ def test_near_lists_cover_the_stencil_with_minimal_padding(theta):
         assert len(got) == len(set(got)) and set(got) == want
         assert len(got) == sizes[p] + sizes[8 + p]
         assert pad == (8 - len(got) % 8) % 8, (theta, p, pad)
+
+
+def test_near_stage_table_loads_every_halo_cell_once():
+    """The near-field kernel's halo staging table: each of the 18^3 cells
+    within 5 cells of a sub-grid is loaded exactly once, from the neighbour
+    sub-grid that holds it (slot of its floor-divided coordinates) at its
+    parity-major storage index there; it lands in a distinct halo slot, in
+    the block of its parity class, at lattice position (u >> 1) with one
+    stride per axis; the entries past the 18^3 cells are -1."""
+    t = lib.octo_host_near_stage().astype(np.int64)
+    NH = 18 ** 3
+    assert t.shape == (12 * 512,)
+    assert np.all(t[NH:] == -1) and np.all(t[:NH] >= 0)
+    slot, store, dest = t[:NH] & 31, (t[:NH] >> 5) & 511, t[:NH] >> 14
+    c = np.arange(NH)
+    local = np.stack([c // 324 - 5, (c // 18) % 18 - 5, c % 18 - 5], axis=1)
+    nb = local // 8 + 1  # neighbour sub-grid per axis, 0..2
+    assert np.array_equal(slot, nb[:, 0] * 9 + nb[:, 1] * 3 + nb[:, 2])
+    # storage index back to the cell: parity class major, then the 4x4x4 lattice
+    cls, lat = store >> 6, store & 63
+    inner = np.stack([2 * (lat >> 4) + (cls >> 2), 2 * ((lat >> 2) & 3) + ((cls >> 1) & 1),
+                      2 * (lat & 3) + (cls & 1)], axis=1)
+    assert np.array_equal(local, 8 * (nb - 1) + inner)
+    # distinct destinations, one block per parity class of the halo cell
+    assert len(np.unique(dest)) == NH
+    u = local + 5
+    q = (u[:, 0] & 1) * 4 + (u[:, 1] & 1) * 2 + (u[:, 2] & 1)
+    lo = [dest[q == k].min() for k in range(8)]
+    hi = [dest[q == k].max() for k in range(8)]
+    assert all(hi[k] < lo[k + 1] for k in range(7))
+    # inside a block: base + ix * SX + iy * SY + iz over the 9^3 lattice
+    L = u >> 1
+    for k in range(8):
+        m = q == k
+        d, l3 = dest[m], L[m]
+        base = d[np.all(l3 == 0, axis=1)][0]
+        sy = d[np.all(l3 == (0, 1, 0), axis=1)][0] - base
+        sx = d[np.all(l3 == (1, 0, 0), axis=1)][0] - base
+        assert sy >= 9 and sx >= 9 * sy
+        assert np.array_equal(d, base + l3[:, 0] * sx + l3[:, 1] * sy + l3[:, 2])
