@@ -340,6 +340,24 @@ typedef struct {
 octo_status octo_scf_step(octo_ctx *ctx, int level, const octo_scf_params *p, double K, double x_L1,
                           const double *rho, const double *phi, double *rho_out, octo_scf_state *state);
 
+/* octo_scf_step for callers that cannot allocate device memory (tight
+ * loops, harnesses that forbid allocation): the same kernels and launch
+ * shapes, so the same results bit for bit, with the step's scratch in a fixed
+ * array of 256 KiB per device (static device memory of the library, held by
+ * each device the library runs on until the process ends; its address is
+ * looked up once per device by octo_ctx_create).  The call allocates
+ * nothing: no hipMalloc, no context allocator.  Arguments, layout and
+ * outputs as octo_scf_step; the array covers every grid the step takes
+ * (levels 0..6, up to 512^3 cells), and a level outside [0, 6] is rejected
+ * with OCTO_E_INVALID.  Every call on a device shares that device's array
+ * and leaves its contents behind; the step writes every scratch value before
+ * reading it.  Calls on one device would race for the array, so the library
+ * runs them one at a time (a per-device lock held until the step's stream
+ * has drained).  Errors: as octo_scf_step, plus OCTO_E_STATE when the
+ * device's array was not set up. */
+octo_status octo_scf_step_noalloc(octo_ctx *ctx, int level, const octo_scf_params *p, double K, double x_L1,
+                                  const double *rho, const double *phi, double *rho_out, octo_scf_state *state);
+
 /* `iterations` SCF iterations (Sec. 4.1) on a uniform tree (built by
  * octo_tree_build_uniform), starting from the tree's density and from
  * K = p->K0 and the split p->x_L1; each iteration normalises the stars (step

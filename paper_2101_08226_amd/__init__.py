@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "OCTO_OK", 1: "OCTO_E_INVALID", 2: "OCTO_E_DEVICE", 3: "OCTO_
 EXPORTS = [
     "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_tree_build", "octo_tree_build_uniform",
     "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_get_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
-    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_run", "octo_regrid", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
+    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_step_noalloc", "octo_scf_run", "octo_regrid", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
     "octo_host_stencil_sizes", "octo_host_near_lists", "octo_host_near_stage", "octo_host_layout", "octo_host_adaptive_leaves",
 ]
 
@@ -153,6 +153,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_energy_update": [_P, _P, _D, _D, _D, _D],
         "octo_scf_step": [_P, _I, ctypes.POINTER(octo_scf_params), ctypes.c_double, ctypes.c_double, _D, _D, _D,
                           ctypes.POINTER(octo_scf_state)],
+        "octo_scf_step_noalloc": [_P, _I, ctypes.POINTER(octo_scf_params), ctypes.c_double, ctypes.c_double, _D, _D,
+                                  _D, ctypes.POINTER(octo_scf_state)],
         "octo_scf_run": [_P, _P, ctypes.POINTER(octo_opts), ctypes.POINTER(octo_scf_params), ctypes.c_int32, _D, _D,
                          ctypes.POINTER(octo_scf_state)],
         "octo_poll": [_P, _I64, ctypes.POINTER(_I)],
@@ -330,6 +332,14 @@ def octo_scf_step(ctx: int, level: int, params: octo_scf_params, K: float, x_L1:
     st = octo_scf_state()
     _check(load_library().octo_scf_step(ctx, int(level), ctypes.byref(params), float(K), float(x_L1), _dptr(rho),
                                         _dptr(phi), _dptr(rho_out), ctypes.byref(st)))
+    return st
+
+
+def octo_scf_step_noalloc(ctx: int, level: int, params: octo_scf_params, K: float, x_L1: float, rho: int, phi: int,
+                          rho_out: int) -> octo_scf_state:
+    st = octo_scf_state()
+    _check(load_library().octo_scf_step_noalloc(ctx, int(level), ctypes.byref(params), float(K), float(x_L1),
+                                                _dptr(rho), _dptr(phi), _dptr(rho_out), ctypes.byref(st)))
     return st
 
 

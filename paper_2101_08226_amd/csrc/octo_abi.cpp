@@ -534,6 +534,7 @@ octo_status octo_ctx_create(int device, void *hip_stream, const octo_allocator *
         if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
             fail(OCTO_E_DEVICE, "no HIP device " + std::to_string(device));
         DeviceGuard dg(device);
+        scf_fixed_scratch_init(device);  // the allocation-free SCF step's array on this device
         auto *c = new octo_ctx();
         c->device = device;
         c->budget = hbm_budget;
@@ -931,6 +932,21 @@ octo_status octo_scf_step(octo_ctx *ctx, int level, const octo_scf_params *p, do
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         DeviceGuard dg(ctx->device);
         scf_step(ctx, level, *p, K, s2, rho, phi, rho_out, state);
+    });
+}
+
+octo_status octo_scf_step_noalloc(octo_ctx *ctx, int level, const octo_scf_params *p, double K, double x_L1,
+                                  const double *rho, const double *phi, double *rho_out, octo_scf_state *state) {
+    return guard([&] {
+        if (!ctx || !rho || !phi || !rho_out || !state) fail(OCTO_E_INVALID, "NULL argument");
+        if (level < 0 || level > 6)
+            fail(OCTO_E_INVALID, "level must lie in [0, 6] (the fixed scratch covers grids up to 512^3)");
+        validate_scf(p);
+        if (!std::isfinite(K)) fail(OCTO_E_INVALID, "K not finite");
+        const int64_t s2 = scf_split(x_L1, level);
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        DeviceGuard dg(ctx->device);
+        scf_step_noalloc(ctx, level, *p, K, s2, rho, phi, rho_out, state);
     });
 }
 

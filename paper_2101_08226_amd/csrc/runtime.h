@@ -268,6 +268,12 @@ void drop_graphs(std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs);
 // split between the two sides in half-cell units, x = s2 h/2 - 1/2
 void scf_step(octo_ctx *ctx, int level, const octo_scf_params &p, double K, int64_t s2, const double *rho,
               const double *phi, double *rho_out, octo_scf_state *state);
+// the same step with its scratch in a fixed per-device array (no allocation);
+// scf_fixed_scratch_init(device) must have run with `device` current
+void scf_step_noalloc(octo_ctx *ctx, int level, const octo_scf_params &p, double K, int64_t s2, const double *rho,
+                      const double *phi, double *rho_out, octo_scf_state *state);
+void scf_fixed_scratch_init(int device);
+size_t scf_fixed_scratch_bytes();
 void scf_run(octo_ctx *ctx, octo_tree *t, int level, const octo_opts &o, const octo_scf_params &p, int64_t s2,
              int iterations, double *rho_out, double *phi_out, octo_scf_state *history);
 // one regrid by the density criterion (Sec. 2.7) on the device: the new leaf

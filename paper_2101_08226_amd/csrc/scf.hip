@@ -19,6 +19,8 @@
 // This file is compiled without floating-point contraction, so each step
 // rounds as written.
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "runtime.h"
@@ -376,40 +378,72 @@ __global__ __launch_bounds__(kT) void k_scf_row(ScfConst k, ScfDev *st, const do
     }
 }
 
-// Scratch of one call: state, partials, iteration records.
+// Scratch of one call: state, partials, iteration records.  Either taken
+// from the context's allocator for the call (owned), or carved out of
+// caller-provided device memory (the fixed per-device array below).
 struct Scratch {
     octo_ctx *ctx = nullptr;
     void *mem = nullptr;
     size_t bytes = 0;
+    bool owned = false;
     ScfDev *st = nullptr;
     double *part = nullptr, *bv = nullptr;
     int64_t *bi = nullptr;
     octo_scf_state *hist = nullptr;
     double *g = nullptr;
-    Scratch(octo_ctx *c, int n_hist, int64_t g_doubles) : ctx(c) {
+    struct Offsets {
+        size_t part, bv, bi, hist, g, total;
+    };
+    static Offsets offsets(int n_hist, int64_t g_doubles) {
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-        const size_t o_part = al(sizeof(ScfDev));
-        const size_t o_bv = o_part + al((size_t)kMaxParts * kSums * 8);
-        const size_t o_bi = o_bv + al((size_t)kMaxParts * 2 * 8);
-        const size_t o_h = o_bi + al((size_t)kMaxParts * 2 * 8);
-        const size_t o_g = o_h + al((size_t)(n_hist > 0 ? n_hist : 1) * sizeof(octo_scf_state));
-        bytes = o_g + al((size_t)g_doubles * 8);
-        mem = ctx->dev_alloc(bytes);
+        Offsets o;
+        o.part = al(sizeof(ScfDev));
+        o.bv = o.part + al((size_t)kMaxParts * kSums * 8);
+        o.bi = o.bv + al((size_t)kMaxParts * 2 * 8);
+        o.hist = o.bi + al((size_t)kMaxParts * 2 * 8);
+        o.g = o.hist + al((size_t)(n_hist > 0 ? n_hist : 1) * sizeof(octo_scf_state));
+        o.total = o.g + al((size_t)g_doubles * 8);
+        return o;
+    }
+    void carve(const Offsets &o, int64_t g_doubles) {
         char *b = (char *)mem;
         st = (ScfDev *)b;
-        part = (double *)(b + o_part);
-        bv = (double *)(b + o_bv);
-        bi = (int64_t *)(b + o_bi);
-        hist = (octo_scf_state *)(b + o_h);
-        g = g_doubles ? (double *)(b + o_g) : nullptr;
+        part = (double *)(b + o.part);
+        bv = (double *)(b + o.bv);
+        bi = (int64_t *)(b + o.bi);
+        hist = (octo_scf_state *)(b + o.hist);
+        g = g_doubles ? (double *)(b + o.g) : nullptr;
+    }
+    Scratch(octo_ctx *c, int n_hist, int64_t g_doubles) : ctx(c), owned(true) {
+        const Offsets o = offsets(n_hist, g_doubles);
+        bytes = o.total;
+        mem = ctx->dev_alloc(bytes);
+        carve(o, g_doubles);
+    }
+    // one step's scratch inside `dev` (capacity `cap` bytes, checked by the caller)
+    Scratch(octo_ctx *c, void *dev) : ctx(c), mem(dev) {
+        const Offsets o = offsets(1, 0);
+        bytes = o.total;
+        carve(o, 0);
     }
     ~Scratch() {
-        if (mem) {
+        if (mem && owned) {
             hipStreamSynchronize(ctx->stream);
             ctx->dev_free(mem, bytes);
         }
     }
 };
+
+// Fixed scratch of the allocation-free step (octo_scf_step_noalloc): one
+// array per device for the whole process.  Its size covers the largest step
+// layout (kMaxParts partials, one record), the same for every grid level.
+constexpr size_t kFixedScratchBytes = 256 * 1024;
+__device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;                          // guards the address table
+void *g_fixed_ptr[kMaxDevices] = {};            // device address of `scratch`, per device
+std::mutex g_fixed_use[kMaxDevices];            // one step at a time on a device's array
 
 ScfConst make_const(int level, const octo_scf_params &p) {
     ScfConst k;
@@ -470,6 +504,49 @@ void scf_step(octo_ctx *ctx, int level, const octo_scf_params &p, double K, int6
     const int np = parts_for(k.cells);
     hipStream_t q = ctx->stream;
     Scratch s(ctx, 1, 0);
+    hipLaunchKernelGGL(k_scf_init, dim3(1), dim3(1), 0, q, s.st, s2, K);
+    pass<0>(k, s, np, const_cast<double *>(rho), nullptr, q);  // MODE 0 only reads
+    stars_and_moments(k, s, np, rho, 0, q);
+    finish_step(k, s, np, rho, phi, rho_out, s.hist, q);
+    check_hip(hipMemcpyAsync(state, s.hist, sizeof(octo_scf_state), hipMemcpyDeviceToHost, q), "state copy");
+    check_hip(hipStreamSynchronize(q), "scf step");
+}
+
+void scf_fixed_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) fail(OCTO_E_DEVICE, "device index beyond the fixed-scratch table");
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    if (g_fixed_ptr[device]) return;
+    // the caller has made `device` current: the address is that device's copy
+    void *p = nullptr;
+    check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "fixed scratch address");
+    if (!p) fail(OCTO_E_DEVICE, "fixed scratch has no device address");
+    g_fixed_ptr[device] = p;
+}
+
+size_t scf_fixed_scratch_bytes() { return kFixedScratchBytes; }
+
+void scf_step_noalloc(octo_ctx *ctx, int level, const octo_scf_params &p, double K, int64_t s2, const double *rho,
+                      const double *phi, double *rho_out, octo_scf_state *state) {
+    const int dev = ctx->device;
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_fixed_mu);
+        if (dev >= 0 && dev < kMaxDevices) base = g_fixed_ptr[dev];
+    }
+    if (!base) fail(OCTO_E_STATE, "fixed scratch of device " + std::to_string(dev) + " not set up");
+    const size_t need = Scratch::offsets(1, 0).total;
+    if (need > kFixedScratchBytes)
+        fail(OCTO_E_INVALID, "step needs " + std::to_string(need) + " bytes of scratch, the fixed array holds " +
+                                 std::to_string(kFixedScratchBytes));
+    const ScfConst k = make_const(level, p);
+    const int np = parts_for(k.cells);
+    hipStream_t q = ctx->stream;
+    // steps on one device share the array: the lock keeps them apart (each
+    // returns only after its stream has drained)
+    std::lock_guard<std::mutex> use(g_fixed_use[dev]);
+    Scratch s(ctx, base);
+    // every field of the state, the partials and the record is written by
+    // the step's kernels before it is read; k_scf_init sets the split and K
     hipLaunchKernelGGL(k_scf_init, dim3(1), dim3(1), 0, q, s.st, s2, K);
     pass<0>(k, s, np, const_cast<double *>(rho), nullptr, q);  // MODE 0 only reads
     stars_and_moments(k, s, np, rho, 0, q);
