@@ -48,6 +48,8 @@ def lib():
         L.orc_solve_source.restype = ctypes.c_int
         L.orc_solve_source.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _D, _D, _I64,
                                        ctypes.c_int64, ctypes.c_int, _D]
+        L.orc_tree_set_centres.restype = ctypes.c_int
+        L.orc_tree_set_centres.argtypes = [_P, ctypes.c_int]
         L.orc_cell_moments.restype = ctypes.c_int
         L.orc_cell_moments.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D]
         L.orc_leaf_cells.argtypes = [_P, _D, _D]
@@ -105,6 +107,17 @@ class Tree:
     @property
     def n_levels(self) -> int:
         return lib().orc_tree_nlev(self._h)
+
+    CENTRES = {"mass": 0, "geometric": 1, "geometric-no-dipole": 2}
+
+    def set_centres(self, mode: str) -> None:
+        """Expansion centres of interior cells for later solves: "mass"
+        (centre of mass, the default reading of Sec. 2.2), "geometric" (the
+        geometric centre, dipole carried) or "geometric-no-dipole" (geometric
+        centre, dipole dropped).  The last two serve the study of the
+        static-sphere residuals (Sec. 3.4) only."""
+        if lib().orc_tree_set_centres(self._h, self.CENTRES[mode]) != 0:
+            raise ValueError(mode)
 
     def solve(self, theta=0.5, G=1.0, amc=True, kernel=None, sample=None, threads=0):
         """phi (n,) and g (3, n) at every leaf cell, or at the sampled leaf-cell

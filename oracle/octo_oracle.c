@@ -88,6 +88,9 @@ typedef struct {
     int nleaves;
     int *leaf_node;
     ocount last; /* interaction counts of the last solve (marked targets only) */
+    int centres; /* expansion centres of interior cells: 0 centre of mass (the
+                    default); 1 geometric centre, dipole kept; 2 geometric
+                    centre, dipole dropped (see orc_tree_set_centres) */
     char err[256];
 } otree;
 
@@ -479,7 +482,7 @@ static void m2m(otree *t, cref a) {
         for (int d = 0; d < 3; ++d) mz[d] += cc[k]->m * cc[k]->z[d];
     }
     double z[3];
-    if (m > 0.0) {
+    if (m > 0.0 && t->centres == 0) {
         for (int d = 0; d < 3; ++d) z[d] = mz[d] / m;
     } else {
         int g[3];
@@ -488,7 +491,7 @@ static void m2m(otree *t, cref a) {
     }
     compose(cc, z, p);
     for (int d = 0; d < 3; ++d) p->z[d] = z[d];
-    memset(p->M1, 0, sizeof p->M1);
+    if (t->centres != 1) memset(p->M1, 0, sizeof p->M1);
 }
 
 /* Second source (a density rate): leaf cells are point sources s h^3 at
@@ -810,6 +813,22 @@ static int solve_impl(otree *t, const oparams *pp, const double *src, const int6
     for (int l = 0; l < OMAXLEV; ++l) free(lev[l]);
     free(lev);
     free(cnt);
+    return 0;
+}
+
+/* Expansion centres of interior cells for later solves of the density.
+ * The paper says multipoles and expansions are taken relative to cell
+ * centres (Sec. 2.2); the default reading is the centre of mass (mode 0),
+ * about which the dipole vanishes and the correction cancels the pair torque
+ * exactly.  Mode 1 expands about geometric centres and carries the dipole
+ * through every shift and interaction (a complete expansion about another
+ * point); mode 2 expands about geometric centres and drops the dipole, as an
+ * implementation that assumes it vanishes would.  Used only to study the
+ * static-sphere residuals of Sec. 3.4; the correction is not exact for modes
+ * 1 and 2.  Returns 0, or 1 for an unknown mode. */
+int orc_tree_set_centres(otree *t, int mode) {
+    if (!t || mode < 0 || mode > 2) return 1;
+    t->centres = mode;
     return 0;
 }
 

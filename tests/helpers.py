@@ -105,3 +105,17 @@ def fft_poisson(level: int, G: float = 1.0):
         return -G * np.fft.irfftn(np.fft.rfftn(pad) * gh, s=(m, m, m), axes=(0, 1, 2))[:n, :n, :n]
 
     return solve
+
+
+def zero_block_density(seed: int) -> np.ndarray:
+    """A 32^3 uniform grid (levels 0-2) with massless regions (reading R11):
+    the 4^3 leaf cells under three root cells (one at the domain corner, two
+    inside), so each such root cell and its eight level-1 cells have no mass,
+    and one 2^3 block under a massive root cell (a massless level-1 cell);
+    uniform random density elsewhere."""
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.1, 1.0, (32, 32, 32))
+    for a, b, c in ((0, 0, 0), (12, 16, 8), (16, 12, 20)):
+        rho[a:a + 4, b:b + 4, c:c + 4] = 0.0
+    rho[6:8, 6:8, 26:28] = 0.0
+    return rho
