@@ -80,6 +80,10 @@ enum { OCTO_FP64 = 0, OCTO_MIXED = 1 };
  *   dx/|x_A - x_B| < theta on geometric centres (Sec. 2.2), evaluated as
  *   (theta*theta)*|i_A - i_B|^2 > 1 on integer cell indices in IEEE double.
  *   Must lie in [0.34, 1): 0.34 is the paper's minimum for 8^3 sub-grids.
+ *   Above 1/sqrt(3) cells that touch at a corner are well separated, and
+ *   their expansions can reach masses next to the shared corner, outside the
+ *   region where they converge: results near concentrated mass then lose all
+ *   accuracy (the paper runs 0.5 and 0.34).
  * G: gravitational constant (1 in code units, Sec. 2.8).
  * precision: OCTO_FP64 computes everything in double precision;
  *   OCTO_MIXED evaluates the leaf near-field sums in single precision with
@@ -207,6 +211,16 @@ octo_status octo_tree_destroy(octo_tree *tree);
 octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, double *phi, double *g,
                        int out_on_device, octo_stats *stats);
 
+/* octo_solve with its net force and torque reductions left in device
+ * memory, for time loops that keep the diagnostics on the device: phi and g
+ * as octo_solve with out_on_device != 0; stats_dev (device, 9 doubles)
+ * receives total_mass, net_force[3], net_torque[3], force_scale and
+ * torque_scale of octo_stats, stream-ordered on the context stream (the call
+ * returns once the work is enqueued; no pair counting, no host copy).
+ * Errors: as octo_solve. */
+octo_status octo_solve_device_stats(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, double *phi, double *g,
+                                    double *stats_dev);
+
 /* Autotune the tree's multipole work shape for these options: for every level
  * with interior nodes, time the multipole-interaction phase with each
  * candidate (LDS-staged work-groups per node and group of source parity
@@ -224,9 +238,18 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
  * trees together (the phases are captured once into a HIP graph per batch
  * signature and replayed).  phi[i], g[i] as in octo_solve for trees[i];
  * stats: NULL or n entries.  Results are identical, bit for bit, to solving
- * each tree alone. */
+ * each tree alone.
+ * status: NULL or n entries, each tree's own outcome: OCTO_OK (solved),
+ * OCTO_E_INVALID (NULL tree or output, or a tree listed twice: the second
+ * entry), OCTO_E_STATE (tree from another context); a failure of the call as
+ * a whole (bad options, a device error) is written for every tree that was
+ * to be solved.  Trees refused on their own are skipped and the others are
+ * solved together; the return value is then the first refused tree's status
+ * (OCTO_OK when every tree was solved), and stats entries of refused trees
+ * are left untouched. */
 octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, const octo_opts *opts,
-                             double *const *phi, double *const *g, int out_on_device, octo_stats *stats);
+                             double *const *phi, double *const *g, int out_on_device, octo_stats *stats,
+                             octo_status *status);
 
 /* ---- time derivative of the potential ----------------------------------- */
 
@@ -442,6 +465,10 @@ octo_status octo_poll(octo_ctx *ctx, octo_ticket ticket, int *done);
 octo_status octo_wait(octo_ctx *ctx, octo_ticket ticket, octo_stats *stats);
 
 const char *octo_last_error(void);
+/* Identifier of the sources the library was built from (a hash of the
+ * headers and the library sources, fixed at build time); bindings compare it
+ * with the sources they were written against before calling anything else. */
+const char *octo_build_id(void);
 
 #ifdef __cplusplus
 }

@@ -76,9 +76,19 @@ def _centres(level: int):
     return X, Y, Z, h
 
 
+# Tie rule of every maximum: the smallest flat index among the cells holding
+# the largest value.  Tests may switch it to the largest index among the cells
+# within TIE_RTOL of the largest value, to measure how much a result depends
+# on which of several cells that tie up to rounding is taken.
+TIE_LAST = False
+TIE_RTOL = 0.0
+
+
 def _argmax(values: np.ndarray, mask: np.ndarray) -> int:
     """Flat index of the largest value where mask holds; ties to the smallest index."""
     v = np.where(mask, values, -np.inf).ravel()
+    if TIE_LAST:
+        return int(np.flatnonzero(v >= v.max() - TIE_RTOL * abs(v.max()))[-1])
     return int(np.flatnonzero(v == v.max())[0])
 
 

@@ -29,8 +29,8 @@ STATUS_NAMES = {0: "OCTO_OK", 1: "OCTO_E_INVALID", 2: "OCTO_E_DEVICE", 3: "OCTO_
 EXPORTS = [
     "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_tree_build", "octo_tree_build_uniform",
     "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_get_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
-    "octo_solve", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_step_noalloc", "octo_scf_run", "octo_regrid", "octo_submit", "octo_poll", "octo_wait", "octo_last_error",
-    "octo_host_stencil_sizes", "octo_host_near_lists", "octo_host_near_stage", "octo_host_layout", "octo_host_adaptive_leaves",
+    "octo_solve", "octo_solve_device_stats", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_step_noalloc", "octo_scf_run", "octo_regrid", "octo_submit", "octo_poll", "octo_wait", "octo_last_error", "octo_build_id",
+    "octo_host_stencil_sizes", "octo_host_near_lists", "octo_host_near_stage", "octo_host_near_mm", "octo_host_layout", "octo_host_adaptive_leaves",
 ]
 
 
@@ -144,9 +144,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_tree_leaves": [_P, ctypes.POINTER(octo_leaf)],
         "octo_tree_destroy": [_P],
         "octo_solve": [_P, _P, ctypes.POINTER(octo_opts), _D, _D, _I, ctypes.POINTER(octo_stats)],
+        "octo_solve_device_stats": [_P, _P, ctypes.POINTER(octo_opts), _D, _D, _D],
         "octo_tree_autotune": [_P, _P, ctypes.POINTER(octo_opts), ctypes.POINTER(ctypes.c_int32)],
         "octo_solve_batch": [_P, _PP, ctypes.c_int32, ctypes.POINTER(octo_opts), ctypes.POINTER(_D),
-                             ctypes.POINTER(_D), _I, ctypes.POINTER(octo_stats)],
+                             ctypes.POINTER(_D), _I, ctypes.POINTER(octo_stats), ctypes.POINTER(ctypes.c_int)],
         "octo_submit": [_P, _P, ctypes.POINTER(octo_opts), _D, _D, ctypes.POINTER(_I64)],
         "octo_solve_dphidt": [_P, _P, ctypes.POINTER(octo_opts), _D, _D],
         "octo_gravity_sources": [_P, _P, _D, _D, _D, _D, _D, _D, _D, _D, _D],
@@ -161,6 +162,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_wait": [_P, _I64, ctypes.POINTER(octo_stats)],
         "octo_host_stencil_sizes": [ctypes.c_double, ctypes.POINTER(ctypes.c_int32)],
         "octo_host_near_stage": [ctypes.POINTER(ctypes.c_int32), _I64, ctypes.POINTER(_I64)],
+        "octo_host_near_mm": [ctypes.c_double, _D, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_int32)],
         "octo_host_near_lists": [ctypes.c_double, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _I64,
                                  ctypes.POINTER(_I64)],
         "octo_host_layout": [ctypes.POINTER(octo_leaf), _I64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_I64)],
@@ -173,6 +176,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         f.restype = ctypes.c_int
     L.octo_last_error.argtypes = []
     L.octo_last_error.restype = ctypes.c_char_p
+    L.octo_build_id.argtypes = []
+    L.octo_build_id.restype = ctypes.c_char_p
+    from .build import source_id
+
+    built, want = L.octo_build_id().decode(), source_id()
+    if built != want:
+        raise RuntimeError(f"{path} was built from other sources (build id {built}, sources {want}): rebuild it "
+                           "with `python -m paper_2101_08226_amd.build` or __graft_entry__.build()")
     _lib = L
     return L
 
@@ -301,15 +312,27 @@ def octo_tree_autotune(ctx: int, tree: int, opts: octo_opts) -> list:
 
 
 def octo_solve_batch(ctx: int, trees: Sequence[int], opts: octo_opts, phi_ptrs: Sequence[int],
-                     g_ptrs: Sequence[int], out_on_device: bool, want_stats: bool = True):
+                     g_ptrs: Sequence[int], out_on_device: bool, want_stats: bool = True, status_out=None):
+    """Solve the trees together; raises on any refused tree unless
+    `status_out` (a list) is given, which then receives every tree's status."""
     n = len(trees)
-    tr = (ctypes.c_void_p * n)(*trees)
+    tr = (ctypes.c_void_p * n)(*[t or None for t in trees])
     ph = (_D * n)(*[_dptr(p) for p in phi_ptrs])
     gg = (_D * n)(*[_dptr(p) for p in g_ptrs])
     st = (octo_stats * n)()
-    _check(load_library().octo_solve_batch(ctx, tr, n, ctypes.byref(opts), ph, gg, int(out_on_device),
-                                           st if want_stats else None))
+    ss = (ctypes.c_int * n)()
+    rc = load_library().octo_solve_batch(ctx, tr, n, ctypes.byref(opts), ph, gg, int(out_on_device),
+                                         st if want_stats else None, ss)
+    if status_out is not None:
+        status_out[:] = list(ss)
+    else:
+        _check(rc)
     return list(st) if want_stats else None
+
+
+def octo_solve_device_stats(ctx: int, tree: int, opts: octo_opts, phi_ptr: int, g_ptr: int, stats_ptr: int) -> None:
+    _check(load_library().octo_solve_device_stats(ctx, tree, ctypes.byref(opts), _dptr(phi_ptr), _dptr(g_ptr),
+                                                  _dptr(stats_ptr)))
 
 
 def octo_solve_dphidt(ctx: int, tree: int, opts: octo_opts, drho_dt: int, dphi_dt: int) -> None:
@@ -367,6 +390,23 @@ def octo_wait(ctx: int, ticket: int) -> octo_stats:
     st = octo_stats()
     _check(load_library().octo_wait(ctx, ticket, ctypes.byref(st)))
     return st
+
+
+MM_STEPS = 17  # reduction steps of 4 per wavefront of the matrix-core near field
+
+
+def octo_host_near_mm(theta: float):
+    """Tables of the matrix-core near field (include/octo_host.h): FP64 and
+    FP32 matrix values, halo offsets, and the partners per block (0: the VALU
+    kernel runs)."""
+    a = np.zeros(4 * MM_STEPS * 2 * 64)
+    a32 = np.zeros(4 * MM_STEPS * 2 * 64, dtype=np.float32)
+    off = np.zeros(4 * MM_STEPS * 64, dtype=np.int32)
+    k = ctypes.c_int32()
+    _check(load_library().octo_host_near_mm(float(theta), a.ctypes.data_as(_D),
+                                            a32.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                            off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(k)))
+    return a, a32, off, k.value
 
 
 def octo_host_stencil_sizes(theta: float) -> np.ndarray:

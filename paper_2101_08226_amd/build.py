@@ -1,4 +1,5 @@
 """Build the HIP library (liboctofmm.so) in-tree for gfx950 with hipcc."""
+import hashlib
 import os
 import subprocess
 import sys
@@ -23,9 +24,24 @@ FLAGS = [
 ]
 
 
+def source_id() -> str:
+    """Hash of every source the library is built from (the headers under
+    include/ and the files under csrc/): the build id compiled into the
+    library, which the binding checks before it calls anything."""
+    h = hashlib.sha256()
+    files = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))]
+    files += [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))]
+    for f in files:
+        if os.path.isfile(f):
+            h.update(os.path.relpath(f, ROOT).encode())
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src):
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", "-x", "hip", *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", out]
+    cmd = ["hipcc", "-x", "hip", *FLAGS, *EXTRA.get(src, []), f'-DOCTO_BUILD_ID="{source_id()}"', "-c",
+           os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -29,7 +29,7 @@ void drop_graphs(std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs) {
 }
 
 void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs,
-              const std::vector<TreeDesc> &want, const octo_opts *o, bool count, bool source) {
+              const std::vector<TreeDesc> &want, const octo_opts *o, bool count, bool source, bool reduce) {
     // tree descriptors (outputs, G, correction switch) live in device memory
     // and are refreshed only when they change
     for (int i = 0; i < plan.n_trees; ++i) {
@@ -43,6 +43,7 @@ void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipG
     LaunchOpts lo;
     lo.precision = o->precision;
     lo.count = count;
+    lo.reduce = reduce;
     lo.source = source;
     lo.amc = o->amc != 0;
     lo.fork = ctx->fork_ev;
@@ -63,9 +64,8 @@ void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipG
     }
     lo.aux = ctx->capture_aux;
     lo.aux_near = ctx->capture_near;
-    const auto key =
-        std::make_pair(theta_bits(o->theta),
-                       (int)o->precision * 8 + (o->amc ? 4 : 0) + (source ? 2 : 0) + (count ? 1 : 0));
+    const auto key = std::make_pair(theta_bits(o->theta), (int)o->precision * 16 + (o->amc ? 8 : 0) +
+                                                               (reduce ? 4 : 0) + (source ? 2 : 0) + (count ? 1 : 0));
     auto it = graphs.find(key);
     if (it == graphs.end()) {
         hipGraph_t g = nullptr;
@@ -276,9 +276,26 @@ static void retire_waves(octo_ctx *ctx) {
     }
 }
 
+static void make_lanes(octo_ctx *ctx) {
+    if (!ctx->lanes.empty()) return;
+    ctx->lanes.resize(ctx->max_inflight_waves);
+    for (Lane &l : ctx->lanes) {
+        for (hipStream_t *q : {&l.s, &l.aux, &l.aux_near})
+            check_hip(hipStreamCreateWithFlags(q, hipStreamNonBlocking), "lane stream");
+        for (hipEvent_t *e : {&l.start, &l.fork, &l.join, &l.fork_near, &l.join_near})
+            check_hip(hipEventCreateWithFlags(e, hipEventDisableTiming), "lane event");
+    }
+}
+
 // Launch waves while fewer than max_inflight_waves are on the device: each
 // wave takes the pending requests with the first request's (theta,
-// precision, correction switch), at most one request per tree.
+// precision, correction switch), at most one request per tree, as many as
+// its work plan fits the context's HBM budget (halving the wave until it
+// does); a request whose plan does not fit even alone, with no wave in
+// flight to free memory, fails on its own ticket (OCTO_E_BUDGET).  Each wave
+// runs on a lane of its own: after the work already on the context stream
+// and the last use of each of its trees (a tree may still be in the other
+// lane's wave).
 static void pump(octo_ctx *ctx) {
     retire_waves(ctx);
     while (!ctx->pending.empty() && (int)ctx->waves.size() < ctx->max_inflight_waves) {
@@ -288,55 +305,86 @@ static void pump(octo_ctx *ctx) {
         const bool amc = first.opts.amc != 0;
         std::vector<octo_ticket> take;
         std::set<octo_tree *> used;
-        std::deque<octo_ticket> rest;
         for (octo_ticket t : ctx->pending) {
             Request &r = ctx->requests.at(t);
             if (r.opts.theta == theta && r.opts.precision == prec && (r.opts.amc != 0) == amc &&
                 !used.count(r.tree)) {
                 used.insert(r.tree);
                 take.push_back(t);
-            } else {
-                rest.push_back(t);
             }
         }
+        std::unique_ptr<BatchPlan> bp;
         std::vector<octo_tree *> trees;
-        std::vector<TreeDesc> descs;
-        for (octo_ticket t : take) {
-            Request &r = ctx->requests.at(t);
-            trees.push_back(r.tree);
-            descs.push_back(desc_for(r.tree, r.phi, r.g, &r.opts));
-        }
-        auto bp = make_batch(trees.data(), (int)trees.size(), descs);
         std::vector<char> img;
-        const size_t bytes = plan_layout(bp->ph, nullptr, bp->plan, img);
         void *mem = nullptr;
-        try {
-            mem = ctx->dev_alloc(bytes);
-        } catch (const Error &) {
-            if (ctx->waves.empty()) throw;  // nothing will free memory
-            return;                         // retry when a wave retires
+        size_t bytes = 0;
+        while (!mem) {
+            trees.clear();
+            std::vector<TreeDesc> descs;
+            for (octo_ticket t : take) {
+                Request &r = ctx->requests.at(t);
+                trees.push_back(r.tree);
+                descs.push_back(desc_for(r.tree, r.phi, r.g, &r.opts));
+            }
+            bp = make_batch(trees.data(), (int)trees.size(), descs);
+            bytes = plan_layout(bp->ph, nullptr, bp->plan, img);
+            try {
+                mem = ctx->dev_alloc(bytes);
+            } catch (const Error &e) {
+                if (e.code != OCTO_E_BUDGET) throw;
+                if (!ctx->waves.empty()) return;  // retry when a wave retires
+                if (take.size() > 1) {
+                    take.resize(take.size() / 2);
+                    continue;
+                }
+                Request &r = ctx->requests.at(take[0]);
+                r.status = OCTO_E_BUDGET;
+                r.err = "the request's work plan (" + std::to_string(bytes) +
+                        " bytes) does not fit the HBM budget with nothing else in flight";
+                r.done = true;
+                ctx->pending.erase(std::find(ctx->pending.begin(), ctx->pending.end(), take[0]));
+                break;
+            }
         }
+        if (!mem) continue;  // the head request failed; try the next
+        std::set<octo_ticket> taken(take.begin(), take.end());
+        std::deque<octo_ticket> rest;
+        for (octo_ticket t : ctx->pending)
+            if (!taken.count(t)) rest.push_back(t);
+        make_lanes(ctx);
+        int lane = 0;
+        for (; lane < (int)ctx->lanes.size(); ++lane) {
+            bool busy = false;
+            for (auto &kv : ctx->waves) busy = busy || kv.second.lane == lane;
+            if (!busy) break;
+        }
+        Lane &L = ctx->lanes.at(lane);
         bp->mem = mem;
         bp->bytes = bytes;
         plan_layout(bp->ph, mem, bp->plan, img);
+        const StencilDevHolder &st = ctx->stencil(theta);
+        check_hip(hipEventRecord(L.start, ctx->stream), "event");
+        check_hip(hipStreamWaitEvent(L.s, L.start, 0), "lane wait");
+        for (octo_tree *t : trees)
+            if (t->last_stream != L.s) check_hip(hipStreamWaitEvent(L.s, t->last_use, 0), "lane wait");
         bp->staging = ctx->pinned_get(img.size(), &bp->staging_bytes);
         memcpy(bp->staging, img.data(), img.size());
-        check_hip(hipMemcpyAsync(mem, bp->staging, img.size(), hipMemcpyHostToDevice, ctx->stream), "wave upload");
-        const StencilDevHolder &st = ctx->stencil(theta);
+        check_hip(hipMemcpyAsync(mem, bp->staging, img.size(), hipMemcpyHostToDevice, L.s), "wave upload");
         LaunchOpts lo;
         lo.precision = prec;
         lo.amc = amc;
-        lo.aux = ctx->aux;
-        lo.fork = ctx->fork_ev;
-        lo.join = ctx->join_ev;
-        lo.aux_near = ctx->aux_near;
-        lo.fork_near = ctx->fork_near_ev;
-        lo.join_near = ctx->join_near_ev;
-        launch_solve(bp->plan, st.dev, lo, ctx->stream);
+        lo.aux = L.aux;
+        lo.fork = L.fork;
+        lo.join = L.join;
+        lo.aux_near = L.aux_near;
+        lo.fork_near = L.fork_near;
+        lo.join_near = L.join_near;
+        launch_solve(bp->plan, st.dev, lo, L.s);
         Wave w;
+        w.lane = lane;
         check_hip(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "event");
-        check_hip(hipEventRecord(w.done, ctx->stream), "event");
-        for (octo_tree *t : trees) check_hip(hipEventRecord(t->last_use, ctx->stream), "event");
+        check_hip(hipEventRecord(w.done, L.s), "event");
+        for (octo_tree *t : trees) tree_release(t, L.s);
         w.tickets = take;
         w.bp = std::move(bp);
         const int id = ctx->next_wave++;
@@ -350,21 +398,57 @@ static void pump(octo_ctx *ctx) {
     }
 }
 
-extern "C" {
-
-octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, const octo_opts *opts,
-                             double *const *phi, double *const *g, int out_on_device, octo_stats *stats) {
-    return guard_b([&] {
-        if (!ctx || !trees || n <= 0 || !phi || !g) fail(OCTO_E_INVALID, "bad batch arguments");
+// The trees of a batch that pass the per-tree checks are solved together;
+// the others get their own status and are left alone.
+static octo_status solve_batch_impl(octo_ctx *ctx, octo_tree *const *trees_in, int32_t n_in, const octo_opts *opts,
+                                    double *const *phi_in, double *const *g_in, int out_on_device,
+                                    octo_stats *stats_in, octo_status *status) {
+    std::vector<int> idx;  // positions of the trees that are solved
+    std::string first_msg;
+    octo_status first = OCTO_OK;
+    bool decided = false;  // per-tree statuses written
+    const octo_status s = guard_b([&] {
+        if (!ctx || !trees_in || n_in <= 0 || !phi_in || !g_in) fail(OCTO_E_INVALID, "bad batch arguments");
         validate(opts);
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
 
         std::set<octo_tree *> seen;
-        for (int i = 0; i < n; ++i) {
-            if (!trees[i] || !phi[i] || !g[i]) fail(OCTO_E_INVALID, "NULL tree or output in batch");
-            if (trees[i]->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
-            if (!seen.insert(trees[i]).second) fail(OCTO_E_INVALID, "a tree appears twice in one batch");
+        for (int i = 0; i < n_in; ++i) {
+            octo_status si = OCTO_OK;
+            const char *why = nullptr;
+            if (!trees_in[i] || !phi_in[i] || !g_in[i]) {
+                si = OCTO_E_INVALID;
+                why = "NULL tree or output in batch";
+            } else if (trees_in[i]->ctx != ctx) {
+                si = OCTO_E_STATE;
+                why = "tree belongs to another context";
+            } else if (!seen.insert(trees_in[i]).second) {
+                si = OCTO_E_INVALID;
+                why = "a tree appears twice in one batch";
+            }
+            if (status) status[i] = si;
+            if (si == OCTO_OK) {
+                idx.push_back(i);
+            } else if (first == OCTO_OK) {
+                first = si;
+                first_msg = std::string(why) + " (batch entry " + std::to_string(i) + ")";
+            }
         }
+        decided = true;
+        if (idx.empty()) fail(first, first_msg);
+        const int n = (int)idx.size();
+        std::vector<octo_tree *> trees_v(n);
+        std::vector<double *> phi_v(n), g_v(n);
+        std::vector<octo_stats> st_v(stats_in ? n : 0);
+        for (int k = 0; k < n; ++k) {
+            trees_v[k] = trees_in[idx[k]];
+            phi_v[k] = phi_in[idx[k]];
+            g_v[k] = g_in[idx[k]];
+        }
+        octo_tree *const *trees = trees_v.data();
+        double *const *phi = phi_v.data();
+        double *const *g = g_v.data();
+        octo_stats *stats = stats_in ? st_v.data() : nullptr;
         hipSetDevice(ctx->device);
         std::vector<octo_tree *> sig(trees, trees + n);
         if (!ctx->batch || ctx->batch->sig != sig) {
@@ -379,6 +463,7 @@ octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, 
             ctx->batch = std::move(bp);
         }
         BatchPlan &bp = *ctx->batch;
+        for (int i = 0; i < n; ++i) tree_acquire(ctx, trees[i]);
         std::vector<TreeDesc> want;
         for (int i = 0; i < n; ++i) {
             octo_tree *t = trees[i];
@@ -388,7 +473,7 @@ octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, 
         if (stats) check_hip(hipEventRecord(ctx->ev0, ctx->stream), "event");
         const bool count = stats != nullptr && ctx->profiling != 2;  // timing-only profiling: no counts
         run_plan(ctx, bp.plan, bp.graphs, want, opts, count);
-        for (int i = 0; i < n; ++i) check_hip(hipEventRecord(trees[i]->last_use, ctx->stream), "event");
+        for (int i = 0; i < n; ++i) tree_release(trees[i], ctx->stream);
         if (stats) {
             check_hip(hipEventRecord(ctx->ev1, ctx->stream), "event");
             if ((size_t)n * 12 > ctx->h_stats_cap) fail(OCTO_E_INVALID, "batch too large for statistics");
@@ -416,8 +501,31 @@ octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, 
                     stats[i].device_ms = ms;
                 }
             }
+            for (int k = 0; k < n; ++k) stats_in[idx[k]] = stats[k];
         }
     });
+    if (s != OCTO_OK) {
+        // a failure of the whole call (arguments, options, device) is every
+        // tree's that was to be solved; trees refused on their own keep
+        // their status
+        if (status && n_in > 0) {
+            if (!decided)
+                for (int i = 0; i < n_in; ++i) status[i] = s;
+            else
+                for (int k : idx) status[k] = s;
+        }
+        return s;
+    }
+    if (first != OCTO_OK) octo::set_error(first_msg);
+    return first;
+}
+
+extern "C" {
+
+octo_status octo_solve_batch(octo_ctx *ctx, octo_tree *const *trees, int32_t n, const octo_opts *opts,
+                             double *const *phi, double *const *g, int out_on_device, octo_stats *stats,
+                             octo_status *status) {
+    return solve_batch_impl(ctx, trees, n, opts, phi, g, out_on_device, stats, status);
 }
 
 octo_status octo_submit(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, double *phi_dev, double *g_dev,
@@ -456,8 +564,10 @@ octo_status octo_poll(octo_ctx *ctx, octo_ticket ticket, int *done) {
         if (it == ctx->requests.end()) fail(OCTO_E_INVALID, "unknown ticket");
         hipSetDevice(ctx->device);
         pump(ctx);
-        *done = ctx->requests.at(ticket).done ? 1 : 0;
+        const Request &r = ctx->requests.at(ticket);
+        *done = r.done ? 1 : 0;
         if (!*done) fail(OCTO_E_PENDING, "pending");
+        if (r.status != OCTO_OK) fail(r.status, r.err);
     });
 }
 
@@ -481,6 +591,12 @@ octo_status octo_wait(octo_ctx *ctx, octo_ticket ticket, octo_stats *stats) {
             }
         }
         Request &r = ctx->requests.at(ticket);
+        if (r.status != OCTO_OK) {
+            const octo_status code = r.status;
+            const std::string msg = r.err;
+            ctx->requests.erase(ticket);
+            fail(code, msg);
+        }
         if (stats) fill(r.stats, r.tree->layout.n_leaf_cells, 0.0, stats);
         ctx->requests.erase(ticket);
     });

@@ -483,7 +483,8 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_tab.size() * 8) +
                al(w32.size() * 4) + al(S.m2l_src.size() * 4) + al(S.leaf_off.size() * 4) +
                al(S.leaf_widx.size() * 4) + al(S.m2l_touch.size() * 4) + al(S.near_touch.size() * 4) +
-               al(S.m2l_src_touch.size() * 4) + al(S.near_stage.size() * 4);
+               al(S.m2l_src_touch.size() * 4) + al(S.near_stage.size() * 4) + al(S.mm_a.size() * 8) +
+               al(S.mm_a32.size() * 4) + al(S.mm_off.size() * 4);
     void *mem = nullptr;
     check_hip(hipMalloc(&mem, b), "stencil alloc");
     h->block.ptr = mem;
@@ -508,6 +509,10 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     h->dev.leaf_widx = (const int32_t *)put(S.leaf_widx.data(), S.leaf_widx.size() * 4);
     h->dev.m2l_src_touch = (const int32_t *)put(S.m2l_src_touch.data(), S.m2l_src_touch.size() * 4);
     h->dev.near_stage = (const int32_t *)put(S.near_stage.data(), S.near_stage.size() * 4);
+    h->dev.mm_a = (const double *)put(S.mm_a.data(), S.mm_a.size() * 8);
+    h->dev.mm_a32 = (const float *)put(S.mm_a32.data(), S.mm_a32.size() * 4);
+    h->dev.mm_off = (const int32_t *)put(S.mm_off.data(), S.mm_off.size() * 4);
+    h->dev.mm_k = S.mm_k;
     for (int k = 0; k < 64; ++k) h->dev.m2l_src_any[k] = S.m2l_src_any[k];
     for (int k = 0; k < 73; ++k) h->dev.leaf_oct_beg[k] = S.leaf_oct_beg[k];
     for (int k = 0; k < 73; ++k) h->dev.m2l_src_beg[k] = S.m2l_src_beg[k];
@@ -525,6 +530,8 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
 extern "C" {
 
 const char *octo_last_error(void) { return g_err.c_str(); }
+
+const char *octo_build_id(void) { return OCTO_BUILD_ID; }
 
 octo_status octo_ctx_create(int device, void *hip_stream, const octo_allocator *alloc, size_t hbm_budget,
                             octo_ctx **out) {
@@ -583,6 +590,14 @@ octo_status octo_ctx_destroy(octo_ctx *ctx) {
         hipStreamDestroy(ctx->capture_aux);
         hipStreamSynchronize(ctx->aux);
         hipStreamDestroy(ctx->aux);
+        for (Lane &l : ctx->lanes) {
+            for (hipStream_t q : {l.s, l.aux, l.aux_near}) {
+                hipStreamSynchronize(q);
+                hipStreamDestroy(q);
+            }
+            for (hipEvent_t e : {l.start, l.fork, l.join, l.fork_near, l.join_near}) hipEventDestroy(e);
+        }
+        ctx->lanes.clear();
         hipEventDestroy(ctx->fork_ev);
         hipEventDestroy(ctx->join_ev);
         hipStreamSynchronize(ctx->aux_near);
@@ -659,7 +674,7 @@ static octo_status make_tree(octo_ctx *ctx, const octo_leaf *leaves, int64_t n, 
             throw;
         }
         check_hip(hipEventCreateWithFlags(&t->last_use, hipEventDisableTiming), "event");
-        check_hip(hipEventRecord(t->last_use, ctx->stream), "event");
+        tree_release(t.get(), ctx->stream);
         ctx->n_trees++;
         *out = t.release();
     });
@@ -723,10 +738,11 @@ octo_status octo_tree_set_density(octo_tree *t, const double *rho, int rho_on_de
         if (!rho_on_device) check_density_host(rho, t->layout.n_leaf_cells);
         std::lock_guard<std::recursive_mutex> lk(t->ctx->mu);
         DeviceGuard dg(t->ctx->device);
+        tree_acquire(t->ctx, t);
         check_hip(hipMemcpyAsync(t->rho, rho, (size_t)t->layout.n_leaf_cells * 8,
                                  rho_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, t->ctx->stream),
                   "density upload");
-        check_hip(hipEventRecord(t->last_use, t->ctx->stream), "event");
+        tree_release(t, t->ctx->stream);
         if (!rho_on_device) check_hip(hipStreamSynchronize(t->ctx->stream), "density upload");
     });
 }
@@ -736,6 +752,7 @@ octo_status octo_tree_get_density(const octo_tree *t, double *rho, int rho_on_de
         if (!t || !rho) fail(OCTO_E_INVALID, "NULL argument");
         std::lock_guard<std::recursive_mutex> lk(t->ctx->mu);
         DeviceGuard dg(t->ctx->device);
+        tree_acquire(t->ctx, const_cast<octo_tree *>(t));
         check_hip(hipMemcpyAsync(rho, t->rho, (size_t)t->layout.n_leaf_cells * 8,
                                  rho_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, t->ctx->stream),
                   "density copy");
@@ -793,6 +810,7 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
 
         DeviceGuard dg(ctx->device);
+        tree_acquire(ctx, tree);
         const int64_t n = tree->layout.n_leaf_cells;
         std::vector<TreeDesc> want = tree->plan.trees_host;
         want[0].phi = out_on_device ? phi : tree->stage;
@@ -803,7 +821,7 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
         // timing-only profiling runs the kernels as a solve without statistics
         const bool count = stats != nullptr && ctx->profiling != 2;
         run_plan(ctx, tree->plan, tree->graphs, want, opts, count);
-        check_hip(hipEventRecord(tree->last_use, ctx->stream), "event");
+        tree_release(tree, ctx->stream);
         if (stats) {
             check_hip(hipEventRecord(ctx->ev1, ctx->stream), "event");
             check_hip(hipMemcpyAsync(ctx->h_stats, tree->plan.d_out, 12 * sizeof(double), hipMemcpyDeviceToHost,
@@ -840,6 +858,30 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
     });
 }
 
+octo_status octo_solve_device_stats(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, double *phi, double *g,
+                                    double *stats_dev) {
+    return guard([&] {
+        if (!ctx || !tree) fail(OCTO_E_INVALID, "NULL argument");
+        if (tree->ctx != ctx) fail(OCTO_E_STATE, "tree belongs to another context");
+        validate_opts(opts);
+        if (!phi || !g || !stats_dev) fail(OCTO_E_INVALID, "NULL output");
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+
+        DeviceGuard dg(ctx->device);
+        tree_acquire(ctx, tree);
+        std::vector<TreeDesc> want = tree->plan.trees_host;
+        want[0].phi = phi;
+        want[0].g = g;
+        want[0].G = opts->G;
+        want[0].amc = opts->amc ? 1 : 0;
+        run_plan(ctx, tree->plan, tree->graphs, want, opts, false, false, true);
+        check_hip(hipMemcpyAsync(stats_dev, tree->plan.d_out, 9 * sizeof(double), hipMemcpyDeviceToDevice,
+                                 ctx->stream),
+                  "stats copy");
+        tree_release(tree, ctx->stream);
+    });
+}
+
 octo_status octo_solve_dphidt(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, const double *drho_dt,
                               double *dphi_dt) {
     return guard([&] {
@@ -850,6 +892,7 @@ octo_status octo_solve_dphidt(octo_ctx *ctx, octo_tree *tree, const octo_opts *o
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
 
         DeviceGuard dg(ctx->device);
+        tree_acquire(ctx, tree);
         std::vector<TreeDesc> want = tree->plan.trees_host;
         want[0].phi = dphi_dt;
         want[0].g = nullptr;
@@ -857,7 +900,7 @@ octo_status octo_solve_dphidt(octo_ctx *ctx, octo_tree *tree, const octo_opts *o
         want[0].G = opts->G;
         want[0].amc = 0;
         run_plan(ctx, tree->plan, tree->graphs, want, opts, false, true);
-        check_hip(hipEventRecord(tree->last_use, ctx->stream), "event");
+        tree_release(tree, ctx->stream);
     });
 }
 
@@ -872,8 +915,9 @@ octo_status octo_gravity_sources(octo_ctx *ctx, octo_tree *tree, const double *o
         for (int k = 0; k < 3; ++k)
             if (!std::isfinite(omega[k])) fail(OCTO_E_INVALID, "omega not finite");
         DeviceGuard dg(ctx->device);
+        tree_acquire(ctx, tree);
         launch_sources(tree->plan, omega, rho, s, phi, g, drho_dt, dphi_dt, src_s, src_e, ctx->stream);
-        check_hip(hipEventRecord(tree->last_use, ctx->stream), "event");
+        tree_release(tree, ctx->stream);
     });
 }
 
@@ -965,6 +1009,7 @@ octo_status octo_scf_run(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, 
         DeviceGuard dg(ctx->device);
         octo_opts o = *opts;
         o.G = p->G;
+        tree_acquire(ctx, tree);
         scf_run(ctx, tree, level, o, *p, s2, iterations, rho_out, phi_out, history);
     });
 }
@@ -981,6 +1026,7 @@ octo_status octo_regrid(octo_ctx *ctx, octo_tree *tree, const octo_regrid_params
         {
             std::lock_guard<std::recursive_mutex> lk(ctx->mu);
             DeviceGuard dg(ctx->device);
+            tree_acquire(ctx, tree);
             regrid_device(ctx, tree, p->l_max, p->rho_r, r);
         }
         const auto t1 = std::chrono::steady_clock::now();
@@ -1015,6 +1061,7 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
         validate_opts(opts);
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         DeviceGuard dg(ctx->device);
+        tree_acquire(ctx, tree);
         if (ctx->batch &&
             std::find(ctx->batch->sig.begin(), ctx->batch->sig.end(), tree) != ctx->batch->sig.end())
             ctx->invalidate_batches();
@@ -1030,7 +1077,7 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
             double best = 1e30;
             for (int rep = 0; rep < 4; ++rep) {
                 run_plan(ctx, tree->plan, tree->graphs, want, opts, false);
-                check_hip(hipEventRecord(tree->last_use, ctx->stream), "event");
+                tree_release(tree, ctx->stream);
                 check_hip(hipStreamSynchronize(ctx->stream), "autotune");
                 float ms = 0.f;
                 hipEventElapsedTime(&ms, ctx->phase_ev[3], ctx->phase_ev[4]);

@@ -57,6 +57,10 @@ struct Stencil {
     double theta = 0;
     std::vector<int32_t> m2l, nearo, leaf, m2l_src, leaf_off, leaf_widx, m2l_touch, near_touch, m2l_src_touch;
     std::vector<int32_t> near_stage;  // the near-field kernel's halo staging table (kNearStage entries)
+    std::vector<double> mm_a;        // near field on the matrix cores: kMmTab matrix values (FP64 row order)
+    std::vector<float> mm_a32;       // the same in FP32 (FP32 row order)
+    std::vector<int32_t> mm_off;     // and kMmOff gather offsets
+    int mm_k = 0;                    // sources per 2x2x2 block (0: not on the matrix cores)
     std::vector<double> leaf_tab;
     int m2l_beg[9], near_beg[9], leaf_beg[9];
     int leaf_oct_beg[73];
@@ -133,7 +137,8 @@ struct StencilDevHolder {
 
 struct LaunchOpts {
     int precision = OCTO_FP64;
-    bool count = true;                   // count evaluated pairs (statistics)
+    bool count = true;                   // count evaluated pairs (statistics; implies reduce)
+    bool reduce = false;                 // net force / torque reductions without pair counts
     bool source = false;                 // second-source solve (potential of the density rate)
     bool amc = true;                     // angular-momentum correction (a kernel variant of the LDS-staged M2L)
     hipEvent_t *phase_events = nullptr;  // 8 events around the 7 phases + 1 before the LDS M2L kernel, or NULL
@@ -180,6 +185,8 @@ struct Request {
     bool done = false;
     int index = 0;  // position in its wave
     double stats[12] = {0};
+    octo_status status = OCTO_OK;  // OCTO_E_BUDGET: its plan does not fit even alone
+    std::string err;
 };
 
 struct Wave {
@@ -187,6 +194,14 @@ struct Wave {
     std::unique_ptr<BatchPlan> bp;
     hipEvent_t done = nullptr;
     bool finished = false;
+    int lane = -1;
+};
+
+// The streams one launch wave of the request server runs on: waves in flight
+// together run on different lanes, so their work overlaps on the device.
+struct Lane {
+    hipStream_t s = nullptr, aux = nullptr, aux_near = nullptr;
+    hipEvent_t start = nullptr, fork = nullptr, join = nullptr, fork_near = nullptr, join_near = nullptr;
 };
 }  // namespace octo
 
@@ -235,6 +250,7 @@ struct octo_ctx {
     std::map<int, octo::Wave> waves;
     int next_wave = 0;
     int max_inflight_waves = 2;
+    std::vector<octo::Lane> lanes;  // max_inflight_waves lanes, created with the first wave
 
     void *dev_alloc(size_t bytes);
     void dev_free(void *p, size_t bytes);
@@ -255,14 +271,29 @@ struct octo_tree {
     double *rho = nullptr;
     double *stage = nullptr;  // device staging of phi, g for host outputs
     hipEvent_t last_use = nullptr;  // recorded after the last work enqueued on the tree's memory
+    hipStream_t last_stream = nullptr;  // the stream last_use was recorded on
     size_t bytes = 0;
     std::map<std::pair<uint64_t, int>, hipGraphExec_t> graphs;  // (theta bits, precision)
 };
 
 namespace octo {
+// Order work on the context stream after the tree's last use on another
+// stream (a launch wave of the request server); a no-op wait is skipped.
+inline void tree_acquire(octo_ctx *ctx, octo_tree *t) {
+    if (t->last_stream && t->last_stream != ctx->stream) {
+        if (hipStreamWaitEvent(ctx->stream, t->last_use, 0) != hipSuccess)
+            throw Error{OCTO_E_DEVICE, "stream wait on a tree's last use"};
+    }
+}
+// record the tree's last use on stream s
+inline void tree_release(octo_tree *t, hipStream_t s) {
+    if (hipEventRecord(t->last_use, s) != hipSuccess) throw Error{OCTO_E_DEVICE, "event record"};
+    t->last_stream = s;
+}
 // launch a plan through a cached graph (captured on first use) or directly
 void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs,
-              const std::vector<TreeDesc> &want, const octo_opts *o, bool count = true, bool source = false);
+              const std::vector<TreeDesc> &want, const octo_opts *o, bool count = true, bool source = false,
+              bool reduce = false);
 void drop_graphs(std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs);
 // self-consistent-field iteration (Sec. 4.1) on the n^3 grid of `level`; s2:
 // split between the two sides in half-cell units, x = s2 h/2 - 1/2

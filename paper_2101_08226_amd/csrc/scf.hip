@@ -584,7 +584,7 @@ void scf_run(octo_ctx *ctx, octo_tree *t, int level, const octo_opts &o, const o
         check_hip(hipMemcpyAsync(history, s.hist, (size_t)iterations * sizeof(octo_scf_state),
                                  hipMemcpyDeviceToHost, q),
                   "history copy");
-    check_hip(hipEventRecord(t->last_use, q), "event");
+    tree_release(t, q);
     check_hip(hipStreamSynchronize(q), "scf run");
 }
 

@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import time
 from collections import deque
-from concurrent.futures import ThreadPoolExecutor
+from concurrent.futures import Future, ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -68,6 +68,20 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
 
     prof = dict(build_s=0.0, builds=0, admit_s=0.0, complete_s=0.0, idle_s=0.0, loops=0)
 
+    def release_lookahead(queue) -> bool:
+        """Destroy the trees built ahead for queued requests after the head
+        of the queue (they are rebuilt later); True when any was freed."""
+        freed = False
+        for later in list(queue)[1:]:
+            if later.build is not None:
+                try:
+                    octo_tree_destroy(later.build.result())
+                    freed = True
+                except OctoError:
+                    pass
+                later.build = None
+        return freed
+
     def build(p: Payload) -> int:
         b0 = time.perf_counter()
         try:
@@ -113,16 +127,7 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                         break
                     # nothing on the device: release trees built ahead so the
                     # head of the queue fits, then retry it
-                    freed = False
-                    for later in list(queue)[1:]:
-                        if later.build is not None:
-                            try:
-                                octo_tree_destroy(later.build.result())
-                                freed = True
-                            except OctoError:
-                                pass
-                            later.build = None
-                    if not freed:
+                    if not release_lookahead(queue):
                         raise
                     slot.build = None
                     break
@@ -130,8 +135,13 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                 tree = Tree(ctx, h)
                 phi = torch.empty(tree.n_leaf_cells, dtype=torch.float64, device=ctx.device)
                 g = torch.empty((3, tree.n_leaf_cells), dtype=torch.float64, device=ctx.device)
-                tk = octo_submit(ctx.handle, h, make_opts(p.theta, 1.0, p.precision, True), phi.data_ptr(),
-                                 g.data_ptr())
+                try:
+                    tk = octo_submit(ctx.handle, h, make_opts(p.theta, 1.0, p.precision, True), phi.data_ptr(),
+                                     g.data_ptr())
+                except OctoError as e:
+                    if e.status != OCTO_E_BUDGET:
+                        raise
+                    break  # not admitted yet: the head stays queued with its tree
                 inflight[tk] = (p, tree, phi, g, time.perf_counter() - t0)
                 queue.popleft()
                 progressed = True
@@ -140,9 +150,29 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
             # completions: requests finish with their launch wave and waves
             # retire in submission order, so stop at the first unfinished one
             for tk in list(inflight):
-                if not octo_poll(ctx.handle, tk):
-                    break
-                st = octo_wait(ctx.handle, tk).as_dict()
+                try:
+                    if not octo_poll(ctx.handle, tk):
+                        break
+                    st = octo_wait(ctx.handle, tk).as_dict()
+                except OctoError as e:
+                    if e.status != OCTO_E_BUDGET:
+                        raise
+                    # its work plan did not fit with nothing else in flight:
+                    # free the trees built ahead and queue it again first
+                    try:
+                        octo_wait(ctx.handle, tk)
+                    except OctoError:
+                        pass  # the failed ticket is gone now
+                    p, tree, phi, g, adm = inflight.pop(tk)
+                    if not release_lookahead(queue) and not inflight:
+                        tree.destroy()
+                        raise  # nothing else holds memory that could be freed
+                    again = _Slot(p)
+                    again.build = Future()
+                    again.build.set_result(tree.handle)
+                    queue.appendleft(again)
+                    progressed = True
+                    continue
                 p, tree, phi, g, adm = inflight.pop(tk)
                 done = time.perf_counter() - t0
                 records.append(Record(p.index, p.arrival, adm, done, tree.n_leaf_cells, p.precision, st))

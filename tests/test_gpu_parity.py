@@ -12,7 +12,7 @@ import pytest
 import oracle
 import paper_2101_08226_amd as lib
 import workloads as w
-from helpers import random_amr_leaves
+from helpers import random_amr_leaves, zero_block_density
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -114,13 +114,56 @@ def test_adaptive_random(ctx, seed, max_level):
     tree.destroy()
 
 
+@pytest.mark.parametrize("theta", [0.5, 0.34])
+def test_massless_cells(ctx, theta):
+    """Reading R11: root and level-1 cells without mass (all their leaf
+    cells at density 0) expand about their geometric centres, carry no
+    moments and skip the correction as targets; massless leaf cells are still
+    targets."""
+    rho = zero_block_density(5)
+    e, st = uniform_case(ctx, rho, theta)
+    assert e[0] <= TOL and e[1] <= TOL
+    assert st["torque"] < 1e-13 and st["force"] < 1e-13
+
+
+@pytest.mark.parametrize("theta", [0.7, 0.5 + 1e-9])
+def test_other_opening_angles(ctx, theta):
+    """Opening angles beyond the two of the paper's runs: 0.7 (fewer
+    multipole pairs, more direct ones) and 0.5 + 1e-9, the non-strict
+    reading of the opening test at 0.5 (cells two widths apart become well
+    separated), on a uniform and an adaptive tree."""
+    e, st = uniform_case(ctx, w.uniform_grid(w.binary_polytrope(0.12, 0.10, 0.35, 0.7), 2), theta)
+    assert e[0] <= TOL and e[1] <= TOL
+    assert st["torque"] < 1e-13 and st["force"] < 1e-13
+    leaves, f = random_amr_leaves(22, max_level=3, n_stars=2)
+    tree = ctx.adaptive_tree(f, 3, 1e-4)
+    phi, g, st = gpu_solve(ctx, tree, theta=theta)
+    tree.destroy()
+    t = oracle.Tree(leaves, w.leaf_density(f, leaves))
+    p_ref, g_ref = t.solve(theta=theta)
+    e = errs(phi, g, p_ref, g_ref)
+    # above 1/sqrt(3) cells touching at a corner are well separated and the
+    # method's own result can come out near zero (even positive) at cells
+    # next to concentrated mass (oracle pin test_corner_neighbours_above_
+    # inverse_sqrt3): phi is no longer of one sign, so it is compared
+    # normwise there, like g
+    e_phi_norm = float(np.max(np.abs(phi - p_ref)) / np.max(np.abs(p_ref)))
+    say(f"  adaptive theta={theta} e_phi={e[0]:.2e} (normwise {e_phi_norm:.2e}) e_g={e[1]:.2e} "
+        f"torque={st['torque']:.2e}")
+    assert (e_phi_norm if theta > 3 ** -0.5 else e[0]) <= TOL and e[1] <= TOL
+    check_counts(st, t)
+    assert st["torque"] < 1e-13 and st["force"] < 1e-13
+
+
 # Mixed precision (FP32 near field; FP64 moments, multipole-to-local terms,
-# correction and final accumulation): the bounds are 4x the largest error
-# measured when the mixed mode also ran the L-term contractions in FP32 (e_phi
-# 2.65e-7, e_g 2.62e-7, adaptive level-3 case), which bounds the FP32 near
-# field alone as well.
-MIXED_PHI = 1.1e-6
+# correction and final accumulation): each bound is 4x the largest error
+# measured on the GPU over the mixed cases of this file (e_phi 2.42e-7 on the
+# adaptive level-3 tree, e_g 2.70e-7 on the 64^3 binary; the full-size sampled
+# cases stay below 2e-8), and the torque bound 4x the largest relative torque
+# (2.53e-9, adaptive level 3).
+MIXED_PHI = 1.0e-6
 MIXED_G = 1.1e-6
+MIXED_TORQUE = 1.1e-8
 
 
 @pytest.mark.parametrize("case", ["c1", "poly64", "amr"])
@@ -150,7 +193,7 @@ def test_mixed_precision_bounds(ctx, case):
     e = errs(phi_l, g_l, p_ref, g_ref)
     say(f"  mixed e_phi={e[0]:.2e} e_g={e[1]:.2e} torque={st['torque']:.2e} (fp64 torque {st64['torque']:.2e})")
     assert e[0] <= MIXED_PHI and e[1] <= MIXED_G
-    assert st["torque"] < 1e-5 and st["force"] < 1e-5
+    assert st["torque"] < MIXED_TORQUE and st["force"] < MIXED_TORQUE
     assert st["m2l_pairs"] == st64["m2l_pairs"] and st["direct_pairs"] == st64["direct_pairs"]
 
 
@@ -227,6 +270,45 @@ def test_served_stream_equals_single():
         c.close()
 
 
+def test_served_tight_budget():
+    """Admission with a budget just above the largest tree (plus its work
+    plan): trees built ahead and launch waves compete for the memory, waves
+    shrink to what fits, and every request still completes with the result
+    of its solve alone."""
+    from paper_2101_08226_amd import serve
+
+    stream = w.mixes.served_stream(10, 400.0, seed=78, min_cells=4096, max_cells=1 << 16,
+                                   count_leaves=lambda f, lv: 512 * len(lib.octo_host_adaptive_leaves(f, lv, 1e-4)))
+    payloads = []
+    for r in stream:
+        lv = lib.octo_host_adaptive_leaves(r.field, r.max_level, 1e-4)
+        payloads.append(serve.Payload(r.index, r.arrival, lv, w.leaf_density(r.field, lv), r.precision))
+    probe = lib.Context(0)
+    try:
+        sizes, single = [], {}
+        for p in payloads:
+            t = probe.tree(p.leaves, p.rho)
+            sizes.append(t.bytes)
+            phi, g, _ = probe.solve(t, precision=p.precision)
+            single[p.index] = (phi.cpu().numpy(), g.cpu().numpy())
+            t.destroy()
+    finally:
+        probe.close()
+    budget = int(max(sizes) * 1.3)
+    say(f"tight budget: {budget} bytes, trees {min(sizes)}..{max(sizes)} bytes")
+    c = lib.Context(0, hbm_budget=budget)
+    try:
+        rec, outs, wall = serve.serve(c, payloads, keep_outputs=True, builders=4, lookahead=6, time_limit=60.0)
+        used, _ = c.memory()
+    finally:
+        c.close()
+    assert sorted(r.index for r in rec) == list(range(len(payloads)))
+    for p in payloads:
+        assert np.array_equal(outs[p.index][0], single[p.index][0]), p.index
+        assert np.array_equal(outs[p.index][1], single[p.index][1]), p.index
+    assert used == 0
+
+
 def test_errors(ctx):
     rho = np.ones((16, 16, 16))
     tree = ctx.uniform_tree(rho)
@@ -282,21 +364,24 @@ def test_c2_full_size_sampled(ctx):
     assert 0 < st["m2l_lds_pairs"] < st["m2l_pairs"]
 
 
-def test_c3_adaptive_full_size_sampled(ctx):
+@pytest.mark.parametrize("max_level", [6, 7])
+def test_c3_adaptive_full_size_sampled(ctx, max_level):
     """The c2 field refined adaptively to level 6 (7736 leaf sub-grids, 3.96M
-    leaf cells): sampled cells against the oracle, leaf list identical to the
-    oracle's builder, invariants over all cells."""
+    leaf cells) and to level 7 (39,012 leaf sub-grids, 20.0M leaf cells, the
+    config's level 7 counted from the root sub-grid as level 0): sampled cells
+    against the oracle, leaf list identical to the oracle's builder,
+    invariants over all cells."""
     f = w.binary_polytrope_128()
-    say("c3 adaptive level 6 build")
-    tree = ctx.adaptive_tree(f, 6, 1e-4)
+    say(f"c3 adaptive level {max_level} build")
+    tree = ctx.adaptive_tree(f, max_level, 1e-4)
     lv = tree.leaves()
-    assert np.array_equal(lv, oracle.build_adaptive_leaves(f.boxmax, 6, 1e-4))
+    assert np.array_equal(lv, oracle.build_adaptive_leaves(f.boxmax, max_level, 1e-4))
     say(f"c3 solve leaves={len(lv)}")
     for prec in (lib.OCTO_FP64, lib.OCTO_MIXED):
         phi, g, st = gpu_solve(ctx, tree, theta=0.5, precision=prec)
         rng = np.random.default_rng(8)
-        # half the samples in the stars (levels 5-6), half anywhere
-        fine = np.nonzero(np.repeat(lv[:, 0] >= 5, 512))[0]
+        # half the samples in the stars (the two finest levels), half anywhere
+        fine = np.nonzero(np.repeat(lv[:, 0] >= max_level - 1, 512))[0]
         sel = np.concatenate([rng.choice(fine, 200, replace=False), rng.choice(tree.n_leaf_cells, 200, replace=False)])
         if prec == lib.OCTO_FP64:
             t = oracle.Tree(lv, w.leaf_density(f, lv))
@@ -309,6 +394,119 @@ def test_c3_adaptive_full_size_sampled(ctx):
             assert st["torque"] < 1e-13 and st["force"] < 1e-13
         else:
             assert e_phi <= MIXED_PHI and e_g <= MIXED_G
+            assert st["torque"] < MIXED_TORQUE
+    tree.destroy()
+
+
+def test_c4_batched_mix(ctx):
+    """The benchmark's batched workload itself: 256 uniform trees of 16^3,
+    32^3 and 64^3 cells, each a seeded single or binary polytrope, solved in
+    one batch: every tree bitwise equal to its own solve, in both precisions,
+    and three trees (the largest of each size) against the oracle on sampled
+    cells."""
+    import torch
+
+    mix = w.mixes.batched_mix(256)
+    trees = [ctx.uniform_tree(w.uniform_grid(b.field, b.level)) for b in mix]
+    say(f"c4 mix: {len(trees)} trees, {sum(t.n_leaf_cells for t in trees)} cells")
+    for prec in (lib.OCTO_FP64, lib.OCTO_MIXED):
+        outs, sts = ctx.solve_batch(trees, precision=prec)
+        torch.cuda.synchronize()
+        for i, t in enumerate(trees):
+            p1, g1, st1 = gpu_solve(ctx, t, precision=prec)
+            assert np.array_equal(outs[i][0].cpu().numpy(), p1) and np.array_equal(outs[i][1].cpu().numpy(), g1), i
+            assert sts[i]["m2l_pairs"] == st1["m2l_pairs"] and sts[i]["direct_pairs"] == st1["direct_pairs"]
+        say(f"  prec={prec}: batch == single for all trees, worst torque {max(s['torque'] for s in sts):.2e}")
+        if prec == lib.OCTO_FP64:
+            assert max(s["torque"] for s in sts) < 1e-13
+            fp64 = outs
+        else:
+            # 4x the worst mixed torque measured over the 256 trees (2.40e-8)
+            assert max(s["torque"] for s in sts) < 1e-7
+    from helpers import grid_ids
+
+    rng = np.random.default_rng(10)
+    for lev in (1, 2, 3):
+        i = max((k for k, b in enumerate(mix) if b.level == lev), key=lambda k: trees[k].n_leaf_cells)
+        n = 8 << lev
+        rho = w.uniform_grid(mix[i].field, lev)
+        sel = rng.choice(n ** 3, 200, replace=False)
+        t = oracle.Tree(w.uniform_leaves(lev), w.grid_to_leaves(rho))
+        p_ref, g_ref = t.solve(theta=0.5, sample=grid_ids(lev, sel))
+        phi = fp64[i][0].cpu().numpy()[sel]
+        g = fp64[i][1].cpu().numpy()[:, sel]
+        e_phi = float(np.max(np.abs(phi - p_ref) / np.abs(p_ref)))
+        e_g = float(np.max(np.abs(g - g_ref)) / np.max(np.abs(g_ref)))
+        say(f"  tree {i} ({n}^3): e_phi={e_phi:.2e} e_g={e_g:.2e}")
+        assert e_phi <= TOL and e_g <= TOL
+    for t in trees:
+        t.destroy()
+
+
+def test_batch_per_tree_status(ctx):
+    """octo_solve_batch reports each tree's outcome: refused entries (a NULL
+    tree, a NULL output, a tree listed twice) get their own status and are
+    skipped; the others are solved together, bitwise as alone."""
+    import torch
+
+    rng = np.random.default_rng(12)
+    trees = [ctx.uniform_tree(rng.uniform(0.1, 1.0, (n, n, n))) for n in (16, 32)]
+    single = [gpu_solve(ctx, t)[:2] for t in trees]
+    outs = [(torch.empty(t.n_leaf_cells, dtype=torch.float64, device="cuda"),
+             torch.empty((3, t.n_leaf_cells), dtype=torch.float64, device="cuda")) for t in trees]
+    handles = [trees[0].handle, 0, trees[1].handle, trees[0].handle, trees[1].handle]
+    phis = [outs[0][0].data_ptr(), outs[0][0].data_ptr(), outs[1][0].data_ptr(), outs[0][0].data_ptr(), 0]
+    gs = [outs[0][1].data_ptr(), outs[0][1].data_ptr(), outs[1][1].data_ptr(), outs[0][1].data_ptr(),
+          outs[1][1].data_ptr()]
+    status = []
+    say("batch with refused entries")
+    sts = lib.octo_solve_batch(ctx.handle, handles, lib.make_opts(), phis, gs, True, status_out=status)
+    torch.cuda.synchronize()
+    assert status == [lib.OCTO_OK, lib.OCTO_E_INVALID, lib.OCTO_OK, lib.OCTO_E_INVALID, lib.OCTO_E_INVALID]
+    for k, i in ((0, 0), (2, 1)):
+        assert sts[k].n_leaf_cells == trees[i].n_leaf_cells
+        assert np.array_equal(outs[i][0].cpu().numpy(), single[i][0])
+        assert np.array_equal(outs[i][1].cpu().numpy(), single[i][1])
+    # every entry refused: the call fails with the first entry's status
+    status = []
+    lib.octo_solve_batch(ctx.handle, [0, 0], lib.make_opts(), [0, 0], [0, 0], True, status_out=status)
+    assert status == [lib.OCTO_E_INVALID, lib.OCTO_E_INVALID]
+    with pytest.raises(lib.OctoError):
+        lib.octo_solve_batch(ctx.handle, [trees[0].handle, trees[0].handle], lib.make_opts(), phis[:2], gs[:2], True)
+    # bad options fail the whole call, for every tree
+    status = []
+    lib.octo_solve_batch(ctx.handle, [t.handle for t in trees], lib.make_opts(theta=0.2), phis[::2][:2], gs[::2][:2],
+                         True, status_out=status)
+    assert status == [lib.OCTO_E_UNSUPPORTED, lib.OCTO_E_UNSUPPORTED]
+    for t in trees:
+        t.destroy()
+
+
+def test_device_stats(ctx):
+    """octo_solve_device_stats: the same potential and acceleration as
+    octo_solve, bit for bit, and the 9 reduction results in device memory
+    equal to the host statistics of a solve that counts pairs (the counting
+    pass changes no sum)."""
+    import torch
+
+    rho = w.uniform_grid(w.binary_polytrope(0.12, 0.10, 0.35, 0.7), 3)
+    tree = ctx.uniform_tree(rho)
+    for prec in (lib.OCTO_FP64, lib.OCTO_MIXED):
+        phi, g, st = gpu_solve(ctx, tree, precision=prec)
+        opts = lib.make_opts(0.5, 1.0, prec, True)
+        d_phi = torch.empty(tree.n_leaf_cells, dtype=torch.float64, device="cuda")
+        d_g = torch.empty((3, tree.n_leaf_cells), dtype=torch.float64, device="cuda")
+        d_st = torch.full((9,), float("nan"), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()  # the fill (torch's stream) before the library's stream writes
+        for _ in range(2):  # capture, then graph replay
+            lib.octo_solve_device_stats(ctx.handle, tree.handle, opts, d_phi.data_ptr(), d_g.data_ptr(),
+                                        d_st.data_ptr())
+            ctx.stream.synchronize()
+            assert np.array_equal(d_phi.cpu().numpy(), phi) and np.array_equal(d_g.cpu().numpy(), g)
+            v = d_st.cpu().numpy()
+            host = np.array([st["total_mass"], *st["net_force"], *st["net_torque"], st["force_scale"],
+                             st["torque_scale"]])
+            assert np.array_equal(v, host), (v, host)
     tree.destroy()
 
 
@@ -389,10 +587,10 @@ def test_coupling_kernels(ctx):
 # dphi/dt: the density rate as a second source (Sec. 2.1)
 # Bar (FP64): max_i |d_i| / max_i |ref_i| <= 1e-12 (normwise: the rate and its
 # potential change sign).  Mixed: MIXED_DPHI, 4x the largest error measured
-# (5.4e-7, orbital rate on the adaptive level-3 tree at theta 0.34).
+# (5.74e-7, orbital rate on the adaptive level-3 tree at theta 0.34).
 # --------------------------------------------------------------------------
 
-MIXED_DPHI = 2.2e-6
+MIXED_DPHI = 2.3e-6
 
 
 def _dev(a):

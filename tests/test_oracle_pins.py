@@ -156,6 +156,29 @@ def test_massless_cells():
     assert rel_err_phi(phi, pd) < 1e-2  # truncation level against the N^2 sum
 
 
+def test_corner_neighbours_above_inverse_sqrt3():
+    """The printed opening test on integer offsets: cells touching at a
+    corner (|d|^2 = 3) become well separated once theta exceeds 1/sqrt(3).
+    Their expansions then reach masses next to the shared corner, outside the
+    region where they converge, and the method loses its accuracy on an
+    adaptive tree (errors of order one, potentials near zero or positive,
+    where the N^2 sum is -4.7e-3), while up to 0.57 it stays at the truncation
+    level of a few per cent at worst.  The paper runs only theta = 0.5 and
+    0.34; the library accepts [0.34, 1) as the text allows."""
+    leaves, f = random_amr_leaves(22, max_level=3, n_stars=2)
+    t = oracle.Tree(leaves, w.leaf_density(f, leaves))
+    x, m = t.leaf_cells()
+    rng = np.random.default_rng(22)
+    ids = np.unique(np.concatenate([rng.choice(t.n_cells, 3000, replace=False), [66004, 69998, 33015]]))
+    pd, _ = oracle.direct_points(x, m, x[:, ids])
+    worst = {}
+    for theta in (0.5, 0.57, 0.578):
+        phi, _ = t.solve(theta=theta, sample=ids)
+        worst[theta] = float(np.max(np.abs(phi - pd) / np.abs(pd)))
+    assert worst[0.5] < 5e-2 and worst[0.57] < 5e-2
+    assert worst[0.578] > 0.5
+
+
 def test_single_leaf_equals_direct_sum():
     rng = np.random.default_rng(8)
     rho = rng.uniform(0.5, 2.0, (1, 512))
