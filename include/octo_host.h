@@ -45,26 +45,6 @@ octo_status octo_host_near_lists(double theta, int32_t *beg, int32_t *d, int64_t
  * Errors: OCTO_E_INVALID for NULL pointers. */
 octo_status octo_host_near_stage(int32_t *out, int64_t cap, int64_t *n);
 
-/* The tables of the near field on the matrix cores for opening angle theta
- * (levels >= 1): for every 2x2x2 block of leaf cells (the children of one
- * parent cell) the same-level leaf partners are the *k = 8|S| children of the
- * |S| parent cells that are not well separated from the block's parent, and
- * phi, g of the block's 8 cells are a fixed matrix times their masses.  The
- * work-group's 4 wavefronts w take kMmSteps = 17 steps s of 4 partners each;
- * a (FP64) and a32 (FP32) hold 4 * 17 * 2 * 64 matrix values, the one of lane
- * l in M-tile i (cells 4i..4i+3) at ((w * 17 + s) * 2 + i) * 64 + l: partner
- * k = 4 (w * 17 + s) + l / 16, row rho = l % 16 meaning cell 4i + rho % 4 and
- * component rho / 4 in a, cell 4i + rho / 4 and component rho % 4 in a32
- * (component 0: 1/|d|, 1..3: d/|d|^3 with d = partner - cell in cell widths,
- * 0 for d = 0 and for padding k >= *k); off holds 4 * 17 * 64 halo offsets,
- * lane l's at (w * 17 + s) * 64 + l: the partner's index in the parity-split
- * halo of octo_host_near_stage relative to the block's lattice position
- * (ix, iy, iz) -> ix * 112 + iy * 12 + iz of the block's parent within the
- * sub-grid.  *k = 0 when the partners do not fit 4 * 4 * 17 (theta < 0.5).
- * Any of a, a32, off may be NULL.
- * Errors: OCTO_E_UNSUPPORTED for theta outside [0.34, 1). */
-octo_status octo_host_near_mm(double theta, double *a, float *a32, int32_t *off, int32_t *k);
-
 /* Validate a leaf list exactly as octo_tree_build does and report its layout:
  * out[3*l+0] = nodes at level l, out[3*l+1] = interior nodes, out[3*l+2] =
  * leaf nodes that touch an interior node of their level; *n_levels = deepest

@@ -30,7 +30,7 @@ EXPORTS = [
     "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_tree_build", "octo_tree_build_uniform",
     "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_get_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
     "octo_solve", "octo_solve_device_stats", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_step_noalloc", "octo_scf_run", "octo_regrid", "octo_submit", "octo_poll", "octo_wait", "octo_last_error", "octo_build_id",
-    "octo_host_stencil_sizes", "octo_host_near_lists", "octo_host_near_stage", "octo_host_near_mm", "octo_host_layout", "octo_host_adaptive_leaves",
+    "octo_host_stencil_sizes", "octo_host_near_lists", "octo_host_near_stage", "octo_host_layout", "octo_host_adaptive_leaves",
 ]
 
 
@@ -162,8 +162,6 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_wait": [_P, _I64, ctypes.POINTER(octo_stats)],
         "octo_host_stencil_sizes": [ctypes.c_double, ctypes.POINTER(ctypes.c_int32)],
         "octo_host_near_stage": [ctypes.POINTER(ctypes.c_int32), _I64, ctypes.POINTER(_I64)],
-        "octo_host_near_mm": [ctypes.c_double, _D, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32),
-                              ctypes.POINTER(ctypes.c_int32)],
         "octo_host_near_lists": [ctypes.c_double, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _I64,
                                  ctypes.POINTER(_I64)],
         "octo_host_layout": [ctypes.POINTER(octo_leaf), _I64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_I64)],
@@ -390,23 +388,6 @@ def octo_wait(ctx: int, ticket: int) -> octo_stats:
     st = octo_stats()
     _check(load_library().octo_wait(ctx, ticket, ctypes.byref(st)))
     return st
-
-
-MM_STEPS = 17  # reduction steps of 4 per wavefront of the matrix-core near field
-
-
-def octo_host_near_mm(theta: float):
-    """Tables of the matrix-core near field (include/octo_host.h): FP64 and
-    FP32 matrix values, halo offsets, and the partners per block (0: the VALU
-    kernel runs)."""
-    a = np.zeros(4 * MM_STEPS * 2 * 64)
-    a32 = np.zeros(4 * MM_STEPS * 2 * 64, dtype=np.float32)
-    off = np.zeros(4 * MM_STEPS * 64, dtype=np.int32)
-    k = ctypes.c_int32()
-    _check(load_library().octo_host_near_mm(float(theta), a.ctypes.data_as(_D),
-                                            a32.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
-                                            off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(k)))
-    return a, a32, off, k.value
 
 
 def octo_host_stencil_sizes(theta: float) -> np.ndarray:

@@ -83,18 +83,6 @@ octo_status octo_host_near_stage(int32_t *out, int64_t cap, int64_t *n) {
     });
 }
 
-octo_status octo_host_near_mm(double theta, double *a, float *a32, int32_t *off, int32_t *k) {
-    return guard_h([&] {
-        if (!k) fail(OCTO_E_INVALID, "NULL output");
-        if (!(theta >= 0.34 && theta < 1.0)) fail(OCTO_E_UNSUPPORTED, "theta must lie in [0.34, 1)");
-        Stencil s = make_stencil(theta);
-        *k = s.mm_k;
-        if (a) std::copy(s.mm_a.begin(), s.mm_a.end(), a);
-        if (a32) std::copy(s.mm_a32.begin(), s.mm_a32.end(), a32);
-        if (off) std::copy(s.mm_off.begin(), s.mm_off.end(), off);
-    });
-}
-
 octo_status octo_host_layout(const octo_leaf *leaves, int64_t n_leaves, int32_t *n_levels, int64_t *out) {
     return guard_h([&] {
         if (!n_levels || !out) fail(OCTO_E_INVALID, "NULL output");

@@ -22,9 +22,6 @@ namespace octo {
 namespace {
 
 constexpr int kXcd = 8;
-// persistent work-groups of the matrix-core near field: two per compute unit
-// of a 256-CU device (a multiple of kXcd)
-constexpr int kNearMmGrid = 512;
 
 // blockIdx -> item: the hardware deals work-groups round-robin over the XCDs;
 // give each XCD a contiguous slice of the item list instead.
@@ -1411,212 +1408,6 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
     }
 }
 
-// ------------------------------------------------------------------ near field on the matrix cores
-// The same-level leaf pairs of k_near as a matrix product: for every 2x2x2
-// block of leaf cells (the children of one parent cell P) the partners are
-// the children of the parent cells P + D that are not well separated from P,
-// the same |S| offsets D for every block, so
-//   [phi, g] of the 8 targets (32 rows) = W (32 x 8|S|) . m (8|S| masses)
-// with one fixed matrix W of 1/|d| and d/|d|^3 (d = 2D + c - t in cell units;
-// 1/h and 1/h^2 applied at the end) and one column of gathered masses per
-// block: a dense contraction with a shared operand, on the MFMA units.
-// A node's 64 blocks are 4 N-tiles of 16 (tile j: P = (j, y, z)); the 8|S|
-// sources are split into steps of 4 (the MFMA depth), kMmSteps per
-// wavefront, each wavefront holding its slice of W in registers for every
-// node it works on (persistent work-groups); the four wavefronts' partial
-// sums are added in wavefront order through LDS (deterministic), each
-// wavefront finishing one N-tile.  Absent and non-leaf partners carry mass
-// 0, as in k_near; cross-level pairs and the root leaf stay on the VALU.
-typedef double mm_v4d __attribute__((ext_vector_type(4)));
-typedef float mm_v4f __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct MmOps;
-template <>
-struct MmOps<double> {
-    using Acc = mm_v4d;
-    __device__ static Acc mac(double a, double b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-    __device__ static const double *tab(const StencilDev &st) { return st.mm_a; }
-};
-template <>
-struct MmOps<float> {
-    using Acc = mm_v4f;
-    __device__ static Acc mac(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-    __device__ static const float *tab(const StencilDev &st) { return st.mm_a32; }
-};
-
-// own tile j == w of a wavefront's accumulators, selected without indexing
-// registers at run time
-template <typename A>
-__device__ inline A pick4(const A &c0, const A &c1, const A &c2, const A &c3, int w) {
-    return w == 0 ? c0 : (w == 1 ? c1 : (w == 2 ? c2 : c3));
-}
-
-template <typename T, bool COUNT>
-__global__ __launch_bounds__(256, 2) void k_near_mm(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
-                                                    const LeafItem *__restrict__ items, int n_items, StencilDev st,
-                                                    int64_t *__restrict__ cnt_out) {
-    using Ops = MmOps<T>;
-    using Acc = typename Ops::Acc;
-    // the other wavefronts' partial tiles: 4 sources x 3 tiles x 2 M-tiles x 64 lanes x 4
-    static_assert(12 * 2 * 64 * 4 <= kNearN, "the partial sums reuse the halo");
-    __shared__ T s_m[kNearN];
-    __shared__ unsigned char s_pres[COUNT ? kNearN : 1];
-    __shared__ int s_nbr[27], s_pnbr[27];
-    __shared__ int s_c[4];
-    const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, lb = l & 15;
-    // this wavefront's slice of W and its gather offsets, for every node
-    T a0[kMmSteps], a1[kMmSteps];
-    int off[kMmSteps];
-    {
-        const GPtr<const T> A = gptr(Ops::tab(st));
-        const GPtr<const int32_t> O = gptr(st.mm_off);
-#pragma unroll
-        for (int k = 0; k < kMmSteps; ++k) {
-            a0[k] = A[((w * kMmSteps + k) * 2 + 0) * 64 + l];
-            a1[k] = A[((w * kMmSteps + k) * 2 + 1) * 64 + l];
-            off[k] = O[(w * kMmSteps + k) * 64 + l];
-        }
-    }
-    // lattice position (y, z) of this lane's block within an N-tile
-    const int lat = (lb >> 2) * kNearY + (lb & 3);
-    // items: each XCD (work-group id modulo 8) walks a contiguous slice; the
-    // grid is a multiple of 8
-    const int xcd = (int)blockIdx.x % kXcd, g8 = (int)gridDim.x / kXcd;
-    const int per = (n_items + kXcd - 1) / kXcd;
-    const int hi = min(n_items, (xcd + 1) * per);
-    for (int it = xcd * per + (int)blockIdx.x / kXcd; it < hi; it += g8) {
-        const LeafItem item = items[it];
-        const LevelDesc ld = L[item.ld];
-        const TreeDesc td = TD[ld.tree];
-        const int node = item.node;
-        __syncthreads();  // the previous node's LDS reads are done
-        if (tid < 27) {
-            s_nbr[tid] = ld.nbr[node * 27 + tid];
-            if (ld.parent_ld >= 0) s_pnbr[tid] = L[ld.parent_ld].nbr[ld.parent[node] * 27 + tid];
-        }
-        __syncthreads();
-        const double h = ld.h;
-        const T ih = (T)(1.0 / h);
-        const size_t NS = (size_t)(ld.n_nodes - ld.n_int) * kCells;
-        int cnt = 0;
-        if (ld.level == 0) {
-            // the root leaf (a one-node tree): every other cell, directly
-            for (int half = 0; half < 2; ++half) {
-                const int sc = tid + 256 * half;
-                int x, y, z;
-                local_xyz(sc, x, y, z);
-                T sp = 0, sgx = 0, sgy = 0, sgz = 0;
-                for (int k = 0; k < kCells; ++k) {
-                    if (k == sc) continue;
-                    int bx, by, bz;
-                    local_xyz(k, bx, by, bz);
-                    const T dx = (T)(bx - x), dy = (T)(by - y), dz = (T)(bz - z);
-                    const T w0 = rsqrt_t(dx * dx + dy * dy + dz * dz);
-                    const T m = (T)ld.mass[k];
-                    const T mw0 = m * w0, mw3 = mw0 * w0 * w0;
-                    sp += mw0;
-                    sgx += mw3 * dx;
-                    sgy += mw3 * dy;
-                    sgz += mw3 * dz;
-                    ++cnt;
-                }
-                const size_t ni = (size_t)(node - ld.n_int) * kCells + sc;
-                ld.nf[ni] = td.G * (double)(-sp * ih);
-                ld.nf[NS + ni] = td.G * (double)(sgx * ih * ih);
-                ld.nf[2 * NS + ni] = td.G * (double)(sgy * ih * ih);
-                ld.nf[3 * NS + ni] = td.G * (double)(sgz * ih * ih);
-            }
-        } else {
-            // the node's 18^3 halo of same-level leaf masses (0 elsewhere),
-            // 24 cells per thread in two rounds of 12 loads in flight
-            const GPtr<const int32_t> stage = gptr(st.near_stage);
-            const GPtr<const double> mass = gptr(ld.mass);
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                constexpr int NU = kNearStage / 512;
-                int e[NU], nb[NU];
-#pragma unroll
-                for (int u = 0; u < NU; ++u) e[u] = stage[(r * NU + u) * 256 + tid];
-#pragma unroll
-                for (int u = 0; u < NU; ++u) nb[u] = e[u] >= 0 ? s_nbr[e[u] & 31] : -1;
-                T v[NU];
-#pragma unroll
-                for (int u = 0; u < NU; ++u)
-                    v[u] = nb[u] >= ld.n_int ? (T)mass[(size_t)nb[u] * kCells + ((e[u] >> 5) & 511)] : (T)0;
-#pragma unroll
-                for (int u = 0; u < NU; ++u)
-                    if (e[u] >= 0) {
-                        s_m[e[u] >> 14] = v[u];
-                        if (COUNT) s_pres[e[u] >> 14] = nb[u] >= ld.n_int ? 1 : 0;
-                    }
-            }
-            __syncthreads();
-            Acc c00 = {0, 0, 0, 0}, c01 = c00, c02 = c00, c03 = c00, c10 = c00, c11 = c00, c12 = c00, c13 = c00;
-#pragma unroll
-            for (int k = 0; k < kMmSteps; ++k) {
-                const int o = off[k] + lat;
-                const T b0 = s_m[o], b1 = s_m[o + kNearX], b2 = s_m[o + 2 * kNearX], b3 = s_m[o + 3 * kNearX];
-                c00 = Ops::mac(a0[k], b0, c00);
-                c10 = Ops::mac(a1[k], b0, c10);
-                c01 = Ops::mac(a0[k], b1, c01);
-                c11 = Ops::mac(a1[k], b1, c11);
-                c02 = Ops::mac(a0[k], b2, c02);
-                c12 = Ops::mac(a1[k], b2, c12);
-                c03 = Ops::mac(a0[k], b3, c03);
-                c13 = Ops::mac(a1[k], b3, c13);
-                if (COUNT && 4 * (w * kMmSteps + k) + (l >> 4) < st.mm_k)
-                    cnt += 8 * (s_pres[o] + s_pres[o + kNearX] + s_pres[o + 2 * kNearX] + s_pres[o + 3 * kNearX]);
-            }
-            __syncthreads();  // every wavefront is done with the halo
-            // partial tiles for the other wavefronts: slot (w, j), j != w
-            const Acc cc[2][4] = {{c00, c01, c02, c03}, {c10, c11, c12, c13}};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (j == w) continue;
-                const int slot = w * 3 + (j < w ? j : j - 1);
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) s_m[((slot * 2 + i) * 64 + l) * 4 + r] = cc[i][j][r];
-            }
-            __syncthreads();
-            // N-tile w: the four wavefronts' partial sums in wavefront order
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const Acc own = i == 0 ? pick4(c00, c01, c02, c03, w) : pick4(c10, c11, c12, c13, w);
-                T v[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    T acc = (T)0;
-#pragma unroll
-                    for (int src = 0; src < 4; ++src)
-                        acc += src == w ? own[r] : s_m[(((src * 3 + (w < src ? w : w - 1)) * 2 + i) * 64 + l) * 4 + r];
-                    v[r] = acc;
-                }
-                // target child t of block P = (w, lb >> 2, lb & 3): cell 2P + t
-                const int t = 4 * i + (l >> 4);
-                const int x = 2 * w + (t >> 2), y = 2 * (lb >> 2) + ((t >> 1) & 1), z = 2 * (lb & 3) + (t & 1);
-                T phi_t = -v[0] * ih, gx_t = v[1] * ih * ih, gy_t = v[2] * ih * ih, gz_t = v[3] * ih * ih;
-                cross_level<T>(L, ld, item, st, s_nbr, s_pnbr, node, x, y, z, t, phi_t, gx_t, gy_t, gz_t, cnt);
-                const size_t ni = (size_t)(node - ld.n_int) * kCells + t * 64 + (w << 4) + lb;
-                ld.nf[ni] = td.G * (double)phi_t;
-                ld.nf[NS + ni] = td.G * (double)gx_t;
-                ld.nf[2 * NS + ni] = td.G * (double)gy_t;
-                ld.nf[3 * NS + ni] = td.G * (double)gz_t;
-            }
-        }
-        if (COUNT) {
-            const int tot = wave_sum(cnt);
-            if (l == 0) s_c[w] = tot;
-            __syncthreads();
-            // the same-level part counted each block's 8 self pairs (d = 0): 512 per node
-            if (tid == 0)
-                cnt_out[it] = (int64_t)s_c[0] + s_c[1] + s_c[2] + s_c[3] - (ld.level == 0 ? 0 : 512);
-        }
-    }
-}
-
 // ------------------------------------------------------------------ stats
 // One work-group per tree: fixed-order sums of the per-node partials (each
 // thread a fixed strided subset, then a fixed-shape tree in LDS).
@@ -1709,20 +1500,11 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     }
     if (p.n_leaf) {
         const bool count = o.count && !src;
-        if (st.mm_k > 0) {
-            // persistent work-groups, two per compute unit at most, a multiple of 8
-            const int grid = std::min(((p.n_leaf + kXcd - 1) / kXcd) * kXcd, kNearMmGrid);
-            auto near = o.precision == OCTO_MIXED ? (count ? k_near_mm<float, true> : k_near_mm<float, false>)
-                                                  : (count ? k_near_mm<double, true> : k_near_mm<double, false>);
-            hipLaunchKernelGGL(near, dim3(grid), dim3(256), 0, sn, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
-                               p.d_leaf_cnt);
-        } else {
-            const int grid = ((p.n_leaf + kXcd - 1) / kXcd) * kXcd;
-            auto near = o.precision == OCTO_MIXED ? (count ? k_near<float, true> : k_near<float, false>)
-                                                  : (count ? k_near<double, true> : k_near<double, false>);
-            hipLaunchKernelGGL(near, dim3(grid), dim3(512), 0, sn, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
-                               p.d_leaf_cnt);
-        }
+        const int grid = ((p.n_leaf + kXcd - 1) / kXcd) * kXcd;
+        auto near = o.precision == OCTO_MIXED ? (count ? k_near<float, true> : k_near<float, false>)
+                                              : (count ? k_near<double, true> : k_near<double, false>);
+        hipLaunchKernelGGL(near, dim3(grid), dim3(512), 0, sn, p.d_levels, p.d_trees, p.d_leaf, p.n_leaf, st,
+                           p.d_leaf_cnt);
     }
     if (near_fork) check_hip(hipEventRecord(o.join_near, o.aux_near), "join");
     mark(2);

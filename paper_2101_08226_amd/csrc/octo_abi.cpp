@@ -483,8 +483,7 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_tab.size() * 8) +
                al(w32.size() * 4) + al(S.m2l_src.size() * 4) + al(S.leaf_off.size() * 4) +
                al(S.leaf_widx.size() * 4) + al(S.m2l_touch.size() * 4) + al(S.near_touch.size() * 4) +
-               al(S.m2l_src_touch.size() * 4) + al(S.near_stage.size() * 4) + al(S.mm_a.size() * 8) +
-               al(S.mm_a32.size() * 4) + al(S.mm_off.size() * 4);
+               al(S.m2l_src_touch.size() * 4) + al(S.near_stage.size() * 4);
     void *mem = nullptr;
     check_hip(hipMalloc(&mem, b), "stencil alloc");
     h->block.ptr = mem;
@@ -509,10 +508,6 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     h->dev.leaf_widx = (const int32_t *)put(S.leaf_widx.data(), S.leaf_widx.size() * 4);
     h->dev.m2l_src_touch = (const int32_t *)put(S.m2l_src_touch.data(), S.m2l_src_touch.size() * 4);
     h->dev.near_stage = (const int32_t *)put(S.near_stage.data(), S.near_stage.size() * 4);
-    h->dev.mm_a = (const double *)put(S.mm_a.data(), S.mm_a.size() * 8);
-    h->dev.mm_a32 = (const float *)put(S.mm_a32.data(), S.mm_a32.size() * 4);
-    h->dev.mm_off = (const int32_t *)put(S.mm_off.data(), S.mm_off.size() * 4);
-    h->dev.mm_k = S.mm_k;
     for (int k = 0; k < 64; ++k) h->dev.m2l_src_any[k] = S.m2l_src_any[k];
     for (int k = 0; k < 73; ++k) h->dev.leaf_oct_beg[k] = S.leaf_oct_beg[k];
     for (int k = 0; k < 73; ++k) h->dev.m2l_src_beg[k] = S.m2l_src_beg[k];

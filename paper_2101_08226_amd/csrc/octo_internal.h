@@ -57,25 +57,7 @@ constexpr int kNearY = 12, kNearX = 112, kNearQ = 9 * kNearX, kNearN = 8 * kNear
 constexpr int kNearStage = 12 * 512;
 // near-field weights by |d| pattern: index (|dx| * 6 + |dy|) * 6 + |dz|
 constexpr int kNearTab = 216;
-// Near field on the matrix cores: per 2x2x2 block of leaf cells (the
-// children of one parent cell P) the same-level leaf partners are the
-// children of the parent cells P + D that are not well separated from P (|S|
-// offsets D), so phi and g of the 8 targets are a fixed [32 x 8|S|] matrix
-// (rows target t * 4 + component: 1/|d| and d/|d|^3 of the cell offset
-// d = 2D + c - t, zero for d = 0) times the 8|S| gathered masses, with one
-// column per block.  The reduction runs in steps of 4 (the MFMA depth);
-// a work-group's 4 wavefronts split the steps, kMmSteps each, so 8|S| must
-// not exceed 4 * 4 * kMmSteps (theta >= 0.5; smaller theta keeps the VALU
-// kernel).  Rows are ordered per precision so that each lane receives the
-// four components of one target.  Per wavefront w, step s, M-tile i
-// (targets 4i..4i+3) and lane l
-// the matrix value sits at ((w * kMmSteps + s) * 2 + i) * 64 + l, the gather
-// offset of the lane's source (k = 4 (w kMmSteps + s) + l / 16) into the
-// parity-split halo, relative to the block's lattice position P, at
-// (w * kMmSteps + s) * 64 + l.
-constexpr int kMmSteps = 17;
-constexpr int kMmTab = 4 * kMmSteps * 2 * 64;
-constexpr int kMmOff = 4 * kMmSteps * 64;
+
 
 struct LevelDesc {
     int32_t level, n_nodes, n_int, n_rec;
@@ -158,12 +140,6 @@ struct StencilDev {
     const int32_t *m2l_src_touch;  // per m2l_src entry: mask of the 27 neighbour sub-grids it reaches
     int32_t m2l_src_any[64];       // target class p, source class q: union of the group's touch masks
     double theta2;
-    // near field on the matrix cores (kMmTab matrix values, kMmOff offsets); mm_k = 8|S| sources per
-    // block, 0 when they do not fit (the VALU near-field kernel runs then)
-    const double *mm_a;
-    const float *mm_a32;
-    const int32_t *mm_off;
-    int32_t mm_k;
 };
 
 __host__ __device__ inline int32_t pack_off(int dx, int dy, int dz) {

@@ -57,10 +57,6 @@ struct Stencil {
     double theta = 0;
     std::vector<int32_t> m2l, nearo, leaf, m2l_src, leaf_off, leaf_widx, m2l_touch, near_touch, m2l_src_touch;
     std::vector<int32_t> near_stage;  // the near-field kernel's halo staging table (kNearStage entries)
-    std::vector<double> mm_a;        // near field on the matrix cores: kMmTab matrix values (FP64 row order)
-    std::vector<float> mm_a32;       // the same in FP32 (FP32 row order)
-    std::vector<int32_t> mm_off;     // and kMmOff gather offsets
-    int mm_k = 0;                    // sources per 2x2x2 block (0: not on the matrix cores)
     std::vector<double> leaf_tab;
     int m2l_beg[9], near_beg[9], leaf_beg[9];
     int leaf_oct_beg[73];

@@ -507,59 +507,6 @@ Stencil make_stencil(double theta) {
         const int dest = q * kNearQ + (ux >> 1) * kNearX + (uy >> 1) * kNearY + (uz >> 1);
         s.near_stage[c] = slot | store << 5 | dest << 14;
     }
-    // near field on the matrix cores: the parent offsets D that are not well
-    // separated (the same test as the stencils above), each with its 8
-    // children c; source k = (D, c) of the block of parent P is the cell
-    // 2P + 2D + c, halo cell u = 2P + 2D + c + 5: class 1 - c per axis,
-    // lattice index P + D + 2 + c per axis
-    std::vector<std::array<int, 6>> src;  // D, c
-    for (int Dx = -2; Dx <= 2; ++Dx)
-        for (int Dy = -2; Dy <= 2; ++Dy)
-            for (int Dz = -2; Dz <= 2; ++Dz)
-                if (t2 * (double)(Dx * Dx + Dy * Dy + Dz * Dz) <= 1.0)
-                    for (int c = 0; c < 8; ++c) src.push_back({Dx, Dy, Dz, c >> 2, (c >> 1) & 1, c & 1});
-    // every non-well-separated parent offset lies within 2 per axis for theta >= 0.34
-    // (|D|^2 <= 1 / 0.34^2 < 9), so the list above is complete
-    s.mm_a.assign(kMmTab, 0.0);
-    s.mm_a32.assign(kMmTab, 0.0f);
-    s.mm_off.assign(kMmOff, 0);
-    if ((int)src.size() <= 16 * kMmSteps) {
-        s.mm_k = (int)src.size();
-        for (int w = 0; w < 4; ++w)
-            for (int st = 0; st < kMmSteps; ++st)
-                for (int l = 0; l < 64; ++l) {
-                    const int k = 4 * (w * kMmSteps + st) + l / 16;
-                    if (k >= s.mm_k) continue;  // padding: zero weight, offset 0
-                    const auto &e = src[k];
-                    const int q = ((1 - e[3]) << 2) | ((1 - e[4]) << 1) | (1 - e[5]);
-                    s.mm_off[(w * kMmSteps + st) * 64 + l] =
-                        q * kNearQ + (e[0] + 2 + e[3]) * kNearX + (e[1] + 2 + e[4]) * kNearY + (e[2] + 2 + e[5]);
-                    // row rho = l & 15 of M-tile i: a target of 4i..4i+3 and a
-                    // component, ordered so that the result lands with all four
-                    // components of one target in one lane: the FP64 MFMA returns
-                    // row rho in lane (rho mod 4) * 16 + column, register rho / 4
-                    // (so rho = comp * 4 + target), the FP32 one in lane
-                    // (rho / 4) * 16 + column, register rho mod 4 (rho = target * 4
-                    // + comp)
-                    const int rho = l & 15;
-                    for (int fp32 = 0; fp32 < 2; ++fp32)
-                        for (int i = 0; i < 2; ++i) {
-                            const int t = 4 * i + (fp32 ? rho >> 2 : rho & 3), comp = fp32 ? rho & 3 : rho >> 2;
-                            const int dx = 2 * e[0] + e[3] - (t >> 2), dy = 2 * e[1] + e[4] - ((t >> 1) & 1),
-                                      dz = 2 * e[2] + e[5] - (t & 1);
-                            double v = 0.0;
-                            if (dx | dy | dz) {
-                                const double r = std::sqrt((double)(dx * dx + dy * dy + dz * dz));
-                                const double w0 = 1.0 / r, w3 = w0 * w0 * w0;
-                                v = comp == 0 ? w0 : (comp == 1 ? dx : comp == 2 ? dy : dz) * w3;
-                            }
-                            if (fp32)
-                                s.mm_a32[((w * kMmSteps + st) * 2 + i) * 64 + l] = (float)v;
-                            else
-                                s.mm_a[((w * kMmSteps + st) * 2 + i) * 64 + l] = v;
-                        }
-                }
-    }
     return s;
 }
 

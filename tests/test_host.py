@@ -199,59 +199,3 @@ def test_near_stage_table_loads_every_halo_cell_once():
         sx = d[np.all(l3 == (1, 0, 0), axis=1)][0] - base
         assert sy >= 9 and sx >= 9 * sy
         assert np.array_equal(d, base + l3[:, 0] * sx + l3[:, 1] * sy + l3[:, 2])
-
-
-@pytest.mark.parametrize("theta", [0.5, 0.55, 0.7])
-def test_near_field_matrix_tables(theta):
-    """The matrix-core near field: emulating the kernel's contraction with the
-    library's tables (one node, random masses in its 18^3 halo, the MFMA
-    operand layout A(row, k) at lane row + 16k, B(k, col) at lane col + 16k)
-    gives, for every block and target cell, the sums over exactly the
-    same-level partners whose parents are not well separated (d != 0):
-    sum m / |d| and sum m d / |d|^3, against a first-principles enumeration."""
-    a, a32, off, K = lib.octo_host_near_mm(theta)
-    D_max = 0
-    cnt = 0
-    for Dx in range(-2, 3):
-        for Dy in range(-2, 3):
-            for Dz in range(-2, 3):
-                cnt += (theta * theta) * (Dx * Dx + Dy * Dy + Dz * Dz) <= 1.0
-    assert K == 8 * cnt and K <= 4 * 4 * lib.MM_STEPS
-    rng = np.random.default_rng(3)
-    m = rng.uniform(0.0, 1.0, (18, 18, 18))
-    m[rng.uniform(size=m.shape) < 0.2] = 0.0
-    H = np.full(8 * 9 * 112, np.nan)
-    for ux in range(18):
-        for uy in range(18):
-            for uz in range(18):
-                q = ((ux & 1) << 2) | ((uy & 1) << 1) | (uz & 1)
-                H[q * 1008 + (ux >> 1) * 112 + (uy >> 1) * 12 + (uz >> 1)] = m[ux, uy, uz]
-    assert off.min() >= 0 and off.max() + 3 * 112 + 3 * 12 + 3 < H.size
-    cells = np.stack(np.meshgrid(np.arange(18), np.arange(18), np.arange(18), indexing="ij")).reshape(3, -1) - 5
-    mflat = m.reshape(-1)
-    S = lib.MM_STEPS
-    A = a.reshape(4, S, 2, 64)
-    A32 = a32.reshape(4, S, 2, 64).astype(np.float64)
-    O = off.reshape(4, S, 64)
-    t2 = theta * theta
-    for P in [(0, 0, 0), (3, 2, 1), (1, 3, 3), (2, 1, 0)]:
-        base = P[0] * 112 + P[1] * 12 + P[2]
-        B = H[O + base]  # (4, S, 64): partner mass of lane l (partner k = 4 (w S + s) + l / 16)
-        assert not np.any(np.isnan(B))
-        for i in range(2):
-            for rho in range(16):
-                lanes_a = rho + 16 * np.arange(4)
-                val64 = float(np.sum(A[:, :, i, lanes_a] * B[:, :, 16 * np.arange(4)]))
-                val32 = float(np.sum(A32[:, :, i, lanes_a] * B[:, :, 16 * np.arange(4)]))
-                for fp32, val in ((0, val64), (1, val32)):
-                    t = 4 * i + (rho >> 2 if fp32 else rho & 3)
-                    comp = rho & 3 if fp32 else rho >> 2
-                    x = np.array([2 * P[0] + (t >> 2), 2 * P[1] + ((t >> 1) & 1), 2 * P[2] + (t & 1)])
-                    d = cells - x[:, None]
-                    Dp = (cells >> 1) - (x >> 1)[:, None]
-                    keep = d.any(axis=0) & (t2 * (Dp * Dp).sum(axis=0).astype(float) <= 1.0)
-                    r = np.sqrt((d[:, keep] ** 2).sum(axis=0))
-                    w_ = 1.0 / r if comp == 0 else d[comp - 1, keep] / r ** 3
-                    ref = float(np.sum(mflat[keep] * w_))
-                    tol = 1e-6 if fp32 else 1e-13
-                    assert abs(val - ref) <= tol * max(1.0, abs(ref)), (P, i, rho, fp32, val, ref)
