@@ -50,11 +50,14 @@ class Record:
 
 
 class _Slot:
-    """A queued request and its tree build (a future of a tree handle)."""
+    """A queued request and its tree build (a future of a tree handle);
+    `frees` counts the trees the server had released when the build was
+    started."""
 
     def __init__(self, p: Payload):
         self.p = p
         self.build = None
+        self.frees = 0
 
 
 def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, poll_sleep: float = 2e-4,
@@ -67,6 +70,7 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
     import torch
 
     prof = dict(build_s=0.0, builds=0, admit_s=0.0, complete_s=0.0, idle_s=0.0, loops=0)
+    frees = [0]  # trees released so far (completed requests and builds given up)
 
     def release_lookahead(queue) -> bool:
         """Destroy the trees built ahead for queued requests after the head
@@ -77,6 +81,7 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                 try:
                     octo_tree_destroy(later.build.result())
                     freed = True
+                    frees[0] += 1
                 except OctoError:
                     pass
                 later.build = None
@@ -110,6 +115,7 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                 if k >= lookahead:
                     break
                 if slot.build is None:
+                    slot.frees = frees[0]
                     slot.build = pool.submit(build, slot.p)
             progressed = False
             prof["loops"] += 1
@@ -126,8 +132,10 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                         slot.build = None  # retry once completions free memory
                         break
                     # nothing on the device: release trees built ahead so the
-                    # head of the queue fits, then retry it
-                    if not release_lookahead(queue):
+                    # head of the queue fits, then retry it; also retry when
+                    # trees were released while the build ran (it may have
+                    # failed against memory that is free now)
+                    if not release_lookahead(queue) and frees[0] == slot.frees:
                         raise
                     slot.build = None
                     break
@@ -179,6 +187,7 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                 if keep_outputs:
                     outputs[p.index] = (phi.cpu().numpy(), g.cpu().numpy())
                 tree.destroy()
+                frees[0] += 1
                 progressed = True
             prof["complete_s"] += time.perf_counter() - a1
             if not progressed:
