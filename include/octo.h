@@ -154,6 +154,17 @@ octo_status octo_ctx_destroy(octo_ctx *ctx);
  * n_leaf_cells, device_ms and phase_ms are zero.  Other values:
  * OCTO_E_INVALID. */
 octo_status octo_ctx_set_profiling(octo_ctx *ctx, int on);
+/* Work shapes of octo_solve_batch with two or more trees.  mode 0 (the
+ * default): every tree runs its own single-tree plan, so each result is
+ * identical, bit for bit, to solving the tree alone.  mode 1: the shapes are
+ * fitted to the batch -- many trees fill the device together, so every
+ * level below the root takes the LDS-staged multipole kernel with one
+ * source-class group count for the whole batch, the one a launch-time model
+ * prices lowest -- and each result agrees with the tree's single solve to
+ * within rounding of the summation order (pair counts unchanged).  The
+ * request server (octo_submit) always runs each tree's own plan.  Other
+ * values: OCTO_E_INVALID. */
+octo_status octo_ctx_set_batch_shapes(octo_ctx *ctx, int mode);
 /* Bytes of device memory currently held by the context's trees. */
 octo_status octo_ctx_memory(const octo_ctx *ctx, size_t *bytes_in_use, size_t *budget);
 
@@ -238,7 +249,8 @@ octo_status octo_tree_autotune(octo_ctx *ctx, octo_tree *tree, const octo_opts *
  * trees together (the phases are captured once into a HIP graph per batch
  * signature and replayed).  phi[i], g[i] as in octo_solve for trees[i];
  * stats: NULL or n entries.  Results are identical, bit for bit, to solving
- * each tree alone.
+ * each tree alone (to within rounding of the summation order with
+ * batch-fitted work shapes, octo_ctx_set_batch_shapes).
  * status: NULL or n entries, each tree's own outcome: OCTO_OK (solved),
  * OCTO_E_INVALID (NULL tree or output, or a tree listed twice: the second
  * entry), OCTO_E_STATE (tree from another context); a failure of the call as

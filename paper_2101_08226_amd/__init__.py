@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "OCTO_OK", 1: "OCTO_E_INVALID", 2: "OCTO_E_DEVICE", 3: "OCTO_
 
 # every symbol include/octo.h declares
 EXPORTS = [
-    "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_tree_build", "octo_tree_build_uniform",
+    "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_ctx_set_batch_shapes", "octo_tree_build", "octo_tree_build_uniform",
     "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_get_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
     "octo_solve", "octo_solve_device_stats", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_step_noalloc", "octo_scf_run", "octo_regrid", "octo_submit", "octo_poll", "octo_wait", "octo_last_error", "octo_build_id",
     "octo_host_stencil_sizes", "octo_host_near_lists", "octo_host_near_stage", "octo_host_layout", "octo_host_adaptive_leaves",
@@ -134,6 +134,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_ctx_destroy": [_P],
         "octo_ctx_memory": [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
         "octo_ctx_set_profiling": [_P, _I],
+        "octo_ctx_set_batch_shapes": [_P, _I],
         "octo_tree_build": [_P, ctypes.POINTER(octo_leaf), _I64, _D, _I, _PP],
         "octo_tree_build_uniform": [_P, _I, _D, _I, _PP],
         "octo_tree_build_adaptive": [_P, DENSITY_FN, BOXMAX_FN, _P, _I, ctypes.c_double, _PP],
@@ -213,6 +214,10 @@ def octo_ctx_destroy(ctx: int) -> None:
 
 def octo_ctx_set_profiling(ctx: int, on) -> None:
     _check(load_library().octo_ctx_set_profiling(ctx, int(on)))
+
+
+def octo_ctx_set_batch_shapes(ctx: int, mode: int) -> None:
+    _check(load_library().octo_ctx_set_batch_shapes(ctx, int(mode)))
 
 
 def octo_ctx_memory(ctx: int):
@@ -485,6 +490,11 @@ class Context:
     def set_profiling(self, on) -> None:
         """0/False off; 1/True phase timings with statistics; 2 timings only."""
         octo_ctx_set_profiling(self.handle, int(on))
+
+    def set_batch_shapes(self, mode: int) -> None:
+        """Batches of several trees: 0 each tree's own plan (bitwise as
+        alone), 1 work shapes fitted to the batch."""
+        octo_ctx_set_batch_shapes(self.handle, int(mode))
 
     def uniform_tree(self, rho) -> "Tree":
         rho = np.ascontiguousarray(rho, dtype=np.float64)

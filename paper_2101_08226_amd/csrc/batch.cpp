@@ -87,17 +87,67 @@ void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipG
     check_hip(hipGraphLaunch(it->second, ctx->stream), "graph launch");
 }
 
-// Concatenate the single-tree plans of several trees.
-static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, const std::vector<TreeDesc> &descs) {
+// A tree's work lists inside a batch: every level below the root with
+// interior nodes takes the LDS-staged multipole kernel with g source-class
+// groups (at most the tree's partial slots); the root keeps its own choice.
+static const PlanHost &batch_lists(octo_tree *t, int g) {
+    auto it = t->ph_batch.find(g);
+    if (it != t->ph_batch.end()) return it->second;
+    const int nl = t->layout.n_levels;
+    std::vector<int> parts = t->parts, lds = t->m2l_lds;
+    for (int l = 1; l < nl; ++l)
+        if (t->layout.lv[l].n_int > 0) {
+            lds[l] = 1;
+            parts[l] = std::min(g, t->parts_alloc[l]);
+        }
+    PlanHost ph;
+    ph.levels = t->ph.levels;
+    ph.trees = t->ph.trees;
+    plan_items(t, parts, lds, ph);
+    return t->ph_batch.emplace(g, std::move(ph)).first->second;
+}
+
+// Concatenate the plans of several trees: each tree's own plan, or with
+// `fitted` (and several trees), shapes fitted to the batch.  Several trees
+// share each launch, so a level's few nodes no longer leave the device idle:
+// all levels below the root go to the LDS-staged kernel, with the
+// source-class group count (the same for every tree) that the launch model
+// prices lowest over the whole batch.
+static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, const std::vector<TreeDesc> &descs,
+                                             bool fitted) {
     auto bp = std::make_unique<BatchPlan>();
     bp->sig.assign(trees, trees + n);
     PlanHost &ph = bp->ph;
+    bool shared = fitted && n > 1;
+    for (int i = 0; i < n; ++i) shared = shared && trees[i]->leaf_lds;
+    int g_best = 0;
+    if (shared) {
+        double best = 1e300;
+        for (int g = 1; g <= 4; g *= 2) {
+            std::vector<int64_t> n_int;
+            std::vector<int> gs;
+            for (int i = 0; i < n; ++i)
+                for (int l = 1; l < trees[i]->layout.n_levels; ++l)
+                    if (trees[i]->layout.lv[l].n_int > 0) {
+                        n_int.push_back(trees[i]->layout.lv[l].n_int);
+                        gs.push_back(std::min(g, trees[i]->parts_alloc[l]));
+                    }
+            if (n_int.empty()) break;
+            const double c = lds_launch_cost(n_int, gs, trees[0]->ctx->n_cu);
+            if (c < best - 1e-9) {
+                best = c;
+                g_best = g;
+            }
+        }
+    }
+    std::vector<const PlanHost *> src(n);
+    for (int i = 0; i < n; ++i) src[i] = g_best ? &batch_lists(trees[i], g_best) : &trees[i]->ph;
     size_t max_lv = 0;
-    for (int i = 0; i < n; ++i) max_lv = std::max(max_lv, trees[i]->ph.interior.size());
+    for (int i = 0; i < n; ++i) max_lv = std::max(max_lv, src[i]->interior.size());
     ph.interior.resize(max_lv);
     ph.l2l.resize(max_lv);
     for (int i = 0; i < n; ++i) {
-        const PlanHost &t = trees[i]->ph;
+        const PlanHost &t = *src[i];
         const int base = (int)ph.levels.size();
         for (LevelDesc d : t.levels) {
             if (d.parent_ld >= 0) d.parent_ld += base;
@@ -326,7 +376,7 @@ static void pump(octo_ctx *ctx) {
                 trees.push_back(r.tree);
                 descs.push_back(desc_for(r.tree, r.phi, r.g, &r.opts));
             }
-            bp = make_batch(trees.data(), (int)trees.size(), descs);
+            bp = make_batch(trees.data(), (int)trees.size(), descs, false);
             bytes = plan_layout(bp->ph, nullptr, bp->plan, img);
             try {
                 mem = ctx->dev_alloc(bytes);
@@ -451,11 +501,12 @@ static octo_status solve_batch_impl(octo_ctx *ctx, octo_tree *const *trees_in, i
         octo_stats *stats = stats_in ? st_v.data() : nullptr;
         hipSetDevice(ctx->device);
         std::vector<octo_tree *> sig(trees, trees + n);
-        if (!ctx->batch || ctx->batch->sig != sig) {
+        if (!ctx->batch || ctx->batch->sig != sig || ctx->batch->fitted != (ctx->batch_shapes == 1)) {
             ctx->invalidate_batches();
             std::vector<TreeDesc> descs;
             for (int i = 0; i < n; ++i) descs.push_back(trees[i]->ph.trees[0]);
-            auto bp = make_batch(trees, n, descs);
+            auto bp = make_batch(trees, n, descs, ctx->batch_shapes == 1);
+            bp->fitted = ctx->batch_shapes == 1;
             const size_t bytes = plan_bytes(bp->ph);
             bp->mem = ctx->dev_alloc(bytes);
             bp->bytes = bytes;

@@ -79,6 +79,44 @@ struct TreeBlock {
     size_t rho = 0, stage = 0, upload = 0, bytes = 0;
 };
 
+}  // namespace
+
+namespace octo {
+// Modelled time of one launch of the LDS-staged multipole kernel over levels
+// of n_int[i] nodes split into g[i] source-class groups each: the items are
+// dealt to the 8 XCDs in equal shares of every level, larger items first
+// (the order the plans give them), and each XCD's CUs take the next item as
+// they free up; the time is the simulated makespan in class-rounds (a round
+// stages and walks one class per work-group, one work-group per CU at a
+// time) plus the downward pass reading g partial slots per node: on MI355X
+// one slot of one node costs about 0.002 of a class-round (uniform 128^3:
+// 23.6 us per class-round, 0.047 us per node-slot).
+double lds_launch_cost(const std::vector<int64_t> &n_int, const std::vector<int> &g, int n_cu) {
+    const int cus = std::max(8, n_cu), per_xcd = std::max(1, cus / 8);
+    std::vector<std::pair<int, int64_t>> groups;  // (classes per item, items per XCD)
+    double slots = 0.0;
+    for (size_t i = 0; i < n_int.size(); ++i) {
+        groups.push_back({8 / g[i], (n_int[i] * g[i] + 7) / 8});
+        slots += (double)n_int[i] * g[i];
+    }
+    std::sort(groups.begin(), groups.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    std::map<int64_t, int64_t> load{{0, per_xcd}};  // CU load -> number of CUs
+    for (const auto &gr : groups) {
+        int64_t left = gr.second;
+        while (left > 0) {
+            auto it = load.begin();
+            const int64_t at = it->first, k = std::min(left, it->second);
+            if ((it->second -= k) == 0) load.erase(it);
+            load[at + gr.first] += k;
+            left -= k;
+        }
+    }
+    return (double)load.rbegin()->first + 0.002 * slots;
+}
+}  // namespace octo
+
+namespace {
+
 // Per-level work shapes (partial slots, LDS-staged multipole kernel) and the
 // data block's offsets: host work only, no context state but its CU count.
 void shape_tree(octo_tree *t, TreeBlock &B) {
@@ -99,15 +137,9 @@ void shape_tree(octo_tree *t, TreeBlock &B) {
         t->m2l_lds[l] = (lds && l >= 1 && t->parts[l] == 1) ? 1 : 0;
     }
     // The LDS-staged levels share one launch: split each node's source parity
-    // classes into g_l groups per level (one work-group each, one work-group
-    // per CU at a time).  The items are dealt to the 8 XCDs in equal shares of
-    // every level, larger items first (the order build_tree_plan gives them),
-    // and each XCD's CUs take the next item as they free up; the time is the
-    // simulated makespan in class-rounds (a round stages and walks one class
-    // per work-group) plus the downward pass reading g_l partial slots per
-    // node: on MI355X one slot of one node costs about 0.002 of a class-round
-    // (c2: 23.6 us per class-round, 0.047 us per node-slot).  Levels are
-    // tuned one at a time from a common best g, fewest nodes first.
+    // classes into g_l groups per level (one work-group each), priced by
+    // lds_launch_cost.  Levels are tuned one at a time from a common best g,
+    // fewest nodes first.
     {
         std::vector<int> lds_levels;
         int g_max = 8;
@@ -117,30 +149,9 @@ void shape_tree(octo_tree *t, TreeBlock &B) {
                 g_max = std::min(g_max, t->parts_alloc[l]);
             }
         if (!lds_levels.empty()) {
-            const int cus = std::max(8, ctx->n_cu), per_xcd = std::max(1, cus / 8);
-            auto cost = [&](const std::vector<int> &g) {
-                // items of each level: (8 / g) classes, n_int * g of them, 1/8 to each XCD
-                std::vector<std::pair<int, int64_t>> groups;  // (classes per item, items per XCD)
-                double slots = 0.0;
-                for (size_t i = 0; i < lds_levels.size(); ++i) {
-                    const int64_t n = L.lv[lds_levels[i]].n_int;
-                    groups.push_back({8 / g[i], (n * g[i] + 7) / 8});
-                    slots += (double)n * g[i];
-                }
-                std::sort(groups.begin(), groups.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
-                std::map<int64_t, int64_t> load{{0, per_xcd}};  // CU load -> number of CUs
-                for (const auto &gr : groups) {
-                    int64_t left = gr.second;
-                    while (left > 0) {
-                        auto it = load.begin();
-                        const int64_t at = it->first, k = std::min(left, it->second);
-                        if ((it->second -= k) == 0) load.erase(it);
-                        load[at + gr.first] += k;
-                        left -= k;
-                    }
-                }
-                return (double)load.rbegin()->first + 0.002 * slots;
-            };
+            std::vector<int64_t> n_int;
+            for (int l : lds_levels) n_int.push_back(L.lv[l].n_int);
+            auto cost = [&](const std::vector<int> &g) { return lds_launch_cost(n_int, g, ctx->n_cu); };
             std::vector<int> g(lds_levels.size(), 1);
             double best_cost = 1e300;
             for (int gu = 1; gu <= g_max; gu *= 2) {
@@ -296,9 +307,41 @@ namespace octo {
 // The plan image goes up from pinned staging, ordered on the context stream.
 void build_tree_plan(octo_tree *t) {
     octo_ctx *ctx = t->ctx;
+    PlanHost &ph = t->ph;
+    plan_items(t, t->parts, t->m2l_lds, ph);
+    t->ph_batch.clear();
+    const size_t bytes = plan_bytes(ph);
+    void *mem = ctx->dev_alloc(bytes);
+    const TreeDesc keep = t->plan.trees_host.empty() ? ph.trees[0] : t->plan.trees_host[0];
+    if (t->plan_block.ptr) {
+        // a rebuilt plan: the old one may still be in use by queued work
+        check_hip(hipStreamSynchronize(ctx->stream), "plan rebuild");
+        ctx->dev_free(t->plan_block.ptr, t->plan_block.bytes);
+    }
+    t->plan_block.ptr = mem;
+    t->plan_block.bytes = bytes;
+    ph.trees[0] = keep;
+    std::vector<char> img;
+    plan_layout(ph, mem, t->plan, img);
+    size_t got = 0;
+    void *pin = ctx->pinned_get(img.size(), &got);
+    memcpy(pin, img.data(), img.size());
+    check_hip(hipMemcpyAsync(mem, pin, img.size(), hipMemcpyHostToDevice, ctx->stream), "plan upload");
+    hipEvent_t done = nullptr;
+    check_hip(hipEventCreateWithFlags(&done, hipEventDisableTiming), "event");
+    check_hip(hipEventRecord(done, ctx->stream), "event");
+    ctx->pinned_put(pin, got, done);
+    drop_graphs(t->graphs);
+    t->bytes = t->data.bytes + bytes;
+}
+
+// The work lists of a tree's plan for given per-level choices: LDS-staged
+// multipole kernel or not, and partial slots (source-class groups of the
+// LDS-staged kernel, stencil chunks of the per-wavefront one); ph holds the
+// tree's level and tree descriptors already.
+void plan_items(const octo_tree *t, const std::vector<int> &parts, const std::vector<int> &m2l_lds, PlanHost &ph) {
     const Layout &L = t->layout;
     const int nl = L.n_levels;
-    PlanHost &ph = t->ph;
     ph.m2l.clear();
     ph.m2l_nodes.clear();
     ph.m2l_leaf.clear();
@@ -313,22 +356,22 @@ void build_tree_plan(octo_tree *t) {
     std::vector<std::vector<char>> defer(nl);
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
-        defer[l].assign(h.n_int, t->parts[l] <= 4 ? 1 : 0);
+        defer[l].assign(h.n_int, parts[l] <= 4 ? 1 : 0);
         for (int n = 0; n < h.n_int; ++n)
             for (int k = 0; k < 8; ++k)
                 if (h.child[8 * n + k] < L.lv[l + 1].n_int) defer[l][n] = 0;
     }
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
-        ph.levels[l].n_parts = t->parts[l];
+        ph.levels[l].n_parts = parts[l];
         for (int n = h.n_int; n < h.n_nodes; ++n) ph.p2m.push_back(NodeItem{l, n});
         for (int n = 0; n < h.n_int; ++n) {
             ph.interior[l].push_back(NodeItem{l, n});
             if (!defer[l][n]) ph.l2l[l].push_back(NodeItem{l, n});
         }
         for (int n = 0; n < h.n_int; ++n) {
-            if (t->m2l_lds[l]) continue;  // ordered below
-            for (int c = 0; c < t->parts[l]; ++c)
+            if (m2l_lds[l]) continue;  // ordered below
+            for (int c = 0; c < parts[l]; ++c)
                 for (int p = 0; p < 8; ++p) ph.m2l.push_back(M2LItem{l, n, p, c});
         }
         // leaf targets next to interior nodes: staged in LDS (below the root)
@@ -351,14 +394,14 @@ void build_tree_plan(octo_tree *t) {
     {
         std::vector<std::vector<M2LItem>> lv_items;
         for (int l = 0; l < nl; ++l) {
-            if (!t->m2l_lds[l] || L.lv[l].n_int == 0) continue;
+            if (!m2l_lds[l] || L.lv[l].n_int == 0) continue;
             std::vector<M2LItem> v;
             for (int n = 0; n < L.lv[l].n_int; ++n)
-                for (int c = 0; c < t->parts[l]; ++c) v.push_back(M2LItem{l, n, 0, c});
+                for (int c = 0; c < parts[l]; ++c) v.push_back(M2LItem{l, n, 0, c});
             lv_items.push_back(std::move(v));
         }
         std::stable_sort(lv_items.begin(), lv_items.end(), [&](const auto &a, const auto &b) {
-            return t->parts[a[0].ld] < t->parts[b[0].ld];  // fewer groups = more classes per item
+            return parts[a[0].ld] < parts[b[0].ld];  // fewer groups = more classes per item
         });
         size_t total = 0;
         for (const auto &v : lv_items) total += v.size();
@@ -386,30 +429,8 @@ void build_tree_plan(octo_tree *t) {
     ph.tree_m2l_beg = {0, (int32_t)ph.m2l.size()};
     ph.tree_m2ln_beg = {0, (int32_t)ph.m2l_nodes.size()};
     ph.tree_m2lf_beg = {0, (int32_t)ph.m2l_leaf.size()};
-    const size_t bytes = plan_bytes(ph);
-    void *mem = ctx->dev_alloc(bytes);
-    const TreeDesc keep = t->plan.trees_host.empty() ? ph.trees[0] : t->plan.trees_host[0];
-    if (t->plan_block.ptr) {
-        // a rebuilt plan: the old one may still be in use by queued work
-        check_hip(hipStreamSynchronize(ctx->stream), "plan rebuild");
-        ctx->dev_free(t->plan_block.ptr, t->plan_block.bytes);
-    }
-    t->plan_block.ptr = mem;
-    t->plan_block.bytes = bytes;
-    ph.trees[0] = keep;
-    std::vector<char> img;
-    plan_layout(ph, mem, t->plan, img);
-    size_t got = 0;
-    void *pin = ctx->pinned_get(img.size(), &got);
-    memcpy(pin, img.data(), img.size());
-    check_hip(hipMemcpyAsync(mem, pin, img.size(), hipMemcpyHostToDevice, ctx->stream), "plan upload");
-    hipEvent_t done = nullptr;
-    check_hip(hipEventCreateWithFlags(&done, hipEventDisableTiming), "event");
-    check_hip(hipEventRecord(done, ctx->stream), "event");
-    ctx->pinned_put(pin, got, done);
-    drop_graphs(t->graphs);
-    t->bytes = t->data.bytes + bytes;
 }
+
 }  // namespace octo
 
 namespace {
@@ -619,6 +640,15 @@ octo_status octo_ctx_set_profiling(octo_ctx *ctx, int on) {
         if (on < 0 || on > 2) fail(OCTO_E_INVALID, "profiling mode must be 0, 1 or 2");
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         ctx->profiling = on;
+    });
+}
+
+octo_status octo_ctx_set_batch_shapes(octo_ctx *ctx, int mode) {
+    return guard([&] {
+        if (!ctx) fail(OCTO_E_INVALID, "ctx is NULL");
+        if (mode != 0 && mode != 1) fail(OCTO_E_INVALID, "batch shape mode must be 0 or 1");
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        ctx->batch_shapes = mode;
     });
 }
 

@@ -169,6 +169,7 @@ struct BatchPlan {
     void *staging = nullptr;  // pinned upload image (asynchronous waves), from the context's pool
     size_t staging_bytes = 0;
     std::vector<double> stats;  // per tree, 12 values, after completion
+    bool fitted = false;        // work shapes fitted to the batch (not each tree's own)
 };
 
 // an asynchronous request
@@ -222,6 +223,7 @@ struct octo_ctx {
     hipEvent_t fork_near_ev = nullptr, join_near_ev = nullptr;
     bool use_graphs = true;
     int profiling = 0;  // 0 off, 1 phase timings with statistics, 2 phase timings only
+    int batch_shapes = 0;  // 1: octo_solve_batch fits the work shapes to the whole batch
     hipEvent_t phase_ev[9] = {};
     double *h_stats = nullptr;  // pinned host staging for stats
     // pinned upload buffers, reused (freeing pinned memory can wait for the
@@ -263,6 +265,9 @@ struct octo_tree {
     octo::DeviceBlock data;        // tables + fields
     octo::DeviceBlock plan_block;  // work plan
     std::vector<int> parts_alloc, parts, m2l_lds;  // per level: multipole work choices
+    // work lists for batched solves by source-class group count (every level
+    // below the root LDS-staged), built on first use
+    std::map<int, octo::PlanHost> ph_batch;
     bool leaf_lds = true;  // leaf targets of multipole work in the LDS-staged kernel
     double *rho = nullptr;
     double *stage = nullptr;  // device staging of phi, g for host outputs
@@ -319,4 +324,6 @@ struct RegridOut {
 };
 void regrid_device(octo_ctx *ctx, octo_tree *t, int l_max, double rho_r, RegridOut &r);
 void build_tree_plan(octo_tree *t);
+void plan_items(const octo_tree *t, const std::vector<int> &parts, const std::vector<int> &m2l_lds, PlanHost &ph);
+double lds_launch_cost(const std::vector<int64_t> &n_int, const std::vector<int> &g, int n_cu);
 }  // namespace octo

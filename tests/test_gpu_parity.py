@@ -16,6 +16,10 @@ from helpers import random_amr_leaves, zero_block_density
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
+# batch-fitted work shapes against each tree's own plan: the same FP64 sums
+# taken in another order; a few thousand terms per target bound the relative
+# change by about n * 2^-53 ~ 1e-13
+FITTED_TOL = 1e-13
 
 
 def say(*a):
@@ -419,10 +423,29 @@ def test_c4_batched_mix(ctx):
         say(f"  prec={prec}: batch == single for all trees, worst torque {max(s['torque'] for s in sts):.2e}")
         if prec == lib.OCTO_FP64:
             assert max(s["torque"] for s in sts) < 1e-13
-            fp64 = outs
         else:
             # 4x the worst mixed torque measured over the 256 trees (2.40e-8)
             assert max(s["torque"] for s in sts) < 1e-7
+        # work shapes fitted to the batch: the same sums in another order
+        ctx.set_batch_shapes(1)
+        try:
+            outs_f, sts_f = ctx.solve_batch(trees, precision=prec)
+            torch.cuda.synchronize()
+        finally:
+            ctx.set_batch_shapes(0)
+        worst = 0.0
+        for i in range(len(trees)):
+            e = errs(outs_f[i][0].cpu().numpy(), outs_f[i][1].cpu().numpy(), outs[i][0].cpu().numpy(),
+                     outs[i][1].cpu().numpy())
+            worst = max(worst, e[0], e[1])
+            assert sts_f[i]["m2l_pairs"] == sts[i]["m2l_pairs"] and sts_f[i]["direct_pairs"] == sts[i]["direct_pairs"]
+        say(f"  prec={prec}: fitted shapes vs own plans: worst relative difference {worst:.2e}")
+        assert worst <= FITTED_TOL
+        if prec == lib.OCTO_FP64:
+            assert max(s["torque"] for s in sts_f) < 1e-13
+            fp64 = outs_f  # the oracle check below takes the fitted-shape results
+        else:
+            assert max(s["torque"] for s in sts_f) < 1e-7
     from helpers import grid_ids
 
     rng = np.random.default_rng(10)
@@ -512,7 +535,9 @@ def test_device_stats(ctx):
 
 def test_batch_mixed_sizes_and_precision(ctx):
     """Trees of different depths in one batch (levels 0-3 and adaptive): every
-    result bitwise equal to its single solve, in both precisions."""
+    result bitwise equal to its single solve, in both precisions; with work
+    shapes fitted to the batch, equal to it to within rounding of the
+    summation order, on graph replay too."""
     rng = np.random.default_rng(9)
     trees = [ctx.uniform_tree(rng.uniform(0.1, 1.0, (n, n, n))) for n in (8, 64, 16)]
     leaves, f = random_amr_leaves(24, max_level=3, n_stars=1)
@@ -523,6 +548,23 @@ def test_batch_mixed_sizes_and_precision(ctx):
         outs, sts = ctx.solve_batch(trees, precision=prec)
         for (p, g), (ps, gs) in zip(outs, single):
             assert np.array_equal(p.cpu().numpy(), ps) and np.array_equal(g.cpu().numpy(), gs)
+        ctx.set_batch_shapes(1)
+        try:
+            first = None
+            for _ in range(2):  # capture, then replay
+                outs_f, sts_f = ctx.solve_batch(trees, precision=prec)
+                got = [(p.cpu().numpy(), g.cpu().numpy()) for p, g in outs_f]
+                for (p, g), (ps, gs) in zip(got, single):
+                    e = errs(p, g, ps, gs)
+                    assert e[0] <= FITTED_TOL and e[1] <= FITTED_TOL, e
+                if first is not None:
+                    for (p, g), (p0, g0) in zip(got, first):
+                        assert np.array_equal(p, p0) and np.array_equal(g, g0)
+                first = got
+            for a_, b_ in zip(sts_f, sts):
+                assert a_["m2l_pairs"] == b_["m2l_pairs"] and a_["direct_pairs"] == b_["direct_pairs"]
+        finally:
+            ctx.set_batch_shapes(0)
     for t in trees:
         t.destroy()
 
