@@ -357,12 +357,14 @@ __global__ __launch_bounds__(256) void k_m2m_src(const LevelDesc *__restrict__ L
 // angular-momentum correction: C_A += -(1/6) [M3_B - (m_B/m_A) M3_A] : D4(R).
 // G is applied once at the end.
 // Accumulators of one target: L0, L1 directly; L2 and L3 as the sums
-// T2 = sum m f2 R R, s1 = sum m f1, T3 = sum m f3 R R R, U = sum m f2 R, from
-// which L2 = -(T2 + s1 I) and L3 = -(T3 + sym(I U)) are formed once at the
-// end (finish_l2_l3); C is the correction.
+// T2 = sum m f2 R R and T3 = sum m f3 R R R, from which L2 = -(T2 + s1 I)
+// and L3 = -(T3 + sym(I U)) are formed once at the end (finish_l2_l3), with
+// s1 = sum m f1 and U = sum m f2 R taken from the traces of T2 and T3: the
+// derivative tensors of 1/r are trace-free (f2 r^2 = -3 f1, f3 r^2 = -5 f2),
+// so tr T2 = -3 s1 and the (a,a,c) trace of T3 is -5 U_c; C is the correction.
 template <typename T>
 struct Acc {
-    T L0, L1[3], L2[6], L3[10], s1, U[3];
+    T L0, L1[3], L2[6], L3[10];
     double C[3];
     T A2, A3;  // FP64 density solves: parts of L0 (m2l_pair_f64)
 };
@@ -370,13 +372,11 @@ struct Acc {
 template <typename T>
 __device__ inline void acc_zero(Acc<T> &a) {
     a.L0 = (T)0;
-    a.s1 = (T)0;
     a.A2 = (T)0;
     a.A3 = (T)0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         a.L1[k] = (T)0;
-        a.U[k] = (T)0;
         a.C[k] = 0.0;
     }
 #pragma unroll
@@ -393,26 +393,33 @@ __device__ inline void acc_close(Acc<T> &a) {
     for (int k = 0; k < 10; ++k) a.L3[k] *= -15.0;
 }
 
-// L2 = -(T2 + s1 I); L3_abc = -(T3_abc + d_ab U_c + d_ac U_b + d_bc U_a)
+// L2 = -(T2 + s1 I); L3_abc = -(T3_abc + d_ab U_c + d_ac U_b + d_bc U_a),
+// with s1 = -tr(T2) / 3 and U_c = -(T3_xxc + T3_yyc + T3_zzc) / 5 (T3 as
+// scaled by acc_close, L2 holding T2 and the dipole terms, whose trace is
+// the dipole's part of -3 s1)
 template <typename T>
 __device__ inline void finish_l2_l3(Acc<T> &a) {
-    a.L2[0] = -(a.L2[0] + a.s1);
+    const T s1 = -(a.L2[0] + a.L2[3] + a.L2[5]) * (T)(1.0 / 3.0);
+    const T Ux = -(a.L3[0] + a.L3[3] + a.L3[5]) * (T)0.2;
+    const T Uy = -(a.L3[1] + a.L3[6] + a.L3[8]) * (T)0.2;
+    const T Uz = -(a.L3[2] + a.L3[7] + a.L3[9]) * (T)0.2;
+    a.L2[0] = -(a.L2[0] + s1);
     a.L2[1] = -a.L2[1];
     a.L2[2] = -a.L2[2];
-    a.L2[3] = -(a.L2[3] + a.s1);
+    a.L2[3] = -(a.L2[3] + s1);
     a.L2[4] = -a.L2[4];
-    a.L2[5] = -(a.L2[5] + a.s1);
+    a.L2[5] = -(a.L2[5] + s1);
     const T three = (T)3;
-    a.L3[0] = -(a.L3[0] + three * a.U[0]);
-    a.L3[1] = -(a.L3[1] + a.U[1]);
-    a.L3[2] = -(a.L3[2] + a.U[2]);
-    a.L3[3] = -(a.L3[3] + a.U[0]);
+    a.L3[0] = -(a.L3[0] + three * Ux);
+    a.L3[1] = -(a.L3[1] + Uy);
+    a.L3[2] = -(a.L3[2] + Uz);
+    a.L3[3] = -(a.L3[3] + Ux);
     a.L3[4] = -a.L3[4];
-    a.L3[5] = -(a.L3[5] + a.U[0]);
-    a.L3[6] = -(a.L3[6] + three * a.U[1]);
-    a.L3[7] = -(a.L3[7] + a.U[2]);
-    a.L3[8] = -(a.L3[8] + a.U[1]);
-    a.L3[9] = -(a.L3[9] + three * a.U[2]);
+    a.L3[5] = -(a.L3[5] + Ux);
+    a.L3[6] = -(a.L3[6] + three * Uy);
+    a.L3[7] = -(a.L3[7] + Uz);
+    a.L3[8] = -(a.L3[8] + Uy);
+    a.L3[9] = -(a.L3[9] + three * Uz);
 }
 
 // Multipole-to-local of one ordered pair, on trace-free source moments (q5,
@@ -432,13 +439,11 @@ __device__ inline void finish_l2_l3(Acc<T> &a) {
 //   L0 = -(A0 + 3/2 A2 + 5/2 A3), A0 = sum m g, A2 = sum p2 R.Q'.R,
 //        A3 = sum p3 O':RRR (A0 kept in L0 until acc_close);
 //   L1_a += (m p1 + 15/2 p3 R.Q'.R) R_a - 3 p2 (Q'R)_a;
-//   s1 -= m p1;  T2 += 3 m p2 RR;  U += 3 m p2 R;
-//   T3 += m p3 RRR (scaled by -15 in acc_close);
+//   T2 += 3 m p2 RR;  T3 += m p3 RRR (scaled by -15 in acc_close);
 //   C_a += 15/2 p3 (n:RR)_a - 35/2 p4 (n:RR.R) R_a.
 // DIP (a second source with a dipole d about the density's centre, w = d.R,
 // no correction): A0 also sums p1 w; the L1 coefficient gains 3 p2 w and
-// L1_a gains -p1 d_a; s1 -= 3 p2 w; T2 += 15 p3 w RR; and
-// L2_ab -= 3 p2 (d_a R_b + d_b R_a).
+// L1_a gains -p1 d_a; T2 += 15 p3 w RR; and L2_ab -= 3 p2 (d_a R_b + d_b R_a).
 // Every update is one fused multiply-add.
 template <bool LEAF_TARGET, bool DIP>
 __device__ inline void m2l_pair_f64(double Rx, double Ry, double Rz, double mB, const double *q, const double *o,
@@ -486,7 +491,6 @@ __device__ inline void m2l_pair_f64(double Rx, double Ry, double Rz, double mB, 
         a.L1[2] = __builtin_fma(-p1, dz, a.L1[2]);
     }
     if (!LEAF_TARGET) {
-        a.s1 -= mp1w;
         const double m2 = mB * k2;
         const double e2 = DIP ? __builtin_fma(2.0 * k3, dw, m2) : m2;
         a.L2[0] = __builtin_fma(e2, xx, a.L2[0]);
@@ -504,9 +508,6 @@ __device__ inline void m2l_pair_f64(double Rx, double Ry, double Rz, double mB, 
             a.L2[4] = __builtin_fma(-fy, Rz, __builtin_fma(-fz, Ry, a.L2[4]));
             a.L2[5] = __builtin_fma(-2.0 * fz, Rz, a.L2[5]);
         }
-        a.U[0] = __builtin_fma(m2, Rx, a.U[0]);
-        a.U[1] = __builtin_fma(m2, Ry, a.U[1]);
-        a.U[2] = __builtin_fma(m2, Rz, a.U[2]);
         const double m3 = mB * p3;
         const double m3x = m3 * Rx, m3y = m3 * Ry, m3z = m3 * Rz;
         a.L3[0] = __builtin_fma(m3x, xx, a.L3[0]);
@@ -681,20 +682,21 @@ __global__ __launch_bounds__(64) void k_m2l(const LevelDesc *__restrict__ L, con
 
 
 #ifndef OCTO_M2L_UNROLL
-#define OCTO_M2L_UNROLL 2
+#define OCTO_M2L_UNROLL 1
 #endif
 
 // Multipole-to-local for all 512 cells of one interior node (LEAF: of one
 // leaf node next to interior nodes of its level, whose cells take only L0, L1
 // and the correction from the interior cells), with the source halo staged in
-// LDS one parity class at a time: the cells of one parity class
-// within 5 cells of the node form a 9x9x9 lattice; each staged cell holds its
-// mass, centre of mass and trace-free moments (16 FP64 values in 8 double2
-// planes, 124 KB; DIP: + the dipole, 10 planes, 155 KB).  Every wavefront (one
-// target parity class) walks the part of its stencil whose sources fall in
-// the staged class.
+// LDS one parity class at a time: the cells of one parity class whose parent
+// cells lie within 2 parent cells of the node form an 8x8x8 lattice, one cell
+// per thread; each staged cell holds its mass, centre of mass and trace-free
+// moments (16 FP64 values in 8 double2 planes, 68 KB: two work-groups per CU,
+// four wavefronts per SIMD, at most 128 VGPRs; DIP: + the dipole, 10 planes,
+// 85 KB, one work-group per CU).  Every wavefront (one target parity class)
+// walks the part of its stencil whose sources fall in the staged class.
 template <typename T, bool DIP, bool AMC, bool LEAF>
-__global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
+__global__ __launch_bounds__(512, DIP ? 2 : 4) void k_m2l_lds(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ TD,
                                                  const M2LItem *__restrict__ items, int n_items, StencilDev st,
                                                  int64_t *__restrict__ cnt_out, int count) {
     const int it = xcd_item(n_items);
@@ -703,8 +705,9 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     const LevelDesc ld = L[item.ld];
     const TreeDesc td = TD[ld.tree];
     const int node = item.node;
-    // halo of one source class: 9x9x9 lattice, rows padded to 12 so that the
-    // lanes of each 16-byte LDS read phase hit distinct banks
+    // halo of one source class: 8x8x8 lattice, x-planes padded to 68 so that
+    // the 8 lanes of each 16-byte LDS read phase (4 z x 2 x positions, see
+    // the lane order below) hit distinct banks
     constexpr int NV = DIP ? 10 : 8;  // double2 planes per source cell
     constexpr int HY = kHaloY, HX = kHaloX, HN = kHaloN;
     __shared__ double2 s_src[NV][HN];
@@ -714,7 +717,10 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     // wave-uniform (one wavefront per parity class): keep it in a scalar register
     const int p = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     if (tid < 27) s_nbr[tid] = ld.nbr[node * 27 + tid];
-    const int s = tid;  // parity-major storage: wavefront p holds class p
+    // wavefront p holds target class p (parity-major storage: cell
+    // p << 6 | i << 4 | j << 2 | k at lattice position (i, j, k)); lane
+    // j << 4 | i << 2 | k, so that consecutive lanes run over k, then i
+    const int s = (p << 6) | (((lane >> 2) & 3) << 4) | ((lane >> 4) << 2) | (lane & 3);
     int x, y, z;
     local_xyz(s, x, y, z);
     const size_t S = (size_t)ld.n_rec * kCells;
@@ -748,72 +754,48 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
     for (int q = 0; q < 8; ++q)
         for (int pp = 0; pp < 8; ++pp)
             if (st.m2l_src_any[pp * 8 + q] & src_mask) q_need |= 1 << q;
-    // Source class q staged in LDS: lattice index i in [0,9) <-> local
-    // coordinate 2i - 4 - parity.  Cells that are not sources get mass -0.0
-    // (counted as absent, contributes exact zeros) and a far-away centre.  A
-    // class's global loads (both cells of this thread, all in flight
-    // together) are issued as soon as this wavefront has finished the
-    // previous class, so that they overlap the other wavefronts' remaining
-    // pairs and the barrier; the LDS stores follow the barrier.
-    // (The neighbour lookups of both cells come before their loads, and the
-    // loads go through the global address space: a generic (flat) load also
-    // counts as an LDS access, so the second lookup's wait would otherwise
-    // wait for the first cell's loads.)
-    double v[2][23];
+    // Source class q staged in LDS, one cell per thread: lattice index
+    // i in [0,8) <-> local coordinate 2i - 4 + parity.  Cells that are not
+    // sources get mass -0.0 (counted as absent, contributes exact zeros) and
+    // a far-away centre.  The loads go through the global address space (a
+    // generic load also counts as an LDS access); the other work-group on
+    // the CU computes while this one stages.
     const GPtr<const double> gmass = gptr(ld.mass), gmp = gptr(ld.mp), gdip = gptr(ld.dip);
-    auto load_class = [&](int q) {
-        const int qx = q >> 2, qy = (q >> 1) & 1, qz = q & 1;
-        int nb[2], si[2];
+    const int cx = tid >> 6, cy = (tid >> 3) & 7, cz = tid & 7;
+    auto stage_class = [&](int q) {
+        const int sx = 2 * cx - 4 + (q >> 2), sy = 2 * cy - 4 + ((q >> 1) & 1), sz = 2 * cz - 4 + (q & 1);
+        const int nb = s_nbr[nbr_slot(sx, sy, sz)];
+        double v[23];
+        if (nb >= 0 && nb < n_src) {
+            const size_t si = (size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7);
+            v[0] = gmass[si];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int cc = tid + 512 * u;
-            const int ix = cc / 81, iy = (cc / 9) % 9, iz = cc % 9;
-            const int sx = 2 * ix - 4 - qx, sy = 2 * iy - 4 - qy, sz = 2 * iz - 4 - qz;
-            nb[u] = cc < 729 ? s_nbr[nbr_slot(sx, sy, sz)] : -1;
-            si[u] = store_idx(sx & 7, sy & 7, sz & 7);
+            for (int k = 0; k < kRec; ++k) v[1 + k] = gmp[k * S + si];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[20 + k] = DIP ? gdip[k * S + si] : 0.0;
+        } else {
+            v[0] = -0.0;
+            v[1] = v[2] = v[3] = 1.0e3;
+#pragma unroll
+            for (int k = 4; k < 23; ++k) v[k] = 0.0;
         }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            if (nb[u] >= 0 && nb[u] < n_src) {
-                const size_t si_ = (size_t)nb[u] * kCells + si[u];
-                v[u][0] = gmass[si_];
-#pragma unroll
-                for (int k = 0; k < kRec; ++k) v[u][1 + k] = gmp[k * S + si_];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) v[u][20 + k] = DIP ? gdip[k * S + si_] : 0.0;
-            } else {
-                v[u][0] = -0.0;
-                v[u][1] = v[u][2] = v[u][3] = 1.0e3;
-#pragma unroll
-                for (int k = 4; k < 23; ++k) v[u][k] = 0.0;
-            }
+        // record: m z(3) q5 o7 [d(3) 0]
+        double r[2 * NV];
+        r[0] = v[0];
+        r[1] = v[1];
+        r[2] = v[2];
+        r[3] = v[3];
+        detrace_q(&v[4], &r[4]);
+        detrace_o(&v[10], &r[9]);
+        if (DIP) {
+            r[16 % (2 * NV)] = v[20];
+            r[17 % (2 * NV)] = v[21];
+            r[18 % (2 * NV)] = v[22];
+            r[19 % (2 * NV)] = 0.0;
         }
-    };
-    auto store_class = [&]() {
+        const int c = cx * HX + cy * HY + cz;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int cc = tid + 512 * u;
-            if (cc < 729) {
-                const int ix = cc / 81, iy = (cc / 9) % 9, iz = cc % 9;
-                const int c = ix * HX + iy * HY + iz;
-                // record: m z(3) q5 o7 [d(3) 0]
-                double r[2 * NV];
-                r[0] = v[u][0];
-                r[1] = v[u][1];
-                r[2] = v[u][2];
-                r[3] = v[u][3];
-                detrace_q(&v[u][4], &r[4]);
-                detrace_o(&v[u][10], &r[9]);
-                if (DIP) {
-                    r[16 % (2 * NV)] = v[u][20];
-                    r[17 % (2 * NV)] = v[u][21];
-                    r[18 % (2 * NV)] = v[u][22];
-                    r[19 % (2 * NV)] = 0.0;
-                }
-#pragma unroll
-                for (int k = 0; k < NV; ++k) s_src[k][c] = make_double2(r[2 * k], r[2 * k + 1]);
-            }
-        }
+        for (int k = 0; k < NV; ++k) s_src[k][c] = make_double2(r[2 * k], r[2 * k + 1]);
     };
     // the needed classes of this item's share, in order (uniform)
     auto next_class = [&](int q) {
@@ -822,9 +804,8 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
         return q;
     };
     int q = next_class(q0 - 1);
-    if (q < q1) load_class(q);
     while (q < q1) {
-        store_class();
+        stage_class(q);
         __syncthreads();
         const int beg = st.m2l_src_beg[p * 9 + q], end = st.m2l_src_beg[p * 9 + q + 1];
         const int hb = (x >> 1) * HX + (y >> 1) * HY + (z >> 1);
@@ -858,17 +839,14 @@ __global__ __launch_bounds__(512) void k_m2l_lds(const LevelDesc *__restrict__ L
             for (int k = beg; k < end; ++k)
                 if (st.m2l_src_touch[k] & src_mask) pair(k);  // uniform
         } else {
-            // independent pairs interleaved per iteration (latency hiding at
-            // two waves per SIMD).  Entries that reach only absent sub-grids
-            // (domain boundary) cost their full work: a per-entry skip breaks
-            // the interleaving and is slower overall.
+            // Entries that reach only absent sub-grids (domain boundary) cost
+            // their full work: a per-entry skip breaks the interleaving and is
+            // slower overall.
 #pragma unroll OCTO_M2L_UNROLL
             for (int k = beg; k < end; ++k) pair(k);
         }
-        const int qn = next_class(q);
-        if (qn < q1) load_class(qn);
         __syncthreads();
-        q = qn;
+        q = next_class(q);
     }
     acc_close<DIP>(a);
     if (!(mA > 0.0)) a.C[0] = a.C[1] = a.C[2] = 0.0;
@@ -1534,11 +1512,27 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
                                p.d_l2l + p.l2l_off[l], n);
         hipLaunchKernelGGL(k_l2l, dim3(2 * n), dim3(256), 0, q, p.d_levels, p.d_l2l + p.l2l_off[l], n, wide ? 1 : 0);
     };
+    // the LDS-staged multipole kernel (dense levels, on the main stream)
+    auto lds_levels = [&]() {
+        if (!p.n_m2l_nodes) return;
+        const int grid = ((p.n_m2l_nodes + kXcd - 1) / kXcd) * kXcd;
+        auto k = src ? k_m2l_lds<double, true, false, false>
+                     : (o.amc ? k_m2l_lds<double, false, true, false> : k_m2l_lds<double, false, false, false>);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes, p.n_m2l_nodes, st,
+                           p.d_m2l_cnt + p.n_m2l, o.count ? 1 : 0);
+    };
     for (int l = p.n_levels_max - 1; l >= lsplit; --l) upward(l, s);
     hipStream_t sm = fork ? o.aux : s;
     if (fork) {
         check_hip(hipEventRecord(o.fork, s), "fork");
         check_hip(hipStreamWaitEvent(o.aux, o.fork, 0), "fork");
+        // the near field overlaps the upward pass (a chain of small
+        // launches) but not the LDS-staged kernel: run together, the two
+        // fill the same CUs and each slows the other by more than it gains
+        if (near_fork) check_hip(hipStreamWaitEvent(s, o.join_near, 0), "join");
+        // issued before the other stream's work, so that a graph replay
+        // dispatches it as soon as the dense levels' upward pass is done
+        lds_levels();
     }
     for (int l = lsplit - 1; l >= 0; --l) upward(l, sm);
     mark(3);
@@ -1561,13 +1555,7 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     for (int l = 0; l < lsplit; ++l) downward(l, sm);
     if (fork) check_hip(hipEventRecord(o.join, o.aux), "join");
     mark(8);
-    if (p.n_m2l_nodes) {
-        const int grid = ((p.n_m2l_nodes + kXcd - 1) / kXcd) * kXcd;
-        auto k = src ? k_m2l_lds<double, true, false, false>
-                     : (o.amc ? k_m2l_lds<double, false, true, false> : k_m2l_lds<double, false, false, false>);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes, p.n_m2l_nodes, st,
-                           p.d_m2l_cnt + p.n_m2l, o.count ? 1 : 0);
-    }
+    if (!fork) lds_levels();
     if (fork) check_hip(hipStreamWaitEvent(s, o.join, 0), "join");
     mark(4);
     for (int l = lsplit; l < p.n_levels_max; ++l) downward(l, s);

@@ -85,14 +85,13 @@ namespace octo {
 // Modelled time of one launch of the LDS-staged multipole kernel over levels
 // of n_int[i] nodes split into g[i] source-class groups each: the items are
 // dealt to the 8 XCDs in equal shares of every level, larger items first
-// (the order the plans give them), and each XCD's CUs take the next item as
-// they free up; the time is the simulated makespan in class-rounds (a round
-// stages and walks one class per work-group, one work-group per CU at a
-// time) plus the downward pass reading g partial slots per node: on MI355X
-// one slot of one node costs about 0.002 of a class-round (uniform 128^3:
-// 23.6 us per class-round, 0.047 us per node-slot).
+// (the order the plans give them), and each XCD's work-group slots (two per
+// CU) take the next item as they free up; the time is the simulated makespan
+// in class-rounds (a round stages and walks one class per work-group) plus
+// the downward pass reading g partial slots per node, about 0.002 of a
+// class-round per slot of one node.
 double lds_launch_cost(const std::vector<int64_t> &n_int, const std::vector<int> &g, int n_cu) {
-    const int cus = std::max(8, n_cu), per_xcd = std::max(1, cus / 8);
+    const int cus = std::max(8, n_cu), per_xcd = std::max(1, 2 * cus / 8);
     std::vector<std::pair<int, int64_t>> groups;  // (classes per item, items per XCD)
     double slots = 0.0;
     for (size_t i = 0; i < n_int.size(); ++i) {

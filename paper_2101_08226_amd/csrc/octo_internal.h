@@ -39,9 +39,10 @@ constexpr int kLoc = 23;
 constexpr int kLacc = 7;
 // per leaf work item partial sums: M, F (3), T (3), S_F, S_T
 constexpr int kStat = 9;
-// halo of one source parity class in the LDS-staged multipole kernel: a 9x9x9
-// lattice, rows padded to 12 (index ix * kHaloX + iy * kHaloY + iz)
-constexpr int kHaloY = 12, kHaloX = 9 * kHaloY, kHaloN = 9 * kHaloX;
+// halo of one source parity class in the LDS-staged multipole kernel: an
+// 8x8x8 lattice (the class's cells whose parent cells lie within 2 parent
+// cells of the node), x-planes padded to 68 (index ix * kHaloX + iy * kHaloY + iz)
+constexpr int kHaloY = 8, kHaloX = 68, kHaloN = 8 * kHaloX;
 // leaf-mass halo of the near-field kernel: the 18^3 cells within 5 cells of a
 // node, split by parity class into eight 9x9x9 lattices (lattice index
 // (ux>>1, uy>>1, uz>>1) of halo cell u = local + 5 at ix * kNearX + iy * kNearY

@@ -471,9 +471,12 @@ Stencil make_stencil(double theta) {
     s.near_beg[8] = (int)s.nearo.size();
     s.leaf_beg[8] = (int)s.leaf.size();
     // the same multipole entries grouped by the parity class of the source
-    // cell, stored as offsets in the staged halo of that class: a target at
-    // x = 2i + px reads lattice index (x + dx + 5) >> 1 = i + ((px + dx + 5) >> 1),
-    // so the offset is the same for every cell of the target class
+    // cell, stored as offsets in the staged halo of that class.  The halo
+    // lattice index of a source cell is its parent cell's offset from the
+    // node plus 2 (multipole partners have parents at most 2 parent cells
+    // away per axis for theta > 1/3): a target at x = 2i + px reads lattice
+    // index ((x + dx) >> 1) + 2 = i + ((px + dx + 4) >> 1), so the offset is
+    // the same for every cell of the target class
     for (int p = 0; p < 8; ++p) {
         int px = p >> 2, py = (p >> 1) & 1, pz = p & 1;
         for (int q = 0; q < 8; ++q) {
@@ -482,8 +485,13 @@ Stencil make_stencil(double theta) {
             for (auto &d : m2l[p]) {
                 int qq = (((px + d[0]) & 1) << 2) | (((py + d[1]) & 1) << 1) | ((pz + d[2]) & 1);
                 if (qq == q) {
-                    s.m2l_src.push_back(((px + d[0] + 5) >> 1) * kHaloX + ((py + d[1] + 5) >> 1) * kHaloY +
-                                        ((pz + d[2] + 5) >> 1));
+                    for (int a = 0; a < 3; ++a) {
+                        const int pa = a == 0 ? px : (a == 1 ? py : pz);
+                        if (pa + d[a] + 4 < 0 || pa + d[a] + 4 > 9)
+                            fail(OCTO_E_UNSUPPORTED, "multipole partner beyond the staged halo");
+                    }
+                    s.m2l_src.push_back(((px + d[0] + 4) >> 1) * kHaloX + ((py + d[1] + 4) >> 1) * kHaloY +
+                                        ((pz + d[2] + 4) >> 1));
                     s.m2l_src_touch.push_back(touch(p, d));
                     s.m2l_src_any[p * 8 + q] |= s.m2l_src_touch.back();
                 }
