@@ -1049,76 +1049,135 @@ __device__ inline void near_octant(const T *__restrict__ s_m, int base, const in
 }
 __device__ inline double rsqrt_t(double v) { return rsqrt(v); }
 
+
 template <typename T>
-__device__ inline void direct_add(T Rx, T Ry, T Rz, T m, T &phi, T &gx, T &gy, T &gz) {
-    const T r2 = Rx * Rx + Ry * Ry + Rz * Rz;
-    const T ir = rsqrt_t(r2);
-    const T mir = m * ir;
-    const T mir3 = mir * ir * ir;
-    phi -= mir;
-    gx -= mir3 * Rx;
-    gy -= mir3 * Ry;
-    gz -= mir3 * Rz;
+__device__ inline const T *xl_weights(const StencilDev &st);
+template <>
+__device__ inline const double *xl_weights<double>(const StencilDev &st) {
+    return st.xl_w;
+}
+template <>
+__device__ inline const float *xl_weights<float>(const StencilDev &st) {
+    return st.xl_w32;
 }
 
-// Cross-level pairs of one leaf cell (x, y, z) of parity class p at AMR
-// boundaries, direct point masses added to phi, g: interior cells of this
-// level near the cell (X1: each of their 8 children, one level down) and
-// leaves one level up near the cell's parent cell (X2).  s_nbr, s_pnbr: the
-// 27 same-level neighbours of the node and of its parent.
-template <typename T>
-__device__ inline void cross_level(const LevelDesc *__restrict__ L, const LevelDesc &ld, const LeafItem &item,
-                                   const StencilDev &st, const int *s_nbr, const int *s_pnbr, int node, int x,
-                                   int y, int z, int p, T &phi_t, T &gx_t, T &gy_t, T &gz_t, int &cnt) {
+// Cross-level pairs of the leaf cells of one node at AMR boundaries, direct
+// point masses added to phi, g: interior cells of this level near a cell (X1:
+// each of their 8 children, one level down) and leaves one level up near the
+// cell's parent cell (X2).  Called by the whole work-group once the
+// same-level sums have read s_m.  The separation of a target centre and a
+// source point is (h/4) n (X1) or (h/2) n (X2) for an odd-integer vector n
+// fixed per entry and child (X1) or per entry and target class (X2), so the
+// weights 1/|n| and n/|n|^3 are table rows, the same for the whole
+// wavefront.  X1 reads the child masses from global memory, the children of
+// the interior neighbours staged in LDS first; X2 stages the (4 + 2r)^3
+// cells of the parent level around the node's 4^3 parent cells in s_m (r:
+// the largest offset component; masses of leaves, -1 (COUNT) or 0
+// elsewhere).  s_nbr, s_pnbr: the 27 same-level neighbours of the node and
+// of its parent.
+template <typename T, bool COUNT>
+__device__ inline void cross_level(const LevelDesc *__restrict__ L, const LevelDesc &ld, int flags,
+                                   const StencilDev &st, T *s_m, const int *s_nbr, const int *s_pnbr, int node,
+                                   int tid, int x, int y, int z, int p, T &phi_t, T &gx_t, T &gy_t, T &gz_t,
+                                   int &cnt) {
+    const bool x1 = (flags & kLeafX1) != 0, x2 = (flags & kLeafX2) != 0 && ld.parent_ld >= 0;
+    if (!x1 && !x2) return;  // uniform over the work-group
+    __shared__ int s_ch[27 * 8];  // children of the interior neighbour sub-grids, -1 elsewhere
+    const int R = st.xl_reach, E = 4 + 2 * R, E3 = E * E * E;
     const double h = ld.h;
-    // cross-level pairs at AMR boundaries (direct point masses)
-    if (item.flags & kLeafX1) {
-        // interior cells B of this level, near (not well separated, parents not): sum over B's children
-        const LevelDesc cl = L[ld.child_ld >= 0 ? ld.child_ld : item.ld];
-        const int beg = st.near_beg[p], end = st.near_beg[p + 1];
+    const T *W = xl_weights<T>(st);
+    __syncthreads();  // the same-level sums are done with s_m
+    if (x1 && tid < 27 * 8) {
+        const int nb = s_nbr[tid >> 3];
+        s_ch[tid] = (nb >= 0 && nb < ld.n_int) ? ld.child[nb * 8 + (tid & 7)] : -1;
+    }
+    if (x2) {
+        const LevelDesc pl = L[ld.parent_ld];
+        const GPtr<const double> pmass = gptr(pl.mass);
+        const int cx = 4 * (ld.coord[3 * node] & 1) - R, cy = 4 * (ld.coord[3 * node + 1] & 1) - R,
+                  cz = 4 * (ld.coord[3 * node + 2] & 1) - R;
+        for (int t = tid; t < E3; t += 512) {
+            const int sx = cx + t / (E * E), sy = cy + (t / E) % E, sz = cz + t % E;
+            const int nb = s_pnbr[nbr_slot(sx, sy, sz)];
+            s_m[t] = nb >= pl.n_int ? (T)pmass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)]
+                                    : (T)(COUNT ? -1 : 0);
+        }
+    }
+    __syncthreads();
+    if (x1) {
+        const LevelDesc cl = L[ld.child_ld >= 0 ? ld.child_ld : 0];
+        const GPtr<const double> cmass = gptr(cl.mass);
         int int_mask = 0;  // neighbour sub-grids that are interior (uniform)
         for (int b = 0; b < 27; ++b) int_mask |= (s_nbr[b] >= 0 && s_nbr[b] < ld.n_int) ? (1 << b) : 0;
         int_mask = __builtin_amdgcn_readfirstlane(int_mask);
-        for (int k = beg; k < end; ++k) {
-            if (!(st.near_touch[k] & int_mask)) continue;  // no lane reaches an interior cell
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        for (int k = 0; k < st.n_xl; ++k) {
+            // no lane of the class reaches an interior cell: skip (uniform)
+            if (!(st.xl_touch[8 * k + p] & int_mask)) continue;
             int dx, dy, dz;
-            unpack(st.nearo[k], dx, dy, dz);
+            unpack(st.xl_off[k], dx, dy, dz);
             const int sx = x + dx, sy = y + dy, sz = z + dz;
-            const int nb = s_nbr[nbr_slot(sx, sy, sz)];
-            if (nb < 0 || nb >= ld.n_int) continue;
+            const int b = nbr_slot(sx, sy, sz);
+            const bool inner = s_ch[b * 8] >= 0;
             const int bx = sx & 7, by = sy & 7, bz = sz & 7;
+            T m[8];
+#pragma unroll
             for (int c = 0; c < 8; ++c) {
-                const int ox = c >> 2, oy = (c >> 1) & 1, oz = c & 1;
-                const int ux = 2 * bx + ox, uy = 2 * by + oy, uz = 2 * bz + oz;
-                const int ch = ld.child[nb * 8 + ((ux >> 3) << 2) + ((uy >> 3) << 1) + (uz >> 3)];
-                const T m = (T)cl.mass[(size_t)ch * kCells + store_idx(ux & 7, uy & 7, uz & 7)];
-                // R = z_A - z_b = (h/2) (1/2 - o - 2 d) per axis
-                const double hh = 0.5 * h;
-                direct_add<T>((T)(hh * (0.5 - ox - 2.0 * dx)), (T)(hh * (0.5 - oy - 2.0 * dy)),
-                              (T)(hh * (0.5 - oz - 2.0 * dz)), m, phi_t, gx_t, gy_t, gz_t);
-                ++cnt;
+                const int ux = 2 * bx + (c >> 2), uy = 2 * by + ((c >> 1) & 1), uz = 2 * bz + (c & 1);
+                const int ch = s_ch[b * 8 + ((ux >> 3) << 2) + ((uy >> 3) << 1) + (uz >> 3)];
+                const size_t at = inner ? (size_t)ch * kCells + store_idx(ux & 7, uy & 7, uz & 7) : 0;
+                m[c] = (T)cmass[at];
             }
+            const T *w = W + 64 * k;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const T mc = inner ? m[c] : (T)0;
+                a0 += mc * w[4 * c];
+                a1 += mc * w[4 * c + 1];
+                a2 += mc * w[4 * c + 2];
+                a3 += mc * w[4 * c + 3];
+            }
+            if (COUNT) cnt += inner ? 8 : 0;
         }
+        // separation (h/4) n: phi -= m / |R|, g -= m R / |R|^3
+        const T s1 = (T)(4.0 / h), s2 = (T)(16.0 / (h * h));
+        phi_t -= a0 * s1;
+        gx_t -= a1 * s2;
+        gy_t -= a2 * s2;
+        gz_t -= a3 * s2;
     }
-    if ((item.flags & kLeafX2) && ld.parent_ld >= 0) {
-        // leaves B one level up, near the parent cell P (not well separated, parents not)
-        const LevelDesc pl = L[ld.parent_ld];
-        const int px = 4 * (ld.coord[3 * node] & 1) + (x >> 1), py = 4 * (ld.coord[3 * node + 1] & 1) + (y >> 1),
-                  pz = 4 * (ld.coord[3 * node + 2] & 1) + (z >> 1);
-        const int pp = ((px & 1) << 2) | ((py & 1) << 1) | (pz & 1);
-        const int beg = st.near_beg[pp], end = st.near_beg[pp + 1];
-        for (int k = beg; k < end; ++k) {
+    if (x2) {
+        // the target's parent cell at (x >> 1, ...) in the node's 4^3 block;
+        // its class among the parent level's cells decides the near list
+        const int ix = x >> 1, iy = y >> 1, iz = z >> 1;
+        const int pp = ((ix & 1) << 2) | ((iy & 1) << 1) | (iz & 1);
+        const int base = ((ix + R) * E + (iy + R)) * E + (iz + R);
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        for (int k = 0; k < st.n_xl; ++k) {
             int dx, dy, dz;
-            unpack(st.nearo[k], dx, dy, dz);
-            const int sx = px + dx, sy = py + dy, sz = pz + dz;
-            const int nb = s_pnbr[nbr_slot(sx, sy, sz)];
-            if (nb < pl.n_int) continue;  // absent or interior
-            const T m = (T)pl.mass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)];
-            // R = z_a - z_B = h (o - 1/2 - 2 d), o = own index bit
-            direct_add<T>((T)(h * ((x & 1) - 0.5 - 2.0 * dx)), (T)(h * ((y & 1) - 0.5 - 2.0 * dy)),
-                          (T)(h * ((z & 1) - 0.5 - 2.0 * dz)), m, phi_t, gx_t, gy_t, gz_t);
-            ++cnt;
+            unpack(st.xl_off[k], dx, dy, dz);
+            const bool member = (st.xl_cls[k] >> pp) & 1;
+            const T m = s_m[base + (dx * E + dy) * E + dz];
+            T mm;
+            if (COUNT) {
+                const bool ok = member && m >= (T)0;
+                mm = ok ? m : (T)0;
+                cnt += ok ? 1 : 0;
+            } else {
+                mm = member ? m : (T)0;
+            }
+            const T *w = W + 64 * k + 32 + 4 * p;
+            a0 += mm * w[0];
+            a1 += mm * w[1];
+            a2 += mm * w[2];
+            a3 += mm * w[3];
         }
+        // separation (h/2) n
+        const T s1 = (T)(2.0 / h), s2 = (T)(4.0 / (h * h));
+        phi_t -= a0 * s1;
+        gx_t -= a1 * s2;
+        gy_t -= a2 * s2;
+        gz_t -= a3 * s2;
     }
 }
 
@@ -1219,7 +1278,8 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
     T phi_t = -sp * ih;
     T gx_t = sgx * ih * ih, gy_t = sgy * ih * ih, gz_t = sgz * ih * ih;
 
-    cross_level<T>(L, ld, item, st, s_nbr, s_pnbr, node, x, y, z, p, phi_t, gx_t, gy_t, gz_t, cnt);
+    cross_level<T, COUNT>(L, ld, item.flags, st, s_m, s_nbr, s_pnbr, node, tid, x, y, z, p, phi_t, gx_t, gy_t, gz_t,
+                          cnt);
     // direct sums enter the FP64 accumulation: phi and g of this cell's
     // direct partners, G applied
     const size_t NS = (size_t)(ld.n_nodes - ld.n_int) * kCells;

@@ -500,10 +500,12 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     h->host = make_stencil(theta);
     const Stencil &S = h->host;
     std::vector<float> w32(S.leaf_tab.begin(), S.leaf_tab.end());
-    size_t b = al(S.m2l.size() * 4) + al(S.nearo.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_tab.size() * 8) +
-               al(w32.size() * 4) + al(S.m2l_src.size() * 4) + al(S.leaf_off.size() * 4) +
-               al(S.leaf_widx.size() * 4) + al(S.m2l_touch.size() * 4) + al(S.near_touch.size() * 4) +
-               al(S.m2l_src_touch.size() * 4) + al(S.near_stage.size() * 4);
+    std::vector<float> xw32(S.xl_w.begin(), S.xl_w.end());
+    size_t b = al(S.m2l.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_tab.size() * 8) + al(w32.size() * 4) +
+               al(S.m2l_src.size() * 4) + al(S.leaf_off.size() * 4) + al(S.leaf_widx.size() * 4) +
+               al(S.m2l_touch.size() * 4) + al(S.m2l_src_touch.size() * 4) + al(S.near_stage.size() * 4) +
+               al(S.xl_off.size() * 4) + al(S.xl_cls.size() * 4) + al(S.xl_touch.size() * 4) +
+               al(S.xl_w.size() * 8) + al(xw32.size() * 4);
     void *mem = nullptr;
     check_hip(hipMalloc(&mem, b), "stencil alloc");
     h->block.ptr = mem;
@@ -517,9 +519,7 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
         return dst;
     };
     h->dev.m2l = (const int32_t *)put(S.m2l.data(), S.m2l.size() * 4);
-    h->dev.nearo = (const int32_t *)put(S.nearo.data(), S.nearo.size() * 4);
     h->dev.m2l_touch = (const int32_t *)put(S.m2l_touch.data(), S.m2l_touch.size() * 4);
-    h->dev.near_touch = (const int32_t *)put(S.near_touch.data(), S.near_touch.size() * 4);
     h->dev.leaf = (const int32_t *)put(S.leaf.data(), S.leaf.size() * 4);
     h->dev.leaf_tab = (const double *)put(S.leaf_tab.data(), S.leaf_tab.size() * 8);
     h->dev.leaf_tab32 = (const float *)put(w32.data(), w32.size() * 4);
@@ -528,12 +528,18 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     h->dev.leaf_widx = (const int32_t *)put(S.leaf_widx.data(), S.leaf_widx.size() * 4);
     h->dev.m2l_src_touch = (const int32_t *)put(S.m2l_src_touch.data(), S.m2l_src_touch.size() * 4);
     h->dev.near_stage = (const int32_t *)put(S.near_stage.data(), S.near_stage.size() * 4);
+    h->dev.xl_off = (const int32_t *)put(S.xl_off.data(), S.xl_off.size() * 4);
+    h->dev.xl_cls = (const int32_t *)put(S.xl_cls.data(), S.xl_cls.size() * 4);
+    h->dev.xl_touch = (const int32_t *)put(S.xl_touch.data(), S.xl_touch.size() * 4);
+    h->dev.xl_w = (const double *)put(S.xl_w.data(), S.xl_w.size() * 8);
+    h->dev.xl_w32 = (const float *)put(xw32.data(), xw32.size() * 4);
+    h->dev.n_xl = (int32_t)S.xl_off.size();
+    h->dev.xl_reach = S.xl_reach;
     for (int k = 0; k < 64; ++k) h->dev.m2l_src_any[k] = S.m2l_src_any[k];
     for (int k = 0; k < 73; ++k) h->dev.leaf_oct_beg[k] = S.leaf_oct_beg[k];
     for (int k = 0; k < 73; ++k) h->dev.m2l_src_beg[k] = S.m2l_src_beg[k];
     for (int p = 0; p < 9; ++p) {
         h->dev.m2l_beg[p] = S.m2l_beg[p];
-        h->dev.near_beg[p] = S.near_beg[p];
         h->dev.leaf_beg[p] = S.leaf_beg[p];
     }
     h->dev.theta2 = theta * theta;

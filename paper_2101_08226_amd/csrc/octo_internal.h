@@ -118,9 +118,7 @@ struct NodeItem {
 // offsets packed as (dx & 255) | (dy & 255) << 8 | (dz & 255) << 16
 struct StencilDev {
     const int32_t *m2l;    // well separated, parents not
-    const int32_t *nearo;  // not well separated, parents not, d != 0
     const int32_t *m2l_touch;   // per m2l entry: mask of the 27 neighbour sub-grids it reaches from the class
-    const int32_t *near_touch;  // the same for the near entries
     const int32_t *leaf;   // m2l followed by near (packed offsets)
     // near-field entries per target class, grouped by the sign octant o of d
     // (o = (dx<0)<<2 | (dy<0)<<1 | (dz<0)): offset into the parity-split halo
@@ -133,8 +131,20 @@ struct StencilDev {
     const int32_t *near_stage;  // kNearStage staging entries of the near-field halo
     const int32_t *m2l_src;  // m2l entries regrouped by source parity class, as halo offsets: the entry
                              // (dx,dy,dz) of target class p reads halo index (x>>1, y>>1, z>>1) + offset
+    // cross-level near partners (AMR boundaries): the offsets d (not well
+    // separated, parents not, d != 0) of all target classes once each; per
+    // entry the mask of the classes whose near list holds it, per (entry,
+    // class) the neighbour sub-grids it reaches, and 16 weight rows of 4
+    // (1/|n|, n/|n|^3): rows 0-7 for the children of a same-level interior
+    // cell, rows 8-15 per target class for a cell one level up
+    const int32_t *xl_off;
+    const int32_t *xl_cls;
+    const int32_t *xl_touch;
+    const double *xl_w;
+    const float *xl_w32;
+    int32_t n_xl;
+    int32_t xl_reach;  // largest |component| of an entry (the staged blocks' margin)
     int32_t m2l_beg[9];
-    int32_t near_beg[9];
     int32_t leaf_beg[9];
     int32_t leaf_oct_beg[73];  // target class p, octant o: [p*9+o, p*9+o+1)
     int32_t m2l_src_beg[73];  // target class p, source class q: [p*9+q, p*9+q+1)

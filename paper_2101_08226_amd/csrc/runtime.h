@@ -58,6 +58,11 @@ struct Stencil {
     std::vector<int32_t> m2l, nearo, leaf, m2l_src, leaf_off, leaf_widx, m2l_touch, near_touch, m2l_src_touch;
     std::vector<int32_t> near_stage;  // the near-field kernel's halo staging table (kNearStage entries)
     std::vector<double> leaf_tab;
+    // cross-level near partners: offsets, class masks, per-class touch masks
+    // (8 per entry), weights (64 per entry), largest component of an offset
+    std::vector<int32_t> xl_off, xl_cls, xl_touch;
+    std::vector<double> xl_w;
+    int xl_reach = 0;
     int m2l_beg[9], near_beg[9], leaf_beg[9];
     int leaf_oct_beg[73];
     int m2l_src_beg[73];

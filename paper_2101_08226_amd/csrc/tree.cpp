@@ -376,6 +376,45 @@ Stencil make_stencil(double theta) {
         for (int pass = 0; pass < 2; ++pass)
             for (auto &d : (pass == 0 ? m2l[p] : nr[p])) s.leaf.push_back(pack_off(d[0], d[1], d[2]));
     }
+    // cross-level near partners at AMR boundaries: every offset of the
+    // target classes' near lists once, with the classes whose list holds it
+    // and, per class, the neighbour sub-grids it reaches.  The separation of
+    // a target cell centre and a source point is a multiple of an
+    // odd-integer vector n: (h/4) n with n = 1 - 2o - 4d per axis for the
+    // child o (0 or 1 per axis) of a same-level cell at offset d (one level
+    // down), and (h/2) n with n = 2b - 1 - 4d for a cell one level up at
+    // offset d from the target's parent cell, b being the target's own index
+    // bit; the table holds 1/|n| and n/|n|^3 per entry for the 8 children,
+    // then for the 8 target classes.
+    {
+        int cls[11][11][11] = {};
+        for (int p = 0; p < 8; ++p)
+            for (auto &d : nr[p]) cls[d[0] + 5][d[1] + 5][d[2] + 5] |= 1 << p;
+        s.xl_reach = 0;
+        for (int dx = -5; dx <= 5; ++dx)
+            for (int dy = -5; dy <= 5; ++dy)
+                for (int dz = -5; dz <= 5; ++dz) {
+                    const int c = cls[dx + 5][dy + 5][dz + 5];
+                    if (!c) continue;
+                    const std::array<int, 3> d{dx, dy, dz};
+                    s.xl_off.push_back(pack_off(dx, dy, dz));
+                    s.xl_cls.push_back(c);
+                    for (int p = 0; p < 8; ++p) s.xl_touch.push_back((c >> p & 1) ? touch(p, d) : 0);
+                    s.xl_reach = std::max(s.xl_reach, std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))));
+                    for (int pass = 0; pass < 2; ++pass)
+                        for (int j = 0; j < 8; ++j) {
+                            const int bit[3] = {j >> 2, (j >> 1) & 1, j & 1};
+                            double n[3], n2 = 0;
+                            for (int a = 0; a < 3; ++a) {
+                                n[a] = pass == 0 ? 1 - 2 * bit[a] - 4 * d[a] : 2 * bit[a] - 1 - 4 * d[a];
+                                n2 += n[a] * n[a];
+                            }
+                            const double r = std::sqrt(n2);
+                            s.xl_w.push_back(1.0 / r);
+                            for (int a = 0; a < 3; ++a) s.xl_w.push_back(n[a] / (r * r * r));
+                        }
+                }
+    }
     // near-field weights by |d| pattern (shared by all target classes, small
     // enough to stay in the scalar cache)
     s.leaf_tab.assign(kNearTab * 4, 0.0);
