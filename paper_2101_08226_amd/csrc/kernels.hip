@@ -765,37 +765,51 @@ __global__ __launch_bounds__(512, DIP ? 2 : 4) void k_m2l_lds(const LevelDesc *_
     auto stage_class = [&](int q) {
         const int sx = 2 * cx - 4 + (q >> 2), sy = 2 * cy - 4 + ((q >> 1) & 1), sz = 2 * cz - 4 + (q & 1);
         const int nb = s_nbr[nbr_slot(sx, sy, sz)];
-        double v[23];
-        if (nb >= 0 && nb < n_src) {
-            const size_t si = (size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7);
-            v[0] = gmass[si];
-#pragma unroll
-            for (int k = 0; k < kRec; ++k) v[1 + k] = gmp[k * S + si];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) v[20 + k] = DIP ? gdip[k * S + si] : 0.0;
-        } else {
-            v[0] = -0.0;
-            v[1] = v[2] = v[3] = 1.0e3;
-#pragma unroll
-            for (int k = 4; k < 23; ++k) v[k] = 0.0;
-        }
-        // record: m z(3) q5 o7 [d(3) 0]
-        double r[2 * NV];
-        r[0] = v[0];
-        r[1] = v[1];
-        r[2] = v[2];
-        r[3] = v[3];
-        detrace_q(&v[4], &r[4]);
-        detrace_o(&v[10], &r[9]);
-        if (DIP) {
-            r[16 % (2 * NV)] = v[20];
-            r[17 % (2 * NV)] = v[21];
-            r[18 % (2 * NV)] = v[22];
-            r[19 % (2 * NV)] = 0.0;
-        }
+        const bool present = nb >= 0 && nb < n_src;
+        const size_t si = present ? (size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7) : 0;
         const int c = cx * HX + cy * HY + cz;
+        // record planes: (m, zx) (zy, zz) (q5_0, q5_1) (q5_2, q5_3) (q5_4, o7_0)
+        // (o7_1, o7_2) (o7_3, o7_4) (o7_5, o7_6) [(d_x, d_y) (d_z, 0)], staged in
+        // two passes (mass, centre and second moments; then third moments and
+        // dipole) so that few values are live next to the accumulators
+        double a[10];
+        if (present) {
+            a[0] = gmass[si];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) s_src[k][c] = make_double2(r[2 * k], r[2 * k + 1]);
+            for (int k = 0; k < 9; ++k) a[1 + k] = gmp[k * S + si];
+        } else {
+            a[0] = -0.0;
+            a[1] = a[2] = a[3] = 1.0e3;
+#pragma unroll
+            for (int k = 4; k < 10; ++k) a[k] = 0.0;
+        }
+        double q5[5];
+        detrace_q(&a[4], q5);
+        s_src[0][c] = make_double2(a[0], a[1]);
+        s_src[1][c] = make_double2(a[2], a[3]);
+        s_src[2][c] = make_double2(q5[0], q5[1]);
+        s_src[3][c] = make_double2(q5[2], q5[3]);
+        __builtin_amdgcn_sched_barrier(0);
+        double o[10], o7[7];
+        if (present) {
+#pragma unroll
+            for (int k = 0; k < 10; ++k) o[k] = gmp[(9 + k) * S + si];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 10; ++k) o[k] = 0.0;
+        }
+        detrace_o(o, o7);
+        s_src[4][c] = make_double2(q5[4], o7[0]);
+        s_src[5][c] = make_double2(o7[1], o7[2]);
+        s_src[6][c] = make_double2(o7[3], o7[4]);
+        s_src[7][c] = make_double2(o7[5], o7[6]);
+        if (DIP) {
+            double d[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) d[k] = present ? gdip[k * S + si] : 0.0;
+            s_src[8 % NV][c] = make_double2(d[0], d[1]);
+            s_src[9 % NV][c] = make_double2(d[2], 0.0);
+        }
     };
     // the needed classes of this item's share, in order (uniform)
     auto next_class = [&](int q) {
