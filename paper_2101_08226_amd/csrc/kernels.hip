@@ -1087,11 +1087,26 @@ __device__ inline const float *xl_weights<float>(const StencilDev &st) {
 // the interior neighbours staged in LDS first; X2 stages the (4 + 2r)^3
 // cells of the parent level around the node's 4^3 parent cells in s_m (r:
 // the largest offset component; masses of leaves, -1 (COUNT) or 0
-// elsewhere).  s_nbr, s_pnbr: the 27 same-level neighbours of the node and
-// of its parent.
+// elsewhere; x2v: this thread's cell, loaded by xl_x2_load).  s_nbr: the 27
+// same-level neighbours of the node.
+// The X2 source of thread tid (one cell of the block per thread), loaded
+// together with the same-level halo and stored once the walk is done.
+template <typename T, bool COUNT>
+__device__ inline T xl_x2_load(const LevelDesc *__restrict__ L, const LevelDesc &ld, int flags, const StencilDev &st,
+                               const int *s_pnbr, int node, int tid) {
+    const int R = st.xl_reach, E = 4 + 2 * R;
+    if (!(flags & kLeafX2) || ld.parent_ld < 0 || tid >= E * E * E) return (T)0;
+    const LevelDesc pl = L[ld.parent_ld];
+    const int sx = 4 * (ld.coord[3 * node] & 1) - R + tid / (E * E), sy = 4 * (ld.coord[3 * node + 1] & 1) - R + (tid / E) % E,
+              sz = 4 * (ld.coord[3 * node + 2] & 1) - R + tid % E;
+    const int nb = s_pnbr[nbr_slot(sx, sy, sz)];
+    return nb >= pl.n_int ? (T)gptr(pl.mass)[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)]
+                          : (T)(COUNT ? -1 : 0);
+}
+
 template <typename T, bool COUNT>
 __device__ inline void cross_level(const LevelDesc *__restrict__ L, const LevelDesc &ld, int flags,
-                                   const StencilDev &st, T *s_m, const int *s_nbr, const int *s_pnbr, int node,
+                                   const StencilDev &st, T *s_m, const int *s_nbr, T x2v, int node,
                                    int tid, int x, int y, int z, int p, T &phi_t, T &gx_t, T &gy_t, T &gz_t,
                                    int &cnt) {
     const bool x1 = (flags & kLeafX1) != 0, x2 = (flags & kLeafX2) != 0 && ld.parent_ld >= 0;
@@ -1105,18 +1120,7 @@ __device__ inline void cross_level(const LevelDesc *__restrict__ L, const LevelD
         const int nb = s_nbr[tid >> 3];
         s_ch[tid] = (nb >= 0 && nb < ld.n_int) ? ld.child[nb * 8 + (tid & 7)] : -1;
     }
-    if (x2) {
-        const LevelDesc pl = L[ld.parent_ld];
-        const GPtr<const double> pmass = gptr(pl.mass);
-        const int cx = 4 * (ld.coord[3 * node] & 1) - R, cy = 4 * (ld.coord[3 * node + 1] & 1) - R,
-                  cz = 4 * (ld.coord[3 * node + 2] & 1) - R;
-        for (int t = tid; t < E3; t += 512) {
-            const int sx = cx + t / (E * E), sy = cy + (t / E) % E, sz = cz + t % E;
-            const int nb = s_pnbr[nbr_slot(sx, sy, sz)];
-            s_m[t] = nb >= pl.n_int ? (T)pmass[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)]
-                                    : (T)(COUNT ? -1 : 0);
-        }
-    }
+    if (x2 && tid < E3) s_m[tid] = x2v;
     __syncthreads();
     if (x1) {
         const LevelDesc cl = L[ld.child_ld >= 0 ? ld.child_ld : 0];
@@ -1222,6 +1226,7 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
         if (ld.parent_ld >= 0) s_pnbr[tid] = L[ld.parent_ld].nbr[ld.parent[node] * 27 + tid];
     }
     __syncthreads();
+    const T x2v = xl_x2_load<T, COUNT>(L, ld, item.flags, st, s_pnbr, node, tid);
     if (ld.level > 0) {
         // all 12 loads of this thread in flight before any store; the cell
         // indices come from the staging table (the same for every
@@ -1292,7 +1297,7 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
     T phi_t = -sp * ih;
     T gx_t = sgx * ih * ih, gy_t = sgy * ih * ih, gz_t = sgz * ih * ih;
 
-    cross_level<T, COUNT>(L, ld, item.flags, st, s_m, s_nbr, s_pnbr, node, tid, x, y, z, p, phi_t, gx_t, gy_t, gz_t,
+    cross_level<T, COUNT>(L, ld, item.flags, st, s_m, s_nbr, x2v, node, tid, x, y, z, p, phi_t, gx_t, gy_t, gz_t,
                           cnt);
     // direct sums enter the FP64 accumulation: phi and g of this cell's
     // direct partners, G applied
