@@ -16,7 +16,8 @@ reductions, and mixed precision.
 Further fields of the default line: the same field to level 7 (20.0M leaf
 cells); the uniform 128^3 grid of that field (c2) with the roofline of its
 multipole kernel and the self-consistent-field iteration; 256 independent
-uniform trees solved together (c4); a Poisson stream of 2,000 solve requests
+uniform trees solved together (c4: work shapes fitted to the batch, and each
+tree's own plan beside it); a Poisson stream of 2,000 solve requests
 served with continuous batching (c5: p50/p99 latency, throughput); the time
 derivative of the potential and one regrid of the headline tree; and the CPU
 oracle timed on this host.  --config c1..c5 runs one workload alone.
