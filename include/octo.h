@@ -86,11 +86,17 @@ enum { OCTO_FP64 = 0, OCTO_MIXED = 1 };
  *   accuracy (the paper runs 0.5 and 0.34).
  * G: gravitational constant (1 in code units, Sec. 2.8).
  * precision: OCTO_FP64 computes everything in double precision;
- *   OCTO_MIXED evaluates the leaf near-field sums in single precision with
- *   single-precision partial sums (weights and masses rounded to float) and
- *   everything else -- moments, multipole-to-local terms, the
- *   angular-momentum correction, the downward pass and the final
- *   accumulation -- in double precision.
+ *   OCTO_MIXED evaluates the leaf near-field sums and the multipole-to-local
+ *   sums of the LDS-staged work (the levels with many interior nodes, and
+ *   leaf cells next to interior cells) in single precision with
+ *   single-precision partial sums (masses, moments and the offsets of the
+ *   centres of mass from the cell centres rounded to float; the separations
+ *   between cell centres are exact), and the rest -- the moments themselves,
+ *   the multipole-to-local terms of the root and other levels with few
+ *   interior nodes, the sums of the angular-momentum correction, the
+ *   downward pass and the final accumulation -- in double precision.  The
+ *   second-source solve of octo_solve_dphidt keeps its multipole work in
+ *   double precision.
  * amc: 1 applies the angular-momentum correction (Sec. 2.2), 0 omits it. */
 typedef struct {
     double theta;

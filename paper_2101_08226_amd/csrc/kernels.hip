@@ -540,13 +540,79 @@ __device__ inline void m2l_pair_f64(double Rx, double Ry, double Rz, double mB, 
     }
 }
 
-// The pair routine of the multipole kernels: FP64 in both precisions (the
-// mixed mode's single precision is the near field's).
+// The pair routine of the per-wavefront multipole kernel and of the
+// LDS-staged kernel's FP64 variants.
 template <bool LEAF_TARGET, bool DIP, typename T>
 __device__ inline void m2l_pair(double Rx, double Ry, double Rz, double mB, const double *q, const double *o,
                                 const double *D, double mu, const double *oA, bool amc, Acc<T> &a) {
-    static_assert(sizeof(T) == sizeof(double), "the multipole work runs in FP64");
+    static_assert(sizeof(T) == sizeof(double), "the FP64 pair routine");
     m2l_pair_f64<LEAF_TARGET, DIP>(Rx, Ry, Rz, mB, q, o, D, mu, oA, amc, a);
+}
+
+// The same pair in FP32 (mixed precision: the multipole bulk in FP32,
+// accumulated in FP32), the correction's per-pair term accumulated in FP64.
+// Same operations and constants as m2l_pair_f64, with 1/|R| from the
+// hardware estimate alone (about 1 ulp in FP32).
+template <bool LEAF_TARGET>
+__device__ inline void m2l_pair_f32(float Rx, float Ry, float Rz, float mB, const float *q, const float *o, float mu,
+                                    const float *oA, bool amc, Acc<float> &a) {
+    const float r2 = Rx * Rx + Ry * Ry + Rz * Rz;
+    const float g = __builtin_amdgcn_rsqf(r2);
+    const float s = g * g, p1 = g * s, p2 = p1 * s, p3 = p2 * s;
+    const float qzz = -(q[0] + q[3]);
+    const float QRx = q[0] * Rx + q[1] * Ry + q[2] * Rz;
+    const float QRy = q[1] * Rx + q[3] * Ry + q[4] * Rz;
+    const float QRz = q[2] * Rx + q[4] * Ry + qzz * Rz;
+    const float RQR = Rx * QRx + Ry * QRy + Rz * QRz;
+    const float xx = Rx * Rx, yy = Ry * Ry, zz = Rz * Rz, xy = Rx * Ry, xz = Rx * Rz, yz = Ry * Rz;
+    const float e = xx - zz, f = yy - zz, u = 2.0f * xy, v = 2.0f * xz, w = 2.0f * yz;
+    float ORx, ORy, ORz;
+    o7_rr(o, e, f, u, v, w, ORx, ORy, ORz);
+    const float ORRR = Rx * ORx + Ry * ORy + Rz * ORz;
+    a.L0 = __builtin_fmaf(mB, g, a.L0);
+    a.A2 = __builtin_fmaf(p2, RQR, a.A2);
+    a.A3 = __builtin_fmaf(p3, ORRR, a.A3);
+    const float mp1 = mB * p1, k2 = 3.0f * p2, k3 = 7.5f * p3;
+    const float c = __builtin_fmaf(k3, RQR, mp1);
+    a.L1[0] = __builtin_fmaf(-k2, QRx, __builtin_fmaf(c, Rx, a.L1[0]));
+    a.L1[1] = __builtin_fmaf(-k2, QRy, __builtin_fmaf(c, Ry, a.L1[1]));
+    a.L1[2] = __builtin_fmaf(-k2, QRz, __builtin_fmaf(c, Rz, a.L1[2]));
+    if (!LEAF_TARGET) {
+        const float m2 = mB * k2;
+        a.L2[0] = __builtin_fmaf(m2, xx, a.L2[0]);
+        a.L2[1] = __builtin_fmaf(m2, xy, a.L2[1]);
+        a.L2[2] = __builtin_fmaf(m2, xz, a.L2[2]);
+        a.L2[3] = __builtin_fmaf(m2, yy, a.L2[3]);
+        a.L2[4] = __builtin_fmaf(m2, yz, a.L2[4]);
+        a.L2[5] = __builtin_fmaf(m2, zz, a.L2[5]);
+        const float m3 = mB * p3;
+        const float m3x = m3 * Rx, m3y = m3 * Ry, m3z = m3 * Rz;
+        a.L3[0] = __builtin_fmaf(m3x, xx, a.L3[0]);
+        a.L3[1] = __builtin_fmaf(m3x, xy, a.L3[1]);
+        a.L3[2] = __builtin_fmaf(m3x, xz, a.L3[2]);
+        a.L3[3] = __builtin_fmaf(m3x, yy, a.L3[3]);
+        a.L3[4] = __builtin_fmaf(m3x, yz, a.L3[4]);
+        a.L3[5] = __builtin_fmaf(m3x, zz, a.L3[5]);
+        a.L3[6] = __builtin_fmaf(m3y, yy, a.L3[6]);
+        a.L3[7] = __builtin_fmaf(m3y, yz, a.L3[7]);
+        a.L3[8] = __builtin_fmaf(m3z, yz, a.L3[8]);
+        a.L3[9] = __builtin_fmaf(m3z, zz, a.L3[9]);
+    }
+    if (amc) {
+        float nx = ORx, ny = ORy, nz = ORz, nR = ORRR;
+        if (!LEAF_TARGET) {
+            float ax, ay, az;
+            o7_rr(oA, e, f, u, v, w, ax, ay, az);
+            nx = __builtin_fmaf(-mu, ax, ORx);
+            ny = __builtin_fmaf(-mu, ay, ORy);
+            nz = __builtin_fmaf(-mu, az, ORz);
+            nR = __builtin_fmaf(-mu, ax * Rx + ay * Ry + az * Rz, ORRR);
+        }
+        const float kR = (-17.5f * (p3 * s)) * nR;
+        a.C[0] += (double)__builtin_fmaf(kR, Rx, k3 * nx);
+        a.C[1] += (double)__builtin_fmaf(kR, Ry, k3 * ny);
+        a.C[2] += (double)__builtin_fmaf(kR, Rz, k3 * nz);
+    }
 }
 
 template <bool LEAF_TARGET, bool DIP, typename T>
@@ -710,7 +776,13 @@ __global__ __launch_bounds__(512, DIP ? 2 : 4) void k_m2l_lds(const LevelDesc *_
     // the lane order below) hit distinct banks
     constexpr int NV = DIP ? 10 : 8;  // double2 planes per source cell
     constexpr int HY = kHaloY, HX = kHaloX, HN = kHaloN;
-    __shared__ double2 s_src[NV][HN];
+    // FP32 (mixed precision): 4 float4 planes per source cell, positions as
+    // offsets from the cell centres (see stage_class)
+    constexpr bool F32 = sizeof(T) == 4;
+    static_assert(!(F32 && DIP), "the second-source multipole work runs in FP64");
+    __shared__ __align__(16) unsigned char s_raw[(F32 ? 4 : NV) * HN * 16];
+    auto s_src = reinterpret_cast<double2 (*)[HN]>(s_raw);
+    auto s_src4 = reinterpret_cast<float4 (*)[HN]>(s_raw);
     __shared__ int s_nbr[27];
     __shared__ int s_cnt[8];
     const int tid = threadIdx.x;
@@ -736,6 +808,19 @@ __global__ __launch_bounds__(512, DIP ? 2 : 4) void k_m2l_lds(const LevelDesc *_
     constexpr bool amc = AMC && !DIP;
     const bool counting = count != 0;
     const double imA = mA > 0.0 ? 1.0 / mA : 0.0;
+    // FP32: the target's offset from its cell centre and its moments in FP32;
+    // the cells' centres are exact multiples of h - 1/2 (h a power of 2)
+    const double hc = ld.h;
+    const int gx0 = 8 * ld.coord[3 * node], gy0 = 8 * ld.coord[3 * node + 1], gz0 = 8 * ld.coord[3 * node + 2];
+    float dAx = 0.f, dAy = 0.f, dAz = 0.f, oAf[7];
+    if constexpr (F32) {
+        dAx = (float)(zAx - centre(gx0 + x, hc));
+        dAy = (float)(zAy - centre(gy0 + y, hc));
+        dAz = (float)(zAz - centre(gz0 + z, hc));
+#pragma unroll
+        for (int k = 0; k < 7; ++k) oAf[k] = (float)oA[k];
+    }
+    const float imAf = (float)imA;
     Acc<T> a;
     acc_zero(a);
     int cnt = 0;
@@ -768,6 +853,35 @@ __global__ __launch_bounds__(512, DIP ? 2 : 4) void k_m2l_lds(const LevelDesc *_
         const bool present = nb >= 0 && nb < n_src;
         const size_t si = present ? (size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7) : 0;
         const int c = cx * HX + cy * HY + cz;
+        if constexpr (F32) {
+            // (m, dz_x, dz_y, dz_z) (q5_0..q5_3) (q5_4, o7_0..o7_2) (o7_3..o7_6),
+            // dz the centre of mass minus the cell centre
+            double a[10];
+            if (present) {
+                a[0] = gmass[si];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) a[1 + k] = gmp[k * S + si];
+                a[1] -= centre(gx0 + sx, hc);
+                a[2] -= centre(gy0 + sy, hc);
+                a[3] -= centre(gz0 + sz, hc);
+            } else {
+                a[0] = -0.0;
+#pragma unroll
+                for (int k = 1; k < 10; ++k) a[k] = 0.0;
+            }
+            double q5[5];
+            detrace_q(&a[4], q5);
+            s_src4[0][c] = make_float4((float)a[0], (float)a[1], (float)a[2], (float)a[3]);
+            s_src4[1][c] = make_float4((float)q5[0], (float)q5[1], (float)q5[2], (float)q5[3]);
+            __builtin_amdgcn_sched_barrier(0);
+            double o[10], o7[7];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) o[k] = present ? gmp[(9 + k) * S + si] : 0.0;
+            detrace_o(o, o7);
+            s_src4[2][c] = make_float4((float)q5[4], (float)o7[0], (float)o7[1], (float)o7[2]);
+            s_src4[3][c] = make_float4((float)o7[3], (float)o7[4], (float)o7[5], (float)o7[6]);
+            return;
+        }
         // record planes: (m, zx) (zy, zz) (q5_0, q5_1) (q5_2, q5_3) (q5_4, o7_0)
         // (o7_1, o7_2) (o7_3, o7_4) (o7_5, o7_6) [(d_x, d_y) (d_z, 0)], staged in
         // two passes (mass, centre and second moments; then third moments and
@@ -831,22 +945,36 @@ __global__ __launch_bounds__(512, DIP ? 2 : 4) void k_m2l_lds(const LevelDesc *_
             int k = beg;
             for (; k + 3 < end; k += 4) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) c4[u] += signbit(s_src[0][hb + st.m2l_src[k + u]].x) ? 0 : 1;
+                for (int u = 0; u < 4; ++u)
+                    c4[u] += signbit(F32 ? (double)s_src4[0][hb + st.m2l_src[k + u]].x
+                                         : s_src[0][hb + st.m2l_src[k + u]].x) ? 0 : 1;
             }
-            for (; k < end; ++k) c4[0] += signbit(s_src[0][hb + st.m2l_src[k]].x) ? 0 : 1;
+            for (; k < end; ++k)
+                c4[0] += signbit(F32 ? (double)s_src4[0][hb + st.m2l_src[k]].x : s_src[0][hb + st.m2l_src[k]].x) ? 0 : 1;
             cnt += c4[0] + c4[1] + c4[2] + c4[3];
         }
         auto pair = [&](int k) {
             const int h = hb + st.m2l_src[k];  // the offset is uniform over the wavefront
-            double r[2 * NV];
+            if constexpr (F32) {
+                // R = z_A - z_B = (c_A - c_B) + (dz_A - dz_B), c_A - c_B = -h d exactly
+                int dx, dy, dz;
+                unpack(st.m2l_src_d[k], dx, dy, dz);
+                const float4 e0 = s_src4[0][h], e1 = s_src4[1][h], e2 = s_src4[2][h], e3 = s_src4[3][h];
+                const float qf[5] = {e1.x, e1.y, e1.z, e1.w, e2.x};
+                const float of[7] = {e2.y, e2.z, e2.w, e3.x, e3.y, e3.z, e3.w};
+                m2l_pair_f32<LEAF>((dAx - e0.y) + (float)(-hc * dx), (dAy - e0.z) + (float)(-hc * dy),
+                                   (dAz - e0.w) + (float)(-hc * dz), e0.x, qf, of, e0.x * imAf, oAf, amc, a);
+            } else {
+                double r[2 * NV];
 #pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                const double2 e = s_src[j][h];
-                r[2 * j] = e.x;
-                r[2 * j + 1] = e.y;
+                for (int j = 0; j < NV; ++j) {
+                    const double2 e = s_src[j][h];
+                    r[2 * j] = e.x;
+                    r[2 * j + 1] = e.y;
+                }
+                m2l_pair<LEAF, DIP, T>(zAx - r[1], zAy - r[2], zAz - r[3], r[0], &r[4], &r[9], &r[16 % (2 * NV)],
+                                       r[0] * imA, oA, amc, a);
             }
-            m2l_pair<LEAF, DIP, T>(zAx - r[1], zAy - r[2], zAz - r[3], r[0], &r[4], &r[9], &r[16 % (2 * NV)],
-                                   r[0] * imA, oA, amc, a);
         };
         if (LEAF) {
 #pragma unroll OCTO_M2L_UNROLL
@@ -1527,6 +1655,9 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
         if (o.phase_events) check_hip(hipEventRecord(o.phase_events[i], s), "phase event");
     };
     const bool src = o.source;
+    // mixed precision: the LDS-staged multipole kernels in FP32 (the
+    // per-wavefront kernel of the root and level 1 and the second source stay FP64)
+    const bool f32 = o.precision == OCTO_MIXED;
     // net force and torque reductions: with statistics (which also count
     // pairs) or on their own; never for the second source
     const bool reduce = !src && (o.count || o.reduce);
@@ -1596,7 +1727,8 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
         if (!p.n_m2l_nodes) return;
         const int grid = ((p.n_m2l_nodes + kXcd - 1) / kXcd) * kXcd;
         auto k = src ? k_m2l_lds<double, true, false, false>
-                     : (o.amc ? k_m2l_lds<double, false, true, false> : k_m2l_lds<double, false, false, false>);
+                     : f32 ? (o.amc ? k_m2l_lds<float, false, true, false> : k_m2l_lds<float, false, false, false>)
+                           : (o.amc ? k_m2l_lds<double, false, true, false> : k_m2l_lds<double, false, false, false>);
         hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, s, p.d_levels, p.d_trees, p.d_m2l_nodes, p.n_m2l_nodes, st,
                            p.d_m2l_cnt + p.n_m2l, o.count ? 1 : 0);
     };
@@ -1615,9 +1747,6 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     }
     for (int l = lsplit - 1; l >= 0; --l) upward(l, sm);
     mark(3);
-    // The multipole work runs in FP64 in both precisions: non-packed FP32
-    // issues at the FP64 rate on this chip, so only the near field (half the
-    // LDS bytes) gains from single precision.
     if (p.n_m2l) {
         const int grid = ((p.n_m2l + kXcd - 1) / kXcd) * kXcd;
         auto k = src ? k_m2l<double, true> : k_m2l<double, false>;
@@ -1627,7 +1756,8 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     if (p.n_m2l_leaf) {
         const int grid = ((p.n_m2l_leaf + kXcd - 1) / kXcd) * kXcd;
         auto k = src ? k_m2l_lds<double, true, false, true>
-                     : (o.amc ? k_m2l_lds<double, false, true, true> : k_m2l_lds<double, false, false, true>);
+                     : f32 ? (o.amc ? k_m2l_lds<float, false, true, true> : k_m2l_lds<float, false, false, true>)
+                           : (o.amc ? k_m2l_lds<double, false, true, true> : k_m2l_lds<double, false, false, true>);
         hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, sm, p.d_levels, p.d_trees, p.d_m2l_leaf, p.n_m2l_leaf, st,
                            p.d_m2l_cnt + p.n_m2l + p.n_m2l_nodes, o.count ? 1 : 0);
     }

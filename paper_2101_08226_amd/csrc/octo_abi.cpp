@@ -503,7 +503,8 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     std::vector<float> xw32(S.xl_w.begin(), S.xl_w.end());
     size_t b = al(S.m2l.size() * 4) + al(S.leaf.size() * 4) + al(S.leaf_tab.size() * 8) + al(w32.size() * 4) +
                al(S.m2l_src.size() * 4) + al(S.leaf_off.size() * 4) + al(S.leaf_widx.size() * 4) +
-               al(S.m2l_touch.size() * 4) + al(S.m2l_src_touch.size() * 4) + al(S.near_stage.size() * 4) +
+               al(S.m2l_touch.size() * 4) + al(S.m2l_src_touch.size() * 4) + al(S.m2l_src_d.size() * 4) +
+               al(S.near_stage.size() * 4) +
                al(S.xl_off.size() * 4) + al(S.xl_cls.size() * 4) + al(S.xl_touch.size() * 4) +
                al(S.xl_w.size() * 8) + al(xw32.size() * 4);
     void *mem = nullptr;
@@ -527,6 +528,7 @@ const StencilDevHolder &octo_ctx::stencil(double theta) {
     h->dev.leaf_off = (const int32_t *)put(S.leaf_off.data(), S.leaf_off.size() * 4);
     h->dev.leaf_widx = (const int32_t *)put(S.leaf_widx.data(), S.leaf_widx.size() * 4);
     h->dev.m2l_src_touch = (const int32_t *)put(S.m2l_src_touch.data(), S.m2l_src_touch.size() * 4);
+    h->dev.m2l_src_d = (const int32_t *)put(S.m2l_src_d.data(), S.m2l_src_d.size() * 4);
     h->dev.near_stage = (const int32_t *)put(S.near_stage.data(), S.near_stage.size() * 4);
     h->dev.xl_off = (const int32_t *)put(S.xl_off.data(), S.xl_off.size() * 4);
     h->dev.xl_cls = (const int32_t *)put(S.xl_cls.data(), S.xl_cls.size() * 4);

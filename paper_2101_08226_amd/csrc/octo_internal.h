@@ -149,6 +149,7 @@ struct StencilDev {
     int32_t leaf_oct_beg[73];  // target class p, octant o: [p*9+o, p*9+o+1)
     int32_t m2l_src_beg[73];  // target class p, source class q: [p*9+q, p*9+q+1)
     const int32_t *m2l_src_touch;  // per m2l_src entry: mask of the 27 neighbour sub-grids it reaches
+    const int32_t *m2l_src_d;      // per m2l_src entry: the offset d (source cell minus target cell), packed
     int32_t m2l_src_any[64];       // target class p, source class q: union of the group's touch masks
     double theta2;
 };

@@ -56,6 +56,7 @@ std::vector<octo_leaf> adaptive_leaves(octo_boxmax_fn boxmax, void *user, int ma
 struct Stencil {
     double theta = 0;
     std::vector<int32_t> m2l, nearo, leaf, m2l_src, leaf_off, leaf_widx, m2l_touch, near_touch, m2l_src_touch;
+    std::vector<int32_t> m2l_src_d;  // per m2l_src entry: its offset d, packed
     std::vector<int32_t> near_stage;  // the near-field kernel's halo staging table (kNearStage entries)
     std::vector<double> leaf_tab;
     // cross-level near partners: offsets, class masks, per-class touch masks

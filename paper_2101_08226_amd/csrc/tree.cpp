@@ -532,6 +532,7 @@ Stencil make_stencil(double theta) {
                     s.m2l_src.push_back(((px + d[0] + 4) >> 1) * kHaloX + ((py + d[1] + 4) >> 1) * kHaloY +
                                         ((pz + d[2] + 4) >> 1));
                     s.m2l_src_touch.push_back(touch(p, d));
+                    s.m2l_src_d.push_back(pack_off(d[0], d[1], d[2]));
                     s.m2l_src_any[p * 8 + q] |= s.m2l_src_touch.back();
                 }
             }

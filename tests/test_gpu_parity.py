@@ -159,15 +159,16 @@ def test_other_opening_angles(ctx, theta):
     assert st["torque"] < 1e-13 and st["force"] < 1e-13
 
 
-# Mixed precision (FP32 near field; FP64 moments, multipole-to-local terms,
-# correction and final accumulation): each bound is 4x the largest error
-# measured on the GPU over the mixed cases of this file (e_phi 2.42e-7 on the
-# adaptive level-3 tree, e_g 2.70e-7 on the 64^3 binary; the full-size sampled
-# cases stay below 2e-8), and the torque bound 4x the largest relative torque
-# (2.53e-9, adaptive level 3).
-MIXED_PHI = 1.0e-6
-MIXED_G = 1.1e-6
-MIXED_TORQUE = 1.1e-8
+# Mixed precision (FP32 near field and FP32 bulk of the LDS-staged multipole
+# work, accumulated in FP32; FP64 moments, the root's and level 1's
+# per-wavefront multipole work, the correction's accumulation and the final
+# accumulation): each bound is 4x the largest error measured on the GPU over
+# the mixed cases of this file (e_phi 2.67e-7 on the sampled level-6 tree,
+# e_g 4.54e-7 on the sampled level-7 tree), and the torque bound 4x the
+# largest relative torque (3.21e-9, sampled level-6 tree).
+MIXED_PHI = 1.1e-6
+MIXED_G = 1.9e-6
+MIXED_TORQUE = 1.3e-8
 
 
 @pytest.mark.parametrize("case", ["c1", "poly64", "amr"])
@@ -434,13 +435,17 @@ def test_c4_batched_mix(ctx):
         finally:
             ctx.set_batch_shapes(0)
         worst = 0.0
+        # mixed precision: the fitted shapes move level 1 from the FP64
+        # per-wavefront kernel to the FP32 LDS-staged one, so the two results
+        # are two mixed solves, each within MIXED_G of the oracle
+        tol = FITTED_TOL if prec == lib.OCTO_FP64 else 2 * MIXED_G
         for i in range(len(trees)):
             e = errs(outs_f[i][0].cpu().numpy(), outs_f[i][1].cpu().numpy(), outs[i][0].cpu().numpy(),
                      outs[i][1].cpu().numpy())
             worst = max(worst, e[0], e[1])
             assert sts_f[i]["m2l_pairs"] == sts[i]["m2l_pairs"] and sts_f[i]["direct_pairs"] == sts[i]["direct_pairs"]
         say(f"  prec={prec}: fitted shapes vs own plans: worst relative difference {worst:.2e}")
-        assert worst <= FITTED_TOL
+        assert worst <= tol
         if prec == lib.OCTO_FP64:
             assert max(s["torque"] for s in sts_f) < 1e-13
             fp64 = outs_f  # the oracle check below takes the fitted-shape results
@@ -554,9 +559,10 @@ def test_batch_mixed_sizes_and_precision(ctx):
             for _ in range(2):  # capture, then replay
                 outs_f, sts_f = ctx.solve_batch(trees, precision=prec)
                 got = [(p.cpu().numpy(), g.cpu().numpy()) for p, g in outs_f]
+                tol = FITTED_TOL if prec == lib.OCTO_FP64 else 2 * MIXED_G  # see test_c4_batched_mix
                 for (p, g), (ps, gs) in zip(got, single):
                     e = errs(p, g, ps, gs)
-                    assert e[0] <= FITTED_TOL and e[1] <= FITTED_TOL, e
+                    assert e[0] <= tol and e[1] <= tol, e
                 if first is not None:
                     for (p, g), (p0, g0) in zip(got, first):
                         assert np.array_equal(p, p0) and np.array_equal(g, g0)
