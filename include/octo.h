@@ -166,7 +166,8 @@ octo_status octo_ctx_set_profiling(octo_ctx *ctx, int on);
  * fitted to the batch -- many trees fill the device together, so every
  * level below the root takes the LDS-staged multipole kernel with one
  * source-class group count for the whole batch, the one a launch-time model
- * prices lowest -- and each result agrees with the tree's single solve to
+ * prices lowest, and the roots' work is split into fewer partial slots --
+ * and each result agrees with the tree's single solve to
  * within rounding of the summation order (pair counts unchanged).  The
  * request server (octo_submit) always runs each tree's own plan.  Other
  * values: OCTO_E_INVALID. */

@@ -89,12 +89,15 @@ void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipG
 
 // A tree's work lists inside a batch: every level below the root with
 // interior nodes takes the LDS-staged multipole kernel with g source-class
-// groups (at most the tree's partial slots); the root keeps its own choice.
-static const PlanHost &batch_lists(octo_tree *t, int g) {
-    auto it = t->ph_batch.find(g);
+// groups (at most the tree's partial slots); the root's per-wavefront work
+// is split into root_parts stencil chunks (at most its partial slots).
+static const PlanHost &batch_lists(octo_tree *t, int g, int root_parts) {
+    const int key = g * 64 + root_parts;
+    auto it = t->ph_batch.find(key);
     if (it != t->ph_batch.end()) return it->second;
     const int nl = t->layout.n_levels;
     std::vector<int> parts = t->parts, lds = t->m2l_lds;
+    if (t->layout.lv[0].n_int > 0 && !lds[0]) parts[0] = std::min(root_parts, t->parts_alloc[0]);
     for (int l = 1; l < nl; ++l)
         if (t->layout.lv[l].n_int > 0) {
             lds[l] = 1;
@@ -104,7 +107,7 @@ static const PlanHost &batch_lists(octo_tree *t, int g) {
     ph.levels = t->ph.levels;
     ph.trees = t->ph.trees;
     plan_items(t, parts, lds, ph);
-    return t->ph_batch.emplace(g, std::move(ph)).first->second;
+    return t->ph_batch.emplace(key, std::move(ph)).first->second;
 }
 
 // Concatenate the plans of several trees: each tree's own plan, or with
@@ -112,7 +115,10 @@ static const PlanHost &batch_lists(octo_tree *t, int g) {
 // share each launch, so a level's few nodes no longer leave the device idle:
 // all levels below the root go to the LDS-staged kernel, with the
 // source-class group count (the same for every tree) that the launch model
-// prices lowest over the whole batch.
+// prices lowest over the whole batch, and the roots' per-wavefront work is
+// split only as far as it takes to give every CU four wavefronts (a single
+// tree splits its root 32 ways, each part writing a partial slot of every
+// root cell that the downward pass then reads).
 static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, const std::vector<TreeDesc> &descs,
                                              bool fitted) {
     auto bp = std::make_unique<BatchPlan>();
@@ -140,8 +146,12 @@ static std::unique_ptr<BatchPlan> make_batch(octo_tree *const *trees, int n, con
             }
         }
     }
+    int roots = 0;
+    for (int i = 0; i < n; ++i) roots += trees[i]->layout.lv[0].n_int > 0 ? 1 : 0;
+    const int n_cu = std::max(8, trees[0]->ctx->n_cu);
+    const int root_parts = std::max(1, std::min(32, (4 * n_cu + 8 * std::max(1, roots) - 1) / (8 * std::max(1, roots))));
     std::vector<const PlanHost *> src(n);
-    for (int i = 0; i < n; ++i) src[i] = g_best ? &batch_lists(trees[i], g_best) : &trees[i]->ph;
+    for (int i = 0; i < n; ++i) src[i] = g_best ? &batch_lists(trees[i], g_best, root_parts) : &trees[i]->ph;
     size_t max_lv = 0;
     for (int i = 0; i < n; ++i) max_lv = std::max(max_lv, src[i]->interior.size());
     ph.interior.resize(max_lv);
