@@ -925,6 +925,43 @@ __global__ __launch_bounds__(512, DIP ? 2 : 4) void k_m2l_lds(const LevelDesc *_
             s_src[9 % NV][c] = make_double2(d[2], 0.0);
         }
     };
+    // second source (one work-group per CU, registers to spare): the next
+    // class's raw values are loaded into registers while this class is
+    // walked, and stored after the barrier that ends the walk
+    double pv[23];
+    auto load_regs = [&](int q) {
+        const int sx = 2 * cx - 4 + (q >> 2), sy = 2 * cy - 4 + ((q >> 1) & 1), sz = 2 * cz - 4 + (q & 1);
+        const int nb = s_nbr[nbr_slot(sx, sy, sz)];
+        if (nb >= 0 && nb < n_src) {
+            const size_t si = (size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7);
+            pv[0] = gmass[si];
+#pragma unroll
+            for (int k = 0; k < kRec; ++k) pv[1 + k] = gmp[k * S + si];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pv[20 + k] = gdip[k * S + si];
+        } else {
+            pv[0] = -0.0;
+            pv[1] = pv[2] = pv[3] = 1.0e3;
+#pragma unroll
+            for (int k = 4; k < 23; ++k) pv[k] = 0.0;
+        }
+    };
+    auto store_regs = [&]() {
+        const int c = cx * HX + cy * HY + cz;
+        double q5[5], o7[7];
+        detrace_q(&pv[4], q5);
+        detrace_o(&pv[10], o7);
+        s_src[0][c] = make_double2(pv[0], pv[1]);
+        s_src[1][c] = make_double2(pv[2], pv[3]);
+        s_src[2][c] = make_double2(q5[0], q5[1]);
+        s_src[3][c] = make_double2(q5[2], q5[3]);
+        s_src[4][c] = make_double2(q5[4], o7[0]);
+        s_src[5][c] = make_double2(o7[1], o7[2]);
+        s_src[6][c] = make_double2(o7[3], o7[4]);
+        s_src[7][c] = make_double2(o7[5], o7[6]);
+        s_src[8 % NV][c] = make_double2(pv[20], pv[21]);
+        s_src[9 % NV][c] = make_double2(pv[22], 0.0);
+    };
     // the needed classes of this item's share, in order (uniform)
     auto next_class = [&](int q) {
         for (++q; q < q1; ++q)
@@ -932,8 +969,14 @@ __global__ __launch_bounds__(512, DIP ? 2 : 4) void k_m2l_lds(const LevelDesc *_
         return q;
     };
     int q = next_class(q0 - 1);
+    if constexpr (DIP) {
+        if (q < q1) load_regs(q);
+    }
     while (q < q1) {
-        stage_class(q);
+        if constexpr (DIP)
+            store_regs();
+        else
+            stage_class(q);
         __syncthreads();
         const int beg = st.m2l_src_beg[p * 9 + q], end = st.m2l_src_beg[p * 9 + q + 1];
         const int hb = (x >> 1) * HX + (y >> 1) * HY + (z >> 1);
@@ -987,8 +1030,12 @@ __global__ __launch_bounds__(512, DIP ? 2 : 4) void k_m2l_lds(const LevelDesc *_
 #pragma unroll OCTO_M2L_UNROLL
             for (int k = beg; k < end; ++k) pair(k);
         }
+        const int qn = next_class(q);
+        if constexpr (DIP) {
+            if (qn < q1) load_regs(qn);
+        }
         __syncthreads();
-        q = next_class(q);
+        q = qn;
     }
     acc_close<DIP>(a);
     if (!(mA > 0.0)) a.C[0] = a.C[1] = a.C[2] = 0.0;
