@@ -289,8 +289,9 @@ def scf_bench(a, lib, w, ctx, level, iters):
 
 def regrid_bench(tree, host_build_ms, l_max=7, rho_r=0.1, n_target=4000, reps=5):
     """One regrid of the adaptive tree by the density criterion on the device
-    (flags, balance, new leaves and densities) plus the host layout of the
-    new tree; the tree's own host build from the analytic field beside it."""
+    (flags, balance, new leaves and densities) plus the new tree's layout
+    (on the device) and work plan; the tree's own host build from the
+    analytic field beside it."""
     say(f"regrid: {reps} runs")
     t2, st = tree.regrid(l_max, rho_r, n_target)  # warm-up
     t2.destroy()

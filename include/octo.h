@@ -212,6 +212,34 @@ octo_status octo_tree_get_density(const octo_tree *tree, double *rho, int rho_on
 octo_status octo_tree_info(const octo_tree *tree, int64_t *n_leaf_cells, int32_t *n_levels, size_t *bytes);
 /* Copy the leaf list (n_leaves entries) into caller memory. */
 octo_status octo_tree_leaves(const octo_tree *tree, octo_leaf *out);
+
+/* The node tables of one level (layout of the tree's device memory; see
+ * octo_tree_level_tables): caller buffers, any of them NULL to skip it.
+ *   nbr       n_nodes x 27: same-level neighbour (dx,dy,dz) at
+ *             (dx+1)*9 + (dy+1)*3 + dz+1, -1 = none (all -1 at level 0)
+ *   child     n_int x 8: child node at level + 1, child (cx,cy,cz) at cx*4+cy*2+cz
+ *   parent    n_nodes: node at level - 1 (-1 at level 0)
+ *   coord     n_nodes x 3: sub-grid index at this level
+ *   out_base  n_nodes: density-layout offset of a leaf's cell (0,0,0), -1 for interior nodes
+ *   flags     n_nodes: a leaf's multipole roles (1: multipole partner of same-level cells,
+ *             2: partner of cells one level up, 4: keeps multipole accumulators), 0 for interior
+ *   int_child n_int: 1 where one of the node's children is interior
+ * Nodes are numbered interior first, then leaves next to an interior node,
+ * then the other leaves, each group in Morton order (x bit above y above z). */
+typedef struct {
+    int32_t *nbr, *child, *parent, *coord;
+    int64_t *out_base;
+    int32_t *flags, *int_child;
+} octo_level_tables;
+
+/* Sizes of level `level` of a tree (sizes[0] nodes, sizes[1] interior nodes,
+ * sizes[2] interior nodes + leaves next to an interior node) and, if out is
+ * not NULL, its node tables copied from device memory (returns when the copy
+ * is done).  For tests and tools that check a layout, e.g. a regridded tree
+ * laid out on the device against octo_host_level_tables of its leaf list.
+ * Errors: OCTO_E_INVALID (NULL sizes, level outside [0, n_levels)). */
+octo_status octo_tree_level_tables(const octo_tree *tree, int32_t level, int64_t *sizes,
+                                   const octo_level_tables *out);
 octo_status octo_tree_destroy(octo_tree *tree);
 
 /* ---- solve -------------------------------------------------------------- */
@@ -434,7 +462,7 @@ typedef struct {
     int64_t n_grids;          /* sub-grids of the new tree, leaves and interior nodes */
     double rho_r_next;        /* (n_grids / n_target)^2 rho_r, or rho_r when n_target <= 0 */
     double flag_ms;           /* host wall time of the device part (flags, balance, new leaves and densities) */
-    double layout_ms;         /* host wall time of laying out and uploading the new tree */
+    double layout_ms;         /* host wall time of the new tree's layout (on the device) and work plan */
 } octo_regrid_stats;
 
 /* One regrid of `tree` by the density criterion of Sec. 2.7, computed on the

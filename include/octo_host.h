@@ -51,6 +51,14 @@ octo_status octo_host_near_stage(int32_t *out, int64_t cap, int64_t *n);
  * level + 1.  out must hold 3 * 10 entries. */
 octo_status octo_host_layout(const octo_leaf *leaves, int64_t n_leaves, int32_t *n_levels, int64_t *out);
 
+/* The layout octo_tree_build gives a leaf list (leaf-list density layout):
+ * sizes of level `level` (as octo_tree_level_tables) and, if out is not
+ * NULL, its node tables in the format of octo_level_tables.
+ * Errors: as octo_tree_build for the list; OCTO_E_INVALID for a level
+ * outside [0, deepest level]. */
+octo_status octo_host_level_tables(const octo_leaf *leaves, int64_t n_leaves, int32_t level, int64_t *sizes,
+                                   const octo_level_tables *out);
+
 /* Leaf list of octo_tree_build_adaptive (same refinement and nesting rule,
  * same order).  If out is NULL or cap is too small only *n is set. */
 octo_status octo_host_adaptive_leaves(octo_boxmax_fn boxmax, void *user, int max_level, double threshold,

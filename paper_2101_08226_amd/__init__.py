@@ -28,9 +28,9 @@ STATUS_NAMES = {0: "OCTO_OK", 1: "OCTO_E_INVALID", 2: "OCTO_E_DEVICE", 3: "OCTO_
 # every symbol include/octo.h declares
 EXPORTS = [
     "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_ctx_set_batch_shapes", "octo_tree_build", "octo_tree_build_uniform",
-    "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_get_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_destroy",
+    "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_get_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_level_tables", "octo_tree_destroy",
     "octo_solve", "octo_solve_device_stats", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_step_noalloc", "octo_scf_run", "octo_regrid", "octo_submit", "octo_poll", "octo_wait", "octo_last_error", "octo_build_id",
-    "octo_host_stencil_sizes", "octo_host_near_lists", "octo_host_near_stage", "octo_host_layout", "octo_host_adaptive_leaves",
+    "octo_host_stencil_sizes", "octo_host_near_lists", "octo_host_near_stage", "octo_host_layout", "octo_host_level_tables", "octo_host_adaptive_leaves",
 ]
 
 
@@ -42,6 +42,12 @@ class OctoError(RuntimeError):
 
 class octo_leaf(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("ix", ctypes.c_int32), ("iy", ctypes.c_int32), ("iz", ctypes.c_int32)]
+
+
+class octo_level_tables(ctypes.Structure):
+    _fields_ = [("nbr", ctypes.c_void_p), ("child", ctypes.c_void_p), ("parent", ctypes.c_void_p),
+                ("coord", ctypes.c_void_p), ("out_base", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+                ("int_child", ctypes.c_void_p)]
 
 
 class octo_opts(ctypes.Structure):
@@ -143,6 +149,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_regrid": [_P, _P, ctypes.POINTER(octo_regrid_params), _PP, ctypes.POINTER(octo_regrid_stats)],
         "octo_tree_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t)],
         "octo_tree_leaves": [_P, ctypes.POINTER(octo_leaf)],
+        "octo_tree_level_tables": [_P, ctypes.c_int32, ctypes.POINTER(_I64), ctypes.POINTER(octo_level_tables)],
         "octo_tree_destroy": [_P],
         "octo_solve": [_P, _P, ctypes.POINTER(octo_opts), _D, _D, _I, ctypes.POINTER(octo_stats)],
         "octo_solve_device_stats": [_P, _P, ctypes.POINTER(octo_opts), _D, _D, _D],
@@ -166,6 +173,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_host_near_lists": [ctypes.c_double, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _I64,
                                  ctypes.POINTER(_I64)],
         "octo_host_layout": [ctypes.POINTER(octo_leaf), _I64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_I64)],
+        "octo_host_level_tables": [ctypes.POINTER(octo_leaf), _I64, ctypes.c_int32, ctypes.POINTER(_I64),
+                                   ctypes.POINTER(octo_level_tables)],
         "octo_host_adaptive_leaves": [BOXMAX_FN, _P, _I, ctypes.c_double, ctypes.POINTER(octo_leaf), _I64,
                                       ctypes.POINTER(_I64)],
     }
@@ -289,6 +298,36 @@ def octo_tree_leaves(tree: int) -> np.ndarray:
     out = np.empty((n // 512, 4), dtype=np.int32)
     _check(load_library().octo_tree_leaves(tree, out.ctypes.data_as(ctypes.POINTER(octo_leaf))))
     return out
+
+
+def _level_tables(call) -> dict:
+    """Sizes, then the tables of one level (the octo_level_tables format) as
+    numpy arrays: nbr (n, 27), child (n_int, 8), parent (n,), coord (n, 3),
+    out_base (n,), flags (n,), int_child (n_int,)."""
+    sizes = np.zeros(3, dtype=np.int64)
+    _check(call(sizes.ctypes.data_as(ctypes.POINTER(_I64)), None))
+    n, n_int, n_rec = (int(v) for v in sizes)
+    t = {"nbr": np.empty((n, 27), np.int32), "child": np.empty((n_int, 8), np.int32),
+         "parent": np.empty(n, np.int32), "coord": np.empty((n, 3), np.int32), "out_base": np.empty(n, np.int64),
+         "flags": np.empty(n, np.int32), "int_child": np.empty(n_int, np.int32)}
+    out = octo_level_tables(*(t[k].ctypes.data for k in ("nbr", "child", "parent", "coord", "out_base", "flags",
+                                                         "int_child")))
+    _check(call(sizes.ctypes.data_as(ctypes.POINTER(_I64)), ctypes.byref(out)))
+    t.update(n_nodes=n, n_int=n_int, n_rec=n_rec)
+    return t
+
+
+def octo_tree_level_tables(tree: int, level: int) -> dict:
+    """The node tables of one level of a tree, copied from device memory."""
+    return _level_tables(lambda sz, out: load_library().octo_tree_level_tables(tree, int(level), sz, out))
+
+
+def octo_host_level_tables(leaves, level: int) -> dict:
+    """The node tables the host builder gives one level of a leaf list."""
+    lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
+    ptr = lv.ctypes.data_as(ctypes.POINTER(octo_leaf))
+    return _level_tables(lambda sz, out: load_library().octo_host_level_tables(ptr, lv.shape[0], int(level), sz,
+                                                                               out))
 
 
 def octo_tree_destroy(tree: int) -> None:
@@ -617,6 +656,9 @@ class Tree:
 
     def leaves(self) -> np.ndarray:
         return octo_tree_leaves(self.handle)
+
+    def level_tables(self, level: int) -> dict:
+        return octo_tree_level_tables(self.handle, level)
 
     def autotune(self, theta=0.5, precision=OCTO_FP64, amc=True, G=1.0) -> list:
         """Pick the multipole work shape per level by timing; returns the choice

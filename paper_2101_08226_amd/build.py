@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liboctofmm.so")
-SOURCES = ["kernels.hip", "scf.hip", "regrid.hip", "tree.cpp", "octo_abi.cpp", "batch.cpp", "host_api.cpp"]
+SOURCES = ["kernels.hip", "scf.hip", "regrid.hip", "layout.hip", "tree.cpp", "octo_abi.cpp", "batch.cpp", "host_api.cpp"]
 # per-source flags: the SCF steps round as written (no contraction into FMA)
 EXTRA = {"scf.hip": ["-ffp-contract=off"], "regrid.hip": ["-ffp-contract=off"]}
 ARCH = os.environ.get("OCTO_ARCH", "gfx950")

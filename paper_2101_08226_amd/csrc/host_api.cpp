@@ -97,6 +97,31 @@ octo_status octo_host_layout(const octo_leaf *leaves, int64_t n_leaves, int32_t 
     });
 }
 
+octo_status octo_host_level_tables(const octo_leaf *leaves, int64_t n_leaves, int32_t level, int64_t *sizes,
+                                   const octo_level_tables *out) {
+    return guard_h([&] {
+        if (!sizes) fail(OCTO_E_INVALID, "NULL sizes");
+        const Layout L = build_layout(leaves, n_leaves, -1);
+        if (level < 0 || level >= L.n_levels) fail(OCTO_E_INVALID, "level out of range");
+        const HostLevel &h = L.lv[level];
+        sizes[0] = h.n_nodes;
+        sizes[1] = h.n_int;
+        sizes[2] = h.n_rec;
+        if (!out) return;
+        auto put = [](auto *dst, const auto &v) {
+            if (dst)
+                for (size_t i = 0; i < v.size(); ++i) dst[i] = v[i];
+        };
+        put(out->nbr, h.nbr);
+        put(out->child, h.child);
+        put(out->parent, h.parent);
+        put(out->coord, h.coord);
+        put(out->out_base, h.out_base);
+        put(out->flags, h.flags);
+        put(out->int_child, h.int_child);
+    });
+}
+
 octo_status octo_host_adaptive_leaves(octo_boxmax_fn boxmax, void *user, int max_level, double threshold,
                                       octo_leaf *out, int64_t cap, int64_t *n) {
     return guard_h([&] {

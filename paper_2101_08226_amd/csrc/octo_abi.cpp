@@ -185,16 +185,17 @@ void shape_tree(octo_tree *t, TreeBlock &B) {
     size_t bytes = 0;
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
+        const size_t nn = h.n_nodes;
         B.nbr[l] = bytes;
-        bytes += al(h.nbr.size() * 4);
+        bytes += al(nn * 27 * 4);
         B.child[l] = bytes;
-        bytes += al(h.child.size() * 4);
+        bytes += al((size_t)h.n_int * 8 * 4);
         B.parent[l] = bytes;
-        bytes += al(h.parent.size() * 4);
+        bytes += al(nn * 4);
         B.coord[l] = bytes;
-        bytes += al(h.coord.size() * 4);
+        bytes += al(nn * 3 * 4);
         B.out[l] = bytes;
-        bytes += al(h.out_base.size() * 8);
+        bytes += al(nn * 8);
     }
     B.rho = bytes;
     bytes += al((size_t)L.n_leaf_cells * 8);
@@ -235,8 +236,11 @@ void stage_tree(const octo_tree *t, const TreeBlock &B, const double *rho_host, 
 
 // Under the context lock: allocate the data block, enqueue the upload of the
 // image (pinned; handed back to the context's pool, reusable once the copy is
-// done) and fill the level and tree descriptors.
-void commit_tree(octo_tree *t, const TreeBlock &B, void *img, size_t img_bytes, const double *rho_dev) {
+// done; none for tables laid out on the device) and fill the level and tree
+// descriptors.  A device density is copied; unless its owner keeps it until
+// the stream has passed the copy (wait_rho false), the copy is waited for.
+void commit_tree(octo_tree *t, const TreeBlock &B, void *img, size_t img_bytes, const double *rho_dev,
+                 bool wait_rho = true) {
     octo_ctx *ctx = t->ctx;
     const Layout &L = t->layout;
     const int nl = L.n_levels;
@@ -245,16 +249,22 @@ void commit_tree(octo_tree *t, const TreeBlock &B, void *img, size_t img_bytes, 
     t->data.bytes = B.bytes;
     char *base = (char *)mem;
     hipStream_t s = ctx->stream;
-    check_hip(hipMemcpyAsync(base, img, rho_dev ? B.rho : B.upload, hipMemcpyHostToDevice, s), "tree upload");
+    if (img)
+        check_hip(hipMemcpyAsync(base, img, rho_dev ? B.rho : B.upload, hipMemcpyHostToDevice, s), "tree upload");
     if (rho_dev)
         check_hip(hipMemcpyAsync(base + B.rho, rho_dev, (size_t)L.n_leaf_cells * 8, hipMemcpyDeviceToDevice, s),
                   "density copy");
-    hipEvent_t done = nullptr;
-    check_hip(hipEventCreateWithFlags(&done, hipEventDisableTiming), "event");
-    check_hip(hipEventRecord(done, s), "event");
-    // a caller's device density is read by the copy: done before returning
-    if (rho_dev) check_hip(hipEventSynchronize(done), "density copy");
-    ctx->pinned_put(img, img_bytes, done);
+    if (img || (rho_dev && wait_rho)) {
+        hipEvent_t done = nullptr;
+        check_hip(hipEventCreateWithFlags(&done, hipEventDisableTiming), "event");
+        check_hip(hipEventRecord(done, s), "event");
+        // a caller's device density is read by the copy: done before returning
+        if (rho_dev && wait_rho) check_hip(hipEventSynchronize(done), "density copy");
+        if (img)
+            ctx->pinned_put(img, img_bytes, done);
+        else
+            hipEventDestroy(done);
+    }
     PlanHost &ph = t->ph;
     ph = PlanHost{};
     ph.levels.resize(nl);
@@ -357,8 +367,7 @@ void plan_items(const octo_tree *t, const std::vector<int> &parts, const std::ve
         const HostLevel &h = L.lv[l];
         defer[l].assign(h.n_int, parts[l] <= 4 ? 1 : 0);
         for (int n = 0; n < h.n_int; ++n)
-            for (int k = 0; k < 8; ++k)
-                if (h.child[8 * n + k] < L.lv[l + 1].n_int) defer[l][n] = 0;
+            if (h.int_child[n]) defer[l][n] = 0;
     }
     for (int l = 0; l < nl; ++l) {
         const HostLevel &h = L.lv[l];
@@ -631,6 +640,7 @@ octo_status octo_ctx_destroy(octo_ctx *ctx) {
         hipEventDestroy(ctx->ev0);
         for (int i = 0; i < 9; ++i) hipEventDestroy(ctx->phase_ev[i]);
         hipEventDestroy(ctx->ev1);
+        layout_device_release(ctx);
         hipHostFree(ctx->h_stats);
         for (auto &b : ctx->pinned_free) {
             if (b.ready) hipEventDestroy(b.ready);
@@ -710,6 +720,54 @@ static octo_status make_tree(octo_ctx *ctx, const octo_leaf *leaves, int64_t n, 
         ctx->n_trees++;
         *out = t.release();
     });
+}
+
+// A tree from a leaf list and densities in device memory (leaf-list layout),
+// laid out on the device under the context lock; the caller keeps both
+// until the context stream has passed this call's work.
+static octo_tree *make_tree_device(octo_ctx *ctx, const octo_leaf *leaves, int64_t n, int levels,
+                                   const double *rho) {
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard dg(ctx->device);
+    auto t = std::make_unique<octo_tree>();
+    t->ctx = ctx;
+    layout_device(ctx, leaves, n, levels, t->layout);
+    TreeBlock B;
+    try {
+        shape_tree(t.get(), B);
+        commit_tree(t.get(), B, nullptr, 0, rho, false);
+    } catch (...) {
+        layout_device_abort(ctx);
+        if (t->data.ptr) {
+            hipStreamSynchronize(ctx->stream);
+            ctx->dev_free(t->data.ptr, t->data.bytes);
+        }
+        throw;
+    }
+    const Layout &L = t->layout;
+    LayTables tb{};
+    char *base = (char *)t->data.ptr;
+    for (int l = 0; l < L.n_levels; ++l) {
+        tb.nbr[l] = (int32_t *)(base + B.nbr[l]);
+        tb.child[l] = (int32_t *)(base + B.child[l]);
+        tb.parent[l] = (int32_t *)(base + B.parent[l]);
+        tb.coord[l] = (int32_t *)(base + B.coord[l]);
+        tb.out_base[l] = (int64_t *)(base + B.out[l]);
+        tb.n_int[l] = L.lv[l].n_int;
+    }
+    layout_device_tables(ctx, tb);
+    try {
+        build_tree_plan(t.get());
+    } catch (...) {
+        hipStreamSynchronize(ctx->stream);
+        ctx->dev_free(t->data.ptr, t->data.bytes);
+        t->data.ptr = nullptr;
+        throw;
+    }
+    check_hip(hipEventCreateWithFlags(&t->last_use, hipEventDisableTiming), "event");
+    tree_release(t.get(), ctx->stream);
+    ctx->n_trees++;
+    return t.release();
 }
 
 octo_status octo_tree_build(octo_ctx *ctx, const octo_leaf *leaves, int64_t n_leaves, const double *rho,
@@ -805,6 +863,37 @@ octo_status octo_tree_leaves(const octo_tree *t, octo_leaf *out) {
     return guard([&] {
         if (!t || !out) fail(OCTO_E_INVALID, "NULL argument");
         std::copy(t->layout.leaves.begin(), t->layout.leaves.end(), out);
+    });
+}
+
+octo_status octo_tree_level_tables(const octo_tree *t, int32_t level, int64_t *sizes, const octo_level_tables *out) {
+    return guard([&] {
+        if (!t || !sizes) fail(OCTO_E_INVALID, "NULL argument");
+        const Layout &L = t->layout;
+        if (level < 0 || level >= L.n_levels) fail(OCTO_E_INVALID, "level out of range");
+        const HostLevel &h = L.lv[level];
+        sizes[0] = h.n_nodes;
+        sizes[1] = h.n_int;
+        sizes[2] = h.n_rec;
+        if (!out) return;
+        octo_ctx *ctx = t->ctx;
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        DeviceGuard dg(ctx->device);
+        check_hip(hipEventSynchronize(t->last_use), "tree tables");
+        const LevelDesc &d = t->ph.levels[level];
+        auto get = [](void *dst, const void *src, size_t bytes) {
+            if (dst && bytes) check_hip(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost), "tree tables");
+        };
+        const size_t nn = h.n_nodes;
+        get(out->nbr, d.nbr, nn * 27 * 4);
+        get(out->child, d.child, (size_t)h.n_int * 8 * 4);
+        get(out->parent, d.parent, nn * 4);
+        get(out->coord, d.coord, nn * 3 * 4);
+        get(out->out_base, d.out_base, nn * 8);
+        if (out->flags)
+            for (size_t i = 0; i < nn; ++i) out->flags[i] = h.flags[i];
+        if (out->int_child)
+            for (int i = 0; i < h.n_int; ++i) out->int_child[i] = h.int_child[i];
     });
 }
 
@@ -1054,17 +1143,15 @@ octo_status octo_regrid(octo_ctx *ctx, octo_tree *tree, const octo_regrid_params
         if (p->l_max < 0 || p->l_max > kMaxLevel) fail(OCTO_E_INVALID, "l_max must lie in [0, 9]");
         if (!std::isfinite(p->rho_r) || p->rho_r <= 0.0) fail(OCTO_E_INVALID, "rho_r must be finite and positive");
         RegridOut r;
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        DeviceGuard dg(ctx->device);
         const auto t0 = std::chrono::steady_clock::now();
-        {
-            std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-            DeviceGuard dg(ctx->device);
-            tree_acquire(ctx, tree);
-            regrid_device(ctx, tree, p->l_max, p->rho_r, r);
-        }
+        tree_acquire(ctx, tree);
+        regrid_device(ctx, tree, p->l_max, p->rho_r, r);
         const auto t1 = std::chrono::steady_clock::now();
-        octo_tree *t = nullptr;
-        const octo_status st = make_tree(ctx, r.leaves.data(), (int64_t)r.leaves.size(), -1, r.rho, 1, &t);
-        if (st != OCTO_OK) throw Error{st, g_err};
+        octo_tree *t = make_tree_device(ctx, r.leaves, r.n_leaves, r.levels, r.rho);
+        // the old tree's last use: the regrid read it
+        tree_release(tree, ctx->stream);
         const auto t2 = std::chrono::steady_clock::now();
         int64_t grids = 0;
         for (const HostLevel &h : t->layout.lv) grids += h.n_nodes;
@@ -1073,7 +1160,7 @@ octo_status octo_regrid(octo_ctx *ctx, octo_tree *tree, const octo_regrid_params
             stats->refined = r.refined;
             stats->balance_refined = r.balance_refined;
             stats->derefined = r.derefined;
-            stats->n_leaves = (int64_t)r.leaves.size();
+            stats->n_leaves = r.n_leaves;
             stats->n_grids = grids;
             const double ratio = (double)grids / (double)p->n_target;
             stats->rho_r_next = p->n_target > 0 ? p->rho_r * (ratio * ratio) : p->rho_r;

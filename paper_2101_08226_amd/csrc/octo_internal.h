@@ -16,6 +16,8 @@
 
 #include <cstdint>
 
+#include "octo.h"
+
 #ifndef __HIPCC__
 #ifndef __host__
 #define __host__
@@ -152,6 +154,46 @@ struct StencilDev {
     const int32_t *m2l_src_d;      // per m2l_src entry: the offset d (source cell minus target cell), packed
     int32_t m2l_src_any[64];       // target class p, source class q: union of the group's touch masks
     double theta2;
+};
+
+// Device tree layout (csrc/layout.hip, csrc/layout_ops.h).  Node presence
+// lives in one dense cell per node position and level (Morton index within the
+// level): 0 absent, kMarkLeaf / kMarkInt while the node set is built and
+// classified, then kIdxBase + the node's index in its level.
+constexpr int32_t kMarkLeaf = 1, kMarkInt = 2, kIdxBase = 16;
+// error codes, lowest first wins (then the lowest item)
+enum : uint64_t { kLayLevel = 1, kLayIndex = 2, kLayDup = 3, kLayInside = 4, kLayGap = 5, kLayNest = 6, kLayFull = 7 };
+// sort key: level << 29 | class << 27 | Morton index (class 0 interior, 1
+// record leaf, 2 other leaf); padding sorts last
+constexpr uint64_t kKeyPad = (1ull << 33) - 1;
+constexpr int kKeyBits = 33;
+// control words: [0] nodes appended, [1] first error (code << 32 | item),
+// [2 + 3 * level + class] first sorted position of (level, class)
+constexpr int kCtlWords = 2 + 3 * (kMaxLevel + 1);
+
+struct LayK {
+    const octo_leaf *leaf;
+    int64_t n_leaf;
+    int32_t *cell;                  // dense presence cells of levels [0, levels)
+    int64_t goff[kMaxLevel + 2];    // first cell of each level: sum of 8^k, k < l
+    int32_t levels;
+    int64_t cap;                    // node capacity
+    unsigned long long *ctl;        // kCtlWords control words
+    uint64_t *node_lm;              // per appended node: level << 32 | Morton index
+    int32_t *node_leaf;             // its position in the leaf list, -1 for interior
+    uint64_t *key;                  // sort input (key, slot)
+    int32_t *val;
+    const uint64_t *skey;           // sort output
+    const int32_t *sval;
+    int32_t *info;                  // per slot: kLeaf* flags of a leaf; 1 if an interior node has an interior child
+    int32_t *host;                  // per sorted position: info, parent index (downloaded)
+};
+
+// the tables of a laid-out tree, per level
+struct LayTables {
+    int32_t *nbr[kMaxLevel + 1], *child[kMaxLevel + 1], *parent[kMaxLevel + 1], *coord[kMaxLevel + 1];
+    int64_t *out_base[kMaxLevel + 1];
+    int32_t n_int[kMaxLevel + 1];
 };
 
 __host__ __device__ inline int32_t pack_off(int dx, int dy, int dz) {

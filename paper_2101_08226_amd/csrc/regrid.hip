@@ -1,7 +1,7 @@
 // One regrid of a tree by the density criterion of Sec. 2.7 ("Refinement
 // Criteria") on the device: flags, 2:1 balance, the new leaf list and the
-// densities moved onto it.  The host receives the leaf list (16 B per leaf)
-// and lays the new tree out; the densities never leave the device.
+// densities moved onto it.  The leaf list and the densities stay on the
+// device, where the new tree is laid out (csrc/layout.hip).
 //
 // Criterion: a cell of level l is flagged when rho > 8^(l + 1 - l_max) rho_r
 // (the largest level L with rho > 8^(L - l_max) rho_r exceeds l).  A leaf
@@ -16,6 +16,7 @@
 //
 // Per-node marks: bit 0 refined by the criterion, bit 1 refined for balance,
 // bit 2 de-refinement candidate, bit 3 de-refinement dropped.
+#include <algorithm>
 #include <vector>
 
 #include "runtime.h"
@@ -310,10 +311,10 @@ void regrid_device(octo_ctx *ctx, octo_tree *t, int l_max, double rho_r, RegridO
     octo_leaf *out_leaf = (octo_leaf *)r.out;
     r.rho = (double *)((char *)r.out + al((size_t)n_new * sizeof(octo_leaf)));
     hipLaunchKernelGGL(k_rg_emit, dim3(total), dim3(kRgT), 0, q, k, dl, rho, marks, cnt, off, out_leaf, r.rho);
-    r.leaves.resize(n_new);
-    check_hip(hipMemcpyAsync(r.leaves.data(), out_leaf, (size_t)n_new * sizeof(octo_leaf), hipMemcpyDeviceToHost, q),
-              "leaf copy");
-    check_hip(hipStreamSynchronize(q), "regrid");
+    check_hip(hipGetLastError(), "regrid emit");
+    r.leaves = out_leaf;
+    r.n_leaves = n_new;
+    r.levels = std::min(nl + 1, kMaxLevel + 1);  // a regrid refines by one level at most
 }
 
 RegridOut::~RegridOut() {

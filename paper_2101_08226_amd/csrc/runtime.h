@@ -33,6 +33,7 @@ struct HostLevel {
     std::vector<int32_t> nbr, child, parent, coord;
     std::vector<int64_t> out_base;
     std::vector<int32_t> flags;  // kLeaf* flags per node (leaf nodes)
+    std::vector<char> int_child;  // per interior node: 1 if one of its children is interior
 };
 
 struct Layout {
@@ -208,6 +209,18 @@ struct Lane {
 };
 }  // namespace octo
 
+namespace octo {
+// the device layout's buffers, kept by the context: the dense cells of
+// `levels` levels (all clear between uses) and the work arrays of `cap` nodes
+struct LayBuf {
+    void *cell = nullptr, *work = nullptr;
+    size_t cell_bytes = 0, work_bytes = 0, sort_bytes = 0;
+    int levels = 0;
+    int64_t cap = 0;
+    LayK pending{};  // the passes of the layout in progress (between layout_device and its tables)
+};
+}  // namespace octo
+
 struct octo_ctx {
     // serialises every call that touches the context (several threads may
     // build trees at once: validation and layout happen before the lock)
@@ -255,6 +268,8 @@ struct octo_ctx {
     int next_wave = 0;
     int max_inflight_waves = 2;
     std::vector<octo::Lane> lanes;  // max_inflight_waves lanes, created with the first wave
+
+    octo::LayBuf lay;  // device layout (regridded trees)
 
     void *dev_alloc(size_t bytes);
     void dev_free(void *p, size_t bytes);
@@ -315,13 +330,15 @@ size_t scf_fixed_scratch_bytes();
 void scf_run(octo_ctx *ctx, octo_tree *t, int level, const octo_opts &o, const octo_scf_params &p, int64_t s2,
              int iterations, double *rho_out, double *phi_out, octo_scf_state *history);
 // one regrid by the density criterion (Sec. 2.7) on the device: the new leaf
-// list (host) and its densities (device, leaf layout), owned until destruction
+// list and its densities (device, leaf layout), owned until destruction
 struct RegridOut {
     octo_ctx *ctx = nullptr;
     void *scratch = nullptr, *out = nullptr;
     size_t scratch_bytes = 0, out_bytes = 0;
     double *rho = nullptr;
-    std::vector<octo_leaf> leaves;
+    const octo_leaf *leaves = nullptr;
+    int64_t n_leaves = 0;
+    int levels = 0;  // the new leaves lie in levels [0, levels)
     int64_t refined = 0, balance_refined = 0, derefined = 0;
     RegridOut() = default;
     RegridOut(const RegridOut &) = delete;
@@ -329,6 +346,16 @@ struct RegridOut {
     ~RegridOut();
 };
 void regrid_device(octo_ctx *ctx, octo_tree *t, int l_max, double rho_r, RegridOut &r);
+// Device layout of a leaf list in device memory (leaf-list layout, levels
+// [0, levels) at most), on the context stream under the context lock:
+// layout_device fills L's counts, leaf flags, parents, interior-child bits and
+// leaf list (one synchronisation; OCTO_E_INVALID for a list that is not a
+// tree); layout_device_tables then writes the node tables of the same list
+// and clears the cells, or layout_device_abort only clears them.
+void layout_device(octo_ctx *ctx, const octo_leaf *leaf, int64_t n, int levels, Layout &L);
+void layout_device_tables(octo_ctx *ctx, const LayTables &t);
+void layout_device_abort(octo_ctx *ctx);
+void layout_device_release(octo_ctx *ctx);
 void build_tree_plan(octo_tree *t);
 void plan_items(const octo_tree *t, const std::vector<int> &parts, const std::vector<int> &m2l_lds, PlanHost &ph);
 double lds_launch_cost(const std::vector<int64_t> &n_int, const std::vector<int> &g, int n_cu);

@@ -216,6 +216,7 @@ Layout build_layout(const octo_leaf *leaves, int64_t n, int grid_level) {
         h.coord.assign((size_t)h.n_nodes * 3, 0);
         h.out_base.assign(h.n_nodes, -1);
         h.flags.assign(h.n_nodes, 0);
+        h.int_child.assign(h.n_int, 0);
         for (int k = 0; k < h.n_nodes; ++k) {
             const int i = v[k];
             const Node &a = nodes[i];
@@ -228,7 +229,11 @@ Layout build_layout(const octo_leaf *leaves, int64_t n, int grid_level) {
             }
             if (l > 0) h.parent[k] = idx[parent[i]];
             if (!a.leaf) {
-                for (int c = 0; c < 8; ++c) h.child[8 * k + c] = idx[childg[(size_t)i * 8 + c]];
+                for (int c = 0; c < 8; ++c) {
+                    const int ch = childg[(size_t)i * 8 + c];
+                    h.child[8 * k + c] = idx[ch];
+                    if (!isleaf[ch]) h.int_child[k] = 1;
+                }
             } else {
                 if (grid_level >= 0)
                     h.out_base[k] = ((int64_t)8 * a.x * gn + 8 * a.y) * gn + 8 * a.z;

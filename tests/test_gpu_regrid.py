@@ -1,5 +1,5 @@
 """GPU parity of the device regrid (octo_regrid, Sec. 2.7) with the oracle's
-regrid.
+regrid, and of the regridded tree's device layout with the host builder's.
 
 Bar: bit-exact.  The leaf lists are integer data; the moved densities are
 copies (new children) or means of 8 cells summed in the same order on both
@@ -40,8 +40,26 @@ def sorted_tree(leaves, rho):
     return leaves[order], rho[order]
 
 
+def check_tables(t2):
+    """The regridded tree is laid out on the device: its node tables, counts,
+    leaf flags and interior-child bits equal the host builder's for its leaf
+    list (integer data: exact)."""
+    leaves = t2.leaves()
+    nl, _ = lib.octo_host_layout(leaves)
+    for l in range(nl):
+        d = t2.level_tables(l)
+        h = lib.octo_host_level_tables(leaves, l)
+        for k in ("n_nodes", "n_int", "n_rec"):
+            assert d[k] == h[k], (l, k, d[k], h[k])
+        for k in ("nbr", "child", "parent", "coord", "out_base", "flags", "int_child"):
+            assert np.array_equal(d[k], h[k]), (l, k)
+    with pytest.raises(lib.OctoError):
+        t2.level_tables(nl)
+
+
 def gpu_regrid(ctx, tree, l_max, rho_r, n_target):
     t2, st = tree.regrid(l_max, rho_r, n_target)
+    check_tables(t2)
     lv, rho = sorted_tree(t2.leaves(), t2.density())
     return t2, lv, rho, st
 
@@ -116,8 +134,14 @@ def test_regrid_full_size_adaptive(ctx):
     say(f"  {info}")
     assert info["refined"] > 0 and info["derefined"] > 0
     compare(lv_g, rho_g, st, lv_o, rho_o, nxt, info)
-    # the new tree solves; its mass is the old one's
-    _, _, s2 = ctx.solve(t2, theta=0.5)
+    # the new tree solves, bitwise as the same leaves laid out on the host;
+    # its mass is the old one's
+    phi2, g2, s2 = ctx.solve(t2, theta=0.5)
+    t3 = ctx.tree(t2.leaves(), t2.density())
+    phi3, g3, _ = ctx.solve(t3, theta=0.5)
+    assert np.array_equal(phi2.cpu().numpy(), phi3.cpu().numpy())
+    assert np.array_equal(g2.cpu().numpy(), g3.cpu().numpy())
+    t3.destroy()
     t2.destroy()
     h = 1.0 / (8 << leaves[:, 0])
     m = float(np.sum(rho.sum(axis=1) * h ** 3))

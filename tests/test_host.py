@@ -199,3 +199,77 @@ def test_near_stage_table_loads_every_halo_cell_once():
         sx = d[np.all(l3 == (1, 0, 0), axis=1)][0] - base
         assert sy >= 9 and sx >= 9 * sy
         assert np.array_equal(d, base + l3[:, 0] * sx + l3[:, 1] * sy + l3[:, 2])
+
+
+def _morton(c):
+    m = np.zeros(len(c), dtype=np.int64)
+    for b in range(10):
+        for a, sh in ((0, 2), (1, 1), (2, 0)):
+            m |= ((c[:, a] >> b) & 1).astype(np.int64) << (3 * b + sh)
+    return m
+
+
+@pytest.mark.parametrize("seed", [2, 5, 8])
+def test_level_tables_describe_the_tree(seed):
+    """The node tables of the leaf-list layout (the format octo_tree_level_tables
+    reports for a tree in device memory) against the tree they describe:
+    children and parents invert each other and nest by coordinate, neighbours
+    sit at their offsets and see each other back, nodes run interior / leaves
+    next to interior nodes / other leaves, each run in Morton order, a leaf's
+    flags follow its neighbours and its parent's neighbours, and out_base
+    names its place in the caller's list."""
+    import helpers
+
+    leaves, _ = helpers.random_amr_leaves(seed, max_level=3 + seed % 2, n_stars=2)
+    leaves = np.asarray(leaves, dtype=np.int32)
+    leaves = leaves[np.random.default_rng(seed).permutation(len(leaves))]
+    nl, _ = lib.octo_host_layout(leaves)
+    T = [lib.octo_host_level_tables(leaves, l) for l in range(nl)]
+    where = {tuple(v): i for i, v in enumerate(leaves.tolist())}
+    for l, t in enumerate(T):
+        n, ni, nr = t["n_nodes"], t["n_int"], t["n_rec"]
+        c = t["coord"].astype(np.int64)
+        assert np.all((c >= 0) & (c < 2 ** l))
+        for lo, hi in ((0, ni), (ni, nr), (nr, n)):
+            assert np.all(np.diff(_morton(c[lo:hi])) > 0)
+        is_int = np.arange(n) < ni
+        if l + 1 < nl:
+            ch = T[l + 1]
+            for k in range(ni):
+                for q in range(8):
+                    j = t["child"][k, q]
+                    assert ch["parent"][j] == k
+                    assert np.array_equal(ch["coord"][j], 2 * c[k] + [q >> 2, (q >> 1) & 1, q & 1])
+                assert t["int_child"][k] == int(np.any(t["child"][k] < ch["n_int"]))
+        else:
+            assert ni == 0
+        if l == 0:
+            assert np.all(t["nbr"] == -1) and t["parent"][0] == -1
+            continue
+        P = T[l - 1]
+        for k in range(n):
+            assert np.array_equal(P["child"][t["parent"][k]][np.dot(c[k] & 1, [4, 2, 1])], k)
+            touches_int = False
+            for o in range(27):
+                d = np.array([o // 9 - 1, (o // 3) % 3 - 1, o % 3 - 1])
+                b = t["nbr"][k, o]
+                q = c[k] + d
+                inside = np.all((q >= 0) & (q < 2 ** l))
+                if b < 0:
+                    # absent: outside the domain, or the parent's neighbour there is a leaf
+                    if inside:
+                        pq = q >> 1
+                        pk = np.flatnonzero(np.all(P["coord"] == pq, axis=1))
+                        assert len(pk) == 1 and pk[0] >= P["n_int"]
+                    continue
+                assert np.array_equal(c[b], q) and t["nbr"][b, 26 - o] == k
+                touches_int |= bool(is_int[b])
+            if k >= ni:
+                # the parent's neighbours that are leaves
+                pn = P["nbr"][t["parent"][k]]
+                x2 = bool(np.any((pn >= P["n_int"]) & (pn >= 0))) if l > 1 else False
+                assert (k < nr) == touches_int
+                assert t["flags"][k] == (5 if touches_int else 0) | (2 if x2 else 0)
+                assert t["out_base"][k] == 512 * where[(l, *c[k])]
+            else:
+                assert t["out_base"][k] == -1 and t["flags"][k] == 0
