@@ -130,7 +130,8 @@ typedef struct {
      * correction, all levels), [4] downward pass (L2L, interior levels),
      * [5] leaves (final shift, potential and acceleration), [6] statistics
      * reduction, [7] the LDS-staged multipole kernel alone (part of [3],
-     * the pairs of m2l_lds_pairs); zeros otherwise */
+     * the pairs of m2l_lds_pairs); for a batch (octo_solve_batch) the phases
+     * of the whole batched launch, the same for every tree; zeros otherwise */
     double phase_ms[8];
 } octo_stats;
 

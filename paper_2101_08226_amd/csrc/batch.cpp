@@ -425,8 +425,15 @@ static void pump(octo_ctx *ctx) {
         const StencilDevHolder &st = ctx->stencil(theta);
         check_hip(hipEventRecord(L.start, ctx->stream), "event");
         check_hip(hipStreamWaitEvent(L.s, L.start, 0), "lane wait");
-        for (octo_tree *t : trees)
-            if (t->last_stream != L.s) check_hip(hipStreamWaitEvent(L.s, t->last_use, 0), "lane wait");
+        {
+            // one wait per distinct event (the trees of a batch share one)
+            std::vector<UseMark *> seen;
+            for (octo_tree *t : trees)
+                if (t->last_stream != L.s && std::find(seen.begin(), seen.end(), t->last_use.get()) == seen.end()) {
+                    seen.push_back(t->last_use.get());
+                    check_hip(hipStreamWaitEvent(L.s, t->last_use->ev, 0), "lane wait");
+                }
+        }
         bp->staging = ctx->pinned_get(img.size(), &bp->staging_bytes);
         memcpy(bp->staging, img.data(), img.size());
         check_hip(hipMemcpyAsync(mem, bp->staging, img.size(), hipMemcpyHostToDevice, L.s), "wave upload");
@@ -444,7 +451,7 @@ static void pump(octo_ctx *ctx) {
         w.lane = lane;
         check_hip(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "event");
         check_hip(hipEventRecord(w.done, L.s), "event");
-        for (octo_tree *t : trees) tree_release(t, L.s);
+        trees_release(trees.data(), (int)trees.size(), L.s);
         w.tickets = take;
         w.bp = std::move(bp);
         const int id = ctx->next_wave++;
@@ -524,7 +531,15 @@ static octo_status solve_batch_impl(octo_ctx *ctx, octo_tree *const *trees_in, i
             ctx->batch = std::move(bp);
         }
         BatchPlan &bp = *ctx->batch;
-        for (int i = 0; i < n; ++i) tree_acquire(ctx, trees[i]);
+        {
+            // one wait per distinct event (the trees of a batch share one)
+            std::vector<UseMark *> seen;
+            for (int i = 0; i < n; ++i)
+                if (std::find(seen.begin(), seen.end(), trees[i]->last_use.get()) == seen.end()) {
+                    seen.push_back(trees[i]->last_use.get());
+                    tree_acquire(ctx, trees[i]);
+                }
+        }
         std::vector<TreeDesc> want;
         for (int i = 0; i < n; ++i) {
             octo_tree *t = trees[i];
@@ -534,7 +549,7 @@ static octo_status solve_batch_impl(octo_ctx *ctx, octo_tree *const *trees_in, i
         if (stats) check_hip(hipEventRecord(ctx->ev0, ctx->stream), "event");
         const bool count = stats != nullptr && ctx->profiling != 2;  // timing-only profiling: no counts
         run_plan(ctx, bp.plan, bp.graphs, want, opts, count);
-        for (int i = 0; i < n; ++i) tree_release(trees[i], ctx->stream);
+        trees_release(trees, n, ctx->stream);
         if (stats) {
             check_hip(hipEventRecord(ctx->ev1, ctx->stream), "event");
             if ((size_t)n * 12 > ctx->h_stats_cap) fail(OCTO_E_INVALID, "batch too large for statistics");
@@ -561,6 +576,7 @@ static octo_status solve_batch_impl(octo_ctx *ctx, octo_tree *const *trees_in, i
                     stats[i].n_leaf_cells = trees[i]->layout.n_leaf_cells;
                     stats[i].device_ms = ms;
                 }
+                if (ctx->profiling) phase_times(ctx, stats[i].phase_ms);  // the whole batch's phases
             }
             for (int k = 0; k < n; ++k) stats_in[idx[k]] = stats[k];
         }

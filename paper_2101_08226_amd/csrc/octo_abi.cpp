@@ -311,6 +311,18 @@ void commit_tree(octo_tree *t, const TreeBlock &B, void *img, size_t img_bytes, 
 }  // namespace
 
 namespace octo {
+// per-phase device times of the last profiled launch (its events have completed)
+void phase_times(const octo_ctx *ctx, double *phase_ms) {
+    for (int i = 0; i < 7; ++i) {
+        float pm = 0.f;
+        hipEventElapsedTime(&pm, ctx->phase_ev[i], ctx->phase_ev[i + 1]);
+        phase_ms[i] = pm;
+    }
+    float pm = 0.f;
+    hipEventElapsedTime(&pm, ctx->phase_ev[8], ctx->phase_ev[4]);
+    phase_ms[7] = pm;
+}
+
 // (Re)build the tree's single-tree plan from its per-level choices: multipole
 // kernel (LDS-staged per node, or chunked per wavefront with `parts` slots).
 // The plan image goes up from pinned staging, ordered on the context stream.
@@ -715,7 +727,6 @@ static octo_status make_tree(octo_ctx *ctx, const octo_leaf *leaves, int64_t n, 
             t->data.ptr = nullptr;
             throw;
         }
-        check_hip(hipEventCreateWithFlags(&t->last_use, hipEventDisableTiming), "event");
         tree_release(t.get(), ctx->stream);
         ctx->n_trees++;
         *out = t.release();
@@ -764,7 +775,6 @@ static octo_tree *make_tree_device(octo_ctx *ctx, const octo_leaf *leaves, int64
         t->data.ptr = nullptr;
         throw;
     }
-    check_hip(hipEventCreateWithFlags(&t->last_use, hipEventDisableTiming), "event");
     tree_release(t.get(), ctx->stream);
     ctx->n_trees++;
     return t.release();
@@ -879,7 +889,7 @@ octo_status octo_tree_level_tables(const octo_tree *t, int32_t level, int64_t *s
         octo_ctx *ctx = t->ctx;
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         DeviceGuard dg(ctx->device);
-        check_hip(hipEventSynchronize(t->last_use), "tree tables");
+        check_hip(hipEventSynchronize(t->last_use->ev), "tree tables");
         const LevelDesc &d = t->ph.levels[level];
         auto get = [](void *dst, const void *src, size_t bytes) {
             if (dst && bytes) check_hip(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost), "tree tables");
@@ -906,8 +916,8 @@ octo_status octo_tree_destroy(octo_tree *t) {
             if (kv.second.tree == t && !kv.second.done)
                 fail(OCTO_E_STATE, "tree has an unfinished request");
         // the tree's own last work, not everything queued on the stream since
-        hipEventSynchronize(t->last_use);
-        hipEventDestroy(t->last_use);
+        hipEventSynchronize(t->last_use->ev);
+        t->last_use.reset();
         if (t->ctx->batch &&
             std::find(t->ctx->batch->sig.begin(), t->ctx->batch->sig.end(), t) != t->ctx->batch->sig.end())
             t->ctx->invalidate_batches();
@@ -964,17 +974,7 @@ octo_status octo_solve(octo_ctx *ctx, octo_tree *tree, const octo_opts *opts, do
                 stats->n_leaf_cells = n;
                 stats->device_ms = dms;
             }
-            if (ctx->profiling)
-            {
-                for (int i = 0; i < 7; ++i) {
-                    float pm = 0.f;
-                    hipEventElapsedTime(&pm, ctx->phase_ev[i], ctx->phase_ev[i + 1]);
-                    stats->phase_ms[i] = pm;
-                }
-                float pm = 0.f;
-                hipEventElapsedTime(&pm, ctx->phase_ev[8], ctx->phase_ev[4]);
-                stats->phase_ms[7] = pm;
-            }
+            if (ctx->profiling) phase_times(ctx, stats->phase_ms);
         }
     });
 }

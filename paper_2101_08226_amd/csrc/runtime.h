@@ -221,6 +221,21 @@ struct LayBuf {
 };
 }  // namespace octo
 
+namespace octo {
+// An event recorded after the last work enqueued on a tree's memory; the
+// trees of one batched launch share one (a single record for all of them:
+// each record is a packet the device processes in order, about 4 us apiece).
+struct UseMark {
+    hipEvent_t ev = nullptr;
+    UseMark() {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) throw Error{OCTO_E_DEVICE, "event"};
+    }
+    ~UseMark() { hipEventDestroy(ev); }
+    UseMark(const UseMark &) = delete;
+    UseMark &operator=(const UseMark &) = delete;
+};
+}  // namespace octo
+
 struct octo_ctx {
     // serialises every call that touches the context (several threads may
     // build trees at once: validation and layout happen before the lock)
@@ -292,7 +307,7 @@ struct octo_tree {
     bool leaf_lds = true;  // leaf targets of multipole work in the LDS-staged kernel
     double *rho = nullptr;
     double *stage = nullptr;  // device staging of phi, g for host outputs
-    hipEvent_t last_use = nullptr;  // recorded after the last work enqueued on the tree's memory
+    std::shared_ptr<octo::UseMark> last_use;  // recorded after the last work enqueued on the tree's memory
     hipStream_t last_stream = nullptr;  // the stream last_use was recorded on
     size_t bytes = 0;
     std::map<std::pair<uint64_t, int>, hipGraphExec_t> graphs;  // (theta bits, precision)
@@ -303,15 +318,22 @@ namespace octo {
 // stream (a launch wave of the request server); a no-op wait is skipped.
 inline void tree_acquire(octo_ctx *ctx, octo_tree *t) {
     if (t->last_stream && t->last_stream != ctx->stream) {
-        if (hipStreamWaitEvent(ctx->stream, t->last_use, 0) != hipSuccess)
+        if (hipStreamWaitEvent(ctx->stream, t->last_use->ev, 0) != hipSuccess)
             throw Error{OCTO_E_DEVICE, "stream wait on a tree's last use"};
     }
 }
-// record the tree's last use on stream s
-inline void tree_release(octo_tree *t, hipStream_t s) {
-    if (hipEventRecord(t->last_use, s) != hipSuccess) throw Error{OCTO_E_DEVICE, "event record"};
-    t->last_stream = s;
+// record the last use of trees[0, n) on stream s: one event for all of them
+// (a fresh one: an event another tree still holds is not moved)
+inline void trees_release(octo_tree *const *trees, int n, hipStream_t s) {
+    if (n <= 0) return;
+    auto m = std::make_shared<UseMark>();
+    if (hipEventRecord(m->ev, s) != hipSuccess) throw Error{OCTO_E_DEVICE, "event record"};
+    for (int i = 0; i < n; ++i) {
+        trees[i]->last_use = m;
+        trees[i]->last_stream = s;
+    }
 }
+inline void tree_release(octo_tree *t, hipStream_t s) { trees_release(&t, 1, s); }
 // launch a plan through a cached graph (captured on first use) or directly
 void run_plan(octo_ctx *ctx, Plan &plan, std::map<std::pair<uint64_t, int>, hipGraphExec_t> &graphs,
               const std::vector<TreeDesc> &want, const octo_opts *o, bool count = true, bool source = false,
@@ -357,6 +379,7 @@ void layout_device_tables(octo_ctx *ctx, const LayTables &t);
 void layout_device_abort(octo_ctx *ctx);
 void layout_device_release(octo_ctx *ctx);
 void build_tree_plan(octo_tree *t);
+void phase_times(const octo_ctx *ctx, double *phase_ms);
 void plan_items(const octo_tree *t, const std::vector<int> &parts, const std::vector<int> &m2l_lds, PlanHost &ph);
 double lds_launch_cost(const std::vector<int64_t> &n_int, const std::vector<int> &g, int n_cu);
 }  // namespace octo
