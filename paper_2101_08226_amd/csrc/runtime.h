@@ -230,7 +230,7 @@ struct UseMark {
     UseMark() {
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) throw Error{OCTO_E_DEVICE, "event"};
     }
-    ~UseMark() { hipEventDestroy(ev); }
+    ~UseMark() { (void)hipEventDestroy(ev); }
     UseMark(const UseMark &) = delete;
     UseMark &operator=(const UseMark &) = delete;
 };
