@@ -12,6 +12,7 @@ and records the latency from arrival to result.
 """
 from __future__ import annotations
 
+import gc
 import time
 from collections import deque
 from concurrent.futures import Future, ThreadPoolExecutor
@@ -102,6 +103,13 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
     records: List[Record] = []
     outputs = {}
     pool = ThreadPoolExecutor(max_workers=max(1, builders))
+    # Objects alive before the run (the payloads, the caller's state) are
+    # moved out of the collector's generations for its duration: a full
+    # collection scanning them holds the interpreter lock for tens of
+    # milliseconds, and every thread that calls into Python (the device
+    # allocator's callbacks in the builders, the admission loop) waits for it.
+    gc.collect()
+    gc.freeze()
     t0 = time.perf_counter()
     try:
         while nxt < len(pending) or queue or inflight:
@@ -206,6 +214,7 @@ def serve(ctx: Context, payloads: List[Payload], keep_outputs: bool = False, pol
                 except OctoError:
                     pass
         pool.shutdown(wait=True)
+        gc.unfreeze()
     wall = time.perf_counter() - t0
     serve.last_profile = prof
     return records, outputs, wall
