@@ -189,6 +189,18 @@ octo_status octo_ctx_memory(const octo_ctx *ctx, size_t *bytes_in_use, size_t *b
  * nesting, density negative or not finite), OCTO_E_BUDGET, OCTO_E_DEVICE. */
 octo_status octo_tree_build(octo_ctx *ctx, const octo_leaf *leaves, int64_t n_leaves, const double *rho,
                             int rho_on_device, octo_tree **out);
+/* The same tree from a leaf list in device memory (for leaf lists produced on
+ * the device): the list is checked and laid out by kernels on the context
+ * stream (node set, classification, a sort, the node tables written in
+ * place), the host receives only per-level counts and per-node flags.  leaves
+ * and rho (n_leaves x 512, same layout as octo_tree_build) are device
+ * memory, read before the call returns; the density is not checked.  Node
+ * numbering and tables equal octo_tree_build's for the same list.
+ * Errors: as octo_tree_build for the list (the first error found by kind:
+ * level, index, duplicate, overlap, gap, nesting), OCTO_E_BUDGET,
+ * OCTO_E_DEVICE. */
+octo_status octo_tree_build_device(octo_ctx *ctx, const octo_leaf *leaves, int64_t n_leaves, const double *rho,
+                                   octo_tree **out);
 /* Uniform tree: every leaf at `level` (0..6), n = 8 * 2^level cells per axis.
  * rho: n^3 densities indexed (ix*n + iy)*n + iz (iz fastest); results of
  * octo_solve use this same grid layout.  Errors as octo_tree_build. */

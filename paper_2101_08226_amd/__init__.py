@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "OCTO_OK", 1: "OCTO_E_INVALID", 2: "OCTO_E_DEVICE", 3: "OCTO_
 
 # every symbol include/octo.h declares
 EXPORTS = [
-    "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_ctx_set_batch_shapes", "octo_tree_build", "octo_tree_build_uniform",
+    "octo_ctx_create", "octo_ctx_destroy", "octo_ctx_memory", "octo_ctx_set_profiling", "octo_ctx_set_batch_shapes", "octo_tree_build", "octo_tree_build_device", "octo_tree_build_uniform",
     "octo_tree_build_adaptive", "octo_tree_set_density", "octo_tree_get_density", "octo_tree_info", "octo_tree_leaves", "octo_tree_level_tables", "octo_tree_destroy",
     "octo_solve", "octo_solve_device_stats", "octo_tree_autotune", "octo_solve_batch", "octo_solve_dphidt", "octo_gravity_sources", "octo_energy_update", "octo_scf_step", "octo_scf_step_noalloc", "octo_scf_run", "octo_regrid", "octo_submit", "octo_poll", "octo_wait", "octo_last_error", "octo_build_id",
     "octo_host_stencil_sizes", "octo_host_near_lists", "octo_host_near_stage", "octo_host_layout", "octo_host_level_tables", "octo_host_adaptive_leaves",
@@ -134,6 +134,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2101_08226_amd.build` "
                            "or __graft_entry__.build()")
+    # PyTorch first: its HIP runtime is then the one the library binds to.
+    # Loaded the other way round, the process holds two HIP runtimes (the
+    # system's, then PyTorch's bundled one) and the second to start finds no
+    # device.
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     sig = {
         "octo_ctx_create": [_I, _P, ctypes.POINTER(octo_allocator), ctypes.c_size_t, _PP],
@@ -142,6 +147,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "octo_ctx_set_profiling": [_P, _I],
         "octo_ctx_set_batch_shapes": [_P, _I],
         "octo_tree_build": [_P, ctypes.POINTER(octo_leaf), _I64, _D, _I, _PP],
+        "octo_tree_build_device": [_P, _P, _I64, _D, _PP],
         "octo_tree_build_uniform": [_P, _I, _D, _I, _PP],
         "octo_tree_build_adaptive": [_P, DENSITY_FN, BOXMAX_FN, _P, _I, ctypes.c_double, _PP],
         "octo_tree_set_density": [_P, _D, _I],
@@ -244,6 +250,13 @@ def octo_tree_build(ctx: int, leaves: np.ndarray, rho_ptr: int, rho_on_device: b
     out = ctypes.c_void_p()
     _check(load_library().octo_tree_build(ctx, lv.ctypes.data_as(ctypes.POINTER(octo_leaf)), lv.shape[0],
                                           _dptr(rho_ptr), int(rho_on_device), ctypes.byref(out)))
+    return out.value
+
+
+def octo_tree_build_device(ctx: int, leaves_ptr: int, n_leaves: int, rho_ptr: int) -> int:
+    """Tree from a leaf list (n_leaves x 4 int32) and densities in device memory."""
+    out = ctypes.c_void_p()
+    _check(load_library().octo_tree_build_device(ctx, leaves_ptr, int(n_leaves), _dptr(rho_ptr), ctypes.byref(out)))
     return out.value
 
 
@@ -545,6 +558,17 @@ class Context:
     def tree(self, leaves, rho) -> "Tree":
         rho = np.ascontiguousarray(rho, dtype=np.float64)
         return Tree(self, octo_tree_build(self.handle, leaves, rho.ctypes.data, False))
+
+    def tree_from_device(self, leaves, rho) -> "Tree":
+        """Tree laid out on the device from a leaf list and densities in
+        device memory (int32 (n, 4) and float64 (n, 512) tensors)."""
+        torch = self.torch
+        leaves = leaves.to(device=self.device, dtype=torch.int32).contiguous()
+        rho = rho.to(device=self.device, dtype=torch.float64).contiguous()
+        if leaves.dim() != 2 or leaves.shape[1] != 4 or rho.numel() != leaves.shape[0] * 512:
+            raise ValueError("leaves must be (n, 4) and rho n x 512 values")
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))  # the tensors are written first
+        return Tree(self, octo_tree_build_device(self.handle, leaves.data_ptr(), leaves.shape[0], rho.data_ptr()))
 
     def adaptive_tree(self, field, max_level: int, threshold: float) -> "Tree":
         return Tree(self, octo_tree_build_adaptive(self.handle, field, max_level, threshold))

@@ -32,6 +32,16 @@ __global__ __launch_bounds__(64) void k_lay_init(unsigned long long *ctl) {
     for (int i = threadIdx.x; i < kCtlWords; i += 64) ctl[i] = i == 0 ? 0ull : ~0ull;
 }
 
+// the deepest level of a leaf list (clamped to [-1, kMaxLevel + 1])
+__global__ __launch_bounds__(kLayT) void k_lay_deepest(const octo_leaf *leaf, int64_t n, int *out) {
+    const int64_t i = (int64_t)blockIdx.x * kLayT + threadIdx.x;
+    if (i < n) atomicMax(out, std::min(std::max(leaf[i].level, -1), kMaxLevel + 1));
+}
+
+__global__ __launch_bounds__(64) void k_lay_set(int *p, int v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
 __global__ __launch_bounds__(kLayT) void k_lay_leaf(LayK k) {
     const int64_t i = (int64_t)blockIdx.x * kLayT + threadIdx.x;
     if (i < k.n_leaf) lay_mark_leaf(k, i);
@@ -252,6 +262,21 @@ void layout_device(octo_ctx *ctx, const octo_leaf *leaf, int64_t n, int levels, 
     }
 }
 
+int layout_device_levels(octo_ctx *ctx, const octo_leaf *leaf, int64_t n) {
+    if (n <= 0) fail(OCTO_E_INVALID, "empty leaf list");
+    LayBuf &b = ctx->lay;
+    hipStream_t s = ctx->stream;
+    if (!b.deepest) b.deepest = (int *)ctx->dev_alloc(256);
+    hipLaunchKernelGGL(k_lay_set, dim3(1), dim3(64), 0, s, b.deepest, -1);
+    hipLaunchKernelGGL(k_lay_deepest, blocks(n), dim3(kLayT), 0, s, leaf, n, b.deepest);
+    check_hip(hipGetLastError(), "layout levels");
+    int d = -1;
+    check_hip(hipMemcpyAsync(&d, b.deepest, 4, hipMemcpyDeviceToHost, s), "layout levels");
+    check_hip(hipStreamSynchronize(s), "layout levels");
+    // a leaf deeper than kMaxLevel (or above the root) fails the layout's range check
+    return std::min(std::max(d, 0), kMaxLevel) + 1;
+}
+
 void layout_device_tables(octo_ctx *ctx, const LayTables &t) {
     LayBuf &b = ctx->lay;
     hipStream_t s = ctx->stream;
@@ -270,6 +295,7 @@ void layout_device_release(octo_ctx *ctx) {
     LayBuf &b = ctx->lay;
     ctx->dev_free(b.cell, b.cell_bytes);
     ctx->dev_free(b.work, b.work_bytes);
+    ctx->dev_free(b.deepest, 256);
     b = LayBuf{};
 }
 

@@ -734,10 +734,11 @@ static octo_status make_tree(octo_ctx *ctx, const octo_leaf *leaves, int64_t n, 
 }
 
 // A tree from a leaf list and densities in device memory (leaf-list layout),
-// laid out on the device under the context lock; the caller keeps both
-// until the context stream has passed this call's work.
+// laid out on the device under the context lock.  The leaves are read before
+// the call returns; the density too when wait_rho, otherwise the caller
+// keeps it until the context stream has passed this call's work.
 static octo_tree *make_tree_device(octo_ctx *ctx, const octo_leaf *leaves, int64_t n, int levels,
-                                   const double *rho) {
+                                   const double *rho, bool wait_rho) {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     DeviceGuard dg(ctx->device);
     auto t = std::make_unique<octo_tree>();
@@ -746,7 +747,7 @@ static octo_tree *make_tree_device(octo_ctx *ctx, const octo_leaf *leaves, int64
     TreeBlock B;
     try {
         shape_tree(t.get(), B);
-        commit_tree(t.get(), B, nullptr, 0, rho, false);
+        commit_tree(t.get(), B, nullptr, 0, rho, wait_rho);
     } catch (...) {
         layout_device_abort(ctx);
         if (t->data.ptr) {
@@ -778,6 +779,18 @@ static octo_tree *make_tree_device(octo_ctx *ctx, const octo_leaf *leaves, int64
     tree_release(t.get(), ctx->stream);
     ctx->n_trees++;
     return t.release();
+}
+
+octo_status octo_tree_build_device(octo_ctx *ctx, const octo_leaf *leaves, int64_t n_leaves, const double *rho,
+                                   octo_tree **out) {
+    return guard([&] {
+        if (!ctx || !leaves || !rho || !out) fail(OCTO_E_INVALID, "NULL argument");
+        if (n_leaves <= 0) fail(OCTO_E_INVALID, "empty leaf list");
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        DeviceGuard dg(ctx->device);
+        const int levels = layout_device_levels(ctx, leaves, n_leaves);
+        *out = make_tree_device(ctx, leaves, n_leaves, levels, rho, true);
+    });
 }
 
 octo_status octo_tree_build(octo_ctx *ctx, const octo_leaf *leaves, int64_t n_leaves, const double *rho,
@@ -1149,7 +1162,7 @@ octo_status octo_regrid(octo_ctx *ctx, octo_tree *tree, const octo_regrid_params
         tree_acquire(ctx, tree);
         regrid_device(ctx, tree, p->l_max, p->rho_r, r);
         const auto t1 = std::chrono::steady_clock::now();
-        octo_tree *t = make_tree_device(ctx, r.leaves, r.n_leaves, r.levels, r.rho);
+        octo_tree *t = make_tree_device(ctx, r.leaves, r.n_leaves, r.levels, r.rho, false);
         // the old tree's last use: the regrid read it
         tree_release(tree, ctx->stream);
         const auto t2 = std::chrono::steady_clock::now();

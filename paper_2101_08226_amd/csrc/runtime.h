@@ -218,6 +218,7 @@ struct LayBuf {
     int levels = 0;
     int64_t cap = 0;
     LayK pending{};  // the passes of the layout in progress (between layout_device and its tables)
+    int *deepest = nullptr;  // one int: the deepest level of a leaf list (layout_device_levels)
 };
 }  // namespace octo
 
@@ -375,6 +376,9 @@ void regrid_device(octo_ctx *ctx, octo_tree *t, int l_max, double rho_r, RegridO
 // tree); layout_device_tables then writes the node tables of the same list
 // and clears the cells, or layout_device_abort only clears them.
 void layout_device(octo_ctx *ctx, const octo_leaf *leaf, int64_t n, int levels, Layout &L);
+// the level count a device leaf list needs (deepest level + 1, at most
+// kMaxLevel + 1; one synchronisation)
+int layout_device_levels(octo_ctx *ctx, const octo_leaf *leaf, int64_t n);
 void layout_device_tables(octo_ctx *ctx, const LayTables &t);
 void layout_device_abort(octo_ctx *ctx);
 void layout_device_release(octo_ctx *ctx);
