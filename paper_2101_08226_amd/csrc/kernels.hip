@@ -154,6 +154,14 @@ __global__ __launch_bounds__(256) void k_p2m(const LevelDesc *__restrict__ L, co
     const double m = (SRC ? td.src : td.rho)[off] * (h * h * h);
     const size_t ci = (size_t)node * kCells + s;
     ld.mass[ci] = m;
+    if (ld.parent_ld >= 0) {
+        // the parent cell's list of child masses (cross-level near pairs)
+        const LevelDesc pl = L[ld.parent_ld];
+        const int px = 4 * (ld.coord[3 * node] & 1) + (x >> 1), py = 4 * (ld.coord[3 * node + 1] & 1) + (y >> 1),
+                  pz = 4 * (ld.coord[3 * node + 2] & 1) + (z >> 1);
+        const size_t pc = (size_t)ld.parent[node] * kCells + store_idx(px, py, pz);
+        pl.cm[pc * 8 + (((x & 1) << 2) | ((y & 1) << 1) | (z & 1))] = m;
+    }
     if (node < ld.n_rec) {
         const size_t S = (size_t)ld.n_rec * kCells;
         ld.mp[ci] = centre(8 * ld.coord[3 * node] + x, h);
@@ -1258,8 +1266,8 @@ __device__ inline const float *xl_weights<float>(const StencilDev &st) {
 // source point is (h/4) n (X1) or (h/2) n (X2) for an odd-integer vector n
 // fixed per entry and child (X1) or per entry and target class (X2), so the
 // weights 1/|n| and n/|n|^3 are table rows, the same for the whole
-// wavefront.  X1 reads the child masses from global memory, the children of
-// the interior neighbours staged in LDS first; X2 stages the (4 + 2r)^3
+// wavefront.  X1 reads each source cell's 8 child masses as one 64-byte
+// record (the level's cm array, filled by the leaf-mass pass); X2 stages the (4 + 2r)^3
 // cells of the parent level around the node's 4^3 parent cells in s_m (r:
 // the largest offset component; masses of leaves, -1 (COUNT) or 0
 // elsewhere; x2v: this thread's cell, loaded by xl_x2_load).  s_nbr: the 27
@@ -1286,20 +1294,19 @@ __device__ inline void cross_level(const LevelDesc *__restrict__ L, const LevelD
                                    int &cnt) {
     const bool x1 = (flags & kLeafX1) != 0, x2 = (flags & kLeafX2) != 0 && ld.parent_ld >= 0;
     if (!x1 && !x2) return;  // uniform over the work-group
-    __shared__ int s_ch[27 * 8];  // children of the interior neighbour sub-grids, -1 elsewhere
     const int R = st.xl_reach, E = 4 + 2 * R, E3 = E * E * E;
     const double h = ld.h;
     const T *W = xl_weights<T>(st);
-    __syncthreads();  // the same-level sums are done with s_m
-    if (x1 && tid < 27 * 8) {
-        const int nb = s_nbr[tid >> 3];
-        s_ch[tid] = (nb >= 0 && nb < ld.n_int) ? ld.child[nb * 8 + (tid & 7)] : -1;
+    if (x2) {
+        __syncthreads();  // the same-level sums are done with s_m
+        if (tid < E3) s_m[tid] = x2v;
+        __syncthreads();
     }
-    if (x2 && tid < E3) s_m[tid] = x2v;
-    __syncthreads();
     if (x1) {
-        const LevelDesc cl = L[ld.child_ld >= 0 ? ld.child_ld : 0];
-        const GPtr<const double> cmass = gptr(cl.mass);
+        // the child masses of this level's interior cells, 8 per cell in one
+        // 64-byte record (the children next to a leaf are leaves, written by
+        // the leaf-mass pass)
+        const GPtr<const double> cmass = gptr(ld.cm);
         int int_mask = 0;  // neighbour sub-grids that are interior (uniform)
         for (int b = 0; b < 27; ++b) int_mask |= (s_nbr[b] >= 0 && s_nbr[b] < ld.n_int) ? (1 << b) : 0;
         int_mask = __builtin_amdgcn_readfirstlane(int_mask);
@@ -1310,17 +1317,12 @@ __device__ inline void cross_level(const LevelDesc *__restrict__ L, const LevelD
             int dx, dy, dz;
             unpack(st.xl_off[k], dx, dy, dz);
             const int sx = x + dx, sy = y + dy, sz = z + dz;
-            const int b = nbr_slot(sx, sy, sz);
-            const bool inner = s_ch[b * 8] >= 0;
-            const int bx = sx & 7, by = sy & 7, bz = sz & 7;
+            const int nb = s_nbr[nbr_slot(sx, sy, sz)];
+            const bool inner = nb >= 0 && nb < ld.n_int;
+            const size_t at = inner ? ((size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)) * 8 : 0;
             T m[8];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int ux = 2 * bx + (c >> 2), uy = 2 * by + ((c >> 1) & 1), uz = 2 * bz + (c & 1);
-                const int ch = s_ch[b * 8 + ((ux >> 3) << 2) + ((uy >> 3) << 1) + (uz >> 3)];
-                const size_t at = inner ? (size_t)ch * kCells + store_idx(ux & 7, uy & 7, uz & 7) : 0;
-                m[c] = (T)cmass[at];
-            }
+            for (int c = 0; c < 8; ++c) m[c] = (T)cmass[at + c];
             const T *w = W + 64 * k;
 #pragma unroll
             for (int c = 0; c < 8; ++c) {

@@ -75,7 +75,7 @@ int n_parts_for(int n_int, int target) {
 // Offsets in a tree's device data block: every index table first, then the
 // density (together one contiguous upload), then the per-level fields.
 struct TreeBlock {
-    std::vector<size_t> nbr, child, parent, coord, out, mass, mp, loc, lacc, nf, dip;
+    std::vector<size_t> nbr, child, parent, coord, out, mass, mp, loc, lacc, nf, dip, cm;
     size_t rho = 0, stage = 0, upload = 0, bytes = 0;
 };
 
@@ -180,7 +180,7 @@ void shape_tree(octo_tree *t, TreeBlock &B) {
             for (size_t i = 0; i < lds_levels.size(); ++i) t->parts[lds_levels[i]] = g[i];
         }
     }
-    for (auto *v : {&B.nbr, &B.child, &B.parent, &B.coord, &B.out, &B.mass, &B.mp, &B.loc, &B.lacc, &B.nf, &B.dip})
+    for (auto *v : {&B.nbr, &B.child, &B.parent, &B.coord, &B.out, &B.mass, &B.mp, &B.loc, &B.lacc, &B.nf, &B.dip, &B.cm})
         v->assign(nl, 0);
     size_t bytes = 0;
     for (int l = 0; l < nl; ++l) {
@@ -214,6 +214,8 @@ void shape_tree(octo_tree *t, TreeBlock &B) {
         bytes += al((size_t)4 * (h.n_nodes - h.n_int) * kCells * 8);
         B.dip[l] = bytes;
         bytes += al((size_t)3 * h.n_rec * kCells * 8);
+        B.cm[l] = bytes;
+        bytes += al((size_t)h.n_int * kCells * 8 * 8);
     }
     B.stage = bytes;
     bytes += al((size_t)L.n_leaf_cells * 8 * 4);
@@ -292,6 +294,7 @@ void commit_tree(octo_tree *t, const TreeBlock &B, void *img, size_t img_bytes, 
         d.lacc = (double *)(base + B.lacc[l]);
         d.nf = (double *)(base + B.nf[l]);
         d.dip = (double *)(base + B.dip[l]);
+        d.cm = (double *)(base + B.cm[l]);
     }
     t->rho = (double *)(base + B.rho);
     t->stage = (double *)(base + B.stage);

@@ -80,6 +80,9 @@ struct LevelDesc {
     double *lacc;             // kLacc * (n_rec - n_int) * 512
     double *nf;               // 4 * (n_nodes - n_int) * 512: direct-sum phi, g of leaf cells
     double *dip;              // 3 * n_rec * 512: dipole of a second source about the density's centres
+    double *cm;               // n_int * 512 * 8: per interior cell (storage index s), the masses of its 8 child
+                              // cells (a*4 + b*2 + c for child (2x+a, 2y+b, 2z+c)), written by the leaf-mass pass
+                              // where the child node is a leaf (the only children the cross-level pairs read)
 };
 
 struct TreeDesc {
