@@ -147,8 +147,8 @@ def tree_counts(leaves):
 
 def hbm_phases(phases, leaves):
     """Algorithmic bytes of the HBM-bound phases over their measured
-    durations (timing-only profiling): P2M reads rho and writes m (16 B per
-    leaf cell); M2M writes a 160 B record (mass, centre, 6 + 10 moments) per
+    durations (timing-only profiling): P2M reads rho and writes m and the
+    parent cell's child-mass entry (24 B per leaf cell); M2M writes a 160 B record (mass, centre, 6 + 10 moments) per
     interior cell and reads each child once (160 B per interior child cell,
     8 B per leaf child cell); L2L reads 184 B of partial sums and writes 184 B
     of locals per interior cell below the root, plus the parent's 184 B per
@@ -156,7 +156,7 @@ def hbm_phases(phases, leaves):
     B) per leaf cell, plus the parent's locals (184 B per 8 leaf cells)."""
     n_leaf, n_int = tree_counts(leaves)
     root_int = 512 if n_int else 0
-    b = {"p2m": 16.0 * n_leaf,
+    b = {"p2m": 24.0 * n_leaf,
          "m2m": 160.0 * n_int + 160.0 * (n_int - root_int) + 8.0 * n_leaf,
          "l2l": (184.0 * 2 + 23.0) * (n_int - root_int),
          "l2p": (32.0 + 32.0 + 23.0) * n_leaf}
