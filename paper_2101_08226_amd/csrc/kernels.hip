@@ -72,6 +72,27 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
+// The sum over the 64 lanes of a wavefront in lane 63 (other lanes hold
+// partial sums), by data-parallel moves within and across the four 16-lane
+// rows: pairs, quads, row_shr 4 and 8 (the row total in lane 15 of each
+// row), then lane 15 of rows 0 and 2 into rows 1 and 3, and lane 31 into rows
+// 2 and 3.  A fixed order: the same inputs give the same bits.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double wave_total_lane63(double v) {
+    v += dpp_move<0xb1, 0xf>(v);   // quad_perm 1,0,3,2
+    v += dpp_move<0x4e, 0xf>(v);   // quad_perm 2,3,0,1
+    v += dpp_move<0x114, 0xf>(v);  // row_shr 4
+    v += dpp_move<0x118, 0xf>(v);  // row_shr 8
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast 15 (rows 1, 3)
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast 31 (rows 2, 3)
+    return v;
+}
+
 // packed symmetric index helpers for 3rd-order tensors:
 // xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
 // sum_{bc} T_abc u_b u_c for each a
@@ -1621,16 +1642,19 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
     td.g[2 * td.n_leaf_cells + o] = gz;
     if (!stats) return;  // uniform
 
-    // per-wavefront partial sums for the diagnostics
+    // per-wavefront partial sums for the diagnostics; |g| and |x| only set
+    // the scales that the net force and torque are divided by, so the
+    // hardware reciprocal square root is accurate enough for them
     const double m = ld.mass[(size_t)node * kCells + s];
     const double fx = m * gx, fy = m * gy, fz = m * gz;
-    const double gn = sqrt(gx * gx + gy * gy + gz * gz);
-    const double xn = sqrt(cx * cx + cy * cy + cz * cz);
+    const double g2 = gx * gx + gy * gy + gz * gz, x2 = cx * cx + cy * cy + cz * cz;
+    const double gn = g2 > 0.0 ? g2 * __builtin_amdgcn_rsq(g2) : 0.0;
+    const double xn = x2 > 0.0 ? x2 * __builtin_amdgcn_rsq(x2) : 0.0;
     double v[kStat] = {m, fx, fy, fz, cy * fz - cz * fy, cz * fx - cx * fz, cx * fy - cy * fx, m * gn, xn * m * gn};
 #pragma unroll
-    for (int k = 0; k < kStat; ++k) v[k] = wave_sum(v[k]);
+    for (int k = 0; k < kStat; ++k) v[k] = wave_total_lane63(v[k]);
     __shared__ double s_v[8][kStat];
-    if (lane == 0) {
+    if (lane == 63) {
 #pragma unroll
         for (int k = 0; k < kStat; ++k) s_v[p][k] = v[k];
     }
@@ -1643,33 +1667,50 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
 }
 
 // ------------------------------------------------------------------ stats
-// One work-group per tree: fixed-order sums of the per-node partials (each
-// thread a fixed strided subset, then a fixed-shape tree in LDS).
-__global__ __launch_bounds__(1024) void k_stats(const int32_t *__restrict__ leaf_beg,
-                                                const int32_t *__restrict__ m2l_beg,
-                                                const int32_t *__restrict__ m2ln_beg,
-                                                const int32_t *__restrict__ m2lf_beg, int n_m2l, int n_m2ln,
-                                                const double *__restrict__ stat, const int64_t *__restrict__ leaf_cnt,
-                                                const int64_t *__restrict__ m2l_cnt, double *__restrict__ out,
-                                                int counts) {
-    const int t = blockIdx.x;
-    constexpr int NT = 1024;
-    __shared__ double sh[kStat][NT / 64];
-    __shared__ long long shc[3][NT / 64];
+// Per tree, kStatBlocks work-groups each sum a contiguous share of the
+// per-node partials (and of the pair counts) in a fixed order and write
+// them to a slot of their own; the last work-group of the tree to finish (a
+// counter, reset by that work-group for the next solve) adds the slots in
+// slot order.  The same inputs give the same bits however the work-groups
+// are scheduled.
+constexpr int kStatT = 256;
+
+__global__ __launch_bounds__(kStatT) void k_stats(const int32_t *__restrict__ leaf_beg,
+                                                  const int32_t *__restrict__ m2l_beg,
+                                                  const int32_t *__restrict__ m2ln_beg,
+                                                  const int32_t *__restrict__ m2lf_beg, int n_m2l, int n_m2ln,
+                                                  const double *__restrict__ stat,
+                                                  const int64_t *__restrict__ leaf_cnt,
+                                                  const int64_t *__restrict__ m2l_cnt, double *__restrict__ part,
+                                                  int *__restrict__ done, double *__restrict__ out, int counts) {
+    const int t = blockIdx.x / kStatBlocks, b = blockIdx.x % kStatBlocks;
+    auto share = [&](const int32_t *beg, int &i0, int &i1) {
+        const int lo = beg[t], n = beg[t + 1] - lo, per = (n + kStatBlocks - 1) / kStatBlocks;
+        i0 = lo + min(n, b * per);
+        i1 = lo + min(n, (b + 1) * per);
+    };
+    __shared__ double sh[kStat][kStatT / 64];
+    __shared__ long long shc[3][kStatT / 64];
+    __shared__ int s_last;
     double acc[kStat];
 #pragma unroll
     for (int k = 0; k < kStat; ++k) acc[k] = 0.0;
     long long c_m2l = 0, c_dir = 0, c_lds = 0;
-    for (int i = leaf_beg[t] + threadIdx.x; i < leaf_beg[t + 1]; i += NT) {
+    int i0, i1;
+    share(leaf_beg, i0, i1);
+    for (int i = i0 + threadIdx.x; i < i1; i += kStatT) {
 #pragma unroll
         for (int k = 0; k < kStat; ++k) acc[k] += stat[(size_t)i * kStat + k];
         if (counts) c_dir += leaf_cnt[i];
     }
     // pair counts only when the kernels counted them (zero otherwise)
     if (counts) {
-        for (int i = m2l_beg[t] + threadIdx.x; i < m2l_beg[t + 1]; i += NT) c_m2l += m2l_cnt[i];
-        for (int i = m2ln_beg[t] + threadIdx.x; i < m2ln_beg[t + 1]; i += NT) c_lds += m2l_cnt[n_m2l + i];
-        for (int i = m2lf_beg[t] + threadIdx.x; i < m2lf_beg[t + 1]; i += NT) c_m2l += m2l_cnt[n_m2l + n_m2ln + i];
+        share(m2l_beg, i0, i1);
+        for (int i = i0 + threadIdx.x; i < i1; i += kStatT) c_m2l += m2l_cnt[i];
+        share(m2ln_beg, i0, i1);
+        for (int i = i0 + threadIdx.x; i < i1; i += kStatT) c_lds += m2l_cnt[n_m2l + i];
+        share(m2lf_beg, i0, i1);
+        for (int i = i0 + threadIdx.x; i < i1; i += kStatT) c_m2l += m2l_cnt[n_m2l + n_m2ln + i];
     }
 #pragma unroll
     for (int k = 0; k < kStat; ++k) acc[k] = wave_sum(acc[k]);
@@ -1685,16 +1726,30 @@ __global__ __launch_bounds__(1024) void k_stats(const int32_t *__restrict__ leaf
         shc[2][wv] = c_lds;
     }
     __syncthreads();
-    // out per tree: 9 sums, multipole pairs, direct pairs, LDS-kernel pairs
+    // this work-group's slot: 9 sums, multipole pairs, direct pairs, LDS-kernel pairs
+    double *slot = part + ((size_t)t * kStatBlocks + b) * 12;
     if (threadIdx.x < kStat) {
         double v = 0.0;
-        for (int w = 0; w < NT / 64; ++w) v += sh[threadIdx.x][w];
-        out[t * 12 + threadIdx.x] = v;
+        for (int w = 0; w < kStatT / 64; ++w) v += sh[threadIdx.x][w];
+        slot[threadIdx.x] = v;
     } else if (threadIdx.x < kStat + 3) {
         long long v = 0;
-        for (int w = 0; w < NT / 64; ++w) v += shc[threadIdx.x - kStat][w];
-        out[t * 12 + threadIdx.x] = (double)v;
+        for (int w = 0; w < kStatT / 64; ++w) v += shc[threadIdx.x - kStat][w];
+        slot[threadIdx.x] = (double)v;  // exact below 2^53
     }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&done[t], 1) == kStatBlocks - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (threadIdx.x < 12) {
+        const double *ps = part + (size_t)t * kStatBlocks * 12;
+        double v = 0.0;
+        for (int j = 0; j < kStatBlocks; ++j) v += ps[j * 12 + threadIdx.x];
+        out[t * 12 + threadIdx.x] = v;
+    }
+    if (threadIdx.x == 0) done[t] = 0;  // ready for the next solve
 }
 
 // ------------------------------------------------------------------ launch
@@ -1827,9 +1882,9 @@ void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipS
     mark(6);
     // the reductions only when they are asked for (a solve with statistics)
     if (reduce)
-        hipLaunchKernelGGL(k_stats, dim3(p.n_trees), dim3(1024), 0, s, p.d_tree_leaf_beg, p.d_tree_m2l_beg,
-                           p.d_tree_m2ln_beg, p.d_tree_m2lf_beg, p.n_m2l, p.n_m2l_nodes, p.d_stat, p.d_leaf_cnt,
-                           p.d_m2l_cnt, p.d_out, o.count ? 1 : 0);
+        hipLaunchKernelGGL(k_stats, dim3(p.n_trees * kStatBlocks), dim3(kStatT), 0, s, p.d_tree_leaf_beg,
+                           p.d_tree_m2l_beg, p.d_tree_m2ln_beg, p.d_tree_m2lf_beg, p.n_m2l, p.n_m2l_nodes, p.d_stat,
+                           p.d_leaf_cnt, p.d_m2l_cnt, p.d_stat_part, p.d_stat_done, p.d_out, o.count ? 1 : 0);
     mark(7);
     check_hip(hipGetLastError(), "kernel launch");
 }

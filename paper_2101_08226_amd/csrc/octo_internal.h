@@ -41,6 +41,9 @@ constexpr int kLoc = 23;
 constexpr int kLacc = 7;
 // per leaf work item partial sums: M, F (3), T (3), S_F, S_T
 constexpr int kStat = 9;
+// work-groups per tree of the final statistics reduction (each a slot of 12
+// values: the 9 sums and 3 pair counts)
+constexpr int kStatBlocks = 16;
 // halo of one source parity class in the LDS-staged multipole kernel: an
 // 8x8x8 lattice (the class's cells whose parent cells lie within 2 parent
 // cells of the node), x-planes padded to 68 (index ix * kHaloX + iy * kHaloY + iz)

@@ -122,6 +122,8 @@ struct Plan {
     int64_t *d_leaf_cnt = nullptr;  // n_leaf
     int64_t *d_m2l_cnt = nullptr;   // n_m2l + n_m2l_nodes
     double *d_out = nullptr;        // n_trees * 12: stats per tree
+    double *d_stat_part = nullptr;  // n_trees * kStatBlocks * 12: the stats reduction's per-work-group slots
+    int32_t *d_stat_done = nullptr; // n_trees: work-groups of the stats reduction finished (zero between solves)
     DeviceBlock block;
     std::vector<TreeDesc> trees_host;  // current tree descriptors (outputs, G, amc)
 };

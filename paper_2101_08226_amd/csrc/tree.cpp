@@ -643,11 +643,15 @@ size_t plan_layout(const PlanHost &ph, void *dev, Plan &p, std::vector<char> &im
     p.d_tree_m2l_beg = (int32_t *)put(ph.tree_m2l_beg.data(), ph.tree_m2l_beg.size() * sizeof(int32_t));
     p.d_tree_m2ln_beg = (int32_t *)put(ph.tree_m2ln_beg.data(), ph.tree_m2ln_beg.size() * sizeof(int32_t));
     p.d_tree_m2lf_beg = (int32_t *)put(ph.tree_m2lf_beg.data(), ph.tree_m2lf_beg.size() * sizeof(int32_t));
+    // the stats reduction's counters start at zero (uploaded with the image)
+    const std::vector<int32_t> zeros(ph.trees.size(), 0);
+    p.d_stat_done = (int32_t *)put(zeros.data(), zeros.size() * sizeof(int32_t));
     p.d_stat = (double *)reserve(ph.leaf.size() * kStat * sizeof(double));
     p.d_leaf_cnt = (int64_t *)reserve(ph.leaf.size() * sizeof(int64_t));
     // per-item pair counts: per-wavefront items, LDS-staged nodes, LDS-staged leaf targets
     p.d_m2l_cnt = (int64_t *)reserve((ph.m2l.size() + ph.m2l_nodes.size() + ph.m2l_leaf.size()) * sizeof(int64_t));
     p.d_out = (double *)reserve(ph.trees.size() * 12 * sizeof(double));
+    p.d_stat_part = (double *)reserve(ph.trees.size() * kStatBlocks * 12 * sizeof(double));
     p.trees_host = ph.trees;
     return off;
 }
