@@ -154,10 +154,11 @@ __device__ inline void o7_rr(const T *o, T e, T f, T u, T v, T w, T &ox, T &oy, 
 }  // namespace
 
 // ------------------------------------------------------------------ P2M
-// Leaf cells become point masses m = rho h^3 at their centres; record leaves
-// also get their (trivial) multipole record.  SRC: the second source (a
-// density rate) instead of the density; its leaf cells are point sources at
-// the same centres, with zero dipole.
+// Leaf cells become point masses m = rho h^3 at their centres (the record
+// leaves' trivial multipole records are written once, k_leaf_records); each
+// mass also goes into its parent cell's child-mass record.  SRC: the second
+// source (a density rate) instead of the density; its leaf cells are point
+// sources at the same centres, with zero dipole.
 template <bool SRC>
 __global__ __launch_bounds__(256) void k_p2m(const LevelDesc *__restrict__ L, const TreeDesc *__restrict__ T,
                                              const NodeItem *__restrict__ items, int n_items) {
@@ -183,15 +184,30 @@ __global__ __launch_bounds__(256) void k_p2m(const LevelDesc *__restrict__ L, co
         const size_t pc = (size_t)ld.parent[node] * kCells + store_idx(px, py, pz);
         pl.cm[pc * 8 + (((x & 1) << 2) | ((y & 1) << 1) | (z & 1))] = m;
     }
-    if (node < ld.n_rec) {
-        const size_t S = (size_t)ld.n_rec * kCells;
-        ld.mp[ci] = centre(8 * ld.coord[3 * node] + x, h);
-        ld.mp[S + ci] = centre(8 * ld.coord[3 * node + 1] + y, h);
-        ld.mp[2 * S + ci] = centre(8 * ld.coord[3 * node + 2] + z, h);
-        for (int c = 3; c < kRec; ++c) ld.mp[c * S + ci] = 0.0;
-        if (SRC)
-            for (int c = 0; c < 3; ++c) ld.dip[c * S + ci] = 0.0;
-    }
+}
+
+// The multipole record of the record leaves' cells, which no solve changes:
+// centre of mass at the cell centre, zero second and third moments, zero
+// dipole of a second source.  Written once per tree (with its work plan),
+// so the leaf-mass pass writes the masses only.
+__global__ __launch_bounds__(256) void k_leaf_records(const LevelDesc *__restrict__ L,
+                                                      const NodeItem *__restrict__ items, int n_items) {
+    const int it = blockIdx.x >> 1;
+    if (it >= n_items) return;
+    const NodeItem item = items[it];
+    const LevelDesc ld = L[item.ld];
+    const int node = item.node;
+    if (node >= ld.n_rec) return;
+    const int s = ((blockIdx.x & 1) << 8) | threadIdx.x;
+    int x, y, z;
+    local_xyz(s, x, y, z);
+    const double h = ld.h;
+    const size_t S = (size_t)ld.n_rec * kCells, ci = (size_t)node * kCells + s;
+    ld.mp[ci] = centre(8 * ld.coord[3 * node] + x, h);
+    ld.mp[S + ci] = centre(8 * ld.coord[3 * node + 1] + y, h);
+    ld.mp[2 * S + ci] = centre(8 * ld.coord[3 * node + 2] + z, h);
+    for (int c = 3; c < kRec; ++c) ld.mp[c * S + ci] = 0.0;
+    for (int c = 0; c < 3; ++c) ld.dip[c * S + ci] = 0.0;
 }
 
 // ------------------------------------------------------------------ M2M
@@ -1753,6 +1769,12 @@ __global__ __launch_bounds__(kStatT) void k_stats(const int32_t *__restrict__ le
 }
 
 // ------------------------------------------------------------------ launch
+
+void launch_leaf_records(const Plan &p, hipStream_t s) {
+    if (p.n_p2m)
+        hipLaunchKernelGGL(k_leaf_records, dim3(2 * p.n_p2m), dim3(256), 0, s, p.d_levels, p.d_p2m, p.n_p2m);
+    check_hip(hipGetLastError(), "kernel launch");
+}
 
 void launch_solve(const Plan &p, const StencilDev &st, const LaunchOpts &o, hipStream_t s) {
     auto mark = [&](int i) {

@@ -351,6 +351,7 @@ void build_tree_plan(octo_tree *t) {
     void *pin = ctx->pinned_get(img.size(), &got);
     memcpy(pin, img.data(), img.size());
     check_hip(hipMemcpyAsync(mem, pin, img.size(), hipMemcpyHostToDevice, ctx->stream), "plan upload");
+    launch_leaf_records(t->plan, ctx->stream);
     hipEvent_t done = nullptr;
     check_hip(hipEventCreateWithFlags(&done, hipEventDisableTiming), "event");
     check_hip(hipEventRecord(done, ctx->stream), "event");

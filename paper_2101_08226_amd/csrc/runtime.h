@@ -155,6 +155,8 @@ struct LaunchOpts {
 
 // enqueue one full solve of a plan on stream s
 void launch_solve(const Plan &plan, const StencilDev &st, const LaunchOpts &o, hipStream_t s);
+// the record leaves' constant multipole records of a tree (once, with its plan)
+void launch_leaf_records(const Plan &plan, hipStream_t s);
 // coupling of the solve to the hydrodynamic update (single-tree plans)
 void launch_sources(const Plan &p, const double omega[3], const double *rho, const double *s, const double *phi,
                     const double *g, const double *drho, const double *dphi, double *src_s, double *src_e,
