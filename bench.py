@@ -126,7 +126,7 @@ def roofline_m2l(pairs, kernel_ms, traffic=None):
     with statistics) x the per-pair count over its own launch duration (HIP
     events around it, kernels one by one, timing-only profiling)."""
     achieved = pairs * M2L_FLOPS_PER_PAIR / (kernel_ms * 1e-3) / 1e12
-    # the multipole kernel is FP64 in both precisions (the mixed mode's FP32 is the near field's)
+    # the FP64 solve's kernel, against the FP64 peak (the mixed mode's FP32 variant is reported by its time only)
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
             "kernel": LDS_KERNEL, "kernel_ms": round(kernel_ms, 4), "pairs_per_launch": int(pairs),
@@ -134,8 +134,7 @@ def roofline_m2l(pairs, kernel_ms, traffic=None):
 
 
 def tree_counts(leaves):
-    """Leaf cells, interior cells, and leaf cells below an interior node (all
-    but root-level leaves) of a leaf list."""
+    """Leaf cells and interior cells of a leaf list."""
     interior = set()
     for l, x, y, z in leaves:
         for k in range(1, int(l) + 1):

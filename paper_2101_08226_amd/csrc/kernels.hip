@@ -172,17 +172,18 @@ __global__ __launch_bounds__(256) void k_p2m(const LevelDesc *__restrict__ L, co
     int x, y, z;
     local_xyz(s, x, y, z);
     const double h = ld.h;
-    const int64_t off = ld.out_base[node] + x * td.sx + y * td.sy + z * td.sz;
-    const double m = (SRC ? td.src : td.rho)[off] * (h * h * h);
+    const int64_t off = gptr(ld.out_base)[node] + x * td.sx + y * td.sy + z * td.sz;
+    const double m = gptr(SRC ? td.src : td.rho)[off] * (h * h * h);
     const size_t ci = (size_t)node * kCells + s;
-    ld.mass[ci] = m;
+    gptr(ld.mass)[ci] = m;
     if (ld.parent_ld >= 0) {
         // the parent cell's list of child masses (cross-level near pairs)
         const LevelDesc pl = L[ld.parent_ld];
-        const int px = 4 * (ld.coord[3 * node] & 1) + (x >> 1), py = 4 * (ld.coord[3 * node + 1] & 1) + (y >> 1),
-                  pz = 4 * (ld.coord[3 * node + 2] & 1) + (z >> 1);
-        const size_t pc = (size_t)ld.parent[node] * kCells + store_idx(px, py, pz);
-        pl.cm[pc * 8 + (((x & 1) << 2) | ((y & 1) << 1) | (z & 1))] = m;
+        const GPtr<const int32_t> coord = gptr(ld.coord);
+        const int px = 4 * (coord[3 * node] & 1) + (x >> 1), py = 4 * (coord[3 * node + 1] & 1) + (y >> 1),
+                  pz = 4 * (coord[3 * node + 2] & 1) + (z >> 1);
+        const size_t pc = (size_t)gptr(ld.parent)[node] * kCells + store_idx(px, py, pz);
+        gptr(pl.cm)[pc * 8 + (((x & 1) << 2) | ((y & 1) << 1) | (z & 1))] = m;
     }
 }
 
@@ -221,6 +222,11 @@ __global__ __launch_bounds__(256) void k_m2m(const LevelDesc *__restrict__ L, co
     const NodeItem item = items[it];
     const LevelDesc ld = L[item.ld];
     const LevelDesc cl = L[ld.child_ld];
+    // the two levels' arrays as global pointers (global loads count only
+    // against the vector-memory counter)
+    const GPtr<const int32_t> child = gptr(ld.child), ccoord = gptr(cl.coord);
+    const GPtr<const double> cmass = gptr(cl.mass), cmp = gptr(cl.mp);
+    const GPtr<double> mass = gptr(ld.mass), mp = gptr(ld.mp);
     const int node = item.node;
     const int s = ((blockIdx.x & 1) << 8) | threadIdx.x;
     int x, y, z;
@@ -230,27 +236,27 @@ __global__ __launch_bounds__(256) void k_m2m(const LevelDesc *__restrict__ L, co
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int cx = 2 * x + (c >> 2), cy = 2 * y + ((c >> 1) & 1), cz = 2 * z + (c & 1);
-        cn[c] = ld.child[node * 8 + ((cx >> 3) << 2) + ((cy >> 3) << 1) + (cz >> 3)];
+        cn[c] = child[node * 8 + ((cx >> 3) << 2) + ((cy >> 3) << 1) + (cz >> 3)];
         cs[c] = store_idx(cx & 7, cy & 7, cz & 7);
     }
     auto child_com = [&](int c, double &zx, double &zy, double &zz) {
         const size_t ci = (size_t)cn[c] * kCells + cs[c];
         if (cn[c] < cl.n_rec) {
-            zx = cl.mp[ci];
-            zy = cl.mp[CS + ci];
-            zz = cl.mp[2 * CS + ci];
+            zx = cmp[ci];
+            zy = cmp[CS + ci];
+            zz = cmp[2 * CS + ci];
         } else {
             const int cx = 2 * x + (c >> 2), cy = 2 * y + ((c >> 1) & 1), cz = 2 * z + (c & 1);
-            const int ch = ld.child[node * 8 + ((cx >> 3) << 2) + ((cy >> 3) << 1) + (cz >> 3)];
-            zx = centre(8 * cl.coord[3 * ch] + (cx & 7), cl.h);
-            zy = centre(8 * cl.coord[3 * ch + 1] + (cy & 7), cl.h);
-            zz = centre(8 * cl.coord[3 * ch + 2] + (cz & 7), cl.h);
+            const int ch = child[node * 8 + ((cx >> 3) << 2) + ((cy >> 3) << 1) + (cz >> 3)];
+            zx = centre(8 * ccoord[3 * ch] + (cx & 7), cl.h);
+            zy = centre(8 * ccoord[3 * ch + 1] + (cy & 7), cl.h);
+            zz = centre(8 * ccoord[3 * ch + 2] + (cz & 7), cl.h);
         }
     };
     double m = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const double cm = cl.mass[(size_t)cn[c] * kCells + cs[c]];
+        const double cm = cmass[(size_t)cn[c] * kCells + cs[c]];
         double zx, zy, zz;
         child_com(c, zx, zy, zz);
         m += cm;
@@ -264,25 +270,25 @@ __global__ __launch_bounds__(256) void k_m2m(const LevelDesc *__restrict__ L, co
         Zy = my / m;
         Zz = mz / m;
     } else {
-        Zx = centre(8 * ld.coord[3 * node] + x, ld.h);
-        Zy = centre(8 * ld.coord[3 * node + 1] + y, ld.h);
-        Zz = centre(8 * ld.coord[3 * node + 2] + z, ld.h);
+        Zx = centre(8 * gptr(ld.coord)[3 * node] + x, ld.h);
+        Zy = centre(8 * gptr(ld.coord)[3 * node + 1] + y, ld.h);
+        Zz = centre(8 * gptr(ld.coord)[3 * node + 2] + z, ld.h);
     }
     double Q[6] = {0, 0, 0, 0, 0, 0};
     double O[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll 1
     for (int c = 0; c < 8; ++c) {
         const size_t ci = (size_t)cn[c] * kCells + cs[c];
-        const double cm = cl.mass[ci];
+        const double cm = cmass[ci];
         double zx, zy, zz;
         child_com(c, zx, zy, zz);
         const double sx = zx - Zx, sy = zy - Zy, sz = zz - Zz;
         double q[6] = {0, 0, 0, 0, 0, 0}, o[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (cn[c] < cl.n_rec) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) q[k] = cl.mp[(3 + k) * CS + ci];
+            for (int k = 0; k < 6; ++k) q[k] = cmp[(3 + k) * CS + ci];
 #pragma unroll
-            for (int k = 0; k < 10; ++k) o[k] = cl.mp[(9 + k) * CS + ci];
+            for (int k = 0; k < 10; ++k) o[k] = cmp[(9 + k) * CS + ci];
         }
         // second moments: q_ab + m s_a s_b
         Q[0] += q[0] + cm * sx * sx;
@@ -306,14 +312,14 @@ __global__ __launch_bounds__(256) void k_m2m(const LevelDesc *__restrict__ L, co
     }
     const size_t pi = (size_t)node * kCells + s;
     const size_t PS = (size_t)ld.n_rec * kCells;
-    ld.mass[pi] = m;
-    ld.mp[pi] = Zx;
-    ld.mp[PS + pi] = Zy;
-    ld.mp[2 * PS + pi] = Zz;
+    mass[pi] = m;
+    mp[pi] = Zx;
+    mp[PS + pi] = Zy;
+    mp[2 * PS + pi] = Zz;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) ld.mp[(3 + k) * PS + pi] = Q[k];
+    for (int k = 0; k < 6; ++k) mp[(3 + k) * PS + pi] = Q[k];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) ld.mp[(9 + k) * PS + pi] = O[k];
+    for (int k = 0; k < 10; ++k) mp[(9 + k) * PS + pi] = O[k];
 }
 
 // Second source: moments of orders 0-3 of the children's second-source
@@ -329,6 +335,11 @@ __global__ __launch_bounds__(256) void k_m2m_src(const LevelDesc *__restrict__ L
     const NodeItem item = items[it];
     const LevelDesc ld = L[item.ld];
     const LevelDesc cl = L[ld.child_ld];
+    // the two levels' arrays as global pointers (global loads count only
+    // against the vector-memory counter)
+    const GPtr<const int32_t> child = gptr(ld.child), ccoord = gptr(cl.coord);
+    const GPtr<const double> cmass = gptr(cl.mass), cmp = gptr(cl.mp), cdip = gptr(cl.dip);
+    const GPtr<double> mass = gptr(ld.mass), mp = gptr(ld.mp), dip = gptr(ld.dip);
     const int node = item.node;
     const int s = ((blockIdx.x & 1) << 8) | threadIdx.x;
     int x, y, z;
@@ -336,32 +347,32 @@ __global__ __launch_bounds__(256) void k_m2m_src(const LevelDesc *__restrict__ L
     const size_t CS = (size_t)cl.n_rec * kCells;
     const size_t pi = (size_t)node * kCells + s;
     const size_t PS = (size_t)ld.n_rec * kCells;
-    const double Zx = ld.mp[pi], Zy = ld.mp[PS + pi], Zz = ld.mp[2 * PS + pi];
+    const double Zx = mp[pi], Zy = mp[PS + pi], Zz = mp[2 * PS + pi];
     double m = 0.0, D[3] = {0, 0, 0};
     double Q[6] = {0, 0, 0, 0, 0, 0};
     double O[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll 1
     for (int c = 0; c < 8; ++c) {
         const int cx = 2 * x + (c >> 2), cy = 2 * y + ((c >> 1) & 1), cz = 2 * z + (c & 1);
-        const int cn = ld.child[node * 8 + ((cx >> 3) << 2) + ((cy >> 3) << 1) + (cz >> 3)];
+        const int cn = child[node * 8 + ((cx >> 3) << 2) + ((cy >> 3) << 1) + (cz >> 3)];
         const size_t ci = (size_t)cn * kCells + store_idx(cx & 7, cy & 7, cz & 7);
-        const double cm = cl.mass[ci];
+        const double cm = cmass[ci];
         double zx, zy, zz;
         double d[3] = {0, 0, 0}, q[6] = {0, 0, 0, 0, 0, 0}, o[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (cn < cl.n_rec) {
-            zx = cl.mp[ci];
-            zy = cl.mp[CS + ci];
-            zz = cl.mp[2 * CS + ci];
+            zx = cmp[ci];
+            zy = cmp[CS + ci];
+            zz = cmp[2 * CS + ci];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) d[k] = cl.dip[k * CS + ci];
+            for (int k = 0; k < 3; ++k) d[k] = cdip[k * CS + ci];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) q[k] = cl.mp[(3 + k) * CS + ci];
+            for (int k = 0; k < 6; ++k) q[k] = cmp[(3 + k) * CS + ci];
 #pragma unroll
-            for (int k = 0; k < 10; ++k) o[k] = cl.mp[(9 + k) * CS + ci];
+            for (int k = 0; k < 10; ++k) o[k] = cmp[(9 + k) * CS + ci];
         } else {
-            zx = centre(8 * cl.coord[3 * cn] + (cx & 7), cl.h);
-            zy = centre(8 * cl.coord[3 * cn + 1] + (cy & 7), cl.h);
-            zz = centre(8 * cl.coord[3 * cn + 2] + (cz & 7), cl.h);
+            zx = centre(8 * ccoord[3 * cn] + (cx & 7), cl.h);
+            zy = centre(8 * ccoord[3 * cn + 1] + (cy & 7), cl.h);
+            zz = centre(8 * ccoord[3 * cn + 2] + (cz & 7), cl.h);
         }
         const double sx = zx - Zx, sy = zy - Zy, sz = zz - Zz;
         m += cm;
@@ -387,13 +398,13 @@ __global__ __launch_bounds__(256) void k_m2m_src(const LevelDesc *__restrict__ L
         O[8] += o[8] + q[5] * sy + 2.0 * q[4] * sz + d[1] * sz * sz + 2.0 * d[2] * sy * sz + cm * sy * sz * sz;  // yzz
         O[9] += o[9] + 3.0 * q[5] * sz + 3.0 * d[2] * sz * sz + cm * sz * sz * sz;                          // zzz
     }
-    ld.mass[pi] = m;
+    mass[pi] = m;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) ld.dip[k * PS + pi] = D[k];
+    for (int k = 0; k < 3; ++k) dip[k * PS + pi] = D[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) ld.mp[(3 + k) * PS + pi] = Q[k];
+    for (int k = 0; k < 6; ++k) mp[(3 + k) * PS + pi] = Q[k];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) ld.mp[(9 + k) * PS + pi] = O[k];
+    for (int k = 0; k < 10; ++k) mp[(9 + k) * PS + pi] = O[k];
 }
 
 // ------------------------------------------------------------------ M2L
@@ -1129,7 +1140,7 @@ __global__ __launch_bounds__(256) void k_sum_parts(const LevelDesc *__restrict__
     const NodeItem item = items[it];
     const LevelDesc ld = L[item.ld];
     const size_t IS = (size_t)ld.n_int * kCells;
-    double *dst = ld.loc + c * IS + (size_t)item.node * kCells + cell;
+    const GPtr<double> dst = gptr(ld.loc) + c * IS + (size_t)item.node * kCells + cell;
     double v = *dst;
     for (int part = 1; part < ld.n_parts; ++part) v += dst[(size_t)part * kLoc * IS];
     *dst = v;
@@ -1174,11 +1185,12 @@ __global__ __launch_bounds__(256) void k_l2l(const LevelDesc *__restrict__ L, co
     const int s = ((blockIdx.x & 1) << 8) | threadIdx.x;
     const size_t IS = (size_t)ld.n_int * kCells;
     const size_t ci = (size_t)node * kCells + s;
+    const GPtr<double> loc = gptr(ld.loc);
     double v[kLoc];
 #pragma unroll
-    for (int c = 0; c < kLoc; ++c) v[c] = ld.loc[c * IS + ci];
+    for (int c = 0; c < kLoc; ++c) v[c] = loc[c * IS + ci];
     for (int part = 1; part < (parts_done ? 1 : ld.n_parts); ++part) {
-        const double *src = ld.loc + (size_t)part * kLoc * IS + ci;
+        const GPtr<const double> src = loc + (size_t)part * kLoc * IS + ci;
 #pragma unroll
         for (int c = 0; c < kLoc; ++c) v[c] += src[c * IS];
     }
@@ -1189,14 +1201,15 @@ __global__ __launch_bounds__(256) void k_l2l(const LevelDesc *__restrict__ L, co
     const bool has_parent = ld.parent_ld >= 0;  // uniform
     if (has_parent) {
         const LevelDesc pl = L[ld.parent_ld];
-        const int pn = ld.parent[node];
-        const int ox = 4 * (ld.coord[3 * node] & 1), oy = 4 * (ld.coord[3 * node + 1] & 1),
-                  oz = 4 * (ld.coord[3 * node + 2] & 1);
+        const int pn = gptr(ld.parent)[node];
+        const GPtr<const int32_t> coord = gptr(ld.coord);
+        const GPtr<const double> pmp = gptr(pl.mp), ploc = gptr(pl.loc);
+        const int ox = 4 * (coord[3 * node] & 1), oy = 4 * (coord[3 * node + 1] & 1), oz = 4 * (coord[3 * node + 2] & 1);
         const size_t PIS = (size_t)pl.n_int * kCells, PRS = (size_t)pl.n_rec * kCells;
         for (int t = threadIdx.x; t < (3 + kLoc) * 64; t += 256) {
             const int c = t >> 6, j = t & 63;
             const size_t pi = (size_t)pn * kCells + store_idx(ox + (j >> 4), oy + ((j >> 2) & 3), oz + (j & 3));
-            s_par[c][j] = c < 3 ? pl.mp[c * PRS + pi] : pl.loc[(c - 3) * PIS + pi];
+            s_par[c][j] = c < 3 ? pmp[c * PRS + pi] : ploc[(c - 3) * PIS + pi];
         }
     }
     __syncthreads();
@@ -1205,15 +1218,15 @@ __global__ __launch_bounds__(256) void k_l2l(const LevelDesc *__restrict__ L, co
         local_xyz(s, x, y, z);
         const int j = ((x >> 1) << 4) | ((y >> 1) << 2) | (z >> 1);
         const size_t RS = (size_t)ld.n_rec * kCells;
-        const double dx = ld.mp[ci] - s_par[0][j], dy = ld.mp[RS + ci] - s_par[1][j],
-                     dz = ld.mp[2 * RS + ci] - s_par[2][j];
+        const GPtr<const double> mp = gptr(ld.mp);
+        const double dx = mp[ci] - s_par[0][j], dy = mp[RS + ci] - s_par[1][j], dz = mp[2 * RS + ci] - s_par[2][j];
         double P[kLoc];
 #pragma unroll
         for (int c = 0; c < kLoc; ++c) P[c] = s_par[3 + c][j];
         l2l_shift(P, dx, dy, dz, v);
     }
 #pragma unroll
-    for (int c = 0; c < kLoc; ++c) ld.loc[c * IS + ci] = v[c];
+    for (int c = 0; c < kLoc; ++c) loc[c * IS + ci] = v[c];
 }
 
 // ------------------------------------------------------------------ leaves
@@ -1317,8 +1330,9 @@ __device__ inline T xl_x2_load(const LevelDesc *__restrict__ L, const LevelDesc 
     const int R = st.xl_reach, E = 4 + 2 * R;
     if (!(flags & kLeafX2) || ld.parent_ld < 0 || tid >= E * E * E) return (T)0;
     const LevelDesc pl = L[ld.parent_ld];
-    const int sx = 4 * (ld.coord[3 * node] & 1) - R + tid / (E * E), sy = 4 * (ld.coord[3 * node + 1] & 1) - R + (tid / E) % E,
-              sz = 4 * (ld.coord[3 * node + 2] & 1) - R + tid % E;
+    const GPtr<const int32_t> coord = gptr(ld.coord);
+    const int sx = 4 * (coord[3 * node] & 1) - R + tid / (E * E), sy = 4 * (coord[3 * node + 1] & 1) - R + (tid / E) % E,
+              sz = 4 * (coord[3 * node + 2] & 1) - R + tid % E;
     const int nb = s_pnbr[nbr_slot(sx, sy, sz)];
     return nb >= pl.n_int ? (T)gptr(pl.mass)[(size_t)nb * kCells + store_idx(sx & 7, sy & 7, sz & 7)]
                           : (T)(COUNT ? -1 : 0);
@@ -1436,8 +1450,8 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
     __shared__ int s_nbr[27];
     __shared__ int s_pnbr[27];
     if (tid < 27) {
-        s_nbr[tid] = ld.nbr[node * 27 + tid];
-        if (ld.parent_ld >= 0) s_pnbr[tid] = L[ld.parent_ld].nbr[ld.parent[node] * 27 + tid];
+        s_nbr[tid] = gptr(ld.nbr)[node * 27 + tid];
+        if (ld.parent_ld >= 0) s_pnbr[tid] = gptr(L[ld.parent_ld].nbr)[gptr(ld.parent)[node] * 27 + tid];
     }
     __syncthreads();
     const T x2v = xl_x2_load<T, COUNT>(L, ld, item.flags, st, s_pnbr, node, tid);
@@ -1517,10 +1531,11 @@ __global__ __launch_bounds__(512) void k_near(const LevelDesc *__restrict__ L, c
     // direct partners, G applied
     const size_t NS = (size_t)(ld.n_nodes - ld.n_int) * kCells;
     const size_t ni = (size_t)(node - ld.n_int) * kCells + s;
-    ld.nf[ni] = td.G * (double)phi_t;
-    ld.nf[NS + ni] = td.G * (double)gx_t;
-    ld.nf[2 * NS + ni] = td.G * (double)gy_t;
-    ld.nf[3 * NS + ni] = td.G * (double)gz_t;
+    const GPtr<double> nf = gptr(ld.nf);
+    nf[ni] = td.G * (double)phi_t;
+    nf[NS + ni] = td.G * (double)gx_t;
+    nf[2 * NS + ni] = td.G * (double)gy_t;
+    nf[3 * NS + ni] = td.G * (double)gz_t;
     if (COUNT) {
         const int tot = wave_sum(cnt);
         __shared__ int s_c[8];
@@ -1555,21 +1570,26 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
     int x, y, z;
     local_xyz(s, x, y, z);
     const double h = ld.h;
-    const int gx0 = 8 * ld.coord[3 * node], gy0 = 8 * ld.coord[3 * node + 1], gz0 = 8 * ld.coord[3 * node + 2];
+    // the level's arrays as global pointers: their loads then count only
+    // against the vector-memory counter, so waits for the scalar loads of
+    // the descriptors do not also wait for them
+    const GPtr<const int32_t> coord = gptr(ld.coord);
+    const GPtr<const double> nf = gptr(ld.nf), lacc = gptr(ld.lacc);
+    const int gx0 = 8 * coord[3 * node], gy0 = 8 * coord[3 * node + 1], gz0 = 8 * coord[3 * node + 2];
     const double cx = centre(gx0 + x, h), cy = centre(gy0 + y, h), cz = centre(gz0 + z, h);
     const size_t NS = (size_t)(ld.n_nodes - ld.n_int) * kCells;
     const size_t ni = (size_t)(node - ld.n_int) * kCells + s;
-    double phi = ld.nf[ni];
-    double gx = ld.nf[NS + ni], gy = ld.nf[2 * NS + ni], gz = ld.nf[3 * NS + ni];
+    double phi = nf[ni];
+    double gx = nf[NS + ni], gy = nf[2 * NS + ni], gz = nf[3 * NS + ni];
 
     // own multipole-to-local sums (record leaves)
     if (item.flags & kLeafLacc) {
         const size_t LS = (size_t)(ld.n_rec - ld.n_int) * kCells;
         const size_t li = (size_t)(node - ld.n_int) * kCells + s;
-        phi += ld.lacc[li];
-        gx += -ld.lacc[LS + li] + ld.lacc[4 * LS + li];
-        gy += -ld.lacc[2 * LS + li] + ld.lacc[5 * LS + li];
-        gz += -ld.lacc[3 * LS + li] + ld.lacc[6 * LS + li];
+        phi += lacc[li];
+        gx += -lacc[LS + li] + lacc[4 * LS + li];
+        gy += -lacc[2 * LS + li] + lacc[5 * LS + li];
+        gz += -lacc[3 * LS + li] + lacc[6 * LS + li];
     }
     // parent expansion shifted to the cell centre, evaluated there.  The 64
     // parent cells over this node (a 4x4x4 block of the parent) are staged in
@@ -1579,9 +1599,10 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
     const bool has_parent = ld.parent_ld >= 0;  // uniform
     if (has_parent) {
         const LevelDesc pl = L[ld.parent_ld];
-        const int pn = ld.parent[node];
-        const int ox = 4 * (ld.coord[3 * node] & 1), oy = 4 * (ld.coord[3 * node + 1] & 1),
-                  oz = 4 * (ld.coord[3 * node + 2] & 1);
+        const int pn = gptr(ld.parent)[node];
+        const int ox = 4 * (coord[3 * node] & 1), oy = 4 * (coord[3 * node + 1] & 1), oz = 4 * (coord[3 * node + 2] & 1);
+        const GPtr<const int32_t> pcoord = gptr(pl.coord);
+        const GPtr<const double> pmp = gptr(pl.mp), ploc = gptr(pl.loc);
         const size_t PIS = (size_t)pl.n_int * kCells, PRS = (size_t)pl.n_rec * kCells;
         // a deferred parent: the sum of its partial slots (in slot order), then
         // the grandparent's finished expansions over the block (2x2x2 cells)
@@ -1594,22 +1615,23 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
         double gpv = 0.0;
         if (gp_stage && tid >= kGpFirst) {
             const LevelDesc gl = L[pl.parent_ld];
-            const int gn = pl.parent[pn];
-            const int gx = 4 * (pl.coord[3 * pn] & 1) + (ox >> 1), gy = 4 * (pl.coord[3 * pn + 1] & 1) + (oy >> 1),
-                      gz = 4 * (pl.coord[3 * pn + 2] & 1) + (oz >> 1);
+            const int gn = gptr(pl.parent)[pn];
+            const int gx = 4 * (pcoord[3 * pn] & 1) + (ox >> 1), gy = 4 * (pcoord[3 * pn + 1] & 1) + (oy >> 1),
+                      gz = 4 * (pcoord[3 * pn + 2] & 1) + (oz >> 1);
             const int c = (tid - kGpFirst) >> 3, k = (tid - kGpFirst) & 7;
             const size_t gi = (size_t)gn * kCells + store_idx(gx + (k >> 2), gy + ((k >> 1) & 1), gz + (k & 1));
-            gpv = c < 3 ? gl.mp[c * (size_t)gl.n_rec * kCells + gi] : gl.loc[(c - 3) * (size_t)gl.n_int * kCells + gi];
+            gpv = c < 3 ? gptr(gl.mp)[c * (size_t)gl.n_rec * kCells + gi]
+                        : gptr(gl.loc)[(c - 3) * (size_t)gl.n_int * kCells + gi];
         }
         for (int t = tid; t < (3 + kLoc) * 64; t += 512) {
             const int c = t >> 6, j = t & 63;
             const size_t pi = (size_t)pn * kCells + store_idx(ox + (j >> 4), oy + ((j >> 2) & 3), oz + (j & 3));
             double v;
             if (c < 3) {
-                v = pl.mp[c * PRS + pi];
+                v = pmp[c * PRS + pi];
             } else {
-                v = pl.loc[(c - 3) * PIS + pi];
-                for (int part = 1; part < parts; ++part) v += pl.loc[((size_t)part * kLoc + c - 3) * PIS + pi];
+                v = ploc[(c - 3) * PIS + pi];
+                for (int part = 1; part < parts; ++part) v += ploc[((size_t)part * kLoc + c - 3) * PIS + pi];
             }
             s_par[c][j] = v;
         }
@@ -1650,18 +1672,19 @@ __global__ __launch_bounds__(512) void k_l2p(const LevelDesc *__restrict__ L, co
         gy += -(P[2] + L2dy + 0.5 * Ty) + P[21];
         gz += -(P[3] + L2dz + 0.5 * Tz) + P[22];
     }
-    const int64_t o = ld.out_base[node] + x * td.sx + y * td.sy + z * td.sz;
-    td.phi[o] = phi;
+    const int64_t o = gptr(ld.out_base)[node] + x * td.sx + y * td.sy + z * td.sz;
+    gptr(td.phi)[o] = phi;
     if (SRC) return;
-    td.g[o] = gx;
-    td.g[td.n_leaf_cells + o] = gy;
-    td.g[2 * td.n_leaf_cells + o] = gz;
+    const GPtr<double> g = gptr(td.g);
+    g[o] = gx;
+    g[td.n_leaf_cells + o] = gy;
+    g[2 * td.n_leaf_cells + o] = gz;
     if (!stats) return;  // uniform
 
     // per-wavefront partial sums for the diagnostics; |g| and |x| only set
     // the scales that the net force and torque are divided by, so the
     // hardware reciprocal square root is accurate enough for them
-    const double m = ld.mass[(size_t)node * kCells + s];
+    const double m = gptr(ld.mass)[(size_t)node * kCells + s];
     const double fx = m * gx, fy = m * gy, fz = m * gz;
     const double g2 = gx * gx + gy * gy + gz * gz, x2 = cx * cx + cy * cy + cz * cz;
     const double gn = g2 > 0.0 ? g2 * __builtin_amdgcn_rsq(g2) : 0.0;
